@@ -67,6 +67,7 @@ def lib():
         L.orc_count_causal_rows.restype = i64
         L.orc_count_causal_per_row.argtypes = [i64, _D, i64, _I32, i64, _I64, c_int, _I64]
         L.orc_num_threads.argtypes = []
+        L.orc_breakpoints.argtypes = [_D, _D, _D, c_int]
         _lib = L
     return _lib
 
@@ -211,3 +212,11 @@ def count_causal_per_row(vtx, tets, rows=None, m_q=DEFAULT_MQ):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def breakpoints(x4, tet):
+    x4, px = _d(x4)
+    tet, pt = _d(tet)
+    out = np.zeros(64)
+    n = _check(lib().orc_breakpoints(px, pt, out.ctypes.data_as(_D), 64), "breakpoints")
+    return out[:n].copy()

@@ -25,10 +25,14 @@
  * code, with the GPU path):
  *   breakpoints = angles where the cone meets a panel edge (edge events),
  *                 angles where a face plane is tangent to the cone section
- *                 (discriminant C_k^2 + d^2 (B_k^2 - a_k^2) = 0),
- *                 angles where a face root escapes to infinity (B_k = a_k);
- *   between consecutive breakpoints (periodic), skip the piece if L at its
- *   midpoint is 0, else apply n_g-point Gauss-Legendre in the smoothstep
+ *                 at a point of the closed panel (C_k^2 + d^2 (B_k^2 - a_k^2)
+ *                 = 0), angles with B_k = 0 when the hyperboloid vertex
+ *                 (t - |d|, p) lies on face k's plane, and angles with
+ *                 B_k = a_k when the apex lies on face k's plane inside the
+ *                 panel's hyperplane (d = 0, C_k = 0: L jumps there);
+ *   between consecutive breakpoints (periodic), skip the piece if L is 0 at
+ *   its midpoint and at its quarter points, else apply n_g-point
+ *   Gauss-Legendre in the smoothstep
  *   variable phi = a + (b - a)(3u^2 - 2u^3);
  *   with no breakpoint at all, the periodic trapezoid rule with 2 n_g nodes.
  *
@@ -57,6 +61,11 @@
 #define ORC_TWO_PI (2.0 * ORC_PI)
 #define ORC_MAX_BP 64
 #define ORC_MAX_NG 96
+/* Breakpoint hints are added within these fractions of the pair scale
+ * |t - tau_min| + diam (see breakpoints()). */
+#define ORC_TANG_TOL 0.05
+#define ORC_VTX_TOL 0.05
+#define ORC_FLAT_TOL 1e-10
 
 enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_PANEL = -2 };
 
@@ -316,10 +325,26 @@ static double wrap_angle(double a) {
   return r;
 }
 
-/* Breakpoints of L (see header comment). Returns count. */
+/* Tolerance scale of one (apex, panel) pair: |t - tau_min| + panel size. */
+static double pair_scale(const orc_panel* P, double t) {
+  return fabs(t - P->tmin) + P->diam;
+}
+
+/* Breakpoints of L (see header comment).  Returns count.
+ *  - edge events: the cone meets one of the 6 panel edges;
+ *  - tangencies: face k touches the cone section (D_k = 0) at a point of
+ *    the closed panel (L has a square-root end there); also kept when the
+ *    point lies within ORC_TANG_TOL * scale outside, where L is analytic but
+ *    steep, so that the smoothstep nodes cluster there;
+ *  - hyperboloid vertex (t - |d|, p) on face k's plane (a_k |d| + C_k = 0):
+ *    angles with B_k = 0 (the second root crosses r = |d| there); kept as a
+ *    hint while |a_k |d| + C_k| <= ORC_VTX_TOL * scale;
+ *  - apex on face k's plane inside the panel's hyperplane (d = 0, C_k = 0):
+ *    L jumps where B_k = a_k. */
 static int breakpoints(const orc_panel* P, const orc_apex* A, double* bp) {
   int nb = 0;
   double d2 = A->d * A->d;
+  double sc = pair_scale(P, A->t);
   /* edge events: cone meets edge V_i V_j */
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j) {
@@ -332,43 +357,63 @@ static int breakpoints(const orc_panel* P, const orc_apex* A, double* bp) {
       double qb = 2.0 * (a0 * a1 - bu * du - bv * dv);
       double qc = a0 * a0 - bu * bu - bv * bv - d2;
       double lam[2];
-      int nl = quad_roots(qa, qb, qc, lam);
+      int nl;
+      double disc = qb * qb - 4.0 * qa * qc;
+      if (qa != 0.0 && disc < 0.0 && disc >= -1e-12 * (qb * qb + fabs(4.0 * qa * qc))) {
+        /* the cone touches the edge: a double root lost to rounding */
+        lam[0] = -qb / (2.0 * qa);
+        nl = 1;
+      } else {
+        nl = quad_roots(qa, qb, qc, lam);
+      }
       for (int m = 0; m < nl; ++m) {
         double l = lam[m];
         if (!(l >= 0.0 && l <= 1.0)) continue;
         if (a0 + a1 * l < 0.0) continue;   /* forward cone branch */
         double ou = bu + l * du, ov = bv + l * dv;
-        if (ou == 0.0 && ov == 0.0) continue;
+        /* a crossing at the foot point itself (s = 0) has no angle */
+        if (ou * ou + ov * ov <= 1e-20 * sc * sc) continue;
         bp[nb++] = wrap_angle(atan2(ov, ou));
       }
     }
   for (int k = 0; k < 4; ++k) {
     double a = P->fa[k], b = P->fb[k], c = P->fc[k], C = A->C[k];
     double beta = sqrt(b * b + c * c);
-    if (!(beta > 0.0)) continue;
+    if (!(beta > 1e-12)) continue;   /* horizontal face: B_k = 0 for all phi */
     double phik = atan2(c, b);
-    /* tangency: beta^2 cos^2(psi) = a^2 - C^2/d^2 */
+    /* tangency: beta^2 cos^2(psi) = a^2 - C^2/d^2, psi = phi - phi_k */
     if (d2 > 0.0) {
       double rhs = a * a - C * C / d2;
       if (rhs >= 0.0 && rhs <= beta * beta) {
         double cv = sqrt(rhs) / beta;
         if (cv > 1.0) cv = 1.0;
         double g = acos(cv);
-        bp[nb++] = wrap_angle(phik + g);
-        bp[nb++] = wrap_angle(phik - g);
-        bp[nb++] = wrap_angle(phik + ORC_PI - g);
-        bp[nb++] = wrap_angle(phik + ORC_PI + g);
+        double cand[4] = {phik + g, phik - g, phik + ORC_PI - g, phik + ORC_PI + g};
+        for (int m = 0; m < 4; ++m) {
+          double ph = cand[m];
+          double Bt = b * cos(ph) + c * sin(ph);
+          double den = Bt * Bt - a * a;
+          if (den == 0.0 || Bt == 0.0) continue;
+          double rt = a * C / den;               /* double root of the squared eq. */
+          double st = (a * rt + C) / Bt;         /* B s = a r + C on the true branch */
+          if (!(st >= 0.0) || !(rt >= fabs(A->d))) continue;
+          double Y[3] = {A->t - rt, A->pu + st * cos(ph), A->pv + st * sin(ph)};
+          double worst = -INFINITY;
+          for (int m2 = 0; m2 < 4; ++m2) {
+            double v = P->fa[m2] * Y[0] + P->fb[m2] * Y[1] + P->fc[m2] * Y[2] - P->fh[m2];
+            if (v > worst) worst = v;
+          }
+          if (worst <= ORC_TANG_TOL * sc) bp[nb++] = wrap_angle(ph);
+        }
       }
     }
-    /* hyperboloid vertex (t - |d|, p) on the face plane (a_k |d| + C_k = 0):
-     * w = |d| is then a root for every phi and the second root crosses it
-     * where B_k = 0 */
-    if (fabs(a * fabs(A->d) + C) <= 1e-10 * (fabs(A->t) + P->diam)) {
+    /* hyperboloid vertex (t - |d|, p) on the face plane */
+    if (fabs(a * fabs(A->d) + C) <= ORC_VTX_TOL * sc) {
       bp[nb++] = wrap_angle(phik + 0.5 * ORC_PI);
       bp[nb++] = wrap_angle(phik - 0.5 * ORC_PI);
     }
-    /* asymptote: B_k = a_k */
-    if (fabs(a) <= beta) {
+    /* apex on the face plane inside the panel hyperplane: jump at B_k = a_k */
+    if (fabs(A->d) <= ORC_FLAT_TOL * sc && fabs(C) <= ORC_FLAT_TOL * sc && fabs(a) <= beta) {
       double cv = a / beta;
       if (cv > 1.0) cv = 1.0;
       if (cv < -1.0) cv = -1.0;
@@ -503,8 +548,14 @@ static double inner_panel(const orc_panel* P, const double* tet, const double* x
       double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + ORC_TWO_PI;
       double H = b - a;
       if (!(H > 0.0)) continue;
+      /* empty-piece test: L at the midpoint, then at the quarter points
+       * (an isolated zero where the cone touches an edge must not empty a
+       * piece) */
       ++nev;
-      if (L_phi(P, &A, a + 0.5 * H) == 0.0) continue;
+      if (L_phi(P, &A, a + 0.5 * H) == 0.0) {
+        nev += 2;
+        if (L_phi(P, &A, a + 0.25 * H) == 0.0 && L_phi(P, &A, a + 0.75 * H) == 0.0) continue;
+      }
       ++nsub;
       for (int g = 0; g < n_g; ++g) {
         double u = gx[g];
@@ -758,4 +809,16 @@ int orc_num_threads(void) {
 #else
   return 1;
 #endif
+}
+
+int orc_breakpoints(const double* x4, const double* tet, double* out, int cap) {
+  orc_panel P;
+  int rc = panel_setup(tet, &P);
+  if (rc) return rc;
+  orc_apex A;
+  apex_setup(&P, x4, &A);
+  double bp[ORC_MAX_BP];
+  int nb = breakpoints(&P, &A, bp);
+  for (int k = 0; k < nb && k < cap; ++k) out[k] = bp[k];
+  return nb;
 }

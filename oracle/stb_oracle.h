@@ -97,6 +97,9 @@ int orc_count_causal_per_row(int64_t nv, const double* vtx, int64_t nt,
 
 int orc_num_threads(void);
 
+/* Breakpoint angles of L for one (apex, panel) pair (sorted); returns count. */
+int orc_breakpoints(const double* x4, const double* tet, double* out, int cap);
+
 #ifdef __cplusplus
 }
 #endif
