@@ -1,0 +1,145 @@
+/*
+ * stb.h -- C ABI of the MI355X space-time boundary element library.
+ *
+ * Method: Poelz & Schanz, "On the space-time discretization of variational
+ * retarded potential boundary integral equations" (arXiv 2103.16841).
+ *
+ *   * The lateral boundary Sigma = (0,T) x Gamma is meshed by N open
+ *     tetrahedral panels that are "vertical": each lies in R x (plane of a
+ *     spatial triangle), so its space-time normal has no time component
+ *     (Sec. 2, the normal field nu_Sigma; Sec. 3, the mesh Sigma_N).
+ *   * Trial/test space: piecewise constants S_h^0 (Sec. 3, def. st_be).
+ *   * Galerkin matrix of the energetic single-layer form,
+ *       A[i][j] = b_V(phi_j, phi_i)
+ *               = - sum_{F in faces(sigma_i)} int_F nu_{F,t} V phi_j dS
+ *     (eq. df_ind with the outer form eq. int_bform); the face integral is
+ *     the composite centroid rule of Fig. int_tri_mid with m_q^2
+ *     sub-triangles per face (m_q = 3 in Exp. 3).
+ *   * V phi_j (x) = S 1_{sigma_j}(x) with the retarded single-layer kernel
+ *     k1 = 1/(4 pi |x - y|) and c = 1 (eq. slp, eq. kfunc); evaluated on the
+ *     cone-panel intersection (eq. tk_para) in the (r, phi) form where the
+ *     k1 integrand is constant (Lemma kernel_para), r exactly, phi by a
+ *     breakpoint-aware Gauss-Legendre rule with n_g nodes per piece.
+ *
+ * Coordinates: space-time points are (t, x, y, z) in geometrized time.
+ * Row i = test panel, column j = trial panel.  Entries of pairs that are not
+ * causal (no outer point of panel i has a backward light cone crossing
+ * panel j, Sec. 3.3) are exactly +0.0.
+ *
+ * Memory: unless a name ends in _dev, pointer arguments are host memory;
+ * inputs are copied, outputs are caller-allocated and written in full.
+ * _dev entry points take device pointers and a HIP stream (as void*; NULL =
+ * the context's stream) and return after enqueueing.  Handles are owned by
+ * the library and released by the matching *_destroy call.  No exception
+ * crosses this interface; every call returns a stb_status and leaves a
+ * message for stb_last_error().  A context is externally synchronised: do
+ * not call into one context from two threads at once.
+ */
+#ifndef STB_H
+#define STB_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STB_OK = 0,
+  STB_E_INVALID_ARG = 1,   /* null pointer, bad size, bad parameter          */
+  STB_E_INVALID_MESH = 2,  /* index out of range, non-finite coordinate,
+                              non-vertical or degenerate panel               */
+  STB_E_NO_MEMORY = 3,     /* device allocation failed or budget exceeded    */
+  STB_E_DEVICE = 4,        /* HIP runtime error                              */
+  STB_E_NOT_FOUND = 5,     /* unknown id / ticket                            */
+  STB_E_BUSY = 6,          /* resource in use                                */
+  STB_E_INTERNAL = 7
+} stb_status;
+
+typedef enum { STB_FP64 = 0, STB_MIXED = 1 } stb_precision;
+
+/* Quadrature parameters.  m_q: sub-triangles per face edge of the outer
+ * centroid rule (1..4, default 3 as in Exp. 3).  n_g: Gauss-Legendre nodes
+ * per phi piece of the inner rule (2..64, default 16).  eta_far: mixed mode
+ * only; a pair is "far" when the distance between the panels' spatial
+ * bounding balls exceeds eta_far times the larger radius.  prec: FP64 or
+ * mixed (far pairs' phi nodes in FP32 with compensated FP32 sums; cone /
+ * panel geometry, near and coincident pairs always in FP64). */
+typedef struct {
+  int32_t m_q;
+  int32_t n_g;
+  double eta_far;
+  stb_precision prec;
+} stb_quad_params;
+
+typedef struct stb_ctx stb_ctx;
+typedef struct stb_mesh stb_mesh;
+typedef struct stb_mat stb_mat;
+
+/* Default parameters (m_q = 3, n_g = 16, eta_far = 2, FP64). */
+stb_quad_params stb_default_params(void);
+
+/* Create a context on HIP device `device` (its own stream). */
+stb_status stb_ctx_create(int32_t device, stb_ctx** out);
+void stb_ctx_destroy(stb_ctx* ctx);
+const char* stb_status_str(stb_status s);
+/* Message of the last failed call on ctx (or of the last failed
+ * stb_ctx_create when ctx is NULL).  Valid until the next call. */
+const char* stb_last_error(const stb_ctx* ctx);
+
+/* Upload a mesh and precompute per-panel geometry on the device: panel
+ * frames, face half-spaces (eq. pnl_ilf), bounding data and the outer
+ * points / weights of eq. int_bform for m_q = 1..4 on demand.
+ *   vtx: nv x 4 doubles (t, x, y, z), row-major;
+ *   tet: nt x 4 int32 vertex indices.
+ * Validates every panel (STB_E_INVALID_MESH names the first bad one). */
+stb_status stb_mesh_create(stb_ctx* ctx, int64_t nv, const double* vtx, int64_t nt,
+                           const int32_t* tet, stb_mesh** out);
+void stb_mesh_destroy(stb_mesh* mesh);
+int64_t stb_mesh_size(const stb_mesh* mesh);
+
+/* Assemble A over all causal pairs into a device-resident sparse store
+ * (rows of candidate columns from a conservative causal cull; every stored
+ * value that is not causal is +0.0).  params NULL = defaults. */
+stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                          stb_mat** out);
+void stb_mat_destroy(stb_mat* mat);
+
+/* n: matrix order; n_causal_pairs: exact number of causal pairs (Sec. 3.3
+ * lit predicate at the outer points); n_stored: stored candidate entries;
+ * bytes: device bytes held by the store. */
+stb_status stb_mat_info(const stb_mat* mat, int64_t* n, int64_t* n_causal_pairs,
+                        int64_t* n_stored, int64_t* bytes);
+/* Dense copy, n x n row-major FP64 (caller-owned host buffer). */
+stb_status stb_mat_to_dense(const stb_mat* mat, double* out);
+/* k individual entries A[row[m]][col[m]] (host arrays). */
+stb_status stb_mat_get(const stb_mat* mat, int64_t k, const int32_t* row, const int32_t* col,
+                       double* out);
+
+/* y = A w for nrhs right-hand sides; w: n x nrhs row-major, y: n x nrhs.
+ * nrhs == 1: FP64 sparse product.  nrhs == 16: FP32 matrix-core product
+ * (A and W rounded to FP32, FP32 accumulation).  Other nrhs: FP64, one
+ * column at a time. */
+stb_status stb_apply(stb_ctx* ctx, const stb_mat* mat, int32_t nrhs, const double* w, double* y);
+stb_status stb_apply_dev(stb_ctx* ctx, const stb_mat* mat, int32_t nrhs, const double* w_dev,
+                         double* y_dev, void* stream);
+
+/* Retarded single-layer potential u(p) = sum_j w_j V phi_j (p) (eq. slp with
+ * w in S_h^0) at np points pts (np x 4, (t, x, y, z)); w has nt entries. */
+stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                           const double* w, int64_t np, const double* pts, double* out);
+
+/* Single-panel potentials out[m] = V phi_{panel[m]} (pts[m]) for k pairs
+ * (pts: k x 4 (t, x, y, z); panel: k indices into the mesh), the inner
+ * integral of eq. tk_para for one panel, one lane per pair with the same
+ * arithmetic as the assembly.  For checks and diagnostics. */
+stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                            int64_t k, const double* pts, const int32_t* panel, double* out);
+
+/* Timing of the last stb_assemble_V on ctx, in milliseconds measured with
+ * HIP events on the context stream: [0] geometry/outer points, [1] cull and
+ * compaction, [2] clip + quadrature + store, [3] total. */
+stb_status stb_last_timings(const stb_ctx* ctx, double* ms4);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -221,6 +221,9 @@ static void apex_setup(const orc_panel* P, const double* x4, orc_apex* A) {
   A->pu = dot3(v, P->e1);
   A->pv = dot3(v, P->e2);
   A->d = dot3(v, P->n);
+  /* apex in the panel's hyperplane up to rounding: d = 0 exactly (a d of
+   * order 1e-17 would turn C_k / d in the tangency condition into noise) */
+  if (fabs(A->d) <= ORC_FLAT_TOL * (fabs(A->t - P->tmin) + P->diam)) A->d = 0.0;
   for (int k = 0; k < 4; ++k)
     A->C[k] = P->fh[k] - P->fa[k] * A->t - P->fb[k] * A->pu - P->fc[k] * A->pv;
 }

@@ -1,0 +1,533 @@
+// stb_device.h -- device-side geometry and quadrature of the energetic
+// single-layer form (Poelz & Schanz, arXiv 2103.16841) for CDNA4 (gfx950).
+//
+// Notation follows the paper: a panel sigma lies in R x Pi (vertical,
+// Sec. 2); its faces are half-spaces of the tangent hyperplane (eq.
+// pnl_ilf); the backward light cone of x is phi_Xi(x - y) = 0 (eq.
+// sgn_dist_cone).  For an apex x = (t, x) with foot point p on Pi and signed
+// distance d, polar coordinates (s, phi) about p and r = sqrt(s^2 + d^2)
+// turn the single-layer integral (eq. slp) over one panel into
+//     V phi_sigma (x) = (1/4pi) int_0^{2pi} L(phi) dphi,
+//     L(phi) = |{ r >= |d| : (t - r, p + s(r) e(phi)) in sigma }|,
+// the constant-integrand form of Lemma kernel_para.  Face k,
+// a_k tau + b_k u + c_k v < h_k, becomes  B_k s - a_k r < C_k  with
+// B_k = b_k cos phi + c_k sin phi and C_k = h_k - a_k t - b_k p_u - c_k p_v.
+//
+// Device evaluation of L uses w = r + s (so r = (w + d^2/w)/2, s =
+// (w - d^2/w)/2, w >= |d|): face k is then the quadratic inequality
+//     Q_k(w) = (B_k - a_k) w^2 - 2 C_k w - d^2 (B_k + a_k) < 0,
+// whose two roots are both genuine (no squaring), with discriminant
+// C_k^2 + d^2 (B_k^2 - a_k^2).  Opening up (B_k > a_k): an admissible
+// interval; opening down: a hole.  L is the r-measure of the w-interval
+// [w(r_lo), w(r_hi)] cut by the intervals, minus the holes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define STB_HD __host__ __device__
+
+namespace stb {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+constexpr int kMaxBp = 48;        // breakpoints per (apex, panel) pair
+constexpr int kMaxNg = 64;        // Gauss nodes per phi piece
+// breakpoint hint tolerances (fractions of |t - tau_min| + panel size)
+constexpr double kTangHint = 0.05;
+constexpr double kVtxHint = 0.05;
+constexpr double kFlatTol = 1e-10;
+constexpr double kLitDead = 1e-12;
+
+// Per-panel record used when the panel is the trial panel (64 doubles).
+struct TrialRec {
+  double o[3], e1[3], e2[3], n[3];   // spatial frame of the panel plane
+  double fa[4], fb[4], fc[4], fh[4]; // unit outward face normals, offsets
+  double V[4][3];                    // vertices in local (tau, u, v)
+  double X[4][4];                    // vertices (t, x, y, z)
+  double tmin, tmax, diam;           // time range; max(spatial diam, span)
+  double cx, cy, cz, rad;            // spatial bounding ball
+  double pad;
+};
+static_assert(sizeof(TrialRec) == 64 * sizeof(double), "TrialRec layout");
+
+// Bounding data of an apex set (the outer points of a test panel, or one
+// evaluation point) for the conservative causal cull.
+struct ApexBox {
+  double tlo, thi;   // apex time range
+  double cx, cy, cz; // centre of the spatial bounding ball
+  double rho;        // its radius
+  double pad[2];
+};
+
+struct Apex {
+  double t, pu, pv, d;
+  double C[4];
+};
+
+STB_HD __forceinline__ double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+STB_HD __forceinline__ double wrap_2pi(double a) {
+  if (a < 0.0) a += kTwoPi;
+  if (a < 0.0) a += kTwoPi;
+  if (a >= kTwoPi) a -= kTwoPi;
+  if (a >= kTwoPi) a -= kTwoPi;
+  return a;
+}
+
+STB_HD __forceinline__ void apex_of(const TrialRec& T, const double* x4, Apex& A) {
+  double v[3] = {x4[1] - T.o[0], x4[2] - T.o[1], x4[3] - T.o[2]};
+  A.t = x4[0];
+  A.pu = dot3(v, T.e1);
+  A.pv = dot3(v, T.e2);
+  A.d = dot3(v, T.n);
+  // an apex in the panel's hyperplane up to rounding is taken exactly in it:
+  // d of order 1e-17 would make C_k / d (tangency) meaningless
+  if (fabs(A.d) <= kFlatTol * (fabs(A.t - T.tmin) + T.diam)) A.d = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) A.C[k] = T.fh[k] - T.fa[k] * A.t - T.fb[k] * A.pu - T.fc[k] * A.pv;
+}
+
+// w-interval of the admissible time range r in [max(|d|, t - tmax), t - tmin].
+// Returns false when empty.
+STB_HD __forceinline__ bool w_range(const TrialRec& T, const Apex& A, double& wlo,
+                                        double& whi) {
+  double ad = fabs(A.d);
+  double rlo = fmax(ad, A.t - T.tmax);
+  double rhi = A.t - T.tmin;
+  if (!(rhi > rlo)) return false;
+  wlo = rlo + sqrt(fmax((rlo - ad) * (rlo + ad), 0.0));
+  whi = rhi + sqrt(fmax((rhi - ad) * (rhi + ad), 0.0));
+  return true;
+}
+
+STB_HD __forceinline__ double r_of_w(double w, double d2) {
+  return d2 > 0.0 ? 0.5 * (w + d2 / w) : 0.5 * w;
+}
+
+// Face data needed by L(phi): fa, fb, fc of the 4 faces.
+struct FaceSet {
+  double fa[4], fb[4], fc[4];
+};
+
+// L(phi) for cos/sin of phi.  C: C_k, d2 = d^2, [wlo, whi]: admissible w-range.
+STB_HD __forceinline__ double L_eval(const FaceSet& F, const double* C, double d2, double wlo,
+                                         double whi, double cs, double sn) {
+  double lo = wlo, hi = whi;
+  double h0[3], h1[3];
+  int nh = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double a = F.fa[k];
+    double B = fma(F.fb[k], cs, F.fc[k] * sn);
+    double e = B - a, f = B + a, Ck = C[k];
+    double D = fma(Ck, Ck, d2 * (e * f));
+    if (e > 0.0) {
+      if (!(D > 0.0)) return 0.0;
+      double q = Ck + copysign(sqrt(D), Ck);
+      double r1 = q / e, r2 = -d2 * f / q;
+      lo = fmax(lo, fmin(r1, r2));
+      hi = fmin(hi, fmax(r1, r2));
+    } else if (e < 0.0) {
+      if (!(D > 0.0)) continue;
+      double q = Ck + copysign(sqrt(D), Ck);
+      double r1 = q / e, r2 = -d2 * f / q;
+      // the area-weighted outward normals sum to zero, so at most three
+      // faces open downwards
+      if (nh < 3) {
+        h0[nh] = fmin(r1, r2);
+        h1[nh] = fmax(r1, r2);
+        ++nh;
+      }
+    } else {
+      // linear: -2 C w - d^2 f < 0
+      if (Ck > 0.0) lo = fmax(lo, -d2 * f / (2.0 * Ck));
+      else if (Ck < 0.0) hi = fmin(hi, -d2 * f / (2.0 * Ck));
+      else if (!(d2 * f > 0.0)) return 0.0;
+    }
+  }
+  if (!(hi > lo)) return 0.0;
+  double len = r_of_w(hi, d2) - r_of_w(lo, d2);
+  // clip the holes to [lo, hi], sort by start and subtract their union
+  double s[3], t[3];
+  int m = 0;
+  for (int k = 0; k < nh; ++k) {
+    double a0 = fmax(h0[k], lo), a1 = fmin(h1[k], hi);
+    if (a1 > a0) { s[m] = a0; t[m] = a1; ++m; }
+  }
+  if (m > 1) {
+    for (int i = 1; i < m; ++i)
+      for (int j = i; j > 0 && s[j - 1] > s[j]; --j) {
+        double ts = s[j]; s[j] = s[j - 1]; s[j - 1] = ts;
+        double tt = t[j]; t[j] = t[j - 1]; t[j - 1] = tt;
+      }
+  }
+  double cs0 = 0.0, ce0 = 0.0;
+  bool open = false;
+  for (int k = 0; k < m; ++k) {
+    if (!open) { cs0 = s[k]; ce0 = t[k]; open = true; }
+    else if (s[k] <= ce0) { ce0 = fmax(ce0, t[k]); }
+    else { len -= r_of_w(ce0, d2) - r_of_w(cs0, d2); cs0 = s[k]; ce0 = t[k]; }
+  }
+  if (open) len -= r_of_w(ce0, d2) - r_of_w(cs0, d2);
+  return len > 0.0 ? len : 0.0;
+}
+
+// Exact extrema of f(y) = |x - y| - (t - tau) over the closed panel:
+// max at a vertex; min among vertices, stationary points on the 6 edges and
+// in the non-vertical faces.  Returns the lit decision with the relative
+// dead zone kLitDead * (|t - tmin| + diam).
+STB_HD inline bool lit_test(const TrialRec& T, const double* x4, const Apex& A) {
+  double mn = 1e300, mx = -1e300;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double dx = x4[1] - T.X[k][1], dy = x4[2] - T.X[k][2], dz = x4[3] - T.X[k][3];
+    double f = sqrt(dx * dx + dy * dy + dz * dz) - (x4[0] - T.X[k][0]);
+    mn = fmin(mn, f);
+    mx = fmax(mx, f);
+  }
+  double dead = kLitDead * (fabs(A.t - T.tmin) + T.diam);
+  if (!(mx > dead)) return false;
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j) {
+      double U[3] = {T.X[j][1] - T.X[i][1], T.X[j][2] - T.X[i][2], T.X[j][3] - T.X[i][3]};
+      double P[3] = {T.X[i][1] - x4[1], T.X[i][2] - x4[2], T.X[i][3] - x4[3]};
+      double Dt = T.X[j][0] - T.X[i][0];
+      double a = dot3(U, U), b = 2.0 * dot3(P, U);
+      double g = a - Dt * Dt;
+      if (!(a > 0.0 && g > 0.0)) continue;
+      double cr0 = P[1] * U[2] - P[2] * U[1];
+      double cr1 = P[2] * U[0] - P[0] * U[2];
+      double cr2 = P[0] * U[1] - P[1] * U[0];
+      double hw = fabs(Dt) / (2.0 * a) * sqrt(4.0 * (cr0 * cr0 + cr1 * cr1 + cr2 * cr2) / g);
+      double lc = -b / (2.0 * a);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        double l = m ? lc + hw : lc - hw;
+        if (!(l > 0.0 && l < 1.0)) continue;
+        double y0 = T.X[i][0] + l * Dt;
+        double y1 = P[0] + l * U[0], y2 = P[1] + l * U[1], y3 = P[2] + l * U[2];
+        double f = sqrt(y1 * y1 + y2 * y2 + y3 * y3) - (x4[0] - y0);
+        mn = fmin(mn, f);
+      }
+    }
+  // faces: tau linear over the face's spatial triangle with gradient g;
+  // stationary point y = p - g |d| / sqrt(1 - |g|^2) when |g| < 1
+  double sc2 = T.diam * T.diam;
+  for (int k = 0; k < 4; ++k) {
+    int i0 = k == 0 ? 1 : 0;
+    int i1 = k <= 1 ? 2 : 1;
+    int i2 = k <= 2 ? 3 : 2;
+    const double* V0 = T.V[i0];
+    double Uu = T.V[i1][1] - V0[1], Uv = T.V[i1][2] - V0[2];
+    double Wu = T.V[i2][1] - V0[1], Wv = T.V[i2][2] - V0[2];
+    double D1 = T.V[i1][0] - V0[0], D2 = T.V[i2][0] - V0[0];
+    double det = Uu * Wv - Uv * Wu;
+    if (!(fabs(det) > 1e-12 * sc2)) continue;
+    double gu = (D1 * Wv - D2 * Uv) / det;
+    double gv = (Uu * D2 - Wu * D1) / det;
+    double g2 = gu * gu + gv * gv;
+    if (!(g2 < 1.0)) continue;
+    double fac = fabs(A.d) / sqrt(1.0 - g2);
+    double yu = A.pu - gu * fac, yv = A.pv - gv * fac;
+    double ru = yu - V0[1], rv = yv - V0[2];
+    double al = (ru * Wv - rv * Wu) / det;
+    double be = (Uu * rv - Uv * ru) / det;
+    if (!(al >= 0.0 && be >= 0.0 && al + be <= 1.0)) continue;
+    double tau = V0[0] + gu * ru + gv * rv;
+    double du = A.pu - yu, dv = A.pv - yv;
+    double f = sqrt(du * du + dv * dv + A.d * A.d) - (A.t - tau);
+    mn = fmin(mn, f);
+  }
+  return mn < -dead;
+}
+
+// Stable roots of qa l^2 + qb l + qc = 0; returns count.
+STB_HD __forceinline__ int roots2(double qa, double qb, double qc, double* r) {
+  if (qa == 0.0) {
+    if (qb == 0.0) return 0;
+    r[0] = -qc / qb;
+    return 1;
+  }
+  double disc = qb * qb - 4.0 * qa * qc;
+  if (disc < 0.0) {
+    // the cone touching an edge: a double root lost to rounding
+    if (disc >= -1e-12 * (qb * qb + fabs(4.0 * qa * qc))) {
+      r[0] = -qb / (2.0 * qa);
+      return 1;
+    }
+    return 0;
+  }
+  double q = -0.5 * (qb + copysign(sqrt(disc), qb));
+  if (q == 0.0) { r[0] = 0.0; return 1; }
+  r[0] = q / qa;
+  r[1] = qc / q;
+  return 2;
+}
+
+// Breakpoints of L (unsorted); returns count (<= kMaxBp).  The set is the
+// phi-rule's definition: edge events; tangencies within kTangHint of the
+// closed panel; B_k = 0 where the hyperboloid vertex is within kVtxHint of
+// face k's plane; B_k = a_k for an apex on face k's plane inside the
+// panel's hyperplane (d = 0, C_k = 0).
+STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
+  int nb = 0;
+  double d2 = A.d * A.d, ad = fabs(A.d);
+  double sc = fabs(A.t - T.tmin) + T.diam;
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j) {
+      double a0 = A.t - T.V[i][0], a1 = T.V[i][0] - T.V[j][0];
+      double bu = T.V[i][1] - A.pu, bv = T.V[i][2] - A.pv;
+      double du = T.V[j][1] - T.V[i][1], dv = T.V[j][2] - T.V[i][2];
+      double qa = a1 * a1 - du * du - dv * dv;
+      double qb = 2.0 * (a0 * a1 - bu * du - bv * dv);
+      double qc = a0 * a0 - bu * bu - bv * bv - d2;
+      double lam[2];
+      int nl = roots2(qa, qb, qc, lam);
+      for (int m = 0; m < nl; ++m) {
+        double l = lam[m];
+        if (!(l >= 0.0 && l <= 1.0)) continue;
+        if (a0 + a1 * l < 0.0) continue;
+        double ou = bu + l * du, ov = bv + l * dv;
+        if (ou * ou + ov * ov <= 1e-20 * sc * sc) continue;
+        bp[nb++] = wrap_2pi(atan2(ov, ou));
+      }
+    }
+  for (int k = 0; k < 4; ++k) {
+    double a = T.fa[k], b = T.fb[k], c = T.fc[k], Ck = A.C[k];
+    double beta = sqrt(b * b + c * c);
+    if (!(beta > 1e-12)) continue;
+    double phik = atan2(c, b);
+    if (d2 > 0.0) {
+      double rhs = a * a - Ck * Ck / d2;
+      if (rhs >= 0.0 && rhs <= beta * beta) {
+        double cv = fmin(sqrt(rhs) / beta, 1.0);
+        double g = acos(cv);
+        double cand[4] = {phik + g, phik - g, phik + kPi - g, phik + kPi + g};
+        for (int m = 0; m < 4; ++m) {
+          double sn, cs;
+          sincos(cand[m], &sn, &cs);
+          double e = b * cs + c * sn - a;
+          if (e == 0.0) continue;
+          double wt = Ck / e;                 // double root of Q_k
+          if (!(wt >= ad) || !(wt > 0.0)) continue;
+          double rt = r_of_w(wt, d2), st = 0.5 * (wt - d2 / wt);
+          double y0 = A.t - rt, y1 = A.pu + st * cs, y2 = A.pv + st * sn;
+          double worst = -1e300;
+#pragma unroll
+          for (int m2 = 0; m2 < 4; ++m2)
+            worst = fmax(worst, T.fa[m2] * y0 + T.fb[m2] * y1 + T.fc[m2] * y2 - T.fh[m2]);
+          if (worst <= kTangHint * sc) bp[nb++] = wrap_2pi(cand[m]);
+        }
+      }
+    }
+    if (fabs(a * ad + Ck) <= kVtxHint * sc) {
+      bp[nb++] = wrap_2pi(phik + 0.5 * kPi);
+      bp[nb++] = wrap_2pi(phik - 0.5 * kPi);
+    }
+    if (ad <= kFlatTol * sc && fabs(Ck) <= kFlatTol * sc && fabs(a) <= beta) {
+      double g = acos(fmax(-1.0, fmin(1.0, a / beta)));
+      bp[nb++] = wrap_2pi(phik + g);
+      bp[nb++] = wrap_2pi(phik - g);
+    }
+  }
+  return nb;
+}
+
+STB_HD __forceinline__ void sort_bp(double* a, int n) {
+  for (int i = 1; i < n; ++i) {
+    double v = a[i];
+    int j = i - 1;
+    while (j >= 0 && a[j] > v) { a[j + 1] = a[j]; --j; }
+    a[j + 1] = v;
+  }
+}
+
+// Panel geometry from its 4 vertices (t, x, y, z).  Returns 0, or 2 for a
+// degenerate spatial projection, 3 for a panel that is not vertical (its
+// spatial projection is not planar), 4 for zero 3-volume.
+STB_HD inline int make_trial(const double (&X)[4][4], TrialRec& R) {
+  // e1 along the farthest pair of spatial points
+  int ia = 0, ib = 1;
+  double best = -1.0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = a + 1; b < 4; ++b) {
+      double dx = X[b][1] - X[a][1], dy = X[b][2] - X[a][2], dz = X[b][3] - X[a][3];
+      double l2 = dx * dx + dy * dy + dz * dz;
+      if (l2 > best) { best = l2; ia = a; ib = b; }
+    }
+  if (!(best > 0.0)) return 2;
+  double dsp = sqrt(best);
+  double e1[3] = {(X[ib][1] - X[ia][1]) / dsp, (X[ib][2] - X[ia][2]) / dsp,
+                  (X[ib][3] - X[ia][3]) / dsp};
+  double nb = -1.0, n[3] = {0, 0, 0};
+  for (int c = 0; c < 4; ++c) {
+    if (c == ia || c == ib) continue;
+    double v[3] = {X[c][1] - X[ia][1], X[c][2] - X[ia][2], X[c][3] - X[ia][3]};
+    double cr[3] = {e1[1] * v[2] - e1[2] * v[1], e1[2] * v[0] - e1[0] * v[2],
+                    e1[0] * v[1] - e1[1] * v[0]};
+    double l = sqrt(dot3(cr, cr));
+    if (l > nb) { nb = l; n[0] = cr[0] / l; n[1] = cr[1] / l; n[2] = cr[2] / l; }
+  }
+  if (!(nb > 1e-12 * dsp)) return 2;
+  double e2[3] = {n[1] * e1[2] - n[2] * e1[1], n[2] * e1[0] - n[0] * e1[2],
+                  n[0] * e1[1] - n[1] * e1[0]};
+  for (int c = 0; c < 3; ++c) {
+    R.o[c] = X[ia][c + 1]; R.e1[c] = e1[c]; R.e2[c] = e2[c]; R.n[c] = n[c];
+  }
+  R.tmin = X[0][0]; R.tmax = X[0][0];
+  double cen[3] = {0, 0, 0};
+  for (int k = 0; k < 4; ++k) {
+    double v[3] = {X[k][1] - R.o[0], X[k][2] - R.o[1], X[k][3] - R.o[2]};
+    if (fabs(dot3(v, n)) > 1e-12 * dsp) return 3;
+    R.V[k][0] = X[k][0];
+    R.V[k][1] = dot3(v, e1);
+    R.V[k][2] = dot3(v, e2);
+    for (int c = 0; c < 4; ++c) R.X[k][c] = X[k][c];
+    R.tmin = fmin(R.tmin, X[k][0]);
+    R.tmax = fmax(R.tmax, X[k][0]);
+    for (int c = 0; c < 3; ++c) cen[c] += 0.25 * X[k][c + 1];
+  }
+  R.diam = fmax(dsp, R.tmax - R.tmin);
+  double a1[3], a2[3], a3[3];
+  for (int c = 0; c < 3; ++c) {
+    a1[c] = R.V[1][c] - R.V[0][c]; a2[c] = R.V[2][c] - R.V[0][c]; a3[c] = R.V[3][c] - R.V[0][c];
+  }
+  double cr[3] = {a1[1] * a2[2] - a1[2] * a2[1], a1[2] * a2[0] - a1[0] * a2[2],
+                  a1[0] * a2[1] - a1[1] * a2[0]};
+  if (!(fabs(dot3(cr, a3)) > 1e-14 * R.diam * R.diam * R.diam)) return 4;
+  for (int k = 0; k < 4; ++k) {
+    int i0 = k == 0 ? 1 : 0, i1 = k <= 1 ? 2 : 1, i2 = k <= 2 ? 3 : 2;
+    double u1[3], u2[3], tk[3];
+    for (int c = 0; c < 3; ++c) {
+      u1[c] = R.V[i1][c] - R.V[i0][c]; u2[c] = R.V[i2][c] - R.V[i0][c]; tk[c] = R.V[k][c] - R.V[i0][c];
+    }
+    double N[3] = {u1[1] * u2[2] - u1[2] * u2[1], u1[2] * u2[0] - u1[0] * u2[2],
+                   u1[0] * u2[1] - u1[1] * u2[0]};
+    if (dot3(N, tk) > 0.0) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
+    double l = sqrt(dot3(N, N));
+    R.fa[k] = N[0] / l; R.fb[k] = N[1] / l; R.fc[k] = N[2] / l;
+    R.fh[k] = (N[0] * R.V[i0][0] + N[1] * R.V[i0][1] + N[2] * R.V[i0][2]) / l;
+  }
+  double rad = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    double dx = X[k][1] - cen[0], dy = X[k][2] - cen[1], dz = X[k][3] - cen[2];
+    rad = fmax(rad, sqrt(dx * dx + dy * dy + dz * dz));
+  }
+  R.cx = cen[0]; R.cy = cen[1]; R.cz = cen[2]; R.rad = rad * (1.0 + 1e-12);
+  R.pad = 0.0;
+  return 0;
+}
+
+// Outer points of eq. int_bform for one test panel: centroids of the m^2
+// congruent sub-triangles of every face with nu_t != 0 (Fig. int_tri_mid),
+// weight -nu_t |F| / m^2.  Returns the number of points.
+STB_HD inline int make_outer(const TrialRec& R, int m, double* P, double* W) {
+  int cnt = 0;
+  double inv = 1.0 / m;
+  for (int k = 0; k < 4; ++k) {
+    int i0 = k == 0 ? 1 : 0, i1 = k <= 1 ? 2 : 1, i2 = k <= 2 ? 3 : 2;
+    double u1[3], u2[3], tk[3];
+    for (int c = 0; c < 3; ++c) {
+      u1[c] = R.V[i1][c] - R.V[i0][c]; u2[c] = R.V[i2][c] - R.V[i0][c]; tk[c] = R.V[k][c] - R.V[i0][c];
+    }
+    double N[3] = {u1[1] * u2[2] - u1[2] * u2[1], u1[2] * u2[0] - u1[0] * u2[2],
+                   u1[0] * u2[1] - u1[1] * u2[0]};
+    double sg = dot3(N, tk) > 0.0 ? -1.0 : 1.0;
+    double nut_area = sg * N[0] * 0.5;       // nu_{F,t} |F| (outward)
+    if (nut_area == 0.0) continue;           // vertical face
+    double wq = -nut_area / (double)(m * m);
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; a + b < m; ++b)
+        for (int up = 0; up < 2; ++up) {
+          double al, be;
+          if (up == 0) { al = (a + 1.0 / 3.0) * inv; be = (b + 1.0 / 3.0) * inv; }
+          else {
+            if (a + b > m - 2) continue;
+            al = (a + 2.0 / 3.0) * inv; be = (b + 2.0 / 3.0) * inv;
+          }
+          for (int c = 0; c < 4; ++c)
+            P[4 * cnt + c] = R.X[i0][c] + al * (R.X[i1][c] - R.X[i0][c]) + be * (R.X[i2][c] - R.X[i0][c]);
+          W[cnt] = wq;
+          ++cnt;
+        }
+  }
+  return cnt;
+}
+
+struct ComboL {          // per (apex, trial) data needed by phase B
+  double C[4];
+  double d2, wlo, whi;
+  double fa[4], fb[4], fc[4];
+};
+
+STB_HD __forceinline__ double L_combo(const ComboL& cb, double cs, double sn) {
+  FaceSet F;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) { F.fa[k] = cb.fa[k]; F.fb[k] = cb.fb[k]; F.fc[k] = cb.fc[k]; }
+  return L_eval(F, cb.C, cb.d2, cb.wlo, cb.whi, cs, sn);
+}
+
+STB_HD __forceinline__ double L_at(const ComboL& cb, double phi) {
+  double sn, cs;
+  sincos(phi, &sn, &cs);
+  return L_combo(cb, cs, sn);
+}
+
+// One Gauss node of a phi piece [a, a + H] in the smoothstep variable.  Not
+// inlined, so every caller sums identically rounded node values.
+static STB_HD __noinline__ double node_value(const ComboL& cb, double a, double H, double u,
+                                          double wg) {
+  double s = u * u * (3.0 - 2.0 * u);
+  double ds = 6.0 * u * (1.0 - u);
+  double L = L_at(cb, a + H * s);
+  double f = H * ds;
+  f = f * wg;
+  return f * L;
+}
+
+
+// The whole inner integral V phi_sigma (x) of one (apex, panel) pair, one
+// lane, in the order the tiled kernel uses: lit test, breakpoints, pieces in
+// phi order, nodes in order.  Returns 0 for a pair that is not lit; *lit
+// receives the lit decision.
+STB_HD inline double inner_serial(const TrialRec& T, const double* x4, int ng, const double* glx,
+                                  const double* glw, bool* lit_out) {
+  Apex A;
+  apex_of(T, x4, A);
+  double wlo = 0.0, whi = 0.0;
+  bool lit = A.t - T.tmin > fabs(A.d) && lit_test(T, x4, A);
+  if (lit_out) *lit_out = lit;
+  if (!lit || !w_range(T, A, wlo, whi)) return 0.0;
+  ComboL cb;
+  for (int k = 0; k < 4; ++k) {
+    cb.C[k] = A.C[k]; cb.fa[k] = T.fa[k]; cb.fb[k] = T.fb[k]; cb.fc[k] = T.fc[k];
+  }
+  cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
+  double bp[kMaxBp];
+  int nb = breakpoints(T, A, bp);
+  sort_bp(bp, nb);
+  double I = 0.0;
+  if (nb == 0) {
+    int m = 2 * ng;
+    double h = kTwoPi / m;
+    for (int k = 0; k < m; ++k) I += h * L_at(cb, k * h);
+    return I / (4.0 * kPi);
+  }
+  for (int k = 0; k < nb; ++k) {
+    double a = bp[k];
+    double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
+    double H = b - a;
+    if (!(H > 0.0)) continue;
+    bool ne = L_at(cb, a + 0.5 * H) != 0.0;
+    if (!ne) ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+    if (!ne) continue;
+    double acc = 0.0;
+    for (int g = 0; g < ng; ++g) acc += node_value(cb, a, H, glx[g], glw[g]);
+    I += acc;
+  }
+  return I / (4.0 * kPi);
+}
+
+}  // namespace stb

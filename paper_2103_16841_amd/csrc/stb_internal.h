@@ -1,0 +1,83 @@
+// stb_internal.h -- handle layouts shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "stb.h"
+#include "stb_device.h"
+
+// ---------------------------------------------------------------- handles
+struct stb_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[5] = {};
+  std::string err;
+  double timings[4] = {0, 0, 0, 0};
+  // Gauss-Legendre nodes on [0,1] for the last n_g used (device copy)
+  int gl_n = 0;
+  double* d_gl = nullptr;   // [2 * kMaxNg]: x then w
+};
+
+struct stb_mesh {
+  stb_ctx* ctx = nullptr;
+  int64_t nv = 0, nt = 0;
+  double* d_vtx = nullptr;
+  int32_t* d_tet = nullptr;
+  stb::TrialRec* d_trial = nullptr;
+  // outer points for one m_q (recomputed when m_q changes)
+  int mq = 0;
+  int maxq = 0;
+  double* d_opts = nullptr;   // [nt][4*mq*mq][4]
+  double* d_ow = nullptr;     // [nt][4*mq*mq]
+  int32_t* d_onq = nullptr;   // [nt]
+  stb::ApexBox* d_box = nullptr;   // [nt]
+};
+
+struct stb_mat {
+  stb_ctx* ctx = nullptr;
+  int64_t n = 0, nnz = 0, n_causal = 0;
+  int64_t* d_rowptr = nullptr;
+  int32_t* d_cols = nullptr;
+  double* d_vals = nullptr;
+  float* d_vals32 = nullptr;     // lazily made for the 16-RHS product
+  // host mirror for stb_mat_get / to_dense
+  std::vector<int64_t> h_rowptr;
+  std::vector<int32_t> h_cols;
+  std::vector<double> h_vals;
+  bool host_valid = false;
+  // blocked copy for the 16-RHS matrix-core product: per 16-row block, the
+  // union of its rows' columns in quads; FP32 values in MFMA A-operand order
+  int64_t nblk = 0, nquad = 0;
+  int64_t* d_bptr = nullptr;     // [nblk + 1] quad offsets
+  int32_t* d_bcol = nullptr;     // [nquad * 4] column of each quad slot (-1 = pad)
+  float* d_bval = nullptr;       // [nquad * 64]
+};
+
+
+stb_status stb_fail(stb_ctx* ctx, stb_status s, const char* fmt, ...);
+extern "C" stb_status stb_mirror_host(stb_mat* M);
+
+#define HIPCHK(ctx, call)                                                                    \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return stb_fail(ctx, e_ == hipErrorOutOfMemory ? STB_E_NO_MEMORY : STB_E_DEVICE,       \
+                      "%s failed: %s", #call, hipGetErrorString(e_));                        \
+  } while (0)
+
+template <typename T>
+static inline hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+static inline void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// 16-RHS product (stb_apply.hip): builds the blocked copy on first use.
+stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y, hipStream_t st);
+void stb_free_blocked(stb_mat* M);

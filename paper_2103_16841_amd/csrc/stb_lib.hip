@@ -1,0 +1,1033 @@
+// stb_lib.hip -- MI355X (gfx950) implementation of the C ABI in include/stb.h.
+//
+// Pipeline of stb_assemble_V (energetic single-layer Galerkin matrix,
+// Poelz & Schanz arXiv 2103.16841, eq. df_ind / eq. int_bform):
+//   k_geometry   per panel: frame, face half-spaces (eq. pnl_ilf), bounds;
+//   k_outer      per test panel: outer points and weights of the composite
+//                centroid rule on its faces (Fig. int_tri_mid);
+//   k_cull_*     conservative causal cull of (test, trial) pairs from the
+//                bounding balls and time ranges (superset of the lit pairs of
+//                Sec. 3.3), compacted per row with wavefront ballots;
+//   k_pairs      per tile (one row, J candidate columns, all outer points):
+//                phase A (one lane per (outer point, trial panel)): exact lit
+//                test, apex data, phi-breakpoints, sort, empty-piece tests,
+//                non-empty pieces pushed to an LDS queue; phase B (one lane
+//                per (piece, Gauss node)): L(phi) at the node, ordered
+//                per-piece sums; then ordered sums over pieces and outer points.
+// The store is CSR over the candidate columns (values aligned with them).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "stb.h"
+#include "stb_device.h"
+
+using namespace stb;
+
+#include "stb_internal.h"
+
+static std::mutex g_err_mu;
+static std::string g_err;
+
+stb_status stb_fail(stb_ctx* ctx, stb_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  else {
+    std::lock_guard<std::mutex> g(g_err_mu);
+    g_err = buf;
+  }
+  return s;
+}
+#define fail stb_fail
+
+static stb_status ensure_gl(stb_ctx* ctx, int ng);
+
+// ---------------------------------------------------------------- kernels
+
+// Panel geometry.  status[j]: 0 ok, 1 non-finite, else as make_trial.
+__global__ void k_geometry(int64_t nt, const double* __restrict__ vtx,
+                           const int32_t* __restrict__ tet, TrialRec* __restrict__ out,
+                           int32_t* __restrict__ status) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nt) return;
+  double X[4][4];
+  int st = 0;
+  for (int k = 0; k < 4; ++k) {
+    const double* v = vtx + 4 * (int64_t)tet[4 * j + k];
+    for (int c = 0; c < 4; ++c) {
+      X[k][c] = v[c];
+      if (!isfinite(v[c])) st = 1;
+    }
+  }
+  if (st == 0) {
+    TrialRec R;
+    st = make_trial(X, R);
+    if (st == 0) out[j] = R;
+  }
+  status[j] = st;
+}
+
+// Outer points of eq. int_bform: centroids of the m^2 congruent sub-triangles
+// of every face with nu_t != 0, weight -nu_t |F| / m^2; plus the apex box.
+__global__ void k_outer(int64_t nt, const TrialRec* __restrict__ rec, int m, int maxq,
+                        double* __restrict__ pts, double* __restrict__ wts,
+                        int32_t* __restrict__ nq, ApexBox* __restrict__ box) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const TrialRec& R = rec[i];
+  double* P = pts + (int64_t)i * maxq * 4;
+  double* W = wts + (int64_t)i * maxq;
+  int cnt = make_outer(R, m, P, W);
+  nq[i] = cnt;
+  ApexBox B;
+  B.tlo = 1e300; B.thi = -1e300;
+  double c[3] = {0, 0, 0};
+  for (int q = 0; q < cnt; ++q) {
+    B.tlo = fmin(B.tlo, P[4 * q]);
+    B.thi = fmax(B.thi, P[4 * q]);
+    for (int d = 0; d < 3; ++d) c[d] += P[4 * q + 1 + d] / cnt;
+  }
+  double rho = 0.0;
+  for (int q = 0; q < cnt; ++q) {
+    double dx = P[4 * q + 1] - c[0], dy = P[4 * q + 2] - c[1], dz = P[4 * q + 3] - c[2];
+    rho = fmax(rho, sqrt(dx * dx + dy * dy + dz * dz));
+  }
+  B.cx = c[0]; B.cy = c[1]; B.cz = c[2]; B.rho = rho * (1.0 + 1e-12);
+  B.pad[0] = B.pad[1] = 0.0;
+  box[i] = B;
+}
+
+// Apex boxes of single evaluation points.
+__global__ void k_point_boxes(int64_t np, const double* __restrict__ pts, ApexBox* __restrict__ box) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  ApexBox B;
+  B.tlo = B.thi = pts[4 * i];
+  B.cx = pts[4 * i + 1]; B.cy = pts[4 * i + 2]; B.cz = pts[4 * i + 3];
+  B.rho = 0.0;
+  B.pad[0] = B.pad[1] = 0.0;
+  box[i] = B;
+}
+
+// Conservative causal test: some apex of the box and some point of the
+// panel with |x - y| = t - tau requires t - tau >= dist >= lower bound, and a
+// crossing needs a point outside the cone: t - tau < dist <= upper bound.
+__device__ __forceinline__ bool maybe_lit(const ApexBox& b, const TrialRec& T) {
+  double dx = b.cx - T.cx, dy = b.cy - T.cy, dz = b.cz - T.cz;
+  double dc = sqrt(dx * dx + dy * dy + dz * dz);
+  double lb = dc - b.rho - T.rad, ub = dc + b.rho + T.rad;
+  double slack = 1e-9 * (fabs(b.thi - T.tmin) + T.diam + b.rho);
+  return (b.thi - T.tmin > lb - slack) && (b.tlo - T.tmax < ub + slack);
+}
+
+constexpr int kCullThreads = 256;
+
+__global__ __launch_bounds__(kCullThreads) void k_cull_count(int64_t nrows,
+                                                             const ApexBox* __restrict__ rows,
+                                                             int64_t nt,
+                                                             const TrialRec* __restrict__ T,
+                                                             int64_t* __restrict__ cnt) {
+  int64_t i = blockIdx.x;
+  if (i >= nrows) return;
+  ApexBox b = rows[i];
+  int c = 0;
+  for (int64_t j = threadIdx.x; j < nt; j += kCullThreads) c += maybe_lit(b, T[j]) ? 1 : 0;
+  typedef hipcub::BlockReduce<int, kCullThreads> BR;
+  __shared__ typename BR::TempStorage tmp;
+  int s = BR(tmp).Sum(c);
+  if (threadIdx.x == 0) cnt[i] = s;
+}
+
+// Fill the candidate columns of each row in ascending order: per 256-wide
+// chunk, a wavefront ballot + mbcnt gives each lane its rank inside the
+// wave; an LDS prefix over the four waves orders the chunk.
+__global__ __launch_bounds__(kCullThreads) void k_cull_fill(int64_t nrows,
+                                                            const ApexBox* __restrict__ rows,
+                                                            int64_t nt,
+                                                            const TrialRec* __restrict__ T,
+                                                            const int64_t* __restrict__ rowptr,
+                                                            int32_t* __restrict__ cols) {
+  int64_t i = blockIdx.x;
+  if (i >= nrows) return;
+  __shared__ int wave_cnt[kCullThreads / 64];
+  ApexBox b = rows[i];
+  int64_t base = rowptr[i];
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t j0 = 0; j0 < nt; j0 += kCullThreads) {
+    int64_t j = j0 + threadIdx.x;
+    bool p = j < nt && maybe_lit(b, T[j]);
+    uint64_t bal = __ballot(p);
+    int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+    if (lane == 0) wave_cnt[wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wave; ++w) off += wave_cnt[w];
+    int tot = 0;
+    for (int w = 0; w < kCullThreads / 64; ++w) tot += wave_cnt[w];
+    if (p) cols[base + off + rank] = (int32_t)j;
+    base += tot;
+    __syncthreads();
+  }
+}
+
+// Tiles: row r owns ceil(cnt_r / J) tiles.
+__global__ void k_tiles(int64_t nrows, const int64_t* __restrict__ rowptr, int J,
+                        int64_t* __restrict__ ntile) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  int64_t c = rowptr[i + 1] - rowptr[i];
+  ntile[i] = (c + J - 1) / J;
+}
+
+// ------------------------------------------------------------ pair kernel
+constexpr int kThreads = 256;
+constexpr int kQueueCap = 1024;
+
+struct PairArgs {
+  int64_t nrows;
+  const int64_t* rowptr;     // candidate CSR
+  const int32_t* cols;
+  const int64_t* tileptr;    // exclusive prefix of tiles per row (nrows + 1)
+  int J;                     // trial panels per tile
+  const TrialRec* trial;
+  const double* apex;        // [nrows][maxq][4]
+  const double* apex_w;      // [nrows][maxq] (nullptr: weight 1)
+  const int32_t* apex_n;     // [nrows] (nullptr: 1)
+  int maxq;
+  const double* trial_w;     // potential mode: density per trial panel
+  double* out_vals;          // matrix mode: aligned with cols
+  double* out_tile;          // potential mode: one partial per tile
+  unsigned long long* n_causal;
+  const double* gl;          // [kMaxNg] nodes on [0,1], then [kMaxNg] weights
+  int ng;
+  int64_t tile0;             // first tile of this launch
+};
+
+__global__ __launch_bounds__(kThreads) void k_pairs(PairArgs P) {
+  __shared__ ComboL s_cb[kThreads];
+  __shared__ double s_qa[kQueueCap], s_qh[kQueueCap], s_qv[kQueueCap];
+  __shared__ uint16_t s_qc[kQueueCap];
+  __shared__ double s_I[kThreads];
+  __shared__ int s_slot0[kThreads], s_nslot[kThreads];
+  __shared__ uint8_t s_lit[kThreads];
+  __shared__ double s_glx[kMaxNg], s_glw[kMaxNg];
+  __shared__ int s_tail, s_filled;
+  __shared__ int64_t s_row, s_start;
+  __shared__ int s_cnt, s_nq;
+
+  const int tid = threadIdx.x;
+  const int64_t tile = P.tile0 + blockIdx.x;
+  if (tid == 0) {
+    // row of this tile: last r with tileptr[r] <= tile
+    int64_t lo = 0, hi = P.nrows;
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (P.tileptr[mid] <= tile) lo = mid; else hi = mid;
+    }
+    int64_t row = lo;
+    int64_t start = (tile - P.tileptr[row]) * P.J;
+    int64_t cnt = P.rowptr[row + 1] - P.rowptr[row] - start;
+    s_row = row;
+    s_start = start;
+    s_cnt = (int)(cnt < P.J ? cnt : P.J);
+    s_nq = P.apex_n ? P.apex_n[row] : 1;
+    s_tail = 0;
+    s_filled = 0;
+  }
+  if (tid < P.ng) { s_glx[tid] = P.gl[tid]; s_glw[tid] = P.gl[kMaxNg + tid]; }
+  __syncthreads();
+  const int64_t row = s_row;
+  const int cnt = s_cnt, nq = s_nq, ng = P.ng;
+  const int ncombo = cnt * nq;
+  const int64_t colbase = P.rowptr[row] + s_start;
+
+  // ---------------- phase A: one lane per (trial jj, apex q)
+  double I_inline = 0.0;
+  int slot0 = 0, nslot = 0;
+  bool lit = false;
+  const int c = tid;
+  if (c < ncombo) {
+    int jj = c / nq, q = c - jj * nq;
+    int32_t j = P.cols[colbase + jj];
+    const TrialRec& T = P.trial[j];
+    const double* x4 = P.apex + ((int64_t)row * P.maxq + q) * 4;
+    double xl[4] = {x4[0], x4[1], x4[2], x4[3]};
+    Apex A;
+    apex_of(T, xl, A);
+    double wlo = 0.0, whi = 0.0;
+    lit = A.t - T.tmin > fabs(A.d) && lit_test(T, xl, A);
+    if (lit && w_range(T, A, wlo, whi)) {
+      ComboL cb;
+      for (int k = 0; k < 4; ++k) {
+        cb.C[k] = A.C[k]; cb.fa[k] = T.fa[k]; cb.fb[k] = T.fb[k]; cb.fc[k] = T.fc[k];
+      }
+      cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
+      s_cb[c] = cb;
+      double bp[kMaxBp];
+      int nb = breakpoints(T, A, bp);
+      sort_bp(bp, nb);
+      if (nb == 0) {
+        // periodic trapezoid rule with 2 n_g nodes
+        int m = 2 * ng;
+        double h = kTwoPi / m;
+        for (int k = 0; k < m; ++k) I_inline += h * L_at(cb, k * h);
+      } else {
+        uint64_t mask = 0;
+        int np = 0;
+        for (int k = 0; k < nb; ++k) {
+          double a = bp[k];
+          double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
+          double H = b - a;
+          if (!(H > 0.0)) continue;
+          bool ne = L_at(cb, a + 0.5 * H) != 0.0;
+          if (!ne) ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+          if (ne) { mask |= (1ull << k); ++np; }
+        }
+        if (np > 0) {
+          int s0 = atomicAdd(&s_tail, np);
+          if (s0 + np <= kQueueCap) {
+            atomicMax(&s_filled, s0 + np);
+            int s = s0;
+            for (int k = 0; k < nb; ++k)
+              if (mask >> k & 1ull) {
+                double a = bp[k];
+                double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
+                s_qa[s] = a; s_qh[s] = b - a; s_qc[s] = (uint16_t)c;
+                ++s;
+              }
+            slot0 = s0;
+            nslot = np;
+          } else {
+            // queue full: integrate this lane's pieces itself, same order
+            for (int k = 0; k < nb; ++k)
+              if (mask >> k & 1ull) {
+                double a = bp[k];
+                double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
+                double acc = 0.0;
+                for (int g = 0; g < ng; ++g) acc += node_value(cb, a, b - a, s_glx[g], s_glw[g]);
+                I_inline += acc;
+              }
+          }
+        }
+      }
+    }
+    s_slot0[c] = slot0;
+    s_nslot[c] = nslot;
+    s_lit[c] = lit ? 1 : 0;
+  }
+  __syncthreads();
+
+  // ---------------- phase B: one lane per (piece, Gauss node)
+  {
+    const int filled = s_filled;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int per = 64 / ng;                 // pieces per wave pass
+    const int seg = lane / ng, g = lane - seg * ng;
+    const int nwaves = kThreads / 64;
+    for (int base = wave * per; base < filled; base += nwaves * per) {
+      int e = base + seg;
+      double v = 0.0;
+      bool act = seg < per && e < filled;
+      if (act) v = node_value(s_cb[s_qc[e]], s_qa[e], s_qh[e], s_glx[g], s_glw[g]);
+      // ordered sum over the n_g lanes of the segment
+      int l0 = seg * ng;
+      double acc = 0.0;
+      for (int k = 0; k < ng; ++k) acc += __shfl(v, (l0 + k) & 63, 64);
+      if (act && g == 0) s_qv[e] = acc;
+    }
+  }
+  __syncthreads();
+
+  // ---------------- per combo: ordered sum over its pieces
+  if (c < ncombo) {
+    double I = I_inline;
+    for (int s = 0; s < nslot; ++s) I += s_qv[slot0 + s];
+    s_I[c] = I / (4.0 * kPi);
+  }
+  __syncthreads();
+
+  // ---------------- per trial panel: outer sum, store
+  if (P.out_vals) {
+    if (tid < cnt) {
+      const double* wq = P.apex_w + (int64_t)row * P.maxq;
+      double s = 0.0;
+      bool any = false;
+      for (int q = 0; q < nq; ++q) {
+        double I = s_I[tid * nq + q];
+        if (I != 0.0) s += wq[q] * I;
+        any |= s_lit[tid * nq + q] != 0;
+      }
+      P.out_vals[colbase + tid] = s;
+      uint64_t bal = __ballot(any);
+      if ((tid & 63) == 0 && bal) atomicAdd(P.n_causal, (unsigned long long)__popcll(bal));
+    }
+  } else if (tid == 0) {
+    // potential mode (nq == 1): ordered sum of w_j I_j over the tile
+    double s = 0.0;
+    for (int jj = 0; jj < cnt; ++jj) {
+      double I = s_I[jj];
+      if (I != 0.0) s += P.trial_w[P.cols[colbase + jj]] * I;
+    }
+    P.out_tile[tile] = s;
+  }
+}
+
+// One lane per (point, panel) pair: the whole inner integral serially.
+__global__ void k_inner_values(int64_t k, const TrialRec* __restrict__ trial,
+                               const double* __restrict__ pts, const int32_t* __restrict__ panel,
+                               const double* __restrict__ gl, int ng, double* __restrict__ out) {
+  int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= k) return;
+  double x4[4] = {pts[4 * m], pts[4 * m + 1], pts[4 * m + 2], pts[4 * m + 3]};
+  out[m] = inner_serial(trial[panel[m]], x4, ng, gl, gl + kMaxNg, nullptr);
+}
+
+// Diagnostics of one (point, panel) pair: sorted breakpoints, then per
+// piece its L at the midpoint and its node sum.  out: [0] = nb, [1..nb] =
+// breakpoints, then 2 nb values.
+__global__ void k_debug_pair(const TrialRec* __restrict__ trial, const double* __restrict__ x,
+                             int32_t panel, const double* __restrict__ gl, int ng,
+                             double* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const TrialRec& T = trial[panel];
+  double x4[4] = {x[0], x[1], x[2], x[3]};
+  Apex A;
+  apex_of(T, x4, A);
+  double bp[kMaxBp];
+  int nb = breakpoints(T, A, bp);
+  sort_bp(bp, nb);
+  out[0] = nb;
+  for (int k = 0; k < nb; ++k) out[1 + k] = bp[k];
+  double wlo = 0.0, whi = 0.0;
+  bool ok = w_range(T, A, wlo, whi);
+  ComboL cb;
+  for (int k = 0; k < 4; ++k) {
+    cb.C[k] = A.C[k]; cb.fa[k] = T.fa[k]; cb.fb[k] = T.fb[k]; cb.fc[k] = T.fc[k];
+  }
+  cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
+  for (int k = 0; k < nb; ++k) {
+    double a = bp[k];
+    double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
+    double H = b - a;
+    double acc = 0.0;
+    if (ok && H > 0.0)
+      for (int g = 0; g < ng; ++g) acc += node_value(cb, a, H, gl[g], gl[kMaxNg + g]);
+    out[1 + nb + 2 * k] = ok ? L_at(cb, a + 0.5 * H) : -1.0;
+    out[2 + nb + 2 * k] = acc;
+  }
+  // then the panel record and the apex data
+  const double* tr = reinterpret_cast<const double*>(&T);
+  for (int k = 0; k < 64; ++k) out[1 + 3 * kMaxBp + k] = tr[k];
+  out[1 + 3 * kMaxBp + 64] = A.t;
+  out[1 + 3 * kMaxBp + 65] = A.pu;
+  out[1 + 3 * kMaxBp + 66] = A.pv;
+  out[1 + 3 * kMaxBp + 67] = A.d;
+  for (int k = 0; k < 4; ++k) out[1 + 3 * kMaxBp + 68 + k] = A.C[k];
+}
+
+extern "C" stb_status stb_debug_pair(stb_ctx* ctx, const stb_mesh* mesh, int32_t ng,
+                                     const double* x4, int32_t panel, double* out /*1+3*kMaxBp+72*/) {
+  if (!ctx || !mesh || !x4 || !out || panel < 0 || panel >= mesh->nt || ng < 2 || ng > kMaxNg)
+    return stb_fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  stb_status s = ensure_gl(ctx, ng);
+  if (s) return s;
+  double *d_x = nullptr, *d_out = nullptr;
+  HIPCHK(ctx, dalloc(&d_x, 4));
+  HIPCHK(ctx, dalloc(&d_out, 1 + 3 * kMaxBp + 72));
+  HIPCHK(ctx, hipMemcpy(d_x, x4, 32, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_debug_pair, dim3(1), dim3(64), 0, ctx->stream, mesh->d_trial, d_x, panel,
+                     ctx->d_gl, ng, d_out);
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(out, d_out, 8 * (1 + 3 * kMaxBp + 72), hipMemcpyDeviceToHost));
+  dfree(d_x);
+  dfree(d_out);
+  return STB_OK;
+}
+
+// Ordered sum of tile partials per evaluation point.
+__global__ void k_tile_reduce(int64_t np, const int64_t* __restrict__ tileptr,
+                              const double* __restrict__ part, double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  double s = 0.0;
+  for (int64_t t = tileptr[i]; t < tileptr[i + 1]; ++t) s += part[t];
+  out[i] = s;
+}
+
+// y = A w (FP64 CSR), one wavefront per row, fixed-order reduction.
+__global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ cols,
+                                              const double* __restrict__ vals,
+                                              const double* __restrict__ w, int nrhs, int col,
+                                              double* __restrict__ y) {
+  int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int64_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64)
+    s += vals[k] * w[(int64_t)cols[k] * nrhs + col];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) y[row * nrhs + col] = s;
+}
+
+// ---------------------------------------------------------------- host helpers
+
+// Gauss-Legendre on [0,1] by Newton iteration on the three-term recurrence.
+static void gauss_legendre01(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), pn = 0.0, dpn = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p_prev = 1.0, p = z;
+      for (int k = 2; k <= n; ++k) {
+        double p_next = ((2 * k - 1) * z * p - (k - 1) * p_prev) / k;
+        p_prev = p;
+        p = p_next;
+      }
+      if (n == 1) { p = z; p_prev = 1.0; }
+      pn = p;
+      dpn = n * (z * p - p_prev) / (z * z - 1.0);
+      double dz = pn / dpn;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p_prev = 1.0, p = z;
+    for (int k = 2; k <= n; ++k) {
+      double p_next = ((2 * k - 1) * z * p - (k - 1) * p_prev) / k;
+      p_prev = p;
+      p = p_next;
+    }
+    dpn = n * (z * p - p_prev) / (z * z - 1.0);
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dpn * dpn);
+  }
+}
+
+static stb_status ensure_gl(stb_ctx* ctx, int ng) {
+  if (ctx->gl_n == ng && ctx->d_gl) return STB_OK;
+  double h[2 * kMaxNg] = {0};
+  gauss_legendre01(ng, h, h + kMaxNg);
+  if (!ctx->d_gl) HIPCHK(ctx, dalloc(&ctx->d_gl, 2 * kMaxNg));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->d_gl, h, sizeof(h), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->gl_n = ng;
+  return STB_OK;
+}
+
+static stb_status check_params(stb_ctx* ctx, const stb_quad_params* p) {
+  if (p->m_q < 1 || p->m_q > 4) return fail(ctx, STB_E_INVALID_ARG, "m_q must be in [1,4], got %d", p->m_q);
+  if (p->n_g < 2 || p->n_g > kMaxNg) return fail(ctx, STB_E_INVALID_ARG, "n_g must be in [2,%d], got %d", kMaxNg, p->n_g);
+  if (p->prec != STB_FP64 && p->prec != STB_MIXED) return fail(ctx, STB_E_INVALID_ARG, "bad precision");
+  return STB_OK;
+}
+
+static stb_status ensure_outer(stb_ctx* ctx, stb_mesh* m, int mq) {
+  if (m->mq == mq && m->d_opts) return STB_OK;
+  dfree(m->d_opts); dfree(m->d_ow); dfree(m->d_onq); dfree(m->d_box);
+  m->d_opts = nullptr; m->d_ow = nullptr; m->d_onq = nullptr; m->d_box = nullptr;
+  int maxq = 4 * mq * mq;
+  HIPCHK(ctx, dalloc(&m->d_opts, (size_t)m->nt * maxq * 4));
+  HIPCHK(ctx, dalloc(&m->d_ow, (size_t)m->nt * maxq));
+  HIPCHK(ctx, dalloc(&m->d_onq, (size_t)m->nt));
+  HIPCHK(ctx, dalloc(&m->d_box, (size_t)m->nt));
+  if (m->nt > 0) {
+    hipLaunchKernelGGL(k_outer, dim3((unsigned)((m->nt + 127) / 128)), dim3(128), 0, ctx->stream,
+                       m->nt, m->d_trial, mq, maxq, m->d_opts, m->d_ow, m->d_onq, m->d_box);
+    HIPCHK(ctx, hipGetLastError());
+  }
+  m->mq = mq;
+  m->maxq = maxq;
+  return STB_OK;
+}
+
+// Exclusive scan of n int64 counts into out[0..n] (device), via hipcub.
+static stb_status device_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t* out, int64_t n) {
+  size_t bytes = 0;
+  HIPCHK(ctx, hipcub::DeviceScan::InclusiveSum(nullptr, bytes, in, out + 1, (int)n, ctx->stream));
+  void* tmp = nullptr;
+  HIPCHK(ctx, hipMalloc(&tmp, bytes > 0 ? bytes : 1));
+  hipError_t e1 = hipMemsetAsync(out, 0, sizeof(int64_t), ctx->stream);
+  hipError_t e2 = hipcub::DeviceScan::InclusiveSum(tmp, bytes, in, out + 1, (int)n, ctx->stream);
+  hipError_t e3 = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(tmp);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+    return fail(ctx, STB_E_DEVICE, "scan failed");
+  return STB_OK;
+}
+
+// Cull rows (apex boxes) against all trial panels into CSR candidates.
+static stb_status cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
+                       int64_t** d_rowptr, int32_t** d_cols, int64_t* nnz) {
+  int64_t* d_cnt = nullptr;
+  HIPCHK(ctx, dalloc(&d_cnt, (size_t)nrows));
+  HIPCHK(ctx, dalloc(d_rowptr, (size_t)nrows + 1));
+  if (nrows > 0) {
+    hipLaunchKernelGGL(k_cull_count, dim3((unsigned)nrows), dim3(kCullThreads), 0, ctx->stream,
+                       nrows, d_rows, m->nt, m->d_trial, d_cnt);
+    HIPCHK(ctx, hipGetLastError());
+  }
+  stb_status s = device_exclusive_scan(ctx, d_cnt, *d_rowptr, nrows);
+  dfree(d_cnt);
+  if (s) return s;
+  HIPCHK(ctx, hipMemcpy(nnz, *d_rowptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIPCHK(ctx, dalloc(d_cols, (size_t)*nnz));
+  if (nrows > 0) {
+    hipLaunchKernelGGL(k_cull_fill, dim3((unsigned)nrows), dim3(kCullThreads), 0, ctx->stream,
+                       nrows, d_rows, m->nt, m->d_trial, *d_rowptr, *d_cols);
+    HIPCHK(ctx, hipGetLastError());
+  }
+  return STB_OK;
+}
+
+static stb_status make_tiles(stb_ctx* ctx, int64_t nrows, const int64_t* d_rowptr, int J,
+                             int64_t** d_tileptr, int64_t* ntiles) {
+  int64_t* d_nt = nullptr;
+  HIPCHK(ctx, dalloc(&d_nt, (size_t)nrows));
+  HIPCHK(ctx, dalloc(d_tileptr, (size_t)nrows + 1));
+  if (nrows > 0) {
+    hipLaunchKernelGGL(k_tiles, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, ctx->stream,
+                       nrows, d_rowptr, J, d_nt);
+    HIPCHK(ctx, hipGetLastError());
+  }
+  stb_status s = device_exclusive_scan(ctx, d_nt, *d_tileptr, nrows);
+  dfree(d_nt);
+  if (s) return s;
+  HIPCHK(ctx, hipMemcpy(ntiles, *d_tileptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return STB_OK;
+}
+
+static stb_status launch_pairs(stb_ctx* ctx, PairArgs& A, int64_t ntiles) {
+  // dispatches stay below 2^31 work-items: chunks of 2^22 tiles
+  const int64_t kChunk = 1ll << 22;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += kChunk) {
+    A.tile0 = t0;
+    int64_t n = std::min(kChunk, ntiles - t0);
+    hipLaunchKernelGGL(k_pairs, dim3((unsigned)n), dim3(kThreads), 0, ctx->stream, A);
+    HIPCHK(ctx, hipGetLastError());
+  }
+  return STB_OK;
+}
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+stb_quad_params stb_default_params(void) {
+  stb_quad_params p;
+  p.m_q = 3;
+  p.n_g = 16;
+  p.eta_far = 2.0;
+  p.prec = STB_FP64;
+  return p;
+}
+
+const char* stb_status_str(stb_status s) {
+  switch (s) {
+    case STB_OK: return "ok";
+    case STB_E_INVALID_ARG: return "invalid argument";
+    case STB_E_INVALID_MESH: return "invalid mesh";
+    case STB_E_NO_MEMORY: return "out of memory";
+    case STB_E_DEVICE: return "device error";
+    case STB_E_NOT_FOUND: return "not found";
+    case STB_E_BUSY: return "busy";
+    case STB_E_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* stb_last_error(const stb_ctx* ctx) {
+  if (ctx) return ctx->err.c_str();
+  std::lock_guard<std::mutex> g(g_err_mu);
+  return g_err.c_str();
+}
+
+stb_status stb_ctx_create(int32_t device, stb_ctx** out) {
+  if (!out) return fail(nullptr, STB_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+    return fail(nullptr, STB_E_DEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev)
+    return fail(nullptr, STB_E_INVALID_ARG, "device %d out of range [0,%d)", device, ndev);
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, STB_E_DEVICE, "hipSetDevice failed");
+  stb_ctx* c = new stb_ctx();
+  c->device = device;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(nullptr, STB_E_DEVICE, "hipStreamCreate failed");
+  }
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return fail(nullptr, STB_E_DEVICE, "hipEventCreate failed");
+    }
+  *out = c;
+  return STB_OK;
+}
+
+void stb_ctx_destroy(stb_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  dfree(ctx->d_gl);
+  for (auto& e : ctx->ev) if (e) (void)hipEventDestroy(e);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+stb_status stb_mesh_create(stb_ctx* ctx, int64_t nv, const double* vtx, int64_t nt,
+                           const int32_t* tet, stb_mesh** out) {
+  if (!ctx || !out) return fail(ctx, STB_E_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (nv <= 0 || nt <= 0 || !vtx || !tet)
+    return fail(ctx, STB_E_INVALID_ARG, "empty mesh or NULL arrays (nv=%lld nt=%lld)",
+                (long long)nv, (long long)nt);
+  if (nt > (int64_t)INT32_MAX) return fail(ctx, STB_E_INVALID_ARG, "too many panels");
+  for (int64_t i = 0; i < 4 * nt; ++i)
+    if (tet[i] < 0 || tet[i] >= nv)
+      return fail(ctx, STB_E_INVALID_MESH, "panel %lld: vertex index %d out of range",
+                  (long long)(i / 4), tet[i]);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  stb_mesh* m = new stb_mesh();
+  m->ctx = ctx;
+  m->nv = nv;
+  m->nt = nt;
+  int32_t* d_status = nullptr;
+  auto cleanup = [&]() {
+    dfree(d_status);
+    stb_mesh_destroy(m);
+  };
+  if (dalloc(&m->d_vtx, (size_t)nv * 4) != hipSuccess || dalloc(&m->d_tet, (size_t)nt * 4) != hipSuccess ||
+      dalloc(&m->d_trial, (size_t)nt) != hipSuccess || dalloc(&d_status, (size_t)nt) != hipSuccess) {
+    cleanup();
+    return fail(ctx, STB_E_NO_MEMORY, "device allocation for %lld panels failed", (long long)nt);
+  }
+  hipError_t e = hipMemcpyAsync(m->d_vtx, vtx, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->d_tet, tet, sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_geometry, dim3((unsigned)((nt + 127) / 128)), dim3(128), 0, ctx->stream, nt,
+                       m->d_vtx, m->d_tet, m->d_trial, d_status);
+    e = hipGetLastError();
+  }
+  std::vector<int32_t> status((size_t)nt);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(status.data(), d_status, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(ctx, STB_E_DEVICE, "mesh upload failed: %s", hipGetErrorString(e));
+  }
+  static const char* why[] = {"ok", "non-finite coordinate", "degenerate spatial projection",
+                              "not vertical (spatial projection not planar)", "zero 3-volume"};
+  for (int64_t j = 0; j < nt; ++j)
+    if (status[j] != 0) {
+      int s = status[j];
+      cleanup();
+      return fail(ctx, STB_E_INVALID_MESH, "panel %lld: %s", (long long)j, why[s >= 0 && s <= 4 ? s : 0]);
+    }
+  dfree(d_status);
+  *out = m;
+  return STB_OK;
+}
+
+void stb_mesh_destroy(stb_mesh* m) {
+  if (!m) return;
+  dfree(m->d_vtx); dfree(m->d_tet); dfree(m->d_trial);
+  dfree(m->d_opts); dfree(m->d_ow); dfree(m->d_onq); dfree(m->d_box);
+  delete m;
+}
+
+int64_t stb_mesh_size(const stb_mesh* m) { return m ? m->nt : 0; }
+
+stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_params* params,
+                          stb_mat** out) {
+  if (!ctx || !mesh_c || !out) return fail(ctx, STB_E_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
+  if (mesh->ctx != ctx) return fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
+  stb_quad_params p = params ? *params : stb_default_params();
+  stb_status s = check_params(ctx, &p);
+  if (s) return s;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if ((s = ensure_gl(ctx, p.n_g))) return s;
+  HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+  if ((s = ensure_outer(ctx, mesh, p.m_q))) return s;
+  HIPCHK(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+  stb_mat* M = new stb_mat();
+  M->ctx = ctx;
+  M->n = mesh->nt;
+  s = cull(ctx, mesh->nt, mesh->d_box, mesh, &M->d_rowptr, &M->d_cols, &M->nnz);
+  if (s) { stb_mat_destroy(M); return s; }
+  int J = kThreads / mesh->maxq;
+  if (J < 1) J = 1;
+  int64_t* d_tileptr = nullptr;
+  int64_t ntiles = 0;
+  s = make_tiles(ctx, mesh->nt, M->d_rowptr, J, &d_tileptr, &ntiles);
+  if (s) { stb_mat_destroy(M); return s; }
+  HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+  unsigned long long* d_causal = nullptr;
+  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess || dalloc(&d_causal, 1) != hipSuccess) {
+    dfree(d_tileptr); dfree(d_causal); stb_mat_destroy(M);
+    return fail(ctx, STB_E_NO_MEMORY, "store of %lld entries does not fit", (long long)M->nnz);
+  }
+  HIPCHK(ctx, hipMemsetAsync(d_causal, 0, sizeof(unsigned long long), ctx->stream));
+  PairArgs A;
+  A.nrows = mesh->nt;
+  A.rowptr = M->d_rowptr;
+  A.cols = M->d_cols;
+  A.tileptr = d_tileptr;
+  A.J = J;
+  A.trial = mesh->d_trial;
+  A.apex = mesh->d_opts;
+  A.apex_w = mesh->d_ow;
+  A.apex_n = mesh->d_onq;
+  A.maxq = mesh->maxq;
+  A.trial_w = nullptr;
+  A.out_vals = M->d_vals;
+  A.out_tile = nullptr;
+  A.n_causal = d_causal;
+  A.gl = ctx->d_gl;
+  A.ng = p.n_g;
+  s = launch_pairs(ctx, A, ntiles);
+  if (s) { dfree(d_tileptr); dfree(d_causal); stb_mat_destroy(M); return s; }
+  HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
+  unsigned long long nc = 0;
+  hipError_t e = hipMemcpyAsync(&nc, d_causal, sizeof(nc), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(d_tileptr);
+  dfree(d_causal);
+  if (e != hipSuccess) {
+    stb_mat_destroy(M);
+    return fail(ctx, STB_E_DEVICE, "assembly failed: %s", hipGetErrorString(e));
+  }
+  M->n_causal = (int64_t)nc;
+  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+  (void)hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
+  (void)hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
+  (void)hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
+  (void)hipEventElapsedTime(&t03, ctx->ev[0], ctx->ev[3]);
+  ctx->timings[0] = t01; ctx->timings[1] = t12; ctx->timings[2] = t23; ctx->timings[3] = t03;
+  *out = M;
+  return STB_OK;
+}
+
+void stb_mat_destroy(stb_mat* M) {
+  if (!M) return;
+  dfree(M->d_rowptr); dfree(M->d_cols); dfree(M->d_vals); dfree(M->d_vals32);
+  stb_free_blocked(M);
+  delete M;
+}
+
+stb_status stb_mat_info(const stb_mat* M, int64_t* n, int64_t* nc, int64_t* nstored, int64_t* bytes) {
+  if (!M) return fail(nullptr, STB_E_INVALID_ARG, "NULL matrix");
+  if (n) *n = M->n;
+  if (nc) *nc = M->n_causal;
+  if (nstored) *nstored = M->nnz;
+  if (bytes)
+    *bytes = (M->n + 1) * 8 + M->nnz * (4 + 8) + (M->d_vals32 ? M->nnz * 4 : 0);
+  return STB_OK;
+}
+
+stb_status stb_mirror_host(stb_mat* M) {
+  if (M->host_valid) return STB_OK;
+  stb_ctx* ctx = M->ctx;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  M->h_rowptr.resize((size_t)M->n + 1);
+  M->h_cols.resize((size_t)M->nnz);
+  M->h_vals.resize((size_t)M->nnz);
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(M->h_rowptr.data(), M->d_rowptr, 8 * (M->n + 1), hipMemcpyDeviceToHost));
+  if (M->nnz) {
+    HIPCHK(ctx, hipMemcpy(M->h_cols.data(), M->d_cols, 4 * M->nnz, hipMemcpyDeviceToHost));
+    HIPCHK(ctx, hipMemcpy(M->h_vals.data(), M->d_vals, 8 * M->nnz, hipMemcpyDeviceToHost));
+  }
+  M->host_valid = true;
+  return STB_OK;
+}
+
+stb_status stb_mat_to_dense(const stb_mat* Mc, double* out) {
+  if (!Mc || !out) return fail(Mc ? Mc->ctx : nullptr, STB_E_INVALID_ARG, "NULL argument");
+  stb_mat* M = const_cast<stb_mat*>(Mc);
+  stb_status s = stb_mirror_host(M);
+  if (s) return s;
+  std::memset(out, 0, sizeof(double) * (size_t)M->n * (size_t)M->n);
+  for (int64_t i = 0; i < M->n; ++i)
+    for (int64_t k = M->h_rowptr[i]; k < M->h_rowptr[i + 1]; ++k) out[i * M->n + M->h_cols[k]] = M->h_vals[k];
+  return STB_OK;
+}
+
+stb_status stb_mat_get(const stb_mat* Mc, int64_t k, const int32_t* row, const int32_t* col, double* out) {
+  if (!Mc || (k > 0 && (!row || !col || !out)) || k < 0)
+    return fail(Mc ? Mc->ctx : nullptr, STB_E_INVALID_ARG, "bad arguments");
+  stb_mat* M = const_cast<stb_mat*>(Mc);
+  stb_status s = stb_mirror_host(M);
+  if (s) return s;
+  for (int64_t m = 0; m < k; ++m) {
+    if (row[m] < 0 || row[m] >= M->n || col[m] < 0 || col[m] >= M->n)
+      return fail(M->ctx, STB_E_INVALID_ARG, "entry %lld out of range", (long long)m);
+    const int32_t* b = M->h_cols.data() + M->h_rowptr[row[m]];
+    const int32_t* e = M->h_cols.data() + M->h_rowptr[row[m] + 1];
+    const int32_t* it = std::lower_bound(b, e, col[m]);
+    out[m] = (it != e && *it == col[m]) ? M->h_vals[it - M->h_cols.data()] : 0.0;
+  }
+  return STB_OK;
+}
+
+stb_status stb_apply_dev(stb_ctx* ctx, const stb_mat* M, int32_t nrhs, const double* w, double* y,
+                         void* stream) {
+  if (!ctx || !M || !w || !y || nrhs < 1) return fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  hipStream_t st = stream ? (hipStream_t)stream : ctx->stream;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (nrhs == 16) return stb_apply16_dev(ctx, const_cast<stb_mat*>(M), w, y, st);
+  int64_t threads = M->n * 64;
+  for (int c = 0; c < nrhs; ++c) {
+    if (M->n > 0) {
+      hipLaunchKernelGGL(k_spmv, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, M->n,
+                         M->d_rowptr, M->d_cols, M->d_vals, w, nrhs, c, y);
+      HIPCHK(ctx, hipGetLastError());
+    }
+  }
+  return STB_OK;
+}
+
+stb_status stb_apply(stb_ctx* ctx, const stb_mat* M, int32_t nrhs, const double* w, double* y) {
+  if (!ctx || !M || !w || !y || nrhs < 1) return fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  double *dw = nullptr, *dy = nullptr;
+  size_t bytes = sizeof(double) * (size_t)M->n * nrhs;
+  if (dalloc(&dw, (size_t)M->n * nrhs) != hipSuccess || dalloc(&dy, (size_t)M->n * nrhs) != hipSuccess) {
+    dfree(dw); dfree(dy);
+    return fail(ctx, STB_E_NO_MEMORY, "apply buffers");
+  }
+  hipError_t e = hipMemcpyAsync(dw, w, bytes, hipMemcpyHostToDevice, ctx->stream);
+  stb_status s = e == hipSuccess ? stb_apply_dev(ctx, M, nrhs, dw, dy, nullptr)
+                                 : fail(ctx, STB_E_DEVICE, "copy failed");
+  if (s == STB_OK) {
+    e = hipMemcpyAsync(y, dy, bytes, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) s = fail(ctx, STB_E_DEVICE, "apply failed: %s", hipGetErrorString(e));
+  }
+  dfree(dw);
+  dfree(dy);
+  return s;
+}
+
+stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_params* params,
+                           const double* w, int64_t np, const double* pts, double* out) {
+  if (!ctx || !mesh_c || !w || (np > 0 && (!pts || !out)) || np < 0)
+    return fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
+  stb_quad_params p = params ? *params : stb_default_params();
+  stb_status s = check_params(ctx, &p);
+  if (s) return s;
+  if (np == 0) return STB_OK;
+  for (int64_t i = 0; i < 4 * np; ++i)
+    if (!std::isfinite(pts[i])) return fail(ctx, STB_E_INVALID_ARG, "non-finite point %lld", (long long)(i / 4));
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if ((s = ensure_gl(ctx, p.n_g))) return s;
+  double *d_pts = nullptr, *d_w = nullptr, *d_part = nullptr, *d_out = nullptr;
+  ApexBox* d_box = nullptr;
+  int64_t *d_rowptr = nullptr, *d_tileptr = nullptr;
+  int32_t* d_cols = nullptr;
+  auto cleanup = [&]() {
+    dfree(d_pts); dfree(d_w); dfree(d_part); dfree(d_out); dfree(d_box);
+    dfree(d_rowptr); dfree(d_tileptr); dfree(d_cols);
+  };
+  if (dalloc(&d_pts, (size_t)np * 4) != hipSuccess || dalloc(&d_w, (size_t)mesh->nt) != hipSuccess ||
+      dalloc(&d_box, (size_t)np) != hipSuccess || dalloc(&d_out, (size_t)np) != hipSuccess) {
+    cleanup();
+    return fail(ctx, STB_E_NO_MEMORY, "potential buffers");
+  }
+  hipError_t e = hipMemcpyAsync(d_pts, pts, sizeof(double) * 4 * np, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_w, w, sizeof(double) * mesh->nt, hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) { cleanup(); return fail(ctx, STB_E_DEVICE, "copy failed"); }
+  hipLaunchKernelGGL(k_point_boxes, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
+                     d_pts, d_box);
+  int64_t nnz = 0, ntiles = 0;
+  s = cull(ctx, np, d_box, mesh, &d_rowptr, &d_cols, &nnz);
+  if (s == STB_OK) s = make_tiles(ctx, np, d_rowptr, kThreads, &d_tileptr, &ntiles);
+  if (s) { cleanup(); return s; }
+  if (dalloc(&d_part, (size_t)ntiles) != hipSuccess) { cleanup(); return fail(ctx, STB_E_NO_MEMORY, "tiles"); }
+  PairArgs A;
+  A.nrows = np;
+  A.rowptr = d_rowptr;
+  A.cols = d_cols;
+  A.tileptr = d_tileptr;
+  A.J = kThreads;
+  A.trial = mesh->d_trial;
+  A.apex = d_pts;
+  A.apex_w = nullptr;
+  A.apex_n = nullptr;
+  A.maxq = 1;
+  A.trial_w = d_w;
+  A.out_vals = nullptr;
+  A.out_tile = d_part;
+  A.n_causal = nullptr;
+  A.gl = ctx->d_gl;
+  A.ng = p.n_g;
+  s = launch_pairs(ctx, A, ntiles);
+  if (s) { cleanup(); return s; }
+  hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
+                     d_tileptr, d_part, d_out);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(double) * np, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  cleanup();
+  if (e != hipSuccess) return fail(ctx, STB_E_DEVICE, "potential failed: %s", hipGetErrorString(e));
+  return STB_OK;
+}
+
+stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                            int64_t k, const double* pts, const int32_t* panel, double* out) {
+  if (!ctx || !mesh || k < 0 || (k > 0 && (!pts || !panel || !out)))
+    return fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  stb_quad_params p = params ? *params : stb_default_params();
+  stb_status s = check_params(ctx, &p);
+  if (s) return s;
+  for (int64_t m = 0; m < k; ++m)
+    if (panel[m] < 0 || panel[m] >= mesh->nt)
+      return fail(ctx, STB_E_INVALID_ARG, "panel index %d out of range", panel[m]);
+  if (k == 0) return STB_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if ((s = ensure_gl(ctx, p.n_g))) return s;
+  double *d_pts = nullptr, *d_out = nullptr;
+  int32_t* d_pan = nullptr;
+  if (dalloc(&d_pts, (size_t)k * 4) != hipSuccess || dalloc(&d_out, (size_t)k) != hipSuccess ||
+      dalloc(&d_pan, (size_t)k) != hipSuccess) {
+    dfree(d_pts); dfree(d_out); dfree(d_pan);
+    return fail(ctx, STB_E_NO_MEMORY, "buffers");
+  }
+  hipError_t e = hipMemcpyAsync(d_pts, pts, 32 * k, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_pan, panel, 4 * k, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_inner_values, dim3((unsigned)((k + 127) / 128)), dim3(128), 0, ctx->stream, k,
+                       mesh->d_trial, d_pts, d_pan, ctx->d_gl, p.n_g, d_out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, 8 * k, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(d_pts); dfree(d_out); dfree(d_pan);
+  if (e != hipSuccess) return fail(ctx, STB_E_DEVICE, "inner values failed: %s", hipGetErrorString(e));
+  return STB_OK;
+}
+
+stb_status stb_last_timings(const stb_ctx* ctx, double* ms4) {
+  if (!ctx || !ms4) return fail(nullptr, STB_E_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 4; ++k) ms4[k] = ctx->timings[k];
+  return STB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,231 @@
+"""ctypes binding of libstb (include/stb.h): argument marshalling only.
+
+Every step of the method runs in the HIP library.  Loading fails loudly
+when the library is not built; there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+STB_FP64, STB_MIXED = 0, 1
+STATUS = {0: "STB_OK", 1: "STB_E_INVALID_ARG", 2: "STB_E_INVALID_MESH", 3: "STB_E_NO_MEMORY",
+          4: "STB_E_DEVICE", 5: "STB_E_NOT_FOUND", 6: "STB_E_BUSY", 7: "STB_E_INTERNAL"}
+
+# Every symbol declared in include/stb.h
+EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_status_str",
+           "stb_last_error", "stb_mesh_create", "stb_mesh_destroy", "stb_mesh_size",
+           "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
+           "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_inner_values",
+           "stb_last_timings"]
+
+
+class QuadParams(ctypes.Structure):
+    _fields_ = [("m_q", ctypes.c_int32), ("n_g", ctypes.c_int32), ("eta_far", ctypes.c_double),
+                ("prec", ctypes.c_int)]
+
+
+class StbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_VP = ctypes.c_void_p
+
+
+def lib_path():
+    return _build.LIB
+
+
+def load():
+    """Load the in-tree libstb.so (built by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        raise ImportError("libstb.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(_build.LIB)
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    L.stb_default_params.restype = QuadParams
+    L.stb_ctx_create.argtypes = [i32, ctypes.POINTER(_VP)]
+    L.stb_ctx_destroy.argtypes = [_VP]
+    L.stb_ctx_destroy.restype = None
+    L.stb_status_str.argtypes = [ctypes.c_int]
+    L.stb_status_str.restype = ctypes.c_char_p
+    L.stb_last_error.argtypes = [_VP]
+    L.stb_last_error.restype = ctypes.c_char_p
+    L.stb_mesh_create.argtypes = [_VP, i64, _D, i64, _I32, ctypes.POINTER(_VP)]
+    L.stb_mesh_destroy.argtypes = [_VP]
+    L.stb_mesh_destroy.restype = None
+    L.stb_mesh_size.argtypes = [_VP]
+    L.stb_mesh_size.restype = i64
+    L.stb_assemble_V.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), ctypes.POINTER(_VP)]
+    L.stb_mat_destroy.argtypes = [_VP]
+    L.stb_mat_destroy.restype = None
+    L.stb_mat_info.argtypes = [_VP, _I64, _I64, _I64, _I64]
+    L.stb_mat_to_dense.argtypes = [_VP, _D]
+    L.stb_mat_get.argtypes = [_VP, i64, _I32, _I32, _D]
+    L.stb_apply.argtypes = [_VP, _VP, i32, _D, _D]
+    L.stb_apply_dev.argtypes = [_VP, _VP, i32, _VP, _VP, _VP]
+    L.stb_potential_S.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _D, i64, _D, _D]
+    L.stb_last_timings.argtypes = [_VP, _D]
+    L.stb_inner_values.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
+    _lib = L
+    return L
+
+
+def _chk(st, ctx=None):
+    if st != 0:
+        msg = load().stb_last_error(ctx)
+        raise StbError(st, msg.decode() if msg else "")
+
+
+def default_params(n_g=None, m_q=None, prec=None, eta_far=None):
+    p = load().stb_default_params()
+    if n_g is not None:
+        p.n_g = n_g
+    if m_q is not None:
+        p.m_q = m_q
+    if prec is not None:
+        p.prec = prec
+    if eta_far is not None:
+        p.eta_far = eta_far
+    return p
+
+
+def _d(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a, a.ctypes.data_as(_D)
+
+
+class Context:
+    def __init__(self, device=0):
+        L = load()
+        h = _VP()
+        _chk(L.stb_ctx_create(device, ctypes.byref(h)), None)
+        self.h = h
+
+    def close(self):
+        if self.h:
+            load().stb_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timings(self):
+        out = np.zeros(4)
+        _chk(load().stb_last_timings(self.h, out.ctypes.data_as(_D)), self.h)
+        return dict(geometry_ms=out[0], cull_ms=out[1], quadrature_ms=out[2], total_ms=out[3])
+
+
+class Mesh:
+    def __init__(self, ctx, vtx, tets):
+        L = load()
+        self.ctx = ctx
+        vtx, pv = _d(vtx)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        h = _VP()
+        _chk(L.stb_mesh_create(ctx.h, vtx.shape[0], pv, tets.shape[0],
+                               tets.ctypes.data_as(_I32), ctypes.byref(h)), ctx.h)
+        self.h = h
+        self.nt = int(tets.shape[0])
+
+    def close(self):
+        if self.h:
+            load().stb_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Matrix:
+    def __init__(self, ctx, h):
+        self.ctx = ctx
+        self.h = h
+        n, nc, ns, nb = (ctypes.c_int64() for _ in range(4))
+        _chk(load().stb_mat_info(h, ctypes.byref(n), ctypes.byref(nc), ctypes.byref(ns),
+                                 ctypes.byref(nb)), ctx.h)
+        self.n, self.n_causal, self.n_stored, self.bytes = n.value, nc.value, ns.value, nb.value
+
+    def close(self):
+        if self.h:
+            load().stb_mat_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def to_dense(self):
+        out = np.zeros((self.n, self.n))
+        _chk(load().stb_mat_to_dense(self.h, out.ctypes.data_as(_D)), self.ctx.h)
+        return out
+
+    def get(self, rows, cols):
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        out = np.zeros(rows.shape[0])
+        _chk(load().stb_mat_get(self.h, rows.shape[0], rows.ctypes.data_as(_I32),
+                                cols.ctypes.data_as(_I32), out.ctypes.data_as(_D)), self.ctx.h)
+        return out
+
+    def apply(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        nrhs = 1 if w.ndim == 1 else w.shape[1]
+        y = np.zeros_like(w)
+        _chk(load().stb_apply(self.ctx.h, self.h, nrhs, w.ctypes.data_as(_D),
+                              y.ctypes.data_as(_D)), self.ctx.h)
+        return y
+
+    def apply_dev(self, w_ptr, y_ptr, nrhs, stream=None):
+        """Device-pointer product (e.g. torch tensors' data_ptr())."""
+        _chk(load().stb_apply_dev(self.ctx.h, self.h, nrhs, _VP(w_ptr), _VP(y_ptr),
+                                  _VP(stream) if stream else None), self.ctx.h)
+
+
+def assemble_V(ctx, mesh, params=None):
+    p = params if params is not None else default_params()
+    h = _VP()
+    _chk(load().stb_assemble_V(ctx.h, mesh.h, ctypes.byref(p), ctypes.byref(h)), ctx.h)
+    return Matrix(ctx, h)
+
+
+def potential_S(ctx, mesh, w, pts, params=None):
+    p = params if params is not None else default_params()
+    w, pw = _d(w)
+    pts, pp = _d(pts, (-1, 4))
+    out = np.zeros(pts.shape[0])
+    _chk(load().stb_potential_S(ctx.h, mesh.h, ctypes.byref(p), pw, pts.shape[0], pp,
+                                out.ctypes.data_as(_D)), ctx.h)
+    return out
+
+
+def inner_values(ctx, mesh, pts, panels, params=None):
+    """V phi_panel (pt) for each (point, panel) pair."""
+    p = params if params is not None else default_params()
+    pts, pp = _d(pts, (-1, 4))
+    panels = np.ascontiguousarray(panels, dtype=np.int32)
+    out = np.zeros(pts.shape[0])
+    _chk(load().stb_inner_values(ctx.h, mesh.h, ctypes.byref(p), pts.shape[0], pp,
+                                 panels.ctypes.data_as(_I32), out.ctypes.data_as(_D)), ctx.h)
+    return out
