@@ -93,6 +93,10 @@ const char* stb_last_error(const stb_ctx* ctx);
  * Validates every panel (STB_E_INVALID_MESH names the first bad one). */
 stb_status stb_mesh_create(stb_ctx* ctx, int64_t nv, const double* vtx, int64_t nt,
                            const int32_t* tet, stb_mesh** out);
+/* Same with vtx / tet in device memory (copied into the mesh on `stream`,
+ * NULL = the context stream); indices are validated on the device. */
+stb_status stb_mesh_create_dev(stb_ctx* ctx, int64_t nv, const double* vtx_dev, int64_t nt,
+                               const int32_t* tet_dev, void* stream, stb_mesh** out);
 void stb_mesh_destroy(stb_mesh* mesh);
 int64_t stb_mesh_size(const stb_mesh* mesh);
 
@@ -126,6 +130,11 @@ stb_status stb_apply_dev(stb_ctx* ctx, const stb_mat* mat, int32_t nrhs, const d
  * w in S_h^0) at np points pts (np x 4, (t, x, y, z)); w has nt entries. */
 stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
                            const double* w, int64_t np, const double* pts, double* out);
+/* Same with w, pts and out in device memory; returns after the result is
+ * written (the call synchronises its stream). */
+stb_status stb_potential_S_dev(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                               const double* w_dev, int64_t np, const double* pts_dev,
+                               double* out_dev, void* stream);
 
 /* Single-panel potentials out[m] = V phi_{panel[m]} (pts[m]) for k pairs
  * (pts: k x 4 (t, x, y, z); panel: k indices into the mesh), the inner
@@ -138,6 +147,11 @@ stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_p
  * HIP events on the context stream: [0] geometry/outer points, [1] cull and
  * compaction, [2] clip + quadrature + store, [3] total. */
 stb_status stb_last_timings(const stb_ctx* ctx, double* ms4);
+
+/* Work of the last stb_assemble_V on ctx: [0] evaluations of L(phi)
+ * (empty-piece tests and Gauss nodes), [1] lit (outer point, trial panel)
+ * pairs, [2] candidate (outer point, trial panel) pairs examined, [3] tiles. */
+stb_status stb_last_work(const stb_ctx* ctx, int64_t* counts4);
 
 #ifdef __cplusplus
 }

@@ -7,8 +7,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstring>
-#include <vector>
 
 #include "stb_internal.h"
 
@@ -56,48 +54,123 @@ void stb_free_blocked(stb_mat* M) {
   M->nblk = M->nquad = 0;
 }
 
-// Host construction of the blocked copy from the CSR mirror.
-static stb_status build_blocked(stb_ctx* ctx, stb_mat* M) {
-  stb_status s = stb_mirror_host(M);
-  if (s) return s;
-  const int64_t n = M->n;
-  const int64_t nblk = (n + 15) / 16;
-  std::vector<int64_t> bptr((size_t)nblk + 1, 0);
-  std::vector<std::vector<int32_t>> ucols((size_t)nblk);
-  for (int64_t b = 0; b < nblk; ++b) {
-    std::vector<int32_t>& u = ucols[(size_t)b];
-    for (int64_t i = b * 16; i < std::min(n, b * 16 + 16); ++i)
-      u.insert(u.end(), M->h_cols.begin() + M->h_rowptr[i], M->h_cols.begin() + M->h_rowptr[i + 1]);
-    std::sort(u.begin(), u.end());
-    u.erase(std::unique(u.begin(), u.end()), u.end());
-    bptr[(size_t)b + 1] = bptr[(size_t)b] + (int64_t)((u.size() + 3) / 4);
+// Blocked copy, built on the device from the CSR: per 16-row block an LDS
+// bitmap over the n columns marks the union of the rows' columns; its
+// popcount prefix gives every column its slot, in column order.
+constexpr int kBlkThreads = 256;
+constexpr int64_t kMaxBlockedN = 262144;   // 2 x n/32 words of LDS <= 64 KiB
+
+__device__ __forceinline__ void blk_mark(int64_t b, int64_t n, const int64_t* rowptr,
+                                         const int32_t* cols, uint32_t* bits, int nw) {
+  for (int w = threadIdx.x; w < nw; w += kBlkThreads) bits[w] = 0u;
+  __syncthreads();
+  int64_t r1 = (b + 1) * 16 < n ? (b + 1) * 16 : n;
+  for (int64_t r = b * 16; r < r1; ++r)
+    for (int64_t k = rowptr[r] + threadIdx.x; k < rowptr[r + 1]; k += kBlkThreads) {
+      int32_t c = cols[k];
+      atomicOr(&bits[c >> 5], 1u << (c & 31));
+    }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlkThreads) void k_blk_count(int64_t nblk, int64_t n,
+                                                           const int64_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ cols,
+                                                           int64_t* __restrict__ nquad) {
+  extern __shared__ uint32_t lds[];
+  int64_t b = blockIdx.x;
+  if (b >= nblk) return;
+  int nw = (int)((n + 31) / 32);
+  blk_mark(b, n, rowptr, cols, lds, nw);
+  int c = 0;
+  for (int w = threadIdx.x; w < nw; w += kBlkThreads) c += __popc(lds[w]);
+  __shared__ int red[kBlkThreads];
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = kBlkThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
   }
-  const int64_t nquad = bptr[(size_t)nblk];
-  std::vector<int32_t> bcol((size_t)nquad * 4, -1);
-  std::vector<float> bval((size_t)nquad * 64, 0.f);
-  for (int64_t b = 0; b < nblk; ++b) {
-    const std::vector<int32_t>& u = ucols[(size_t)b];
-    int64_t q0 = bptr[(size_t)b];
-    for (size_t k = 0; k < u.size(); ++k) bcol[(size_t)q0 * 4 + k] = u[k];
-    for (int64_t i = b * 16; i < std::min(n, b * 16 + 16); ++i) {
-      int r = (int)(i - b * 16);
-      for (int64_t k = M->h_rowptr[i]; k < M->h_rowptr[i + 1]; ++k) {
-        size_t pos = (size_t)(std::lower_bound(u.begin(), u.end(), M->h_cols[k]) - u.begin());
-        int64_t q = q0 + (int64_t)(pos / 4);
-        int kk = (int)(pos % 4);
-        bval[(size_t)q * 64 + (size_t)(kk * 16 + r)] = (float)M->h_vals[k];
-      }
+  if (threadIdx.x == 0) nquad[b] = (red[0] + 3) / 4;
+}
+
+__global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t n,
+                                                          const int64_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ cols,
+                                                          const double* __restrict__ vals,
+                                                          const int64_t* __restrict__ qptr,
+                                                          int32_t* __restrict__ bcol,
+                                                          float* __restrict__ bval) {
+  extern __shared__ uint32_t lds[];
+  int64_t b = blockIdx.x;
+  if (b >= nblk) return;
+  int nw = (int)((n + 31) / 32);
+  uint32_t* bits = lds;
+  int* pre = reinterpret_cast<int*>(lds + nw);
+  blk_mark(b, n, rowptr, cols, bits, nw);
+  // exclusive prefix of popcounts over the words: per-thread chunk, then a
+  // serial scan of the 256 chunk sums by thread 0
+  __shared__ int csum[kBlkThreads];
+  int per = (nw + kBlkThreads - 1) / kBlkThreads;
+  int w0 = threadIdx.x * per, w1 = min(nw, w0 + per);
+  int acc = 0;
+  for (int w = w0; w < w1; ++w) { pre[w] = acc; acc += __popc(bits[w]); }
+  csum[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = 0; t < kBlkThreads; ++t) { int v = csum[t]; csum[t] = run; run += v; }
+  }
+  __syncthreads();
+  for (int w = w0; w < w1; ++w) pre[w] += csum[threadIdx.x];
+  __syncthreads();
+  int64_t q0 = qptr[b], nq = qptr[b + 1] - q0;
+  for (int64_t k = threadIdx.x; k < nq * 4; k += kBlkThreads) bcol[q0 * 4 + k] = -1;
+  for (int64_t k = threadIdx.x; k < nq * 64; k += kBlkThreads) bval[q0 * 64 + k] = 0.f;
+  __syncthreads();
+  for (int w = threadIdx.x; w < nw; w += kBlkThreads) {
+    uint32_t m = bits[w];
+    int slot = pre[w];
+    while (m) {
+      int bit = __ffs(m) - 1;
+      bcol[q0 * 4 + slot] = w * 32 + bit;
+      ++slot;
+      m &= m - 1;
     }
   }
+  int64_t r1 = (b + 1) * 16 < n ? (b + 1) * 16 : n;
+  for (int64_t r = b * 16; r < r1; ++r)
+    for (int64_t k = rowptr[r] + threadIdx.x; k < rowptr[r + 1]; k += kBlkThreads) {
+      int32_t c = cols[k];
+      uint32_t below = bits[c >> 5] & ((1u << (c & 31)) - 1u);
+      int slot = pre[c >> 5] + __popc(below);
+      bval[(q0 + slot / 4) * 64 + (slot % 4) * 16 + (int)(r - b * 16)] = (float)vals[k];
+    }
+}
+
+static stb_status build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st) {
+  const int64_t n = M->n;
+  if (n > kMaxBlockedN)
+    return stb_fail(ctx, STB_E_INVALID_ARG, "16-RHS product supports n <= %lld", (long long)kMaxBlockedN);
+  const int64_t nblk = (n + 15) / 16;
+  size_t lds = sizeof(uint32_t) * 2 * (size_t)((n + 31) / 32);
+  int64_t* d_nq = nullptr;
   stb_free_blocked(M);
+  HIPCHK(ctx, dalloc(&d_nq, (size_t)nblk));
   HIPCHK(ctx, dalloc(&M->d_bptr, (size_t)nblk + 1));
+  hipLaunchKernelGGL(k_blk_count, dim3((unsigned)nblk), dim3(kBlkThreads), lds / 2, st, nblk, n,
+                     M->d_rowptr, M->d_cols, d_nq);
+  HIPCHK(ctx, hipGetLastError());
+  stb_status s = stb_exclusive_scan(ctx, d_nq, M->d_bptr, nblk, st);
+  dfree(d_nq);
+  if (s) return s;
+  int64_t nquad = 0;
+  HIPCHK(ctx, hipMemcpy(&nquad, M->d_bptr + nblk, sizeof(int64_t), hipMemcpyDeviceToHost));
   HIPCHK(ctx, dalloc(&M->d_bcol, (size_t)nquad * 4));
   HIPCHK(ctx, dalloc(&M->d_bval, (size_t)nquad * 64));
-  HIPCHK(ctx, hipMemcpy(M->d_bptr, bptr.data(), 8 * (nblk + 1), hipMemcpyHostToDevice));
-  if (nquad) {
-    HIPCHK(ctx, hipMemcpy(M->d_bcol, bcol.data(), 4 * nquad * 4, hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(M->d_bval, bval.data(), 4 * nquad * 64, hipMemcpyHostToDevice));
-  }
+  hipLaunchKernelGGL(k_blk_fill, dim3((unsigned)nblk), dim3(kBlkThreads), lds, st, nblk, n, M->d_rowptr,
+                     M->d_cols, M->d_vals, M->d_bptr, M->d_bcol, M->d_bval);
+  HIPCHK(ctx, hipGetLastError());
   M->nblk = nblk;
   M->nquad = nquad;
   return STB_OK;
@@ -105,7 +178,7 @@ static stb_status build_blocked(stb_ctx* ctx, stb_mat* M) {
 
 stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y, hipStream_t st) {
   if (!M->d_bptr) {
-    stb_status s = build_blocked(ctx, M);
+    stb_status s = build_blocked(ctx, M, st);
     if (s) return s;
   }
   float* w32 = nullptr;

@@ -15,6 +15,7 @@ struct stb_ctx {
   hipEvent_t ev[5] = {};
   std::string err;
   double timings[4] = {0, 0, 0, 0};
+  int64_t work[4] = {0, 0, 0, 0};   // last assembly: L evals, lit pairs, pairs, tiles
   // Gauss-Legendre nodes on [0,1] for the last n_g used (device copy)
   int gl_n = 0;
   double* d_gl = nullptr;   // [2 * kMaxNg]: x then w
@@ -81,3 +82,5 @@ static inline void dfree(void* p) {
 // 16-RHS product (stb_apply.hip): builds the blocked copy on first use.
 stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y, hipStream_t st);
 void stb_free_blocked(stb_mat* M);
+// Exclusive prefix sum of n counts into out[0..n] (device memory); syncs st.
+stb_status stb_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, hipStream_t st);

@@ -56,6 +56,16 @@ static stb_status ensure_gl(stb_ctx* ctx, int ng);
 
 // ---------------------------------------------------------------- kernels
 
+// status[j] = 5 when a vertex index of panel j is out of range.
+__global__ void k_check_index(int64_t nt, int64_t nv, const int32_t* __restrict__ tet,
+                              int32_t* __restrict__ status) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nt) return;
+  int bad = 0;
+  for (int k = 0; k < 4; ++k) bad |= (tet[4 * j + k] < 0 || tet[4 * j + k] >= nv);
+  status[j] = bad ? 5 : 0;
+}
+
 // Panel geometry.  status[j]: 0 ok, 1 non-finite, else as make_trial.
 __global__ void k_geometry(int64_t nt, const double* __restrict__ vtx,
                            const int32_t* __restrict__ tet, TrialRec* __restrict__ out,
@@ -195,6 +205,7 @@ __global__ void k_tiles(int64_t nrows, const int64_t* __restrict__ rowptr, int J
 // ------------------------------------------------------------ pair kernel
 constexpr int kThreads = 256;
 constexpr int kQueueCap = 1024;
+constexpr int kBlocksPerCU = 8;   // resident + queued blocks of the persistent grid
 
 struct PairArgs {
   int64_t nrows;
@@ -213,7 +224,8 @@ struct PairArgs {
   unsigned long long* n_causal;
   const double* gl;          // [kMaxNg] nodes on [0,1], then [kMaxNg] weights
   int ng;
-  int64_t tile0;             // first tile of this launch
+  int64_t ntiles;            // tiles of the whole launch (grid-stride loop)
+  unsigned long long* work;  // optional [3]: L(phi) evaluations, lit pairs, pairs
 };
 
 __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs P) {
@@ -229,7 +241,12 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs P) {
   __shared__ int s_cnt, s_nq;
 
   const int tid = threadIdx.x;
-  const int64_t tile = P.tile0 + blockIdx.x;
+  if (tid < P.ng) { s_glx[tid] = P.gl[tid]; s_glw[tid] = P.gl[kMaxNg + tid]; }
+  unsigned long long w_eval = 0, w_lit = 0, w_pairs = 0;
+  // persistent blocks: tiles b, b + G, b + 2G, ... (consecutive tiles of a
+  // row land on different blocks, which evens out their cost)
+  for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
+  __syncthreads();
   if (tid == 0) {
     // row of this tile: last r with tileptr[r] <= tile
     int64_t lo = 0, hi = P.nrows;
@@ -247,7 +264,6 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs P) {
     s_tail = 0;
     s_filled = 0;
   }
-  if (tid < P.ng) { s_glx[tid] = P.gl[tid]; s_glw[tid] = P.gl[kMaxNg + tid]; }
   __syncthreads();
   const int64_t row = s_row;
   const int cnt = s_cnt, nq = s_nq, ng = P.ng;
@@ -269,7 +285,9 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs P) {
     apex_of(T, xl, A);
     double wlo = 0.0, whi = 0.0;
     lit = A.t - T.tmin > fabs(A.d) && lit_test(T, xl, A);
+    ++w_pairs;
     if (lit && w_range(T, A, wlo, whi)) {
+      ++w_lit;
       ComboL cb;
       for (int k = 0; k < 4; ++k) {
         cb.C[k] = A.C[k]; cb.fa[k] = T.fa[k]; cb.fb[k] = T.fb[k]; cb.fc[k] = T.fc[k];
@@ -284,6 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs P) {
         int m = 2 * ng;
         double h = kTwoPi / m;
         for (int k = 0; k < m; ++k) I_inline += h * L_at(cb, k * h);
+        w_eval += m;
       } else {
         uint64_t mask = 0;
         int np = 0;
@@ -293,9 +312,14 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs P) {
           double H = b - a;
           if (!(H > 0.0)) continue;
           bool ne = L_at(cb, a + 0.5 * H) != 0.0;
-          if (!ne) ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+          ++w_eval;
+          if (!ne) {
+            ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+            w_eval += 2;
+          }
           if (ne) { mask |= (1ull << k); ++np; }
         }
+        w_eval += (unsigned long long)np * ng;
         if (np > 0) {
           int s0 = atomicAdd(&s_tail, np);
           if (s0 + np <= kQueueCap) {
@@ -382,6 +406,12 @@ __global__ __launch_bounds__(kThreads) void k_pairs(PairArgs P) {
       if (I != 0.0) s += P.trial_w[P.cols[colbase + jj]] * I;
     }
     P.out_tile[tile] = s;
+  }
+  }  // tiles
+  if (P.work) {
+    atomicAdd(P.work + 0, w_eval);
+    atomicAdd(P.work + 1, w_lit);
+    atomicAdd(P.work + 2, w_pairs);
   }
 }
 
@@ -554,18 +584,23 @@ static stb_status ensure_outer(stb_ctx* ctx, stb_mesh* m, int mq) {
 }
 
 // Exclusive scan of n int64 counts into out[0..n] (device), via hipcub.
-static stb_status device_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t* out, int64_t n) {
+stb_status stb_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t* out, int64_t n,
+                              hipStream_t st) {
   size_t bytes = 0;
-  HIPCHK(ctx, hipcub::DeviceScan::InclusiveSum(nullptr, bytes, in, out + 1, (int)n, ctx->stream));
+  HIPCHK(ctx, hipcub::DeviceScan::InclusiveSum(nullptr, bytes, in, out + 1, (int)n, st));
   void* tmp = nullptr;
   HIPCHK(ctx, hipMalloc(&tmp, bytes > 0 ? bytes : 1));
-  hipError_t e1 = hipMemsetAsync(out, 0, sizeof(int64_t), ctx->stream);
-  hipError_t e2 = hipcub::DeviceScan::InclusiveSum(tmp, bytes, in, out + 1, (int)n, ctx->stream);
-  hipError_t e3 = hipStreamSynchronize(ctx->stream);
+  hipError_t e1 = hipMemsetAsync(out, 0, sizeof(int64_t), st);
+  hipError_t e2 = hipcub::DeviceScan::InclusiveSum(tmp, bytes, in, out + 1, (int)n, st);
+  hipError_t e3 = hipStreamSynchronize(st);
   (void)hipFree(tmp);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
     return fail(ctx, STB_E_DEVICE, "scan failed");
   return STB_OK;
+}
+
+static stb_status device_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t* out, int64_t n) {
+  return stb_exclusive_scan(ctx, in, out, n, ctx->stream);
 }
 
 // Cull rows (apex boxes) against all trial panels into CSR candidates.
@@ -610,14 +645,13 @@ static stb_status make_tiles(stb_ctx* ctx, int64_t nrows, const int64_t* d_rowpt
 }
 
 static stb_status launch_pairs(stb_ctx* ctx, PairArgs& A, int64_t ntiles) {
-  // dispatches stay below 2^31 work-items: chunks of 2^22 tiles
-  const int64_t kChunk = 1ll << 22;
-  for (int64_t t0 = 0; t0 < ntiles; t0 += kChunk) {
-    A.tile0 = t0;
-    int64_t n = std::min(kChunk, ntiles - t0);
-    hipLaunchKernelGGL(k_pairs, dim3((unsigned)n), dim3(kThreads), 0, ctx->stream, A);
-    HIPCHK(ctx, hipGetLastError());
-  }
+  if (ntiles <= 0) return STB_OK;
+  int ncu = 0;
+  HIPCHK(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  int64_t grid = std::min<int64_t>(ntiles, (int64_t)std::max(ncu, 1) * kBlocksPerCU);
+  A.ntiles = ntiles;
+  hipLaunchKernelGGL(k_pairs, dim3((unsigned)grid), dim3(kThreads), 0, ctx->stream, A);
+  HIPCHK(ctx, hipGetLastError());
   return STB_OK;
 }
 
@@ -687,19 +721,22 @@ void stb_ctx_destroy(stb_ctx* ctx) {
   delete ctx;
 }
 
-stb_status stb_mesh_create(stb_ctx* ctx, int64_t nv, const double* vtx, int64_t nt,
-                           const int32_t* tet, stb_mesh** out) {
+static stb_status mesh_create_impl(stb_ctx* ctx, int64_t nv, const double* vtx, int64_t nt,
+                                   const int32_t* tet, bool dev, hipStream_t ust, stb_mesh** out) {
   if (!ctx || !out) return fail(ctx, STB_E_INVALID_ARG, "NULL argument");
   *out = nullptr;
   if (nv <= 0 || nt <= 0 || !vtx || !tet)
     return fail(ctx, STB_E_INVALID_ARG, "empty mesh or NULL arrays (nv=%lld nt=%lld)",
                 (long long)nv, (long long)nt);
-  if (nt > (int64_t)INT32_MAX) return fail(ctx, STB_E_INVALID_ARG, "too many panels");
-  for (int64_t i = 0; i < 4 * nt; ++i)
-    if (tet[i] < 0 || tet[i] >= nv)
-      return fail(ctx, STB_E_INVALID_MESH, "panel %lld: vertex index %d out of range",
-                  (long long)(i / 4), tet[i]);
+  if (nt > (int64_t)INT32_MAX || nv > (int64_t)INT32_MAX)
+    return fail(ctx, STB_E_INVALID_ARG, "too many panels or vertices");
+  if (!dev)
+    for (int64_t i = 0; i < 4 * nt; ++i)
+      if (tet[i] < 0 || tet[i] >= nv)
+        return fail(ctx, STB_E_INVALID_MESH, "panel %lld: vertex index %d out of range",
+                    (long long)(i / 4), tet[i]);
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (dev && ust) HIPCHK(ctx, hipStreamSynchronize(ust));
   stb_mesh* m = new stb_mesh();
   m->ctx = ctx;
   m->nv = nv;
@@ -714,15 +751,30 @@ stb_status stb_mesh_create(stb_ctx* ctx, int64_t nv, const double* vtx, int64_t 
     cleanup();
     return fail(ctx, STB_E_NO_MEMORY, "device allocation for %lld panels failed", (long long)nt);
   }
-  hipError_t e = hipMemcpyAsync(m->d_vtx, vtx, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(m->d_tet, tet, sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, ctx->stream);
+  hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  hipError_t e = hipMemcpyAsync(m->d_vtx, vtx, sizeof(double) * 4 * nv, kind, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->d_tet, tet, sizeof(int32_t) * 4 * nt, kind, ctx->stream);
+  std::vector<int32_t> status((size_t)nt);
+  if (dev && e == hipSuccess) {
+    // indices first, on the device: the geometry kernel gathers through them
+    hipLaunchKernelGGL(k_check_index, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, ctx->stream, nt, nv,
+                       m->d_tet, d_status);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(status.data(), d_status, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess)
+      for (int64_t j = 0; j < nt; ++j)
+        if (status[j] != 0) {
+          cleanup();
+          return fail(ctx, STB_E_INVALID_MESH, "panel %lld: vertex index out of range", (long long)j);
+        }
+  }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_geometry, dim3((unsigned)((nt + 127) / 128)), dim3(128), 0, ctx->stream, nt,
                        m->d_vtx, m->d_tet, m->d_trial, d_status);
     e = hipGetLastError();
   }
-  std::vector<int32_t> status((size_t)nt);
   if (e == hipSuccess)
     e = hipMemcpyAsync(status.data(), d_status, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -741,6 +793,16 @@ stb_status stb_mesh_create(stb_ctx* ctx, int64_t nv, const double* vtx, int64_t 
   dfree(d_status);
   *out = m;
   return STB_OK;
+}
+
+stb_status stb_mesh_create(stb_ctx* ctx, int64_t nv, const double* vtx, int64_t nt,
+                           const int32_t* tet, stb_mesh** out) {
+  return mesh_create_impl(ctx, nv, vtx, nt, tet, false, nullptr, out);
+}
+
+stb_status stb_mesh_create_dev(stb_ctx* ctx, int64_t nv, const double* vtx_dev, int64_t nt,
+                               const int32_t* tet_dev, void* stream, stb_mesh** out) {
+  return mesh_create_impl(ctx, nv, vtx_dev, nt, tet_dev, true, (hipStream_t)stream, out);
 }
 
 void stb_mesh_destroy(stb_mesh* m) {
@@ -778,12 +840,12 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   s = make_tiles(ctx, mesh->nt, M->d_rowptr, J, &d_tileptr, &ntiles);
   if (s) { stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
-  unsigned long long* d_causal = nullptr;
-  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess || dalloc(&d_causal, 1) != hipSuccess) {
+  unsigned long long* d_causal = nullptr;   // [0] causal pairs, [1..3] work counters
+  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess || dalloc(&d_causal, 4) != hipSuccess) {
     dfree(d_tileptr); dfree(d_causal); stb_mat_destroy(M);
     return fail(ctx, STB_E_NO_MEMORY, "store of %lld entries does not fit", (long long)M->nnz);
   }
-  HIPCHK(ctx, hipMemsetAsync(d_causal, 0, sizeof(unsigned long long), ctx->stream));
+  HIPCHK(ctx, hipMemsetAsync(d_causal, 0, 4 * sizeof(unsigned long long), ctx->stream));
   PairArgs A;
   A.nrows = mesh->nt;
   A.rowptr = M->d_rowptr;
@@ -799,13 +861,14 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   A.out_vals = M->d_vals;
   A.out_tile = nullptr;
   A.n_causal = d_causal;
+  A.work = d_causal + 1;
   A.gl = ctx->d_gl;
   A.ng = p.n_g;
   s = launch_pairs(ctx, A, ntiles);
   if (s) { dfree(d_tileptr); dfree(d_causal); stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
-  unsigned long long nc = 0;
-  hipError_t e = hipMemcpyAsync(&nc, d_causal, sizeof(nc), hipMemcpyDeviceToHost, ctx->stream);
+  unsigned long long cnts[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(cnts, d_causal, sizeof(cnts), hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   dfree(d_tileptr);
   dfree(d_causal);
@@ -813,7 +876,9 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
     stb_mat_destroy(M);
     return fail(ctx, STB_E_DEVICE, "assembly failed: %s", hipGetErrorString(e));
   }
-  M->n_causal = (int64_t)nc;
+  M->n_causal = (int64_t)cnts[0];
+  for (int k = 0; k < 3; ++k) ctx->work[k] = (int64_t)cnts[k + 1];
+  ctx->work[3] = ntiles;
   float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
   (void)hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
   (void)hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
@@ -925,35 +990,19 @@ stb_status stb_apply(stb_ctx* ctx, const stb_mat* M, int32_t nrhs, const double*
   return s;
 }
 
-stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_params* params,
-                           const double* w, int64_t np, const double* pts, double* out) {
-  if (!ctx || !mesh_c || !w || (np > 0 && (!pts || !out)) || np < 0)
-    return fail(ctx, STB_E_INVALID_ARG, "bad arguments");
-  stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
-  stb_quad_params p = params ? *params : stb_default_params();
-  stb_status s = check_params(ctx, &p);
-  if (s) return s;
-  if (np == 0) return STB_OK;
-  for (int64_t i = 0; i < 4 * np; ++i)
-    if (!std::isfinite(pts[i])) return fail(ctx, STB_E_INVALID_ARG, "non-finite point %lld", (long long)(i / 4));
-  HIPCHK(ctx, hipSetDevice(ctx->device));
+// Potential with device inputs and output, on the context stream.
+static stb_status potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p,
+                                 const double* d_w, int64_t np, const double* d_pts, double* d_out) {
+  stb_status s;
   if ((s = ensure_gl(ctx, p.n_g))) return s;
-  double *d_pts = nullptr, *d_w = nullptr, *d_part = nullptr, *d_out = nullptr;
+  double* d_part = nullptr;
   ApexBox* d_box = nullptr;
   int64_t *d_rowptr = nullptr, *d_tileptr = nullptr;
   int32_t* d_cols = nullptr;
   auto cleanup = [&]() {
-    dfree(d_pts); dfree(d_w); dfree(d_part); dfree(d_out); dfree(d_box);
-    dfree(d_rowptr); dfree(d_tileptr); dfree(d_cols);
+    dfree(d_part); dfree(d_box); dfree(d_rowptr); dfree(d_tileptr); dfree(d_cols);
   };
-  if (dalloc(&d_pts, (size_t)np * 4) != hipSuccess || dalloc(&d_w, (size_t)mesh->nt) != hipSuccess ||
-      dalloc(&d_box, (size_t)np) != hipSuccess || dalloc(&d_out, (size_t)np) != hipSuccess) {
-    cleanup();
-    return fail(ctx, STB_E_NO_MEMORY, "potential buffers");
-  }
-  hipError_t e = hipMemcpyAsync(d_pts, pts, sizeof(double) * 4 * np, hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_w, w, sizeof(double) * mesh->nt, hipMemcpyHostToDevice, ctx->stream);
-  if (e != hipSuccess) { cleanup(); return fail(ctx, STB_E_DEVICE, "copy failed"); }
+  if (dalloc(&d_box, (size_t)np) != hipSuccess) return fail(ctx, STB_E_NO_MEMORY, "potential buffers");
   hipLaunchKernelGGL(k_point_boxes, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
                      d_pts, d_box);
   int64_t nnz = 0, ntiles = 0;
@@ -976,18 +1025,65 @@ stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_
   A.out_vals = nullptr;
   A.out_tile = d_part;
   A.n_causal = nullptr;
+  A.work = nullptr;
   A.gl = ctx->d_gl;
   A.ng = p.n_g;
   s = launch_pairs(ctx, A, ntiles);
   if (s) { cleanup(); return s; }
   hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
                      d_tileptr, d_part, d_out);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(double) * np, hipMemcpyDeviceToHost, ctx->stream);
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   cleanup();
   if (e != hipSuccess) return fail(ctx, STB_E_DEVICE, "potential failed: %s", hipGetErrorString(e));
   return STB_OK;
+}
+
+stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_params* params,
+                           const double* w, int64_t np, const double* pts, double* out) {
+  if (!ctx || !mesh_c || !w || (np > 0 && (!pts || !out)) || np < 0)
+    return fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
+  if (mesh->ctx != ctx) return fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
+  stb_quad_params p = params ? *params : stb_default_params();
+  stb_status s = check_params(ctx, &p);
+  if (s) return s;
+  if (np == 0) return STB_OK;
+  for (int64_t i = 0; i < 4 * np; ++i)
+    if (!std::isfinite(pts[i])) return fail(ctx, STB_E_INVALID_ARG, "non-finite point %lld", (long long)(i / 4));
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  double *d_pts = nullptr, *d_w = nullptr, *d_out = nullptr;
+  if (dalloc(&d_pts, (size_t)np * 4) != hipSuccess || dalloc(&d_w, (size_t)mesh->nt) != hipSuccess ||
+      dalloc(&d_out, (size_t)np) != hipSuccess) {
+    dfree(d_pts); dfree(d_w); dfree(d_out);
+    return fail(ctx, STB_E_NO_MEMORY, "potential buffers");
+  }
+  hipError_t e = hipMemcpyAsync(d_pts, pts, sizeof(double) * 4 * np, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_w, w, sizeof(double) * mesh->nt, hipMemcpyHostToDevice, ctx->stream);
+  s = e == hipSuccess ? potential_core(ctx, mesh, p, d_w, np, d_pts, d_out)
+                      : fail(ctx, STB_E_DEVICE, "copy failed");
+  if (s == STB_OK) {
+    e = hipMemcpy(out, d_out, sizeof(double) * np, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) s = fail(ctx, STB_E_DEVICE, "copy back failed: %s", hipGetErrorString(e));
+  }
+  dfree(d_pts); dfree(d_w); dfree(d_out);
+  return s;
+}
+
+stb_status stb_potential_S_dev(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_params* params,
+                               const double* w_dev, int64_t np, const double* pts_dev, double* out_dev,
+                               void* stream) {
+  if (!ctx || !mesh_c || !w_dev || (np > 0 && (!pts_dev || !out_dev)) || np < 0)
+    return fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
+  if (mesh->ctx != ctx) return fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
+  stb_quad_params p = params ? *params : stb_default_params();
+  stb_status s = check_params(ctx, &p);
+  if (s) return s;
+  if (np == 0) return STB_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (stream) HIPCHK(ctx, hipStreamSynchronize((hipStream_t)stream));
+  return potential_core(ctx, mesh, p, w_dev, np, pts_dev, out_dev);
 }
 
 stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
@@ -1027,6 +1123,12 @@ stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_p
 stb_status stb_last_timings(const stb_ctx* ctx, double* ms4) {
   if (!ctx || !ms4) return fail(nullptr, STB_E_INVALID_ARG, "NULL argument");
   for (int k = 0; k < 4; ++k) ms4[k] = ctx->timings[k];
+  return STB_OK;
+}
+
+stb_status stb_last_work(const stb_ctx* ctx, int64_t* counts4) {
+  if (!ctx || !counts4) return fail(nullptr, STB_E_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 4; ++k) counts4[k] = ctx->work[k];
   return STB_OK;
 }
 

@@ -20,8 +20,8 @@ STATUS = {0: "STB_OK", 1: "STB_E_INVALID_ARG", 2: "STB_E_INVALID_MESH", 3: "STB_
 EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_status_str",
            "stb_last_error", "stb_mesh_create", "stb_mesh_destroy", "stb_mesh_size",
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
-           "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_inner_values",
-           "stb_last_timings"]
+           "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
+           "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_mesh_create_dev"]
 
 
 class QuadParams(ctypes.Structure):
@@ -78,6 +78,10 @@ def load():
     L.stb_potential_S.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _D, i64, _D, _D]
     L.stb_last_timings.argtypes = [_VP, _D]
     L.stb_inner_values.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
+    L.stb_last_work.argtypes = [_VP, _I64]
+    L.stb_mesh_create_dev.argtypes = [_VP, i64, _VP, i64, _VP, _VP, ctypes.POINTER(_VP)]
+    L.stb_potential_S_dev.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _VP, i64, _VP, _VP,
+                                      _VP]
     _lib = L
     return L
 
@@ -131,11 +135,20 @@ class Context:
         _chk(load().stb_last_timings(self.h, out.ctypes.data_as(_D)), self.h)
         return dict(geometry_ms=out[0], cull_ms=out[1], quadrature_ms=out[2], total_ms=out[3])
 
+    def work(self):
+        out = np.zeros(4, dtype=np.int64)
+        _chk(load().stb_last_work(self.h, out.ctypes.data_as(_I64)), self.h)
+        return dict(L_evals=int(out[0]), lit_pairs=int(out[1]), apex_pairs=int(out[2]),
+                    tiles=int(out[3]))
+
 
 class Mesh:
-    def __init__(self, ctx, vtx, tets):
+    def __init__(self, ctx, vtx, tets, _handle=None, _nt=None):
         L = load()
         self.ctx = ctx
+        if _handle is not None:
+            self.h, self.nt = _handle, _nt
+            return
         vtx, pv = _d(vtx)
         tets = np.ascontiguousarray(tets, dtype=np.int32)
         h = _VP()
@@ -143,6 +156,14 @@ class Mesh:
                                tets.ctypes.data_as(_I32), ctypes.byref(h)), ctx.h)
         self.h = h
         self.nt = int(tets.shape[0])
+
+    @classmethod
+    def from_device(cls, ctx, vtx_ptr, nv, tet_ptr, nt, stream=None):
+        """Mesh from device arrays (e.g. torch tensors' data_ptr())."""
+        h = _VP()
+        _chk(load().stb_mesh_create_dev(ctx.h, nv, _VP(vtx_ptr), nt, _VP(tet_ptr),
+                                        _VP(stream) if stream else None, ctypes.byref(h)), ctx.h)
+        return cls(ctx, None, None, _handle=h, _nt=int(nt))
 
     def close(self):
         if self.h:
@@ -229,3 +250,10 @@ def inner_values(ctx, mesh, pts, panels, params=None):
     _chk(load().stb_inner_values(ctx.h, mesh.h, ctypes.byref(p), pts.shape[0], pp,
                                  panels.ctypes.data_as(_I32), out.ctypes.data_as(_D)), ctx.h)
     return out
+
+
+def potential_S_dev(ctx, mesh, w_ptr, np_, pts_ptr, out_ptr, params=None, stream=None):
+    """Potential with device pointers (density, points (t,x,y,z), output)."""
+    p = params if params is not None else default_params()
+    _chk(load().stb_potential_S_dev(ctx.h, mesh.h, ctypes.byref(p), _VP(w_ptr), np_, _VP(pts_ptr),
+                                    _VP(out_ptr), _VP(stream) if stream else None), ctx.h)

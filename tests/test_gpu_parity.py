@@ -32,6 +32,8 @@ def _rel_err(a, ref, scale=None):
 
 @pytest.fixture(scope="module")
 def stb():
+    import torch
+    torch.cuda.init()          # torch's HIP state first, then the library
     from paper_2103_16841_amd import stb as s
     print("loading", s.lib_path(), flush=True)
     s.load()
@@ -241,3 +243,58 @@ def test_single_panel_and_empty_points(stb, ctx):
     ref = oracle.assemble_rows(vtx, tets)
     assert _rel_err(A.to_dense(), ref).max() <= RTOL
     assert stb.potential_S(ctx, m, np.ones(1), np.zeros((0, 4))).shape == (0,)
+
+
+def test_device_pointer_paths(stb, ctx):
+    """Mesh ingest, products and potential from device-resident inputs."""
+    import torch
+    mesh = inputs.icosphere_mesh(level=0, S=6, T=3.0, jitter=0.2, seed=12)
+    dev = torch.device("cuda:0")
+    vtx = torch.from_numpy(mesh.vtx).to(dev)
+    tet = torch.from_numpy(mesh.tets).to(dev)
+    torch.cuda.synchronize()
+    m = stb.Mesh.from_device(ctx, vtx.data_ptr(), mesh.nv, tet.data_ptr(), mesh.nt)
+    A = stb.assemble_V(ctx, m)
+    ref = oracle.assemble_rows(mesh.vtx, mesh.tets)
+    assert _rel_err(A.to_dense(), ref).max() <= RTOL
+    w = inputs.density_normal(mesh.nt, seed=1)
+    wd = torch.from_numpy(w).to(dev)
+    yd = torch.empty_like(wd)
+    torch.cuda.synchronize()
+    A.apply_dev(wd.data_ptr(), yd.data_ptr(), 1)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(yd.cpu().numpy() - ref @ w) <= RTOL * _row_scale(ref, w))
+    W = np.random.default_rng(2).standard_normal((mesh.nt, 16))
+    Wd = torch.from_numpy(W).to(dev)
+    Yd = torch.empty_like(Wd)
+    torch.cuda.synchronize()
+    A.apply_dev(Wd.data_ptr(), Yd.data_ptr(), 16)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(Yd.cpu().numpy() - ref @ W) <= 2e-6 * (np.abs(ref) @ np.abs(W)))
+    pts = inputs.shell_points(64, mesh.T, seed=3)
+    pd = torch.from_numpy(pts).to(dev)
+    ud = torch.empty(64, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    stb.potential_S_dev(ctx, m, wd.data_ptr(), 64, pd.data_ptr(), ud.data_ptr())
+    uo = oracle.potential(mesh.vtx, mesh.tets, w, pts)
+    absref = oracle.potential(mesh.vtx, mesh.tets, np.abs(w), pts)
+    assert np.all(np.abs(ud.cpu().numpy() - uo) <= RTOL * np.maximum(absref, 1e-300))
+    bad = tet.clone()
+    bad[3, 2] = mesh.nv + 5
+    torch.cuda.synchronize()
+    with pytest.raises(stb.StbError) as e:
+        stb.Mesh.from_device(ctx, vtx.data_ptr(), mesh.nv, bad.data_ptr(), mesh.nt)
+    assert e.value.status == 2
+
+
+def test_work_counters(stb, ctx, cube):
+    m = stb.Mesh(ctx, cube.vtx, cube.tets)
+    stb.assemble_V(ctx, m)
+    w = ctx.work()
+    st = oracle.Stats()
+    oracle.assemble_rows(cube.vtx, cube.tets, stats=st)
+    # the same rule: lit (outer point, panel) pairs and L evaluations (piece
+    # tests and Gauss nodes) agree up to hint breakpoints decided differently
+    # within rounding
+    assert abs(w["lit_pairs"] - st.n_lit) <= 0.01 * st.n_lit
+    assert abs(w["L_evals"] - st.n_eval) <= 0.02 * st.n_eval
