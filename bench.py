@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--points", type=int, default=1000)
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
@@ -79,6 +81,14 @@ def main():
     y_d = torch.empty(nt, dtype=torch.float64, device=dev)
     Y_d = torch.empty((nt, 16), dtype=torch.float64, device=dev)
     u_d = torch.empty(args.points, dtype=torch.float64, device=dev)
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     torch.cuda.synchronize()
     ctx = stb.Context(0)
     rec = {}

@@ -68,6 +68,44 @@ STB_HD __forceinline__ double dot3(const double* a, const double* b) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// sin and cos of an angle of moderate size (|x| < 64 pi; here x in
+// [0, 4 pi)): Cody-Waite reduction by pi/2 with a two-part pi/2, then the
+// Taylor polynomials of sin (to x^17) and cos (to x^18) on [-pi/4, pi/4],
+// whose truncation errors there are below 1e-17.
+STB_HD __forceinline__ void sincos_small(double x, double* s, double* c) {
+  const double kInvPio2 = 0.63661977236758134308;
+  const double kPio2Hi = 1.5707963267948966192e+00;   // nearest double to pi/2
+  const double kPio2Lo = 6.1232339957367660359e-17;   // pi/2 - kPio2Hi
+  double k = rint(x * kInvPio2);
+  double r = fma(-k, kPio2Hi, x);
+  r = fma(-k, kPio2Lo, r);
+  double r2 = r * r;
+  // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
+  double ps = -1.0 / 355687428096000.0;                 // -1/17!
+  ps = fma(ps, r2, 1.0 / 1307674368000.0);              //  1/15!
+  ps = fma(ps, r2, -1.0 / 6227020800.0);                // -1/13!
+  ps = fma(ps, r2, 1.0 / 39916800.0);                   //  1/11!
+  ps = fma(ps, r2, -1.0 / 362880.0);                    // -1/9!
+  ps = fma(ps, r2, 1.0 / 5040.0);                       //  1/7!
+  ps = fma(ps, r2, -1.0 / 120.0);                       // -1/5!
+  ps = fma(ps, r2, 1.0 / 6.0);                          //  1/3! (sign below)
+  double sr = fma(-r * r2, ps, r);
+  double pc = 1.0 / 6402373705728000.0;                 //  1/18!
+  pc = fma(pc, r2, -1.0 / 20922789888000.0);            // -1/16!
+  pc = fma(pc, r2, 1.0 / 87178291200.0);                //  1/14!
+  pc = fma(pc, r2, -1.0 / 479001600.0);                 // -1/12!
+  pc = fma(pc, r2, 1.0 / 3628800.0);                    //  1/10!
+  pc = fma(pc, r2, -1.0 / 40320.0);                     // -1/8!
+  pc = fma(pc, r2, 1.0 / 720.0);                        //  1/6!
+  pc = fma(pc, r2, -1.0 / 24.0);                        // -1/4!
+  pc = fma(pc, r2, 0.5);                                //  1/2! (sign below)
+  double cr = fma(-r2, pc, 1.0);
+  int q = ((int)k) & 3;
+  double ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = (q == 1 || q == 2) ? -cc : cc;
+}
+
 STB_HD __forceinline__ double wrap_2pi(double a) {
   if (a < 0.0) a += kTwoPi;
   if (a < 0.0) a += kTwoPi;
@@ -106,16 +144,32 @@ STB_HD __forceinline__ double r_of_w(double w, double d2) {
   return d2 > 0.0 ? 0.5 * (w + d2 / w) : 0.5 * w;
 }
 
+// r(w1) - r(w0) for w1 >= w0 > 0 (or d^2 = 0).
+STB_HD __forceinline__ double rdiff(double w0, double w1, double d2) {
+  double h = 0.5 * (w1 - w0);
+  return d2 > 0.0 ? h * (1.0 - d2 / (w0 * w1)) : h;
+}
+
 // Face data needed by L(phi): fa, fb, fc of the 4 faces.
 struct FaceSet {
   double fa[4], fb[4], fc[4];
 };
 
+// Order two intervals by start (registers only).
+STB_HD __forceinline__ void order2(double& s0, double& e0, double& s1, double& e1) {
+  if (s1 < s0) {
+    double ts = s0, te = e0;
+    s0 = s1; e0 = e1; s1 = ts; e1 = te;
+  }
+}
+
 // L(phi) for cos/sin of phi.  C: C_k, d2 = d^2, [wlo, whi]: admissible w-range.
+// Everything stays in registers: at most three holes (the area-weighted
+// outward normals sum to zero, so at most three faces open downwards).
 STB_HD __forceinline__ double L_eval(const FaceSet& F, const double* C, double d2, double wlo,
-                                         double whi, double cs, double sn) {
+                                     double whi, double cs, double sn) {
   double lo = wlo, hi = whi;
-  double h0[3], h1[3];
+  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, c0 = 0.0, c1 = 0.0;
   int nh = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -133,13 +187,11 @@ STB_HD __forceinline__ double L_eval(const FaceSet& F, const double* C, double d
       if (!(D > 0.0)) continue;
       double q = Ck + copysign(sqrt(D), Ck);
       double r1 = q / e, r2 = -d2 * f / q;
-      // the area-weighted outward normals sum to zero, so at most three
-      // faces open downwards
-      if (nh < 3) {
-        h0[nh] = fmin(r1, r2);
-        h1[nh] = fmax(r1, r2);
-        ++nh;
-      }
+      double u0 = fmin(r1, r2), u1 = fmax(r1, r2);
+      if (nh == 0) { a0 = u0; a1 = u1; }
+      else if (nh == 1) { b0 = u0; b1 = u1; }
+      else { c0 = u0; c1 = u1; }
+      nh = nh < 3 ? nh + 1 : 3;
     } else {
       // linear: -2 C w - d^2 f < 0
       if (Ck > 0.0) lo = fmax(lo, -d2 * f / (2.0 * Ck));
@@ -148,29 +200,26 @@ STB_HD __forceinline__ double L_eval(const FaceSet& F, const double* C, double d
     }
   }
   if (!(hi > lo)) return 0.0;
-  double len = r_of_w(hi, d2) - r_of_w(lo, d2);
-  // clip the holes to [lo, hi], sort by start and subtract their union
-  double s[3], t[3];
-  int m = 0;
-  for (int k = 0; k < nh; ++k) {
-    double a0 = fmax(h0[k], lo), a1 = fmin(h1[k], hi);
-    if (a1 > a0) { s[m] = a0; t[m] = a1; ++m; }
-  }
-  if (m > 1) {
-    for (int i = 1; i < m; ++i)
-      for (int j = i; j > 0 && s[j - 1] > s[j]; --j) {
-        double ts = s[j]; s[j] = s[j - 1]; s[j - 1] = ts;
-        double tt = t[j]; t[j] = t[j - 1]; t[j - 1] = tt;
-      }
-  }
-  double cs0 = 0.0, ce0 = 0.0;
-  bool open = false;
-  for (int k = 0; k < m; ++k) {
-    if (!open) { cs0 = s[k]; ce0 = t[k]; open = true; }
-    else if (s[k] <= ce0) { ce0 = fmax(ce0, t[k]); }
-    else { len -= r_of_w(ce0, d2) - r_of_w(cs0, d2); cs0 = s[k]; ce0 = t[k]; }
-  }
-  if (open) len -= r_of_w(ce0, d2) - r_of_w(cs0, d2);
+  // r(w1) - r(w0) = (w1 - w0) (1 - d^2 / (w0 w1)) / 2: one division per piece
+  double len = rdiff(lo, hi, d2);
+  if (nh == 0) return len;
+  // clip the holes to [lo, hi] (empty ones become [hi, hi]), sort by start,
+  // subtract the measure of their union
+  if (nh < 2) { b0 = hi; b1 = hi; }
+  if (nh < 3) { c0 = hi; c1 = hi; }
+  a0 = fmin(fmax(a0, lo), hi); a1 = fmax(fmin(a1, hi), a0);
+  b0 = fmin(fmax(b0, lo), hi); b1 = fmax(fmin(b1, hi), b0);
+  c0 = fmin(fmax(c0, lo), hi); c1 = fmax(fmin(c1, hi), c0);
+  order2(a0, a1, b0, b1);
+  order2(b0, b1, c0, c1);
+  order2(a0, a1, b0, b1);
+  // merge: [a0,a1], [b0,b1], [c0,c1] sorted by start
+  if (b0 <= a1) { a1 = fmax(a1, b1); b0 = b1 = a1; }
+  if (c0 <= a1) { a1 = fmax(a1, c1); c0 = c1 = a1; }
+  else if (c0 <= b1) { b1 = fmax(b1, c1); c0 = c1 = b1; }
+  if (a1 > a0) len -= rdiff(a0, a1, d2);
+  if (b1 > b0) len -= rdiff(b0, b1, d2);
+  if (c1 > c0) len -= rdiff(c0, c1, d2);
   return len > 0.0 ? len : 0.0;
 }
 
@@ -189,6 +238,7 @@ STB_HD inline bool lit_test(const TrialRec& T, const double* x4, const Apex& A) 
   }
   double dead = kLitDead * (fabs(A.t - T.tmin) + T.diam);
   if (!(mx > dead)) return false;
+  if (mn < -dead) return true;     // a vertex inside the cone already decides
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j) {
       double U[3] = {T.X[j][1] - T.X[i][1], T.X[j][2] - T.X[i][2], T.X[j][3] - T.X[i][3]};
@@ -243,6 +293,24 @@ STB_HD inline bool lit_test(const TrialRec& T, const double* x4, const Apex& A) 
   return mn < -dead;
 }
 
+// Quick rejection by the bounding 4-ball of the panel (Theorem
+// phi_xi_sphere): over the closed ball B_r(y), y = (tau_c, c), the cone
+// function phi_Xi(x - z) ranges exactly over [phi - d_r(|x - c|),
+// phi + r sqrt 2] with phi = phi_Xi(x - y).  A ball entirely inside or
+// outside the cone (beyond a small margin) cannot be lit; otherwise the
+// exact test decides.
+STB_HD __forceinline__ bool ball_rejects(const TrialRec& T, const double* x4) {
+  const double s2 = 1.4142135623730951;
+  double tc = 0.5 * (T.tmin + T.tmax), ht = 0.5 * (T.tmax - T.tmin);
+  double r = sqrt(T.rad * T.rad + ht * ht) * (1.0 + 1e-12);
+  double dx = x4[1] - T.cx, dy = x4[2] - T.cy, dz = x4[3] - T.cz;
+  double al = sqrt(dx * dx + dy * dy + dz * dz);
+  double phi = al - (x4[0] - tc);
+  double dr = al < r / s2 ? al + sqrt(fmax(r * r - al * al, 0.0)) : r * s2;
+  double margin = 1e-9 * (fabs(x4[0] - T.tmin) + T.diam);
+  return (phi + r * s2 < -margin) || (phi - dr > margin);
+}
+
 // Stable roots of qa l^2 + qb l + qc = 0; returns count.
 STB_HD __forceinline__ int roots2(double qa, double qb, double qc, double* r) {
   if (qa == 0.0) {
@@ -275,8 +343,17 @@ STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
   int nb = 0;
   double d2 = A.d * A.d, ad = fabs(A.d);
   double sc = fabs(A.t - T.tmin) + T.diam;
+  // cone function at the vertices: an edge with both ends strictly inside
+  // the backward cone (a convex set) cannot meet it
+  double fv[4];
+  for (int k = 0; k < 4; ++k) {
+    double du = T.V[k][1] - A.pu, dv = T.V[k][2] - A.pv;
+    fv[k] = sqrt(du * du + dv * dv + d2) - (A.t - T.V[k][0]);
+  }
+  const double inside = -1e-9 * sc;
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j) {
+      if (fv[i] < inside && fv[j] < inside) continue;
       double a0 = A.t - T.V[i][0], a1 = T.V[i][0] - T.V[j][0];
       double bu = T.V[i][1] - A.pu, bv = T.V[i][2] - A.pv;
       double du = T.V[j][1] - T.V[i][1], dv = T.V[j][2] - T.V[i][2];
@@ -307,7 +384,7 @@ STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
         double cand[4] = {phik + g, phik - g, phik + kPi - g, phik + kPi + g};
         for (int m = 0; m < 4; ++m) {
           double sn, cs;
-          sincos(cand[m], &sn, &cs);
+          sincos_small(cand[m], &sn, &cs);
           double e = b * cs + c * sn - a;
           if (e == 0.0) continue;
           double wt = Ck / e;                 // double root of Q_k
@@ -471,7 +548,7 @@ STB_HD __forceinline__ double L_combo(const ComboL& cb, double cs, double sn) {
 
 STB_HD __forceinline__ double L_at(const ComboL& cb, double phi) {
   double sn, cs;
-  sincos(phi, &sn, &cs);
+  sincos_small(phi, &sn, &cs);
   return L_combo(cb, cs, sn);
 }
 
@@ -497,7 +574,7 @@ STB_HD inline double inner_serial(const TrialRec& T, const double* x4, int ng, c
   Apex A;
   apex_of(T, x4, A);
   double wlo = 0.0, whi = 0.0;
-  bool lit = A.t - T.tmin > fabs(A.d) && lit_test(T, x4, A);
+  bool lit = A.t - T.tmin > fabs(A.d) && !ball_rejects(T, x4) && lit_test(T, x4, A);
   if (lit_out) *lit_out = lit;
   if (!lit || !w_range(T, A, wlo, whi)) return 0.0;
   ComboL cb;

@@ -226,188 +226,269 @@ struct PairArgs {
   int ng;
   int64_t ntiles;            // tiles of the whole launch (grid-stride loop)
   unsigned long long* work;  // optional [3]: L(phi) evaluations, lit pairs, pairs
+  unsigned long long* prof;  // optional [8]: clock ticks per phase (diagnostics)
 };
 
-__global__ __launch_bounds__(kThreads) void k_pairs(PairArgs P) {
-  __shared__ ComboL s_cb[kThreads];
+__global__ __launch_bounds__(kThreads, 2) void k_pairs(PairArgs P) {
+  __shared__ ComboL s_cb[kThreads];               // by lit index
   __shared__ double s_qa[kQueueCap], s_qh[kQueueCap], s_qv[kQueueCap];
-  __shared__ uint16_t s_qc[kQueueCap];
-  __shared__ double s_I[kThreads];
+  __shared__ uint16_t s_qc[kQueueCap];            // lit index owning the piece
+  __shared__ int s_qpre[kQueueCap + 1];           // prefix of non-empty pieces
+  __shared__ uint8_t s_qne[kQueueCap];
+  __shared__ int s_part[kThreads];
+  __shared__ double s_I[kThreads];                // by combo
+  __shared__ double s_inl[kThreads];              // by lit index: pieces done inline
   __shared__ int s_slot0[kThreads], s_nslot[kThreads];
-  __shared__ uint8_t s_lit[kThreads];
+  __shared__ int16_t s_lidx[kThreads];            // combo -> lit index (-1: not lit)
+  __shared__ uint16_t s_lcombo[kThreads];         // lit index -> combo
   __shared__ double s_glx[kMaxNg], s_glw[kMaxNg];
-  __shared__ int s_tail, s_filled;
+  __shared__ int s_nlit, s_tail, s_filled;
   __shared__ int64_t s_row, s_start;
   __shared__ int s_cnt, s_nq;
 
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   if (tid < P.ng) { s_glx[tid] = P.gl[tid]; s_glw[tid] = P.gl[kMaxNg + tid]; }
   unsigned long long w_eval = 0, w_lit = 0, w_pairs = 0;
+  unsigned long long pt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long t_prev = 0;
+#define STB_PHASE(k)                                         \
+  if (P.prof && tid == 0) {                                  \
+    long long t_now = clock64();                             \
+    pt[k] += (unsigned long long)(t_now - t_prev);           \
+    t_prev = t_now;                                          \
+  }
   // persistent blocks: tiles b, b + G, b + 2G, ... (consecutive tiles of a
   // row land on different blocks, which evens out their cost)
   for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
-  __syncthreads();
-  if (tid == 0) {
-    // row of this tile: last r with tileptr[r] <= tile
-    int64_t lo = 0, hi = P.nrows;
-    while (hi - lo > 1) {
-      int64_t mid = (lo + hi) >> 1;
-      if (P.tileptr[mid] <= tile) lo = mid; else hi = mid;
-    }
-    int64_t row = lo;
-    int64_t start = (tile - P.tileptr[row]) * P.J;
-    int64_t cnt = P.rowptr[row + 1] - P.rowptr[row] - start;
-    s_row = row;
-    s_start = start;
-    s_cnt = (int)(cnt < P.J ? cnt : P.J);
-    s_nq = P.apex_n ? P.apex_n[row] : 1;
-    s_tail = 0;
-    s_filled = 0;
-  }
-  __syncthreads();
-  const int64_t row = s_row;
-  const int cnt = s_cnt, nq = s_nq, ng = P.ng;
-  const int ncombo = cnt * nq;
-  const int64_t colbase = P.rowptr[row] + s_start;
-
-  // ---------------- phase A: one lane per (trial jj, apex q)
-  double I_inline = 0.0;
-  int slot0 = 0, nslot = 0;
-  bool lit = false;
-  const int c = tid;
-  if (c < ncombo) {
-    int jj = c / nq, q = c - jj * nq;
-    int32_t j = P.cols[colbase + jj];
-    const TrialRec& T = P.trial[j];
-    const double* x4 = P.apex + ((int64_t)row * P.maxq + q) * 4;
-    double xl[4] = {x4[0], x4[1], x4[2], x4[3]};
-    Apex A;
-    apex_of(T, xl, A);
-    double wlo = 0.0, whi = 0.0;
-    lit = A.t - T.tmin > fabs(A.d) && lit_test(T, xl, A);
-    ++w_pairs;
-    if (lit && w_range(T, A, wlo, whi)) {
-      ++w_lit;
-      ComboL cb;
-      for (int k = 0; k < 4; ++k) {
-        cb.C[k] = A.C[k]; cb.fa[k] = T.fa[k]; cb.fb[k] = T.fb[k]; cb.fc[k] = T.fc[k];
+    __syncthreads();
+    if (tid == 0) {
+      // row of this tile: last r with tileptr[r] <= tile
+      int64_t lo = 0, hi = P.nrows;
+      while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (P.tileptr[mid] <= tile) lo = mid; else hi = mid;
       }
-      cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
-      s_cb[c] = cb;
-      double bp[kMaxBp];
-      int nb = breakpoints(T, A, bp);
-      sort_bp(bp, nb);
-      if (nb == 0) {
-        // periodic trapezoid rule with 2 n_g nodes
-        int m = 2 * ng;
-        double h = kTwoPi / m;
-        for (int k = 0; k < m; ++k) I_inline += h * L_at(cb, k * h);
-        w_eval += m;
-      } else {
-        uint64_t mask = 0;
-        int np = 0;
-        for (int k = 0; k < nb; ++k) {
-          double a = bp[k];
-          double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
-          double H = b - a;
-          if (!(H > 0.0)) continue;
-          bool ne = L_at(cb, a + 0.5 * H) != 0.0;
-          ++w_eval;
-          if (!ne) {
-            ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
-            w_eval += 2;
-          }
-          if (ne) { mask |= (1ull << k); ++np; }
+      int64_t row = lo;
+      int64_t start = (tile - P.tileptr[row]) * P.J;
+      int64_t cnt = P.rowptr[row + 1] - P.rowptr[row] - start;
+      s_row = row;
+      s_start = start;
+      s_cnt = (int)(cnt < P.J ? cnt : P.J);
+      s_nq = P.apex_n ? P.apex_n[row] : 1;
+      s_nlit = 0;
+      s_tail = 0;
+      s_filled = 0;
+    }
+    __syncthreads();
+    if (P.prof && tid == 0) t_prev = clock64();
+    const int64_t row = s_row;
+    const int cnt = s_cnt, nq = s_nq, ng = P.ng;
+    const int ncombo = cnt * nq;
+    const int64_t colbase = P.rowptr[row] + s_start;
+    const double* apex_row = P.apex + (int64_t)row * P.maxq * 4;
+
+    // ---- A1: one lane per (trial jj, apex q): lit test, compaction
+    if (tid < ncombo) {
+      int jj = tid / nq, q = tid - jj * nq;
+      const TrialRec& T = P.trial[P.cols[colbase + jj]];
+      double xl[4] = {apex_row[4 * q], apex_row[4 * q + 1], apex_row[4 * q + 2], apex_row[4 * q + 3]};
+      Apex A;
+      apex_of(T, xl, A);
+      ++w_pairs;
+      bool lit = A.t - T.tmin > fabs(A.d) && !ball_rejects(T, xl) && lit_test(T, xl, A);
+      int li = -1;
+      if (lit) li = atomicAdd(&s_nlit, 1);
+      s_lidx[tid] = (int16_t)li;
+      if (lit) s_lcombo[li] = (uint16_t)tid;
+    }
+    __syncthreads();
+    STB_PHASE(0)
+
+    // ---- A2: one lane per lit combo: breakpoints, pieces into the queue
+    const int nlit = s_nlit;
+    if (tid < nlit) {
+      const int c = s_lcombo[tid], li = tid;
+      int jj = c / nq, q = c - jj * nq;
+      const TrialRec& T = P.trial[P.cols[colbase + jj]];
+      double xl[4] = {apex_row[4 * q], apex_row[4 * q + 1], apex_row[4 * q + 2], apex_row[4 * q + 3]};
+      Apex A;
+      apex_of(T, xl, A);
+      ++w_lit;
+      double wlo = 0.0, whi = 0.0, inl = 0.0;
+      int slot0 = 0, nslot = 0;
+      if (w_range(T, A, wlo, whi)) {
+        ComboL cb;
+        for (int k = 0; k < 4; ++k) {
+          cb.C[k] = A.C[k]; cb.fa[k] = T.fa[k]; cb.fb[k] = T.fb[k]; cb.fc[k] = T.fc[k];
         }
-        w_eval += (unsigned long long)np * ng;
-        if (np > 0) {
+        cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
+        s_cb[li] = cb;
+        double bp[kMaxBp];
+        int nb = breakpoints(T, A, bp);
+        sort_bp(bp, nb);
+        if (nb == 0) {
+          // periodic trapezoid rule with 2 n_g nodes
+          int m = 2 * ng;
+          double h = kTwoPi / m;
+          for (int k = 0; k < m; ++k) inl += h * L_at(cb, k * h);
+          w_eval += m;
+        } else {
+          int np = 0;
+          for (int k = 0; k < nb; ++k) {
+            double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
+            np += (b - bp[k] > 0.0);
+          }
           int s0 = atomicAdd(&s_tail, np);
           if (s0 + np <= kQueueCap) {
             atomicMax(&s_filled, s0 + np);
             int s = s0;
-            for (int k = 0; k < nb; ++k)
-              if (mask >> k & 1ull) {
-                double a = bp[k];
-                double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
-                s_qa[s] = a; s_qh[s] = b - a; s_qc[s] = (uint16_t)c;
-                ++s;
-              }
+            for (int k = 0; k < nb; ++k) {
+              double a = bp[k];
+              double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
+              if (!(b - a > 0.0)) continue;
+              s_qa[s] = a; s_qh[s] = b - a; s_qc[s] = (uint16_t)li;
+              ++s;
+            }
             slot0 = s0;
             nslot = np;
           } else {
-            // queue full: integrate this lane's pieces itself, same order
-            for (int k = 0; k < nb; ++k)
-              if (mask >> k & 1ull) {
-                double a = bp[k];
-                double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
-                double acc = 0.0;
-                for (int g = 0; g < ng; ++g) acc += node_value(cb, a, b - a, s_glx[g], s_glw[g]);
-                I_inline += acc;
+            // queue full: this lane does its pieces itself, in order
+            for (int k = 0; k < nb; ++k) {
+              double a = bp[k];
+              double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
+              double H = b - a;
+              if (!(H > 0.0)) continue;
+              bool ne = L_at(cb, a + 0.5 * H) != 0.0;
+              ++w_eval;
+              if (!ne) {
+                ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+                w_eval += 2;
               }
+              if (!ne) continue;
+              double acc = 0.0;
+              for (int g = 0; g < ng; ++g) acc += node_value(cb, a, H, s_glx[g], s_glw[g]);
+              w_eval += ng;
+              inl += acc;
+            }
           }
         }
       }
+      s_inl[li] = inl;
+      s_slot0[li] = slot0;
+      s_nslot[li] = nslot;
     }
-    s_slot0[c] = slot0;
-    s_nslot[c] = nslot;
-    s_lit[c] = lit ? 1 : 0;
-  }
-  __syncthreads();
+    __syncthreads();
+    STB_PHASE(1)
 
-  // ---------------- phase B: one lane per (piece, Gauss node)
-  {
+    // ---- A3: one lane per queued piece: empty-piece test
     const int filled = s_filled;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int per = 64 / ng;                 // pieces per wave pass
-    const int seg = lane / ng, g = lane - seg * ng;
-    const int nwaves = kThreads / 64;
-    for (int base = wave * per; base < filled; base += nwaves * per) {
-      int e = base + seg;
-      double v = 0.0;
-      bool act = seg < per && e < filled;
-      if (act) v = node_value(s_cb[s_qc[e]], s_qa[e], s_qh[e], s_glx[g], s_glw[g]);
-      // ordered sum over the n_g lanes of the segment
-      int l0 = seg * ng;
-      double acc = 0.0;
-      for (int k = 0; k < ng; ++k) acc += __shfl(v, (l0 + k) & 63, 64);
-      if (act && g == 0) s_qv[e] = acc;
-    }
-  }
-  __syncthreads();
-
-  // ---------------- per combo: ordered sum over its pieces
-  if (c < ncombo) {
-    double I = I_inline;
-    for (int s = 0; s < nslot; ++s) I += s_qv[slot0 + s];
-    s_I[c] = I / (4.0 * kPi);
-  }
-  __syncthreads();
-
-  // ---------------- per trial panel: outer sum, store
-  if (P.out_vals) {
-    if (tid < cnt) {
-      const double* wq = P.apex_w + (int64_t)row * P.maxq;
-      double s = 0.0;
-      bool any = false;
-      for (int q = 0; q < nq; ++q) {
-        double I = s_I[tid * nq + q];
-        if (I != 0.0) s += wq[q] * I;
-        any |= s_lit[tid * nq + q] != 0;
+    for (int e = tid; e < filled; e += kThreads) {
+      const ComboL& cb = s_cb[s_qc[e]];
+      double a = s_qa[e], H = s_qh[e];
+      bool ne = L_at(cb, a + 0.5 * H) != 0.0;
+      ++w_eval;
+      if (!ne) {
+        ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+        w_eval += 2;
       }
-      P.out_vals[colbase + tid] = s;
-      uint64_t bal = __ballot(any);
-      if ((tid & 63) == 0 && bal) atomicAdd(P.n_causal, (unsigned long long)__popcll(bal));
+      s_qne[e] = ne ? 1 : 0;
+      s_qv[e] = 0.0;
     }
-  } else if (tid == 0) {
-    // potential mode (nq == 1): ordered sum of w_j I_j over the tile
-    double s = 0.0;
-    for (int jj = 0; jj < cnt; ++jj) {
-      double I = s_I[jj];
-      if (I != 0.0) s += P.trial_w[P.cols[colbase + jj]] * I;
+    __syncthreads();
+    // exclusive prefix of the non-empty flags (chunk per lane, then lane 0)
+    {
+      const int per = (filled + kThreads - 1) / kThreads;
+      const int e0 = tid * per, e1 = min(filled, e0 + per);
+      int acc = 0;
+      for (int e = e0; e < e1; ++e) { s_qpre[e] = acc; acc += s_qne[e]; }
+      s_part[tid] = acc;
+      __syncthreads();
+      if (tid == 0) {
+        int run = 0;
+        for (int t = 0; t < kThreads; ++t) { int v = s_part[t]; s_part[t] = run; run += v; }
+        s_qpre[filled] = run;
+      }
+      __syncthreads();
+      for (int e = e0; e < e1; ++e) s_qpre[e] += s_part[tid];
     }
-    P.out_tile[tile] = s;
-  }
+    __syncthreads();
+    STB_PHASE(2)
+
+    // ---- B: one lane per (non-empty piece, Gauss node)
+    {
+      const int nne = s_qpre[filled];
+      const int per = 64 / ng;                 // pieces per wave pass
+      const int seg = lane / ng, g = lane - seg * ng;
+      const int nwaves = kThreads / 64;
+      for (int base = wave * per; base < nne; base += nwaves * per) {
+        int k = base + seg;
+        bool act = seg < per && k < nne;
+        double v = 0.0;
+        int e = 0;
+        if (act) {
+          // the queued piece whose non-empty rank is k
+          int lo = 0, hi = filled - 1;
+          while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (s_qpre[mid] + s_qne[mid] <= k) lo = mid + 1; else hi = mid;
+          }
+          e = lo;
+          v = node_value(s_cb[s_qc[e]], s_qa[e], s_qh[e], s_glx[g], s_glw[g]);
+        }
+        // ordered sum over the n_g lanes of the segment
+        int l0 = seg * ng;
+        double acc = 0.0;
+        for (int kk = 0; kk < ng; ++kk) acc += __shfl(v, (l0 + kk) & 63, 64);
+        if (act && g == 0) s_qv[e] = acc;
+      }
+      w_eval += (tid == 0) ? (unsigned long long)nne * ng : 0ull;
+    }
+    __syncthreads();
+    STB_PHASE(3)
+
+    // ---- per combo: ordered sum over its pieces (empty pieces hold +0.0)
+    if (tid < ncombo) {
+      int li = s_lidx[tid];
+      double I = 0.0;
+      if (li >= 0) {
+        I = s_inl[li];
+        for (int s = 0; s < s_nslot[li]; ++s) I += s_qv[s_slot0[li] + s];
+      }
+      s_I[tid] = I / (4.0 * kPi);
+    }
+    __syncthreads();
+
+    // ---- per trial panel: outer sum, store
+    if (P.out_vals) {
+      if (tid < cnt) {
+        const double* wq = P.apex_w + (int64_t)row * P.maxq;
+        double s = 0.0;
+        bool any = false;
+        for (int q = 0; q < nq; ++q) {
+          double I = s_I[tid * nq + q];
+          if (I != 0.0) s += wq[q] * I;
+          any |= s_lidx[tid * nq + q] >= 0;
+        }
+        P.out_vals[colbase + tid] = s;
+        uint64_t bal = __ballot(any);
+        if ((tid & 63) == 0 && bal) atomicAdd(P.n_causal, (unsigned long long)__popcll(bal));
+      }
+    } else if (tid == 0) {
+      // potential mode (nq == 1): ordered sum of w_j I_j over the tile
+      double s = 0.0;
+      for (int jj = 0; jj < cnt; ++jj) {
+        double I = s_I[jj];
+        if (I != 0.0) s += P.trial_w[P.cols[colbase + jj]] * I;
+      }
+      P.out_tile[tile] = s;
+    }
+    __syncthreads();
+    STB_PHASE(4)
   }  // tiles
+#undef STB_PHASE
+  if (P.prof && tid == 0)
+    for (int k = 0; k < 5; ++k) atomicAdd(P.prof + k, pt[k]);
   if (P.work) {
     atomicAdd(P.work + 0, w_eval);
     atomicAdd(P.work + 1, w_lit);
@@ -707,7 +788,25 @@ stb_status stb_ctx_create(int32_t device, stb_ctx** out) {
       delete c;
       return fail(nullptr, STB_E_DEVICE, "hipEventCreate failed");
     }
+  if (getenv("STB_PHASE_TICKS")) {
+    if (hipMalloc((void**)&c->d_prof, 8 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->d_prof, 0, 8 * sizeof(unsigned long long)) != hipSuccess)
+      c->d_prof = nullptr;
+  }
   *out = c;
+  return STB_OK;
+}
+
+// Diagnostics: accumulated per-phase clock ticks of the pair kernel (all
+// blocks, thread 0) since the last call; zeros unless STB_PHASE_TICKS was set
+// when the context was created.
+stb_status stb_debug_phase_ticks(stb_ctx* ctx, unsigned long long* out8) {
+  if (!ctx || !out8) return fail(ctx, STB_E_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 8; ++k) out8[k] = 0;
+  if (!ctx->d_prof) return STB_OK;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(out8, ctx->d_prof, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  HIPCHK(ctx, hipMemset(ctx->d_prof, 0, 8 * sizeof(unsigned long long)));
   return STB_OK;
 }
 
@@ -716,6 +815,7 @@ void stb_ctx_destroy(stb_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   dfree(ctx->d_gl);
+  dfree(ctx->d_prof);
   for (auto& e : ctx->ev) if (e) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -862,6 +962,7 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   A.out_tile = nullptr;
   A.n_causal = d_causal;
   A.work = d_causal + 1;
+  A.prof = ctx->d_prof;
   A.gl = ctx->d_gl;
   A.ng = p.n_g;
   s = launch_pairs(ctx, A, ntiles);
@@ -1026,6 +1127,7 @@ static stb_status potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_pa
   A.out_tile = d_part;
   A.n_causal = nullptr;
   A.work = nullptr;
+  A.prof = nullptr;
   A.gl = ctx->d_gl;
   A.ng = p.n_g;
   s = launch_pairs(ctx, A, ntiles);
