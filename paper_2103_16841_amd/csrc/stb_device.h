@@ -144,10 +144,28 @@ STB_HD __forceinline__ double r_of_w(double w, double d2) {
   return d2 > 0.0 ? 0.5 * (w + d2 / w) : 0.5 * w;
 }
 
-// r(w1) - r(w0) for w1 >= w0 > 0 (or d^2 = 0).
+// 1/x to within an ulp for normal, finite, non-zero x: the hardware
+// reciprocal estimate refined by two Newton steps (e = 1 - x r, r += r e).
+// Much shorter than an IEEE division; every use below has |x| well inside
+// the normal range.
+STB_HD __forceinline__ double frcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+#else
+  double r = 1.0 / x;
+#endif
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// r(w1) - r(w0) = (w1 - w0) (1 - d^2 / (w0 w1)) / 2 for w1 >= w0 > 0 (or
+// d^2 = 0, where w0 may be 0).
 STB_HD __forceinline__ double rdiff(double w0, double w1, double d2) {
   double h = 0.5 * (w1 - w0);
-  return d2 > 0.0 ? h * (1.0 - d2 / (w0 * w1)) : h;
+  double g = fma(-d2, frcp(w0 * w1), 1.0);
+  return d2 > 0.0 ? h * g : h;
 }
 
 // Face data needed by L(phi): fa, fb, fc of the 4 faces.
@@ -155,72 +173,89 @@ struct FaceSet {
   double fa[4], fb[4], fc[4];
 };
 
-// Order two intervals by start (registers only).
+// Order two intervals by start (registers only, selects).
 STB_HD __forceinline__ void order2(double& s0, double& e0, double& s1, double& e1) {
-  if (s1 < s0) {
-    double ts = s0, te = e0;
-    s0 = s1; e0 = e1; s1 = ts; e1 = te;
-  }
+  bool sw = s1 < s0;
+  double ts = s0, te = e0;
+  s0 = sw ? s1 : s0;
+  e0 = sw ? e1 : e0;
+  s1 = sw ? ts : s1;
+  e1 = sw ? te : e1;
 }
 
 // L(phi) for cos/sin of phi.  C: C_k, d2 = d^2, [wlo, whi]: admissible w-range.
-// Everything stays in registers: at most three holes (the area-weighted
-// outward normals sum to zero, so at most three faces open downwards).
+//
+// In w = r + sqrt(r^2 - d^2) face k's constraint reads
+//   Q_k(w) = (B_k - a_k) w^2 - 2 C_k w - d^2 (B_k + a_k) < 0,  w >= |d|.
+// With e = B_k - a_k, f = B_k + a_k, D = C_k^2 + d^2 e f and
+// q = C_k + sign(C_k) sqrt(D), the roots are q / e and -d^2 f / q (the
+// second is the root of the linear case e = 0).  e > 0: the admissible set
+// is the open interval between the roots (empty when D <= 0); e < 0: the
+// complement of that interval (all of w when D <= 0); e = 0: a half-line
+// w > root (C_k > 0) or w < root (C_k < 0), or all / nothing (C_k = 0).
+// L is the r-measure of [wlo, whi] intersected with every face's set.
+//
+// Branch-free: every face takes the same instructions and selects the
+// outcome, so lanes evaluating different pairs do not diverge.  Holes (e < 0)
+// are clipped to the admissible interval, sorted by start and swept once.
 STB_HD __forceinline__ double L_eval(const FaceSet& F, const double* C, double d2, double wlo,
                                      double whi, double cs, double sn) {
+  const double kNone = 1e300;
   double lo = wlo, hi = whi;
-  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, c0 = 0.0, c1 = 0.0;
-  int nh = 0;
+  bool dead = false;
+  double hs[4], he[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     double a = F.fa[k];
     double B = fma(F.fb[k], cs, F.fc[k] * sn);
     double e = B - a, f = B + a, Ck = C[k];
     double D = fma(Ck, Ck, d2 * (e * f));
-    if (e > 0.0) {
-      if (!(D > 0.0)) return 0.0;
-      double q = Ck + copysign(sqrt(D), Ck);
-      double r1 = q / e, r2 = -d2 * f / q;
-      lo = fmax(lo, fmin(r1, r2));
-      hi = fmin(hi, fmax(r1, r2));
-    } else if (e < 0.0) {
-      if (!(D > 0.0)) continue;
-      double q = Ck + copysign(sqrt(D), Ck);
-      double r1 = q / e, r2 = -d2 * f / q;
-      double u0 = fmin(r1, r2), u1 = fmax(r1, r2);
-      if (nh == 0) { a0 = u0; a1 = u1; }
-      else if (nh == 1) { b0 = u0; b1 = u1; }
-      else { c0 = u0; c1 = u1; }
-      nh = nh < 3 ? nh + 1 : 3;
-    } else {
-      // linear: -2 C w - d^2 f < 0
-      if (Ck > 0.0) lo = fmax(lo, -d2 * f / (2.0 * Ck));
-      else if (Ck < 0.0) hi = fmin(hi, -d2 * f / (2.0 * Ck));
-      else if (!(d2 * f > 0.0)) return 0.0;
-    }
+    bool two = D > 0.0;
+    double q = Ck + copysign(sqrt(fmax(D, 0.0)), Ck);
+    double w1 = q * frcp(e);
+    double w2 = -d2 * f * frcp(q);
+    double mn = fmin(w1, w2), mx = fmax(w1, w2);
+    bool pos = e > 0.0, neg = e < 0.0, zer = !(pos || neg);
+    bool cut = pos && two;
+    dead = dead || (pos && !two) || (zer && Ck == 0.0 && !(d2 * f > 0.0));
+    lo = cut ? fmax(lo, mn) : lo;
+    hi = cut ? fmin(hi, mx) : hi;
+    lo = (zer && Ck > 0.0) ? fmax(lo, w2) : lo;
+    hi = (zer && Ck < 0.0) ? fmin(hi, w2) : hi;
+    bool hole = neg && two;
+    hs[k] = hole ? mn : kNone;
+    he[k] = hole ? mx : kNone;
   }
-  if (!(hi > lo)) return 0.0;
-  // r(w1) - r(w0) = (w1 - w0) (1 - d^2 / (w0 w1)) / 2: one division per piece
-  double len = rdiff(lo, hi, d2);
-  if (nh == 0) return len;
-  // clip the holes to [lo, hi] (empty ones become [hi, hi]), sort by start,
-  // subtract the measure of their union
-  if (nh < 2) { b0 = hi; b1 = hi; }
-  if (nh < 3) { c0 = hi; c1 = hi; }
-  a0 = fmin(fmax(a0, lo), hi); a1 = fmax(fmin(a1, hi), a0);
-  b0 = fmin(fmax(b0, lo), hi); b1 = fmax(fmin(b1, hi), b0);
-  c0 = fmin(fmax(c0, lo), hi); c1 = fmax(fmin(c1, hi), c0);
-  order2(a0, a1, b0, b1);
-  order2(b0, b1, c0, c1);
-  order2(a0, a1, b0, b1);
-  // merge: [a0,a1], [b0,b1], [c0,c1] sorted by start
-  if (b0 <= a1) { a1 = fmax(a1, b1); b0 = b1 = a1; }
-  if (c0 <= a1) { a1 = fmax(a1, c1); c0 = c1 = a1; }
-  else if (c0 <= b1) { b1 = fmax(b1, c1); c0 = c1 = b1; }
-  if (a1 > a0) len -= rdiff(a0, a1, d2);
-  if (b1 > b0) len -= rdiff(b0, b1, d2);
-  if (c1 > c0) len -= rdiff(c0, c1, d2);
-  return len > 0.0 ? len : 0.0;
+  // clip the holes to [lo, hi] (absent ones become [hi, hi]), sort by start
+  // (five compare-exchanges), then sweep and add the gaps between them: a sum
+  // of non-negative measures, exactly 0 when the holes cover [lo, hi]
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    hs[k] = fmin(fmax(hs[k], lo), hi);
+    he[k] = fmax(fmin(he[k], hi), hs[k]);
+  }
+  order2(hs[0], he[0], hs[1], he[1]);
+  order2(hs[2], he[2], hs[3], he[3]);
+  order2(hs[0], he[0], hs[2], he[2]);
+  order2(hs[1], he[1], hs[3], he[3]);
+  order2(hs[1], he[1], hs[2], he[2]);
+  // A gap whose r-measure is below kWulp * w (4 ulp of w) is a rounding
+  // artefact, e.g. [|d|, |d| + a few ulp] where two roots meet at the
+  // hyperbola's vertex (r is flat in w there: measure ~1e-30), and counts
+  // as empty.
+  const double kWulp = 8.881784197001252e-16;
+  double len = 0.0, c = lo;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double g1 = fmax(hs[k], c);
+    double m = rdiff(c, g1, d2);
+    len += (m > kWulp * g1) ? m : 0.0;
+    c = fmax(he[k], c);
+  }
+  double m = rdiff(c, hi, d2);
+  len += (m > kWulp * hi) ? m : 0.0;
+  bool empty = dead || !(hi > lo);
+  return empty ? 0.0 : len;
 }
 
 // Exact extrema of f(y) = |x - y| - (t - tau) over the closed panel:
