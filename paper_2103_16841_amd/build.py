@@ -6,8 +6,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstb.so")
-SOURCES = [os.path.join(CSRC, "stb_lib.hip"), os.path.join(CSRC, "stb_apply.hip")]
-HEADERS = [os.path.join(CSRC, "stb_device.h"), os.path.join(ROOT, "include", "stb.h")]
+SOURCES = [os.path.join(CSRC, "stb_lib.hip"), os.path.join(CSRC, "stb_pairs.hip"),
+           os.path.join(CSRC, "stb_apply.hip")]
+HEADERS = [os.path.join(CSRC, "stb_device.h"), os.path.join(CSRC, "stb_internal.h"),
+           os.path.join(CSRC, "stb_pairs.h"), os.path.join(ROOT, "include", "stb.h")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -15,8 +15,8 @@ struct stb_ctx {
   hipEvent_t ev[5] = {};
   std::string err;
   double timings[4] = {0, 0, 0, 0};
-  int64_t work[4] = {0, 0, 0, 0};   // last assembly: L evals, lit pairs, pairs, tiles
-  unsigned long long* d_prof = nullptr;   // per-phase clock ticks (STB_PHASE_TICKS set)
+  int64_t work[4] = {0, 0, 0, 0};   // last assembly: L evals, lit combos, apexes, pieces
+  struct PairWorkspace* ws = nullptr;   // pair pipeline lists (grown on demand)
   // Gauss-Legendre nodes on [0,1] for the last n_g used (device copy)
   int gl_n = 0;
   double* d_gl = nullptr;   // [2 * kMaxNg]: x then w

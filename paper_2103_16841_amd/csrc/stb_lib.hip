@@ -8,12 +8,8 @@
 //   k_cull_*     conservative causal cull of (test, trial) pairs from the
 //                bounding balls and time ranges (superset of the lit pairs of
 //                Sec. 3.3), compacted per row with wavefront ballots;
-//   k_pairs      per tile (one row, J candidate columns, all outer points):
-//                phase A (one lane per (outer point, trial panel)): exact lit
-//                test, apex data, phi-breakpoints, sort, empty-piece tests,
-//                non-empty pieces pushed to an LDS queue; phase B (one lane
-//                per (piece, Gauss node)): L(phi) at the node, ordered
-//                per-piece sums; then ordered sums over pieces and outer points.
+//   pair pipeline (stb_pairs.hip): lit test, breakpoints, empty-piece tests,
+//                Gauss nodes, ordered sums, store.
 // The store is CSR over the candidate columns (values aligned with them).
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
@@ -33,6 +29,7 @@
 using namespace stb;
 
 #include "stb_internal.h"
+#include "stb_pairs.h"
 
 static std::mutex g_err_mu;
 static std::string g_err;
@@ -168,7 +165,8 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_fill(int64_t nrows,
                                                             int64_t nt,
                                                             const TrialRec* __restrict__ T,
                                                             const int64_t* __restrict__ rowptr,
-                                                            int32_t* __restrict__ cols) {
+                                                            int32_t* __restrict__ cols,
+                                                            int32_t* __restrict__ rowof) {
   int64_t i = blockIdx.x;
   if (i >= nrows) return;
   __shared__ int wave_cnt[kCullThreads / 64];
@@ -187,312 +185,12 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_fill(int64_t nrows,
     for (int w = 0; w < wave; ++w) off += wave_cnt[w];
     int tot = 0;
     for (int w = 0; w < kCullThreads / 64; ++w) tot += wave_cnt[w];
-    if (p) cols[base + off + rank] = (int32_t)j;
+    if (p) {
+      cols[base + off + rank] = (int32_t)j;
+      rowof[base + off + rank] = (int32_t)i;
+    }
     base += tot;
     __syncthreads();
-  }
-}
-
-// Tiles: row r owns ceil(cnt_r / J) tiles.
-__global__ void k_tiles(int64_t nrows, const int64_t* __restrict__ rowptr, int J,
-                        int64_t* __restrict__ ntile) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
-  int64_t c = rowptr[i + 1] - rowptr[i];
-  ntile[i] = (c + J - 1) / J;
-}
-
-// ------------------------------------------------------------ pair kernel
-constexpr int kThreads = 256;
-constexpr int kQueueCap = 1024;
-constexpr int kBlocksPerCU = 8;   // resident + queued blocks of the persistent grid
-
-struct PairArgs {
-  int64_t nrows;
-  const int64_t* rowptr;     // candidate CSR
-  const int32_t* cols;
-  const int64_t* tileptr;    // exclusive prefix of tiles per row (nrows + 1)
-  int J;                     // trial panels per tile
-  const TrialRec* trial;
-  const double* apex;        // [nrows][maxq][4]
-  const double* apex_w;      // [nrows][maxq] (nullptr: weight 1)
-  const int32_t* apex_n;     // [nrows] (nullptr: 1)
-  int maxq;
-  const double* trial_w;     // potential mode: density per trial panel
-  double* out_vals;          // matrix mode: aligned with cols
-  double* out_tile;          // potential mode: one partial per tile
-  unsigned long long* n_causal;
-  const double* gl;          // [kMaxNg] nodes on [0,1], then [kMaxNg] weights
-  int ng;
-  int64_t ntiles;            // tiles of the whole launch (grid-stride loop)
-  unsigned long long* work;  // optional [3]: L(phi) evaluations, lit pairs, pairs
-  unsigned long long* prof;  // optional [8]: clock ticks per phase (diagnostics)
-};
-
-__global__ __launch_bounds__(kThreads, 2) void k_pairs(PairArgs P) {
-  __shared__ ComboL s_cb[kThreads];               // by lit index
-  __shared__ double s_qa[kQueueCap], s_qh[kQueueCap], s_qv[kQueueCap];
-  __shared__ uint16_t s_qc[kQueueCap];            // lit index owning the piece
-  __shared__ int s_qpre[kQueueCap + 1];           // prefix of non-empty pieces
-  __shared__ uint8_t s_qne[kQueueCap];
-  __shared__ int s_part[kThreads];
-  __shared__ double s_I[kThreads];                // by combo
-  __shared__ double s_inl[kThreads];              // by lit index: pieces done inline
-  __shared__ int s_slot0[kThreads], s_nslot[kThreads];
-  __shared__ int16_t s_lidx[kThreads];            // combo -> lit index (-1: not lit)
-  __shared__ uint16_t s_lcombo[kThreads];         // lit index -> combo
-  __shared__ double s_glx[kMaxNg], s_glw[kMaxNg];
-  __shared__ int s_nlit, s_tail, s_filled;
-  __shared__ int64_t s_row, s_start;
-  __shared__ int s_cnt, s_nq;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  if (tid < P.ng) { s_glx[tid] = P.gl[tid]; s_glw[tid] = P.gl[kMaxNg + tid]; }
-  unsigned long long w_eval = 0, w_lit = 0, w_pairs = 0;
-  unsigned long long pt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  long long t_prev = 0;
-#define STB_PHASE(k)                                         \
-  if (P.prof && tid == 0) {                                  \
-    long long t_now = clock64();                             \
-    pt[k] += (unsigned long long)(t_now - t_prev);           \
-    t_prev = t_now;                                          \
-  }
-  // persistent blocks: tiles b, b + G, b + 2G, ... (consecutive tiles of a
-  // row land on different blocks, which evens out their cost)
-  for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
-    __syncthreads();
-    if (tid == 0) {
-      // row of this tile: last r with tileptr[r] <= tile
-      int64_t lo = 0, hi = P.nrows;
-      while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (P.tileptr[mid] <= tile) lo = mid; else hi = mid;
-      }
-      int64_t row = lo;
-      int64_t start = (tile - P.tileptr[row]) * P.J;
-      int64_t cnt = P.rowptr[row + 1] - P.rowptr[row] - start;
-      s_row = row;
-      s_start = start;
-      s_cnt = (int)(cnt < P.J ? cnt : P.J);
-      s_nq = P.apex_n ? P.apex_n[row] : 1;
-      s_nlit = 0;
-      s_tail = 0;
-      s_filled = 0;
-    }
-    __syncthreads();
-    if (P.prof && tid == 0) t_prev = clock64();
-    const int64_t row = s_row;
-    const int cnt = s_cnt, nq = s_nq, ng = P.ng;
-    const int ncombo = cnt * nq;
-    const int64_t colbase = P.rowptr[row] + s_start;
-    const double* apex_row = P.apex + (int64_t)row * P.maxq * 4;
-
-    // ---- A1: one lane per (trial jj, apex q): lit test, compaction
-    if (tid < ncombo) {
-      int jj = tid / nq, q = tid - jj * nq;
-      const TrialRec& T = P.trial[P.cols[colbase + jj]];
-      double xl[4] = {apex_row[4 * q], apex_row[4 * q + 1], apex_row[4 * q + 2], apex_row[4 * q + 3]};
-      Apex A;
-      apex_of(T, xl, A);
-      ++w_pairs;
-      bool lit = A.t - T.tmin > fabs(A.d) && !ball_rejects(T, xl) && lit_test(T, xl, A);
-      int li = -1;
-      if (lit) li = atomicAdd(&s_nlit, 1);
-      s_lidx[tid] = (int16_t)li;
-      if (lit) s_lcombo[li] = (uint16_t)tid;
-    }
-    __syncthreads();
-    STB_PHASE(0)
-
-    // ---- A2: one lane per lit combo: breakpoints, pieces into the queue
-    const int nlit = s_nlit;
-    if (tid < nlit) {
-      const int c = s_lcombo[tid], li = tid;
-      int jj = c / nq, q = c - jj * nq;
-      const TrialRec& T = P.trial[P.cols[colbase + jj]];
-      double xl[4] = {apex_row[4 * q], apex_row[4 * q + 1], apex_row[4 * q + 2], apex_row[4 * q + 3]};
-      Apex A;
-      apex_of(T, xl, A);
-      ++w_lit;
-      double wlo = 0.0, whi = 0.0, inl = 0.0;
-      int slot0 = 0, nslot = 0;
-      if (w_range(T, A, wlo, whi)) {
-        ComboL cb;
-        for (int k = 0; k < 4; ++k) {
-          cb.C[k] = A.C[k]; cb.fa[k] = T.fa[k]; cb.fb[k] = T.fb[k]; cb.fc[k] = T.fc[k];
-        }
-        cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
-        s_cb[li] = cb;
-        double bp[kMaxBp];
-        int nb = breakpoints(T, A, bp);
-        sort_bp(bp, nb);
-        if (nb == 0) {
-          // periodic trapezoid rule with 2 n_g nodes
-          int m = 2 * ng;
-          double h = kTwoPi / m;
-          for (int k = 0; k < m; ++k) inl += h * L_at(cb, k * h);
-          w_eval += m;
-        } else {
-          int np = 0;
-          for (int k = 0; k < nb; ++k) {
-            double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
-            np += (b - bp[k] > 0.0);
-          }
-          int s0 = atomicAdd(&s_tail, np);
-          if (s0 + np <= kQueueCap) {
-            atomicMax(&s_filled, s0 + np);
-            int s = s0;
-            for (int k = 0; k < nb; ++k) {
-              double a = bp[k];
-              double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
-              if (!(b - a > 0.0)) continue;
-              s_qa[s] = a; s_qh[s] = b - a; s_qc[s] = (uint16_t)li;
-              ++s;
-            }
-            slot0 = s0;
-            nslot = np;
-          } else {
-            // queue full: this lane does its pieces itself, in order
-            for (int k = 0; k < nb; ++k) {
-              double a = bp[k];
-              double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
-              double H = b - a;
-              if (!(H > 0.0)) continue;
-              bool ne = L_at(cb, a + 0.5 * H) != 0.0;
-              ++w_eval;
-              if (!ne) {
-                ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
-                w_eval += 2;
-              }
-              if (!ne) continue;
-              double acc = 0.0;
-              for (int g = 0; g < ng; ++g) acc += node_value(cb, a, H, s_glx[g], s_glw[g]);
-              w_eval += ng;
-              inl += acc;
-            }
-          }
-        }
-      }
-      s_inl[li] = inl;
-      s_slot0[li] = slot0;
-      s_nslot[li] = nslot;
-    }
-    __syncthreads();
-    STB_PHASE(1)
-
-    // ---- A3: one lane per queued piece: empty-piece test
-    const int filled = s_filled;
-    for (int e = tid; e < filled; e += kThreads) {
-      const ComboL& cb = s_cb[s_qc[e]];
-      double a = s_qa[e], H = s_qh[e];
-      bool ne = L_at(cb, a + 0.5 * H) != 0.0;
-      ++w_eval;
-      if (!ne) {
-        ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
-        w_eval += 2;
-      }
-      s_qne[e] = ne ? 1 : 0;
-      s_qv[e] = 0.0;
-    }
-    __syncthreads();
-    // exclusive prefix of the non-empty flags (chunk per lane, then lane 0)
-    {
-      const int per = (filled + kThreads - 1) / kThreads;
-      const int e0 = tid * per, e1 = min(filled, e0 + per);
-      int acc = 0;
-      for (int e = e0; e < e1; ++e) { s_qpre[e] = acc; acc += s_qne[e]; }
-      s_part[tid] = acc;
-      __syncthreads();
-      if (tid == 0) {
-        int run = 0;
-        for (int t = 0; t < kThreads; ++t) { int v = s_part[t]; s_part[t] = run; run += v; }
-        s_qpre[filled] = run;
-      }
-      __syncthreads();
-      for (int e = e0; e < e1; ++e) s_qpre[e] += s_part[tid];
-    }
-    __syncthreads();
-    STB_PHASE(2)
-
-    // ---- B: one lane per (non-empty piece, Gauss node)
-    {
-      const int nne = s_qpre[filled];
-      const int per = 64 / ng;                 // pieces per wave pass
-      const int seg = lane / ng, g = lane - seg * ng;
-      const int nwaves = kThreads / 64;
-      for (int base = wave * per; base < nne; base += nwaves * per) {
-        int k = base + seg;
-        bool act = seg < per && k < nne;
-        double v = 0.0;
-        int e = 0;
-        if (act) {
-          // the queued piece whose non-empty rank is k
-          int lo = 0, hi = filled - 1;
-          while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (s_qpre[mid] + s_qne[mid] <= k) lo = mid + 1; else hi = mid;
-          }
-          e = lo;
-          v = node_value(s_cb[s_qc[e]], s_qa[e], s_qh[e], s_glx[g], s_glw[g]);
-        }
-        // ordered sum over the n_g lanes of the segment
-        int l0 = seg * ng;
-        double acc = 0.0;
-        for (int kk = 0; kk < ng; ++kk) acc += __shfl(v, (l0 + kk) & 63, 64);
-        if (act && g == 0) s_qv[e] = acc;
-      }
-      w_eval += (tid == 0) ? (unsigned long long)nne * ng : 0ull;
-    }
-    __syncthreads();
-    STB_PHASE(3)
-
-    // ---- per combo: ordered sum over its pieces (empty pieces hold +0.0)
-    if (tid < ncombo) {
-      int li = s_lidx[tid];
-      double I = 0.0;
-      if (li >= 0) {
-        I = s_inl[li];
-        for (int s = 0; s < s_nslot[li]; ++s) I += s_qv[s_slot0[li] + s];
-      }
-      s_I[tid] = I / (4.0 * kPi);
-    }
-    __syncthreads();
-
-    // ---- per trial panel: outer sum, store
-    if (P.out_vals) {
-      if (tid < cnt) {
-        const double* wq = P.apex_w + (int64_t)row * P.maxq;
-        double s = 0.0;
-        bool any = false;
-        for (int q = 0; q < nq; ++q) {
-          double I = s_I[tid * nq + q];
-          if (I != 0.0) s += wq[q] * I;
-          any |= s_lidx[tid * nq + q] >= 0;
-        }
-        P.out_vals[colbase + tid] = s;
-        uint64_t bal = __ballot(any);
-        if ((tid & 63) == 0 && bal) atomicAdd(P.n_causal, (unsigned long long)__popcll(bal));
-      }
-    } else if (tid == 0) {
-      // potential mode (nq == 1): ordered sum of w_j I_j over the tile
-      double s = 0.0;
-      for (int jj = 0; jj < cnt; ++jj) {
-        double I = s_I[jj];
-        if (I != 0.0) s += P.trial_w[P.cols[colbase + jj]] * I;
-      }
-      P.out_tile[tile] = s;
-    }
-    __syncthreads();
-    STB_PHASE(4)
-  }  // tiles
-#undef STB_PHASE
-  if (P.prof && tid == 0)
-    for (int k = 0; k < 5; ++k) atomicAdd(P.prof + k, pt[k]);
-  if (P.work) {
-    atomicAdd(P.work + 0, w_eval);
-    atomicAdd(P.work + 1, w_lit);
-    atomicAdd(P.work + 2, w_pairs);
   }
 }
 
@@ -569,13 +267,16 @@ extern "C" stb_status stb_debug_pair(stb_ctx* ctx, const stb_mesh* mesh, int32_t
   return STB_OK;
 }
 
-// Ordered sum of tile partials per evaluation point.
-__global__ void k_tile_reduce(int64_t np, const int64_t* __restrict__ tileptr,
-                              const double* __restrict__ part, double* __restrict__ out) {
+// Potential per evaluation point: ordered sum over its candidates of
+// w_j I_j (exact zeros skipped).
+__global__ void k_point_sum(int64_t np, const int64_t* __restrict__ rowptr,
+                            const int32_t* __restrict__ cols, const double* __restrict__ I,
+                            const double* __restrict__ w, double* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np) return;
   double s = 0.0;
-  for (int64_t t = tileptr[i]; t < tileptr[i + 1]; ++t) s += part[t];
+  for (int64_t c = rowptr[i]; c < rowptr[i + 1]; ++c)
+    if (I[c] != 0.0) s += w[cols[c]] * I[c];
   out[i] = s;
 }
 
@@ -684,9 +385,10 @@ static stb_status device_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t
   return stb_exclusive_scan(ctx, in, out, n, ctx->stream);
 }
 
-// Cull rows (apex boxes) against all trial panels into CSR candidates.
+// Cull rows (apex boxes) against all trial panels into CSR candidates, with
+// the row of every candidate alongside.
 static stb_status cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
-                       int64_t** d_rowptr, int32_t** d_cols, int64_t* nnz) {
+                       int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz) {
   int64_t* d_cnt = nullptr;
   HIPCHK(ctx, dalloc(&d_cnt, (size_t)nrows));
   HIPCHK(ctx, dalloc(d_rowptr, (size_t)nrows + 1));
@@ -700,39 +402,12 @@ static stb_status cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const
   if (s) return s;
   HIPCHK(ctx, hipMemcpy(nnz, *d_rowptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost));
   HIPCHK(ctx, dalloc(d_cols, (size_t)*nnz));
+  HIPCHK(ctx, dalloc(d_rowof, (size_t)*nnz));
   if (nrows > 0) {
     hipLaunchKernelGGL(k_cull_fill, dim3((unsigned)nrows), dim3(kCullThreads), 0, ctx->stream,
-                       nrows, d_rows, m->nt, m->d_trial, *d_rowptr, *d_cols);
+                       nrows, d_rows, m->nt, m->d_trial, *d_rowptr, *d_cols, *d_rowof);
     HIPCHK(ctx, hipGetLastError());
   }
-  return STB_OK;
-}
-
-static stb_status make_tiles(stb_ctx* ctx, int64_t nrows, const int64_t* d_rowptr, int J,
-                             int64_t** d_tileptr, int64_t* ntiles) {
-  int64_t* d_nt = nullptr;
-  HIPCHK(ctx, dalloc(&d_nt, (size_t)nrows));
-  HIPCHK(ctx, dalloc(d_tileptr, (size_t)nrows + 1));
-  if (nrows > 0) {
-    hipLaunchKernelGGL(k_tiles, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, ctx->stream,
-                       nrows, d_rowptr, J, d_nt);
-    HIPCHK(ctx, hipGetLastError());
-  }
-  stb_status s = device_exclusive_scan(ctx, d_nt, *d_tileptr, nrows);
-  dfree(d_nt);
-  if (s) return s;
-  HIPCHK(ctx, hipMemcpy(ntiles, *d_tileptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost));
-  return STB_OK;
-}
-
-static stb_status launch_pairs(stb_ctx* ctx, PairArgs& A, int64_t ntiles) {
-  if (ntiles <= 0) return STB_OK;
-  int ncu = 0;
-  HIPCHK(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
-  int64_t grid = std::min<int64_t>(ntiles, (int64_t)std::max(ncu, 1) * kBlocksPerCU);
-  A.ntiles = ntiles;
-  hipLaunchKernelGGL(k_pairs, dim3((unsigned)grid), dim3(kThreads), 0, ctx->stream, A);
-  HIPCHK(ctx, hipGetLastError());
   return STB_OK;
 }
 
@@ -788,25 +463,7 @@ stb_status stb_ctx_create(int32_t device, stb_ctx** out) {
       delete c;
       return fail(nullptr, STB_E_DEVICE, "hipEventCreate failed");
     }
-  if (getenv("STB_PHASE_TICKS")) {
-    if (hipMalloc((void**)&c->d_prof, 8 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMemset(c->d_prof, 0, 8 * sizeof(unsigned long long)) != hipSuccess)
-      c->d_prof = nullptr;
-  }
   *out = c;
-  return STB_OK;
-}
-
-// Diagnostics: accumulated per-phase clock ticks of the pair kernel (all
-// blocks, thread 0) since the last call; zeros unless STB_PHASE_TICKS was set
-// when the context was created.
-stb_status stb_debug_phase_ticks(stb_ctx* ctx, unsigned long long* out8) {
-  if (!ctx || !out8) return fail(ctx, STB_E_INVALID_ARG, "NULL argument");
-  for (int k = 0; k < 8; ++k) out8[k] = 0;
-  if (!ctx->d_prof) return STB_OK;
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  HIPCHK(ctx, hipMemcpy(out8, ctx->d_prof, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-  HIPCHK(ctx, hipMemset(ctx->d_prof, 0, 8 * sizeof(unsigned long long)));
   return STB_OK;
 }
 
@@ -815,7 +472,7 @@ void stb_ctx_destroy(stb_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   dfree(ctx->d_gl);
-  dfree(ctx->d_prof);
+  stb_free_workspace(ctx);
   for (auto& e : ctx->ev) if (e) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -931,55 +588,35 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   stb_mat* M = new stb_mat();
   M->ctx = ctx;
   M->n = mesh->nt;
-  s = cull(ctx, mesh->nt, mesh->d_box, mesh, &M->d_rowptr, &M->d_cols, &M->nnz);
-  if (s) { stb_mat_destroy(M); return s; }
-  int J = kThreads / mesh->maxq;
-  if (J < 1) J = 1;
-  int64_t* d_tileptr = nullptr;
-  int64_t ntiles = 0;
-  s = make_tiles(ctx, mesh->nt, M->d_rowptr, J, &d_tileptr, &ntiles);
-  if (s) { stb_mat_destroy(M); return s; }
+  int32_t* d_rowof = nullptr;
+  s = cull(ctx, mesh->nt, mesh->d_box, mesh, &M->d_rowptr, &M->d_cols, &d_rowof, &M->nnz);
+  if (s) { dfree(d_rowof); stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
-  unsigned long long* d_causal = nullptr;   // [0] causal pairs, [1..3] work counters
-  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess || dalloc(&d_causal, 4) != hipSuccess) {
-    dfree(d_tileptr); dfree(d_causal); stb_mat_destroy(M);
+  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess) {
+    dfree(d_rowof); stb_mat_destroy(M);
     return fail(ctx, STB_E_NO_MEMORY, "store of %lld entries does not fit", (long long)M->nnz);
   }
-  HIPCHK(ctx, hipMemsetAsync(d_causal, 0, 4 * sizeof(unsigned long long), ctx->stream));
-  PairArgs A;
-  A.nrows = mesh->nt;
-  A.rowptr = M->d_rowptr;
-  A.cols = M->d_cols;
-  A.tileptr = d_tileptr;
-  A.J = J;
-  A.trial = mesh->d_trial;
-  A.apex = mesh->d_opts;
-  A.apex_w = mesh->d_ow;
-  A.apex_n = mesh->d_onq;
-  A.maxq = mesh->maxq;
-  A.trial_w = nullptr;
-  A.out_vals = M->d_vals;
-  A.out_tile = nullptr;
-  A.n_causal = d_causal;
-  A.work = d_causal + 1;
-  A.prof = ctx->d_prof;
-  A.gl = ctx->d_gl;
-  A.ng = p.n_g;
-  s = launch_pairs(ctx, A, ntiles);
-  if (s) { dfree(d_tileptr); dfree(d_causal); stb_mat_destroy(M); return s; }
+  PairJob J;
+  J.nnz = M->nnz;
+  J.rows = d_rowof;
+  J.cols = M->d_cols;
+  J.trial = mesh->d_trial;
+  J.apex = mesh->d_opts;
+  J.apex_w = mesh->d_ow;
+  J.apex_n = mesh->d_onq;
+  J.maxq = mesh->maxq;
+  J.gl = ctx->d_gl;
+  J.ng = p.n_g;
+  J.out = M->d_vals;
+  unsigned long long causal = 0, work[4];
+  J.n_causal = &causal;
+  s = stb_run_pairs(ctx, J, work);
+  dfree(d_rowof);
+  if (s) { stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
-  unsigned long long cnts[4] = {0, 0, 0, 0};
-  hipError_t e = hipMemcpyAsync(cnts, d_causal, sizeof(cnts), hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  dfree(d_tileptr);
-  dfree(d_causal);
-  if (e != hipSuccess) {
-    stb_mat_destroy(M);
-    return fail(ctx, STB_E_DEVICE, "assembly failed: %s", hipGetErrorString(e));
-  }
-  M->n_causal = (int64_t)cnts[0];
-  for (int k = 0; k < 3; ++k) ctx->work[k] = (int64_t)cnts[k + 1];
-  ctx->work[3] = ntiles;
+  HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
+  M->n_causal = (int64_t)causal;
+  for (int k = 0; k < 4; ++k) ctx->work[k] = (int64_t)work[k];
   float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
   (void)hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
   (void)hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
@@ -1096,44 +733,37 @@ static stb_status potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_pa
                                  const double* d_w, int64_t np, const double* d_pts, double* d_out) {
   stb_status s;
   if ((s = ensure_gl(ctx, p.n_g))) return s;
-  double* d_part = nullptr;
+  double* d_I = nullptr;
   ApexBox* d_box = nullptr;
-  int64_t *d_rowptr = nullptr, *d_tileptr = nullptr;
-  int32_t* d_cols = nullptr;
+  int64_t* d_rowptr = nullptr;
+  int32_t *d_cols = nullptr, *d_rowof = nullptr;
   auto cleanup = [&]() {
-    dfree(d_part); dfree(d_box); dfree(d_rowptr); dfree(d_tileptr); dfree(d_cols);
+    dfree(d_I); dfree(d_box); dfree(d_rowptr); dfree(d_cols); dfree(d_rowof);
   };
   if (dalloc(&d_box, (size_t)np) != hipSuccess) return fail(ctx, STB_E_NO_MEMORY, "potential buffers");
   hipLaunchKernelGGL(k_point_boxes, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
                      d_pts, d_box);
-  int64_t nnz = 0, ntiles = 0;
-  s = cull(ctx, np, d_box, mesh, &d_rowptr, &d_cols, &nnz);
-  if (s == STB_OK) s = make_tiles(ctx, np, d_rowptr, kThreads, &d_tileptr, &ntiles);
+  int64_t nnz = 0;
+  s = cull(ctx, np, d_box, mesh, &d_rowptr, &d_cols, &d_rowof, &nnz);
   if (s) { cleanup(); return s; }
-  if (dalloc(&d_part, (size_t)ntiles) != hipSuccess) { cleanup(); return fail(ctx, STB_E_NO_MEMORY, "tiles"); }
-  PairArgs A;
-  A.nrows = np;
-  A.rowptr = d_rowptr;
-  A.cols = d_cols;
-  A.tileptr = d_tileptr;
-  A.J = kThreads;
-  A.trial = mesh->d_trial;
-  A.apex = d_pts;
-  A.apex_w = nullptr;
-  A.apex_n = nullptr;
-  A.maxq = 1;
-  A.trial_w = d_w;
-  A.out_vals = nullptr;
-  A.out_tile = d_part;
-  A.n_causal = nullptr;
-  A.work = nullptr;
-  A.prof = nullptr;
-  A.gl = ctx->d_gl;
-  A.ng = p.n_g;
-  s = launch_pairs(ctx, A, ntiles);
+  if (dalloc(&d_I, (size_t)nnz) != hipSuccess) { cleanup(); return fail(ctx, STB_E_NO_MEMORY, "candidates"); }
+  PairJob J;
+  J.nnz = nnz;
+  J.rows = d_rowof;
+  J.cols = d_cols;
+  J.trial = mesh->d_trial;
+  J.apex = d_pts;
+  J.apex_w = nullptr;
+  J.apex_n = nullptr;
+  J.maxq = 1;
+  J.gl = ctx->d_gl;
+  J.ng = p.n_g;
+  J.out = d_I;
+  unsigned long long work[4];
+  s = stb_run_pairs(ctx, J, work);
   if (s) { cleanup(); return s; }
-  hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
-                     d_tileptr, d_part, d_out);
+  hipLaunchKernelGGL(k_point_sum, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
+                     d_rowptr, d_cols, d_I, d_w, d_out);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   cleanup();

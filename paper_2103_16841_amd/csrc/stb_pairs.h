@@ -1,0 +1,24 @@
+// stb_pairs.h -- the pair pipeline (stb_pairs.hip) as seen by the library.
+#pragma once
+#include "stb_internal.h"
+
+// One pipeline run over a candidate set (device arrays, context stream).
+struct PairJob {
+  int64_t nnz = 0;                   // candidates
+  const int32_t* rows = nullptr;     // [nnz] row of each candidate
+  const int32_t* cols = nullptr;     // [nnz] trial panel of each candidate
+  const stb::TrialRec* trial = nullptr;
+  const double* apex = nullptr;      // [rows][maxq][4] (t, x, y, z)
+  const double* apex_w = nullptr;    // [rows][maxq] outer weights; nullptr: potential
+  const int32_t* apex_n = nullptr;   // [rows] apexes per row; nullptr: one
+  int maxq = 1;
+  const double* gl = nullptr;        // [2 kMaxNg]: Gauss nodes on [0,1], then weights
+  int ng = 0;
+  double* out = nullptr;             // [nnz] matrix entry or inner integral
+  unsigned long long* n_causal = nullptr;   // host: += candidates with a lit apex
+};
+
+// Runs the pipeline; work[0..3] receive L evaluations, lit combos, apexes
+// tested and pieces.  Synchronises the context stream.
+stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long work[4]);
+void stb_free_workspace(stb_ctx* ctx);

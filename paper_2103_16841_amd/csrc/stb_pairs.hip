@@ -1,0 +1,494 @@
+// stb_pairs.hip -- the pair pipeline: every (outer point, trial panel)
+// combination of a candidate set, through the lit test, the phi-breakpoints,
+// the empty-piece tests and the Gauss nodes, as a chain of flat kernels that
+// hand their work on through lists in HBM.
+//
+// A candidate is one (row, trial panel) pair of the cull's CSR: a row is a
+// test panel (matrix) or an evaluation point (potential); its apexes are the
+// row's outer points of eq. int_bform (matrix) or the point itself.
+//
+//   k_lit     one lane per candidate: for each of its apexes the exact lit
+//             test of Sec. 3.3 (bounding-ball pre-test of Theorem
+//             phi_xi_sphere first); lit (candidate, apex) combos are appended
+//             to the combo list, contiguous per candidate, by wave-aggregated
+//             atomics (ballot-free prefix of the per-lane counts).
+//   k_bp      one lane per lit combo: apex data, admissible w-range, the
+//             phi-breakpoints (sorted) and the pieces between them, appended
+//             to the piece list, contiguous per combo in phi order; a combo
+//             without breakpoints gets two half-periods of the trapezoid rule.
+//   k_empty   one lane per piece: L at the midpoint (then the quarter points)
+//             decides whether the piece is empty; non-empty pieces go to the
+//             job list.
+//   k_nodes   one lane per job: the n_g Gauss nodes of the piece in order
+//             (smoothstep map), summed in order.
+//   k_combine one lane per combo: ordered sum over its pieces, / (4 pi).
+//   k_store   one lane per candidate: matrix entry = ordered sum over the
+//             apexes of w_q I_q (eq. int_bform); potential: I itself.
+//
+// Every list position is handed out by atomics, but every sum runs in a
+// fixed order (nodes, pieces in phi order, apexes in q order), so results do
+// not depend on the schedule.  The candidate range is processed in chunks
+// sized to the workspace; a chunk whose lists would overflow is split and
+// redone.  Lists cost a few hundred bytes per combo: the HBM traffic is a few
+// percent of what the FP64 arithmetic takes, while each stage runs at full
+// lane occupancy with its own register budget.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "stb_internal.h"
+#include "stb_pairs.h"
+
+using namespace stb;
+
+namespace {
+
+constexpr int kBlk = 256;
+constexpr int kMaxBlocks = 256 * 16;
+
+enum {
+  CNT_COMBO = 0, CNT_PIECE, CNT_JOB, CNT_EVAL, CNT_PAIRS, CNT_CAUSAL, CNT_N
+};
+
+// Block-wide list allocation: every thread of the block calls it (n = 0
+// when it has nothing to append), with the same LDS scratch; one atomic per
+// block.  Same-address atomics serialise in the memory system, so they are
+// kept to one per few hundred list entries.  Returns the first slot of this
+// thread's n entries; slots are in thread order within the block.
+struct AllocLds {
+  unsigned wtot[kBlk / 64];
+  unsigned long long base;
+};
+
+__device__ __forceinline__ unsigned long long block_alloc(unsigned long long* ctr, unsigned n,
+                                                          AllocLds& sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned incl = n;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    unsigned v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) sh.wtot[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned run = 0;
+#pragma unroll
+    for (int w = 0; w < kBlk / 64; ++w) {
+      unsigned t = sh.wtot[w];
+      sh.wtot[w] = run;
+      run += t;
+    }
+    sh.base = run ? atomicAdd(ctr, (unsigned long long)run) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long r = sh.base + sh.wtot[wave] + (incl - n);
+  __syncthreads();   // the scratch is reused by the next call
+  return r;
+}
+
+// Sum of a per-lane count over the block, added to *ctr once per block.
+__device__ __forceinline__ void block_count(unsigned long long* ctr, unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr, v);
+}
+
+struct Lists {
+  // per candidate of the chunk
+  uint64_t* mask;        // lit apexes (bit q)
+  int32_t* combo0;       // first combo of the candidate
+  // per combo
+  uint32_t* key;         // (candidate in chunk) << 8 | q
+  ComboL* cb;
+  int32_t* p0;           // first piece
+  int32_t* np;           // pieces
+  double* I;             // inner integral
+  // per piece
+  double* pa;            // start angle (trapezoid half: 0 or 1)
+  double* ph;            // length (trapezoid half: -1)
+  int32_t* pc;           // owning combo
+  double* pv;            // ordered node sum
+  int32_t* job;          // non-empty pieces
+  unsigned long long* cnt;
+  int64_t cap_cand, cap_combo, cap_piece;
+};
+
+struct Geo {
+  const int32_t* rows;   // row of each candidate (global index)
+  const int32_t* cols;   // trial panel of each candidate
+  const TrialRec* trial;
+  const double* apex;    // [rows][maxq][4]
+  const double* apex_w;  // [rows][maxq] (matrix) or nullptr (potential)
+  const int32_t* apex_n; // [rows] or nullptr (one apex)
+  int maxq;
+};
+
+__global__ __launch_bounds__(kBlk) void k_lit(Geo g, Lists L, int64_t c0, int64_t nc) {
+  __shared__ AllocLds sh;
+  unsigned long long pairs = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < nc; base += (int64_t)gridDim.x * kBlk) {
+    const int64_t c = base + threadIdx.x;
+    const bool v = c < nc;
+    uint64_t m = 0;
+    int nq = 0;
+    if (v) {
+      const int64_t cg = c0 + c;
+      const int32_t i = g.rows[cg];
+      const TrialRec& T = g.trial[g.cols[cg]];
+      nq = g.apex_n ? g.apex_n[i] : 1;
+      const double* xr = g.apex + (int64_t)i * g.maxq * 4;
+      for (int q = 0; q < nq; ++q) {
+        double x4[4] = {xr[4 * q], xr[4 * q + 1], xr[4 * q + 2], xr[4 * q + 3]};
+        Apex A;
+        apex_of(T, x4, A);
+        bool lit = A.t - T.tmin > fabs(A.d) && !ball_rejects(T, x4) && lit_test(T, x4, A);
+        m |= (uint64_t)lit << q;
+      }
+      pairs += (unsigned long long)nq;
+    }
+    const unsigned n = (unsigned)__popcll(m);
+    const unsigned long long b = block_alloc(L.cnt + CNT_COMBO, n, sh);
+    if (v) {
+      L.mask[c] = m;
+      L.combo0[c] = (int32_t)std::min<unsigned long long>(b, 0x7fffffffull);
+      if (b + n <= (unsigned long long)L.cap_combo) {
+        unsigned long long k = b;
+        for (int q = 0; q < nq; ++q)
+          if ((m >> q) & 1ull) L.key[k++] = ((uint32_t)c << 8) | (uint32_t)q;
+      }
+    }
+  }
+  block_count(L.cnt + CNT_PAIRS, pairs);
+}
+
+__global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t ncombo) {
+  __shared__ AllocLds sh;
+  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < ncombo; base += (int64_t)gridDim.x * kBlk) {
+    const int64_t k = base + threadIdx.x;
+    const bool v = k < ncombo;
+    double bp[kMaxBp];
+    int nb = 0;
+    unsigned np = 0;
+    if (v) {
+      const uint32_t key = L.key[k];
+      const int64_t cg = c0 + (key >> 8);
+      const int q = (int)(key & 255u);
+      const int32_t i = g.rows[cg];
+      const TrialRec& T = g.trial[g.cols[cg]];
+      const double* xq = g.apex + ((int64_t)i * g.maxq + q) * 4;
+      double x4[4] = {xq[0], xq[1], xq[2], xq[3]};
+      Apex A;
+      apex_of(T, x4, A);
+      double wlo = 0.0, whi = 0.0;
+      if (w_range(T, A, wlo, whi)) {
+        ComboL cb;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          cb.C[f] = A.C[f]; cb.fa[f] = T.fa[f]; cb.fb[f] = T.fb[f]; cb.fc[f] = T.fc[f];
+        }
+        cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
+        L.cb[k] = cb;
+        nb = breakpoints(T, A, bp);
+        sort_bp(bp, nb);
+        if (nb == 0) {
+          np = 2;
+        } else {
+          for (int m = 0; m < nb; ++m) {
+            double e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
+            np += (e - bp[m] > 0.0) ? 1u : 0u;
+          }
+        }
+      }
+    }
+    const unsigned long long p0 = block_alloc(L.cnt + CNT_PIECE, np, sh);
+    if (v) {
+      L.p0[k] = (int32_t)std::min<unsigned long long>(p0, 0x7fffffffull);
+      L.np[k] = (int32_t)np;
+      if (np && p0 + np <= (unsigned long long)L.cap_piece) {
+        if (nb == 0) {
+          for (int h = 0; h < 2; ++h) {
+            L.pa[p0 + h] = (double)h;
+            L.ph[p0 + h] = -1.0;
+            L.pc[p0 + h] = (int32_t)k;
+          }
+        } else {
+          unsigned long long s = p0;
+          for (int m = 0; m < nb; ++m) {
+            double a = bp[m];
+            double e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
+            if (!(e - a > 0.0)) continue;
+            L.pa[s] = a;
+            L.ph[s] = e - a;
+            L.pc[s] = (int32_t)k;
+            ++s;
+          }
+        }
+      }
+    }
+  }
+}
+
+// kEmptyPer pieces per thread and pass (coalesced: piece base + j kBlk +
+// tid), so that one list allocation covers kEmptyPer * kBlk pieces.
+constexpr int kEmptyPer = 8;
+
+__global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
+  __shared__ AllocLds sh;
+  unsigned long long evals = 0;
+  const int64_t step = (int64_t)gridDim.x * kBlk * kEmptyPer;
+  for (int64_t base = (int64_t)blockIdx.x * kBlk * kEmptyPer; base < npiece; base += step) {
+    unsigned flags = 0;
+#pragma unroll 1
+    for (int j = 0; j < kEmptyPer; ++j) {
+      const int64_t p = base + (int64_t)j * kBlk + threadIdx.x;
+      if (p >= npiece) break;
+      const double H = L.ph[p];
+      bool ne = true;   // trapezoid half (H < 0): always evaluated
+      if (!(H < 0.0)) {
+        const ComboL& cb = L.cb[L.pc[p]];
+        const double a = L.pa[p];
+        ne = L_at(cb, a + 0.5 * H) != 0.0;
+        ++evals;
+        if (!ne) {
+          ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+          evals += 2;
+        }
+      }
+      L.pv[p] = 0.0;
+      flags |= (ne ? 1u : 0u) << j;
+    }
+    unsigned long long s = block_alloc(L.cnt + CNT_JOB, (unsigned)__popc(flags), sh);
+    for (int j = 0; j < kEmptyPer; ++j)
+      if ((flags >> j) & 1u) L.job[s++] = (int32_t)(base + (int64_t)j * kBlk + threadIdx.x);
+  }
+  block_count(L.cnt + CNT_EVAL, evals);
+}
+
+// The n_g nodes of one piece.  Gauss piece [a, a + H]: phi = a + H s(u_g),
+// weight H s'(u_g) w_g with s(u) = 3u^2 - 2u^3.  Trapezoid half h of the
+// period (no breakpoints): phi = (h n_g + g) 2 pi / (2 n_g), weight
+// 2 pi / (2 n_g).
+__global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, int64_t njob, const double* __restrict__ gl,
+                                                int ng) {
+  unsigned long long evals = 0;
+  const double ht = kTwoPi / (2 * ng);
+  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < njob; base += (int64_t)gridDim.x * kBlk) {
+    const int64_t k = base + threadIdx.x;
+    if (k >= njob) continue;
+    const int32_t p = L.job[k];
+    const double H = L.ph[p], a = L.pa[p];
+    const ComboL cb = L.cb[L.pc[p]];
+    const bool trap = H < 0.0;
+    double acc = 0.0;
+    for (int gi = 0; gi < ng; ++gi) {
+      const double u = gl[gi];
+      const double s = u * u * (3.0 - 2.0 * u);
+      const double ds = 6.0 * u * (1.0 - u);
+      const double phi = trap ? (a * ng + gi) * ht : a + H * s;
+      const double wt = trap ? ht : (H * ds) * gl[kMaxNg + gi];
+      acc += wt * L_at(cb, phi);
+    }
+    evals += (unsigned long long)ng;
+    L.pv[p] = acc;
+  }
+  block_count(L.cnt + CNT_EVAL, evals);
+}
+
+__global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo) {
+  int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+  for (; k < ncombo; k += (int64_t)gridDim.x * kBlk) {
+    const int32_t p0 = L.p0[k], np = L.np[k];
+    double I = 0.0;
+    for (int s = 0; s < np; ++s) I += L.pv[p0 + s];
+    L.I[k] = I / (4.0 * kPi);
+  }
+}
+
+// Matrix: out[c] = sum over lit apexes q (ascending) of w_q I_q, skipping
+// exact zeros; a candidate with any lit apex is a causal pair.  Potential:
+// out[c] = I of the single apex (0 when not lit).
+__global__ __launch_bounds__(kBlk) void k_store(Geo g, Lists L, int64_t c0, int64_t nc,
+                                                double* __restrict__ out) {
+  unsigned long long causal = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < nc; base += (int64_t)gridDim.x * kBlk) {
+    const int64_t c = base + threadIdx.x;
+    if (c < nc) {
+      const uint64_t m = L.mask[c];
+      int32_t idx = L.combo0[c];
+      double s = 0.0;
+      if (g.apex_w) {
+        const int32_t i = g.rows[c0 + c];
+        const double* wq = g.apex_w + (int64_t)i * g.maxq;
+        const int nq = g.apex_n ? g.apex_n[i] : 1;
+        for (int q = 0; q < nq; ++q) {
+          if (!((m >> q) & 1ull)) continue;
+          const double I = L.I[idx++];
+          if (I != 0.0) s += wq[q] * I;
+        }
+      } else if (m) {
+        s = L.I[idx];
+      }
+      out[c0 + c] = s;
+      causal += m ? 1ull : 0ull;
+    }
+  }
+  block_count(L.cnt + CNT_CAUSAL, causal);
+}
+
+unsigned grid_for(int64_t n, int per = 1) {
+  int64_t b = (n + (int64_t)kBlk * per - 1) / ((int64_t)kBlk * per);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, kMaxBlocks));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host
+
+struct PairWorkspace {
+  int64_t cap_cand = 0, cap_combo = 0, cap_piece = 0;
+  void* base = nullptr;
+  Lists L{};
+};
+
+void stb_free_workspace(stb_ctx* ctx) {
+  if (!ctx->ws) return;
+  dfree(ctx->ws->base);
+  delete ctx->ws;
+  ctx->ws = nullptr;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Lay the lists out in one allocation.
+static size_t ws_bytes(int64_t cc, int64_t cb, int64_t cp) {
+  size_t b = 0;
+  b += align256(cc * 8) + align256(cc * 4);
+  b += align256(cb * 4) + align256(cb * sizeof(ComboL)) + 2 * align256(cb * 4) + align256(cb * 8);
+  b += 2 * align256(cp * 8) + align256(cp * 4) + align256(cp * 8) + align256(cp * 4);
+  b += align256(CNT_N * 8);
+  return b;
+}
+
+static stb_status ensure_workspace(stb_ctx* ctx, int64_t want_cand, int64_t want_combo,
+                                   int64_t want_piece) {
+  PairWorkspace* w = ctx->ws;
+  if (w && w->cap_cand >= want_cand && w->cap_combo >= want_combo && w->cap_piece >= want_piece)
+    return STB_OK;
+  if (w) {
+    want_cand = std::max(want_cand, w->cap_cand);
+    want_combo = std::max(want_combo, w->cap_combo);
+    want_piece = std::max(want_piece, w->cap_piece);
+  }
+  stb_free_workspace(ctx);
+  void* base = nullptr;
+  // halve the request until it fits
+  for (;;) {
+    if (hipMalloc(&base, ws_bytes(want_cand, want_combo, want_piece)) == hipSuccess) break;
+    (void)hipGetLastError();
+    base = nullptr;
+    if (want_combo <= 4096) return stb_fail(ctx, STB_E_NO_MEMORY, "pair workspace does not fit");
+    want_cand = std::max<int64_t>(want_cand / 2, 1024);
+    want_combo /= 2;
+    want_piece /= 2;
+  }
+  w = new PairWorkspace();
+  w->base = base;
+  w->cap_cand = want_cand;
+  w->cap_combo = want_combo;
+  w->cap_piece = want_piece;
+  char* p = (char*)base;
+  auto take = [&](size_t bytes) { char* r = p; p += align256(bytes); return (void*)r; };
+  Lists& L = w->L;
+  L.mask = (uint64_t*)take(want_cand * 8);
+  L.combo0 = (int32_t*)take(want_cand * 4);
+  L.key = (uint32_t*)take(want_combo * 4);
+  L.cb = (ComboL*)take(want_combo * sizeof(ComboL));
+  L.p0 = (int32_t*)take(want_combo * 4);
+  L.np = (int32_t*)take(want_combo * 4);
+  L.I = (double*)take(want_combo * 8);
+  L.pa = (double*)take(want_piece * 8);
+  L.ph = (double*)take(want_piece * 8);
+  L.pc = (int32_t*)take(want_piece * 4);
+  L.pv = (double*)take(want_piece * 8);
+  L.job = (int32_t*)take(want_piece * 4);
+  L.cnt = (unsigned long long*)take(CNT_N * 8);
+  L.cap_cand = want_cand;
+  L.cap_combo = want_combo;
+  L.cap_piece = want_piece;
+  ctx->ws = w;
+  return STB_OK;
+}
+
+stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long work[4]) {
+  for (int k = 0; k < 4; ++k) work[k] = 0;
+  if (job.nnz <= 0) return STB_OK;
+  // sizes: the whole candidate set when it is small, else chunks of up to
+  // 2^24 candidates (the combo key holds 24 bits of candidate index)
+  const int64_t kCandMax = (int64_t)1 << 24;
+  const int64_t want_cand = std::min<int64_t>(job.nnz, kCandMax);
+  const int64_t want_combo = std::min<int64_t>(want_cand * job.maxq, (int64_t)1 << 26);
+  const int64_t want_piece = std::min<int64_t>(want_combo * 8, (int64_t)1 << 28);
+  stb_status s = ensure_workspace(ctx, want_cand, want_combo, want_piece);
+  if (s) return s;
+  PairWorkspace* w = ctx->ws;
+  Lists L = w->L;
+  Geo g;
+  g.rows = job.rows; g.cols = job.cols; g.trial = job.trial;
+  g.apex = job.apex; g.apex_w = job.apex_w; g.apex_n = job.apex_n; g.maxq = job.maxq;
+  hipStream_t st = ctx->stream;
+  unsigned long long h[CNT_N];
+  // first guess: ~4 lit apexes and ~4 pieces per lit apex; adapted below
+  int64_t chunk = std::min<int64_t>(w->cap_cand, std::max<int64_t>(1, w->cap_combo / 4));
+  chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, w->cap_piece / 16));
+  int64_t c0 = 0;
+  auto rd = [&](int k, unsigned long long* v) -> stb_status {
+    HIPCHK(ctx, hipMemcpyAsync(v, L.cnt + k, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return STB_OK;
+  };
+  while (c0 < job.nnz) {
+    const int64_t nc = std::min<int64_t>(chunk, job.nnz - c0);
+    HIPCHK(ctx, hipMemsetAsync(L.cnt, 0, CNT_N * 8, st));
+    hipLaunchKernelGGL(k_lit, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc);
+    HIPCHK(ctx, hipGetLastError());
+    unsigned long long ncombo = 0, npiece = 0, njob = 0;
+    if ((s = rd(CNT_COMBO, &ncombo))) return s;
+    if (ncombo > (unsigned long long)w->cap_combo) {
+      chunk = std::max<int64_t>(1, (int64_t)((double)nc * w->cap_combo / ncombo * 0.8));
+      continue;
+    }
+    hipLaunchKernelGGL(k_bp, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, g, L, c0, (int64_t)ncombo);
+    HIPCHK(ctx, hipGetLastError());
+    if ((s = rd(CNT_PIECE, &npiece))) return s;
+    if (npiece > (unsigned long long)w->cap_piece) {
+      chunk = std::max<int64_t>(1, (int64_t)((double)nc * w->cap_piece / npiece * 0.8));
+      continue;
+    }
+    hipLaunchKernelGGL(k_empty, dim3(grid_for(npiece, kEmptyPer)), dim3(kBlk), 0, st, L, (int64_t)npiece);
+    HIPCHK(ctx, hipGetLastError());
+    if ((s = rd(CNT_JOB, &njob))) return s;
+    hipLaunchKernelGGL(k_nodes, dim3(grid_for(njob)), dim3(kBlk), 0, st, L, (int64_t)njob, job.gl,
+                       job.ng);
+    HIPCHK(ctx, hipGetLastError());
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, L, (int64_t)ncombo);
+    HIPCHK(ctx, hipGetLastError());
+    hipLaunchKernelGGL(k_store, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc, job.out);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipMemcpyAsync(h, L.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    work[0] += h[CNT_EVAL];
+    work[1] += h[CNT_COMBO];
+    work[2] += h[CNT_PAIRS];
+    work[3] += h[CNT_PIECE];
+    if (job.n_causal) *job.n_causal += h[CNT_CAUSAL];
+    c0 += nc;
+    // next chunk: as large as the lists allow at this chunk's densities
+    double fc = (double)w->cap_combo / std::max<unsigned long long>(ncombo, 1);
+    double fp = (double)w->cap_piece / std::max<unsigned long long>(npiece, 1);
+    int64_t next = (int64_t)((double)nc * std::min(fc, fp) * 0.7);
+    chunk = std::max<int64_t>(1, std::min<int64_t>(next, w->cap_cand));
+  }
+  return STB_OK;
+}

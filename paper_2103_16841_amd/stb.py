@@ -139,7 +139,7 @@ class Context:
         out = np.zeros(4, dtype=np.int64)
         _chk(load().stb_last_work(self.h, out.ctypes.data_as(_I64)), self.h)
         return dict(L_evals=int(out[0]), lit_pairs=int(out[1]), apex_pairs=int(out[2]),
-                    tiles=int(out[3]))
+                    pieces=int(out[3]))
 
 
 class Mesh:
