@@ -23,11 +23,16 @@ if ROOT not in sys.path:
 
 METRIC = "causal element-pairs/s, FP64 vs mixed at rel.err≤1e-6; serving p50/p99 latency"
 FP64_VECTOR_PEAK = 78.6e12      # MI355X dense FP64 vector FLOP/s
-# algorithmic FLOPs per unit of work (op counts of the formulas)
-FLOP_PER_L = 80.0               # one L(phi): 4 face quadratics + r-measure + node map
-FLOP_PER_LIT = 760.0            # per lit (outer point, panel): lit extrema, breakpoints
-FLOP_PER_APEX = 100.0           # per candidate (outer point, panel): apex data, vertex test
-
+# Algorithmic FLOPs of one L(phi) evaluation, counted from the formulas
+# (FMA = 2, divide / sqrt / sin / cos = 1): node map 12, sin + cos 2, per face
+# B, e, f, D, sqrt D, q and the two roots 14 (x 4 faces = 56), r-measure of
+# the admissible interval 6, interval bookkeeping 4.
+FLOP_PER_L = 80.0
+# HBM bytes per k_nodes launch on this workload: rocprofv3 FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0 (factors from a plain 1 GiB copy), averaged over the 16
+# assembly launches (profiles/k_nodes_icosphere_L2_S32.md).  Must be reset to
+# None whenever k_nodes changes, until it is profiled again.
+K_NODES_TRAFFIC_BYTES = 28.45e9
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -93,13 +98,19 @@ def main():
     ctx = stb.Context(0)
     rec = {}
 
-    def step():
+    kt_acc = {}
+
+    def step(timed):
         m = stb.Mesh.from_device(ctx, vtx_d.data_ptr(), nv, tet_d.data_ptr(), nt)
         A = stb.assemble_V(ctx, m)
         rec["timings"] = ctx.timings()
         rec["work"] = ctx.work()
         rec["causal"] = A.n_causal
         rec["stored"] = A.n_stored
+        if timed:
+            for k, (ms_k, n_k, u_k) in ctx.kernel_times().items():
+                a = kt_acc.setdefault(k, [0.0, 0, 0])
+                a[0] += ms_k; a[1] += n_k; a[2] += u_k
         A.apply_dev(w_d.data_ptr(), y_d.data_ptr(), 1)
         A.apply_dev(W_d.data_ptr(), Y_d.data_ptr(), 16)
         stb.potential_S_dev(ctx, m, wp_d.data_ptr(), args.points, pts_d.data_ptr(), u_d.data_ptr())
@@ -107,21 +118,21 @@ def main():
         m.close()
 
     for _ in range(args.warmup):
-        step()
+        step(False)
     torch.cuda.synchronize()
-    quad_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
-        quad_ms.append(rec["timings"]["quadrature_ms"])
+        step(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
     value = rec["causal"] / (ms * 1e-3)
-    w = rec["work"]
-    flops = FLOP_PER_L * w["L_evals"] + FLOP_PER_LIT * w["lit_pairs"] + FLOP_PER_APEX * w["apex_pairs"]
-    kern_s = float(np.mean(quad_ms)) * 1e-3
-    achieved = flops / kern_s / 1e12
+    # dominant kernel: the FP64 Gauss-node kernel; its launches were timed
+    # with HIP events on the library's stream during the timed steps
+    k_ms, k_n, k_units = kt_acc.get("nodes_fp64", [0.0, 0, 0])
+    avg_ms = k_ms / max(k_n, 1)
+    flops_per_launch = FLOP_PER_L * k_units / max(k_n, 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     out = {
         "metric": METRIC,
         "value": value,
@@ -143,12 +154,14 @@ def main():
             "causal_pairs": rec["causal"], "stored_candidates": rec["stored"],
         },
         "phase_ms": rec["timings"],
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt_acc.items() if v[1]},
         "roofline": {
-            "bound": "alu", "kernel": "k_pairs",
+            "bound": "alu", "kernel": "k_nodes",
             "achieved": achieved, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": None,
-            "algorithmic_flops_per_launch": flops, "avg_launch_ms": kern_s * 1e3,
-            "work": w,
+            "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": K_NODES_TRAFFIC_BYTES,
+            "flop_per_L": FLOP_PER_L, "L_evals_per_launch": k_units / max(k_n, 1),
+            "algorithmic_flops_per_launch": flops_per_launch, "avg_launch_ms": avg_ms,
+            "launches": k_n, "work": rec["work"],
         },
     }
     ctx.close()

@@ -150,8 +150,21 @@ stb_status stb_last_timings(const stb_ctx* ctx, double* ms4);
 
 /* Work of the last stb_assemble_V on ctx: [0] evaluations of L(phi)
  * (empty-piece tests and Gauss nodes), [1] lit (outer point, trial panel)
- * pairs, [2] candidate (outer point, trial panel) pairs examined, [3] tiles. */
+ * pairs, [2] candidate (outer point, trial panel) pairs examined, [3] phi
+ * pieces. */
 stb_status stb_last_work(const stb_ctx* ctx, int64_t* counts4);
+
+/* Per-kernel device time of the pair pipeline in the last stb_assemble_V or
+ * potential call on ctx (HIP events on the context stream around every
+ * launch): ms8[k] total milliseconds, launches8[k] launch count and
+ * units8[k] work units for kernel kind k = 0 lit test (units: apexes
+ * tested), 1 breakpoints (lit combos), 2 empty-piece test (L evaluations
+ * at midpoints and quarter points), 3 unused (0), 4 Gauss nodes FP64
+ * (L evaluations), 5 Gauss nodes mixed FP32 (L evaluations), 6 piece/apex
+ * sums and store (candidates), 7 unused (0).  All three arrays are caller-allocated with
+ * 8 entries. */
+stb_status stb_last_kernel_times(const stb_ctx* ctx, double* ms8, int64_t* launches8,
+                                 int64_t* units8);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,10 @@ struct stb_ctx {
   double timings[4] = {0, 0, 0, 0};
   int64_t work[4] = {0, 0, 0, 0};   // last assembly: L evals, lit combos, apexes, pieces
   struct PairWorkspace* ws = nullptr;   // pair pipeline lists (grown on demand)
+  hipEvent_t kev[16] = {};              // pair pipeline: start/stop per kernel kind
+  double kern_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t kern_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t kern_units[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // Gauss-Legendre nodes on [0,1] for the last n_g used (device copy)
   int gl_n = 0;
   double* d_gl = nullptr;   // [2 * kMaxNg]: x then w

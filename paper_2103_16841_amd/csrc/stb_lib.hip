@@ -474,6 +474,7 @@ void stb_ctx_destroy(stb_ctx* ctx) {
   dfree(ctx->d_gl);
   stb_free_workspace(ctx);
   for (auto& e : ctx->ev) if (e) (void)hipEventDestroy(e);
+  for (auto& e : ctx->kev) if (e) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -855,6 +856,17 @@ stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_p
 stb_status stb_last_timings(const stb_ctx* ctx, double* ms4) {
   if (!ctx || !ms4) return fail(nullptr, STB_E_INVALID_ARG, "NULL argument");
   for (int k = 0; k < 4; ++k) ms4[k] = ctx->timings[k];
+  return STB_OK;
+}
+
+stb_status stb_last_kernel_times(const stb_ctx* ctx, double* ms8, int64_t* launches8,
+                                 int64_t* units8) {
+  if (!ctx || !ms8 || !launches8 || !units8) return fail(nullptr, STB_E_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 8; ++k) {
+    ms8[k] = ctx->kern_ms[k];
+    launches8[k] = ctx->kern_n[k];
+    units8[k] = ctx->kern_units[k];
+  }
   return STB_OK;
 }
 

@@ -16,9 +16,9 @@
 //             phi-breakpoints (sorted) and the pieces between them, appended
 //             to the piece list, contiguous per combo in phi order; a combo
 //             without breakpoints gets two half-periods of the trapezoid rule.
-//   k_empty   one lane per piece: L at the midpoint (then the quarter points)
-//             decides whether the piece is empty; non-empty pieces go to the
-//             job list.
+//   k_empty   one lane per piece: L at the midpoint, then, for the pieces where
+//             it is zero, at the quarter points (block-local queue); the
+//             non-empty pieces go to the job list.
 //   k_nodes   one lane per job: the n_g Gauss nodes of the piece in order
 //             (smoothstep map), summed in order.
 //   k_combine one lane per combo: ordered sum over its pieces, / (4 pi).
@@ -48,7 +48,8 @@ constexpr int kBlk = 256;
 constexpr int kMaxBlocks = 256 * 16;
 
 enum {
-  CNT_COMBO = 0, CNT_PIECE, CNT_JOB, CNT_EVAL, CNT_PAIRS, CNT_CAUSAL, CNT_N
+  CNT_COMBO = 0, CNT_PIECE, CNT_JOB, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
+  CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_N
 };
 
 // Block-wide list allocation: every thread of the block calls it (n = 0
@@ -101,7 +102,7 @@ struct Lists {
   int32_t* combo0;       // first combo of the candidate
   // per combo
   uint32_t* key;         // (candidate in chunk) << 8 | q
-  ComboL* cb;
+  double* cb;            // ComboL fields, structure of arrays: field f at f * cap_combo
   int32_t* p0;           // first piece
   int32_t* np;           // pieces
   double* I;             // inner integral
@@ -114,6 +115,25 @@ struct Lists {
   unsigned long long* cnt;
   int64_t cap_cand, cap_combo, cap_piece;
 };
+
+constexpr int kComboF = (int)(sizeof(ComboL) / sizeof(double));
+static_assert(sizeof(ComboL) == kComboF * sizeof(double), "ComboL holds doubles only");
+
+// Combo data in structure-of-arrays form: lanes reading neighbouring combos
+// touch neighbouring addresses of each field.
+__device__ __forceinline__ void store_combo(const Lists& L, int64_t k, const ComboL& cb) {
+  const double* src = reinterpret_cast<const double*>(&cb);
+#pragma unroll
+  for (int f = 0; f < kComboF; ++f) L.cb[(int64_t)f * L.cap_combo + k] = src[f];
+}
+
+__device__ __forceinline__ ComboL load_combo(const Lists& L, int64_t k) {
+  ComboL cb;
+  double* dst = reinterpret_cast<double*>(&cb);
+#pragma unroll
+  for (int f = 0; f < kComboF; ++f) dst[f] = L.cb[(int64_t)f * L.cap_combo + k];
+  return cb;
+}
 
 struct Geo {
   const int32_t* rows;   // row of each candidate (global index)
@@ -189,7 +209,7 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
           cb.C[f] = A.C[f]; cb.fa[f] = T.fa[f]; cb.fb[f] = T.fb[f]; cb.fc[f] = T.fc[f];
         }
         cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
-        L.cb[k] = cb;
+        store_combo(L, k, cb);
         nb = breakpoints(T, A, bp);
         sort_bp(bp, nb);
         if (nb == 0) {
@@ -230,40 +250,61 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
   }
 }
 
-// kEmptyPer pieces per thread and pass (coalesced: piece base + j kBlk +
-// tid), so that one list allocation covers kEmptyPer * kBlk pieces.
+// The empty-piece test, kEmptyPer pieces per thread and pass (coalesced:
+// piece base + j kBlk + tid), so that one list allocation covers
+// kEmptyPer * kBlk pieces.  L at the midpoint first; the pieces where it is
+// zero go to a block-local LDS queue whose quarter-point evaluations are
+// then shared by all lanes of the block (dense, and on combo data the block
+// has just read).
 constexpr int kEmptyPer = 8;
 
 __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
   __shared__ AllocLds sh;
-  unsigned long long evals = 0;
+  __shared__ int32_t s_q[kEmptyPer * kBlk];
+  __shared__ int s_nq;
+  unsigned long long ev_mid = 0, ev_quarter = 0;
   const int64_t step = (int64_t)gridDim.x * kBlk * kEmptyPer;
   for (int64_t base = (int64_t)blockIdx.x * kBlk * kEmptyPer; base < npiece; base += step) {
-    unsigned flags = 0;
+    if (threadIdx.x == 0) s_nq = 0;
+    __syncthreads();
+    unsigned ne = 0;
 #pragma unroll 1
     for (int j = 0; j < kEmptyPer; ++j) {
       const int64_t p = base + (int64_t)j * kBlk + threadIdx.x;
       if (p >= npiece) break;
       const double H = L.ph[p];
-      bool ne = true;   // trapezoid half (H < 0): always evaluated
+      bool nz = true;   // trapezoid half (H < 0): always evaluated
       if (!(H < 0.0)) {
-        const ComboL& cb = L.cb[L.pc[p]];
-        const double a = L.pa[p];
-        ne = L_at(cb, a + 0.5 * H) != 0.0;
-        ++evals;
-        if (!ne) {
-          ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
-          evals += 2;
-        }
+        nz = L_at(load_combo(L, L.pc[p]), L.pa[p] + 0.5 * H) != 0.0;
+        ++ev_mid;
       }
       L.pv[p] = 0.0;
-      flags |= (ne ? 1u : 0u) << j;
+      ne |= (nz ? 1u : 0u) << j;
+      if (!nz) s_q[atomicAdd(&s_nq, 1)] = (int32_t)p;
     }
-    unsigned long long s = block_alloc(L.cnt + CNT_JOB, (unsigned)__popc(flags), sh);
+    __syncthreads();
+    const int nq = s_nq;
+    // quarter points of the queued pieces; thread tid owns entries tid + m kBlk
+    unsigned qne = 0;
+#pragma unroll 1
+    for (int m = 0; m < kEmptyPer; ++m) {
+      const int e = m * kBlk + threadIdx.x;
+      if (e >= nq) break;
+      const int32_t p = s_q[e];
+      const ComboL cb = load_combo(L, L.pc[p]);
+      const double a = L.pa[p], H = L.ph[p];
+      bool nz = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+      ev_quarter += 2;
+      qne |= (nz ? 1u : 0u) << m;
+    }
+    unsigned long long s = block_alloc(L.cnt + CNT_JOB, (unsigned)(__popc(ne) + __popc(qne)), sh);
     for (int j = 0; j < kEmptyPer; ++j)
-      if ((flags >> j) & 1u) L.job[s++] = (int32_t)(base + (int64_t)j * kBlk + threadIdx.x);
+      if ((ne >> j) & 1u) L.job[s++] = (int32_t)(base + (int64_t)j * kBlk + threadIdx.x);
+    for (int m = 0; m < kEmptyPer; ++m)
+      if ((qne >> m) & 1u) L.job[s++] = s_q[m * kBlk + threadIdx.x];
   }
-  block_count(L.cnt + CNT_EVAL, evals);
+  block_count(L.cnt + CNT_EVAL_MID, ev_mid);
+  block_count(L.cnt + CNT_EVAL_QUARTER, ev_quarter);
 }
 
 // The n_g nodes of one piece.  Gauss piece [a, a + H]: phi = a + H s(u_g),
@@ -279,7 +320,7 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, int64_t njob, const 
     if (k >= njob) continue;
     const int32_t p = L.job[k];
     const double H = L.ph[p], a = L.pa[p];
-    const ComboL cb = L.cb[L.pc[p]];
+    const ComboL cb = load_combo(L, L.pc[p]);
     const bool trap = H < 0.0;
     double acc = 0.0;
     for (int gi = 0; gi < ng; ++gi) {
@@ -293,7 +334,7 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, int64_t njob, const 
     evals += (unsigned long long)ng;
     L.pv[p] = acc;
   }
-  block_count(L.cnt + CNT_EVAL, evals);
+  block_count(L.cnt + CNT_EVAL_NODES, evals);
 }
 
 __global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo) {
@@ -404,7 +445,7 @@ static stb_status ensure_workspace(stb_ctx* ctx, int64_t want_cand, int64_t want
   L.mask = (uint64_t*)take(want_cand * 8);
   L.combo0 = (int32_t*)take(want_cand * 4);
   L.key = (uint32_t*)take(want_combo * 4);
-  L.cb = (ComboL*)take(want_combo * sizeof(ComboL));
+  L.cb = (double*)take(want_combo * sizeof(ComboL));
   L.p0 = (int32_t*)take(want_combo * 4);
   L.np = (int32_t*)take(want_combo * 4);
   L.I = (double*)take(want_combo * 8);
@@ -448,37 +489,78 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     HIPCHK(ctx, hipStreamSynchronize(st));
     return STB_OK;
   };
+  for (int k = 0; k < 8; ++k) { ctx->kern_ms[k] = 0.0; ctx->kern_n[k] = 0; ctx->kern_units[k] = 0; }
+  for (auto& e : ctx->kev)
+    if (!e) HIPCHK(ctx, hipEventCreate(&e));
+  bool used[8] = {false, false, false, false, false, false, false, false};
+  // brackets a launch of kernel kind k with events (per chunk, read after
+  // the chunk's synchronisation)
+  auto t0 = [&](int k) { used[k] = true; return hipEventRecord(ctx->kev[2 * k], st); };
+  auto t1 = [&](int k) { return hipEventRecord(ctx->kev[2 * k + 1], st); };
   while (c0 < job.nnz) {
     const int64_t nc = std::min<int64_t>(chunk, job.nnz - c0);
+    for (auto& u : used) u = false;
     HIPCHK(ctx, hipMemsetAsync(L.cnt, 0, CNT_N * 8, st));
+    HIPCHK(ctx, t0(0));
     hipLaunchKernelGGL(k_lit, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc);
     HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, t1(0));
     unsigned long long ncombo = 0, npiece = 0, njob = 0;
     if ((s = rd(CNT_COMBO, &ncombo))) return s;
     if (ncombo > (unsigned long long)w->cap_combo) {
+      if (nc == 1) return stb_fail(ctx, STB_E_INTERNAL, "pair lists too small for one candidate");
       chunk = std::max<int64_t>(1, (int64_t)((double)nc * w->cap_combo / ncombo * 0.8));
       continue;
     }
+    HIPCHK(ctx, t0(1));
     hipLaunchKernelGGL(k_bp, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, g, L, c0, (int64_t)ncombo);
     HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, t1(1));
     if ((s = rd(CNT_PIECE, &npiece))) return s;
     if (npiece > (unsigned long long)w->cap_piece) {
+      if (nc == 1) return stb_fail(ctx, STB_E_INTERNAL, "pair lists too small for one candidate");
       chunk = std::max<int64_t>(1, (int64_t)((double)nc * w->cap_piece / npiece * 0.8));
       continue;
     }
-    hipLaunchKernelGGL(k_empty, dim3(grid_for(npiece, kEmptyPer)), dim3(kBlk), 0, st, L, (int64_t)npiece);
-    HIPCHK(ctx, hipGetLastError());
+    if (npiece) {
+      HIPCHK(ctx, t0(2));
+      hipLaunchKernelGGL(k_empty, dim3(grid_for(npiece, kEmptyPer)), dim3(kBlk), 0, st, L,
+                         (int64_t)npiece);
+      HIPCHK(ctx, hipGetLastError());
+      HIPCHK(ctx, t1(2));
+    }
     if ((s = rd(CNT_JOB, &njob))) return s;
-    hipLaunchKernelGGL(k_nodes, dim3(grid_for(njob)), dim3(kBlk), 0, st, L, (int64_t)njob, job.gl,
-                       job.ng);
-    HIPCHK(ctx, hipGetLastError());
-    hipLaunchKernelGGL(k_combine, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, L, (int64_t)ncombo);
-    HIPCHK(ctx, hipGetLastError());
+    if (njob) {
+      HIPCHK(ctx, t0(4));
+      hipLaunchKernelGGL(k_nodes, dim3(grid_for(njob)), dim3(kBlk), 0, st, L, (int64_t)njob, job.gl,
+                         job.ng);
+      HIPCHK(ctx, hipGetLastError());
+      HIPCHK(ctx, t1(4));
+    }
+    HIPCHK(ctx, t0(6));
+    if (ncombo) {
+      hipLaunchKernelGGL(k_combine, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, L, (int64_t)ncombo);
+      HIPCHK(ctx, hipGetLastError());
+    }
     hipLaunchKernelGGL(k_store, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc, job.out);
     HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, t1(6));
     HIPCHK(ctx, hipMemcpyAsync(h, L.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipStreamSynchronize(st));
-    work[0] += h[CNT_EVAL];
+    for (int k = 0; k < 8; ++k) {
+      if (!used[k]) continue;
+      float ms = 0.0f;
+      HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->kev[2 * k], ctx->kev[2 * k + 1]));
+      ctx->kern_ms[k] += ms;
+      ctx->kern_n[k] += 1;
+    }
+    const unsigned long long evals = h[CNT_EVAL_MID] + h[CNT_EVAL_QUARTER] + h[CNT_EVAL_NODES];
+    ctx->kern_units[0] += (int64_t)h[CNT_PAIRS];
+    ctx->kern_units[1] += (int64_t)ncombo;
+    ctx->kern_units[2] += (int64_t)(h[CNT_EVAL_MID] + h[CNT_EVAL_QUARTER]);
+    ctx->kern_units[4] += (int64_t)h[CNT_EVAL_NODES];
+    ctx->kern_units[6] += (int64_t)nc;
+    work[0] += evals;
     work[1] += h[CNT_COMBO];
     work[2] += h[CNT_PAIRS];
     work[3] += h[CNT_PIECE];

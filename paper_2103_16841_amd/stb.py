@@ -21,7 +21,11 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_last_error", "stb_mesh_create", "stb_mesh_destroy", "stb_mesh_size",
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
            "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
-           "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_mesh_create_dev"]
+           "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_mesh_create_dev",
+           "stb_last_kernel_times"]
+
+KERNEL_KINDS = ["lit", "breakpoints", "empty_test", "unused3", "nodes_fp64", "nodes_fp32",
+                "sums_store", "unused7"]
 
 
 class QuadParams(ctypes.Structure):
@@ -79,6 +83,7 @@ def load():
     L.stb_last_timings.argtypes = [_VP, _D]
     L.stb_inner_values.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
     L.stb_last_work.argtypes = [_VP, _I64]
+    L.stb_last_kernel_times.argtypes = [_VP, _D, _I64, _I64]
     L.stb_mesh_create_dev.argtypes = [_VP, i64, _VP, i64, _VP, _VP, ctypes.POINTER(_VP)]
     L.stb_potential_S_dev.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _VP, i64, _VP, _VP,
                                       _VP]
@@ -134,6 +139,15 @@ class Context:
         out = np.zeros(4)
         _chk(load().stb_last_timings(self.h, out.ctypes.data_as(_D)), self.h)
         return dict(geometry_ms=out[0], cull_ms=out[1], quadrature_ms=out[2], total_ms=out[3])
+
+    def kernel_times(self):
+        """{kind: (total ms, launches, work units)} of the pair pipeline's last run."""
+        ms = np.zeros(8)
+        n = np.zeros(8, dtype=np.int64)
+        u = np.zeros(8, dtype=np.int64)
+        _chk(load().stb_last_kernel_times(self.h, ms.ctypes.data_as(_D), n.ctypes.data_as(_I64),
+                                          u.ctypes.data_as(_I64)), self.h)
+        return {k: (float(ms[i]), int(n[i]), int(u[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     def work(self):
         out = np.zeros(4, dtype=np.int64)
