@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--points", type=int, default=1000)
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -61,6 +62,45 @@ def cpu_baseline(mesh, nrows):
             "kind": "oracle",
             "sample": "%d seeded rows x all %d columns (%d causal pairs) in %.2f s" %
                       (nrows, mesh.nt, pairs, dt)}
+
+
+def mixed_leg(args, ctx, stb, step, paramsmx, vtx_d, tet_d, nv, nt, rec):
+    """The same step with the mixed-precision assembly; its entries compared
+    with the FP64 assembly's (which match the oracle to 1e-10)."""
+    import numpy as np
+    import torch
+    causal64 = rec["causal"]
+    m = stb.Mesh.from_device(ctx, vtx_d.data_ptr(), nv, tet_d.data_ptr(), nt)
+    A64 = stb.assemble_V(ctx, m)
+    _, _, v64 = A64.export()
+    A64.close()
+    Amx = stb.assemble_V(ctx, m, paramsmx)
+    _, _, vmx = Amx.export()
+    Amx.close()
+    m.close()
+    scale = np.abs(v64).max()
+    err = np.abs(vmx - v64) / np.maximum(np.abs(v64), 1e-5 * scale)
+    zeros_ok = bool(np.array_equal(vmx == 0.0, v64 == 0.0))
+    del v64, vmx
+    acc = {}
+    for _ in range(args.warmup):
+        step(False, paramsmx, acc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True, paramsmx, acc)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    assert rec["causal"] == causal64
+    kern = {k: v[0] / args.steps for k, v in acc.items() if v[1]}
+    return {
+        "value": causal64 / (ms * 1e-3), "unit": "causal element-pairs/s", "ms_per_step": ms,
+        "max_rel_err_vs_fp64": float(err.max()), "err_floor": "1e-5 max|A|",
+        "exact_zeros_preserved": zeros_ok, "eta_far": paramsmx.eta_far,
+        "kernel_ms_per_step": kern,
+        "fp32_node_evals": acc.get("nodes_fp32", [0, 0, 0])[2] // args.steps,
+        "entries_recomputed_fp64": acc.get("mixed_restore", [0, 0, 0])[2] // args.steps,
+    }
 
 
 def main():
@@ -99,17 +139,19 @@ def main():
     rec = {}
 
     kt_acc = {}
+    params64 = stb.default_params()
+    paramsmx = stb.default_params(prec=stb.STB_MIXED)
 
-    def step(timed):
+    def step(timed, params=params64, acc=kt_acc):
         m = stb.Mesh.from_device(ctx, vtx_d.data_ptr(), nv, tet_d.data_ptr(), nt)
-        A = stb.assemble_V(ctx, m)
+        A = stb.assemble_V(ctx, m, params)
         rec["timings"] = ctx.timings()
         rec["work"] = ctx.work()
         rec["causal"] = A.n_causal
         rec["stored"] = A.n_stored
         if timed:
             for k, (ms_k, n_k, u_k) in ctx.kernel_times().items():
-                a = kt_acc.setdefault(k, [0.0, 0, 0])
+                a = acc.setdefault(k, [0.0, 0, 0])
                 a[0] += ms_k; a[1] += n_k; a[2] += u_k
         A.apply_dev(w_d.data_ptr(), y_d.data_ptr(), 1)
         A.apply_dev(W_d.data_ptr(), Y_d.data_ptr(), 16)
@@ -164,6 +206,8 @@ def main():
             "launches": k_n, "work": rec["work"],
         },
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg(args, ctx, stb, step, paramsmx, vtx_d, tet_d, nv, nt, rec)
     ctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, args.cpu_rows)

@@ -58,11 +58,17 @@ typedef enum { STB_FP64 = 0, STB_MIXED = 1 } stb_precision;
 
 /* Quadrature parameters.  m_q: sub-triangles per face edge of the outer
  * centroid rule (1..4, default 3 as in Exp. 3).  n_g: Gauss-Legendre nodes
- * per phi piece of the inner rule (2..64, default 16).  eta_far: mixed mode
- * only; a pair is "far" when the distance between the panels' spatial
- * bounding balls exceeds eta_far times the larger radius.  prec: FP64 or
- * mixed (far pairs' phi nodes in FP32 with compensated FP32 sums; cone /
- * panel geometry, near and coincident pairs always in FP64). */
+ * per phi piece of the inner rule (2..64, default 16).  prec: FP64 or mixed.
+ * Mixed (stb_assemble_V only; the potential is always FP64): the phi nodes
+ * of "far" (outer point, trial panel) pairs -- the point farther than
+ * eta_far times the radius of the panel's spatial bounding ball from that
+ * ball (default 0.5) -- solve the face quadratics and measure the r-gaps in
+ * FP32 about the middle of the pair's admissible range, with Kahan-summed
+ * FP32 node sums; lit test, breakpoints, empty-piece tests, angles and the
+ * quadratics' coefficients stay FP64.  Every entry carries a first-order
+ * bound of its FP32 error; entries whose bound exceeds 5e-6 of their size
+ * are recomputed with FP64 nodes, which keeps entries within 1e-6 relative
+ * of the FP64 assembly. */
 typedef struct {
   int32_t m_q;
   int32_t n_g;
@@ -74,7 +80,7 @@ typedef struct stb_ctx stb_ctx;
 typedef struct stb_mesh stb_mesh;
 typedef struct stb_mat stb_mat;
 
-/* Default parameters (m_q = 3, n_g = 16, eta_far = 2, FP64). */
+/* Default parameters (m_q = 3, n_g = 16, eta_far = 0.5, FP64). */
 stb_quad_params stb_default_params(void);
 
 /* Create a context on HIP device `device` (its own stream). */
@@ -118,6 +124,12 @@ stb_status stb_mat_to_dense(const stb_mat* mat, double* out);
 stb_status stb_mat_get(const stb_mat* mat, int64_t k, const int32_t* row, const int32_t* col,
                        double* out);
 
+/* Export the store in CSR form into caller-allocated host arrays: rowptr
+ * (n + 1 entries), cols and vals (n_stored entries each, see stb_mat_info);
+ * columns ascend within a row; stored entries of non-causal pairs are 0.0.
+ * Any of the three pointers may be NULL to skip that array. */
+stb_status stb_mat_export(const stb_mat* mat, int64_t* rowptr, int32_t* cols, double* vals);
+
 /* y = A w for nrhs right-hand sides; w: n x nrhs row-major, y: n x nrhs.
  * nrhs == 1: FP64 sparse product.  nrhs == 16: FP32 matrix-core product
  * (A and W rounded to FP32, FP32 accumulation).  Other nrhs: FP64, one
@@ -159,9 +171,11 @@ stb_status stb_last_work(const stb_ctx* ctx, int64_t* counts4);
  * launch): ms8[k] total milliseconds, launches8[k] launch count and
  * units8[k] work units for kernel kind k = 0 lit test (units: apexes
  * tested), 1 breakpoints (lit combos), 2 empty-piece test (L evaluations
- * at midpoints and quarter points), 3 unused (0), 4 Gauss nodes FP64
- * (L evaluations), 5 Gauss nodes mixed FP32 (L evaluations), 6 piece/apex
- * sums and store (candidates), 7 unused (0).  All three arrays are caller-allocated with
+ * at midpoints and quarter points), 3 mixed precision: second sums and
+ * store (entries recomputed in FP64), 4 Gauss nodes FP64 (L evaluations),
+ * 5 Gauss nodes FP32 of far pairs (L evaluations), 6 piece/apex sums and
+ * store (candidates), 7 mixed precision: FP64 Gauss nodes of the
+ * recomputed entries (L evaluations).  All three arrays are caller-allocated with
  * 8 entries. */
 stb_status stb_last_kernel_times(const stb_ctx* ctx, double* ms8, int64_t* launches8,
                                  int64_t* units8);

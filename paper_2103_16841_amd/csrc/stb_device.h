@@ -568,7 +568,7 @@ STB_HD inline int make_outer(const TrialRec& R, int m, double* P, double* W) {
   return cnt;
 }
 
-struct ComboL {          // per (apex, trial) data needed by phase B
+struct ComboL {          // per (apex, trial panel) data needed by L(phi)
   double C[4];
   double d2, wlo, whi;
   double fa[4], fb[4], fc[4];
@@ -579,6 +579,165 @@ STB_HD __forceinline__ double L_combo(const ComboL& cb, double cs, double sn) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) { F.fa[k] = cb.fa[k]; F.fb[k] = cb.fb[k]; F.fc[k] = cb.fc[k]; }
   return L_eval(F, cb.C, cb.d2, cb.wlo, cb.whi, cs, sn);
+}
+
+// ------------------------------------------------------------ mixed precision
+//
+// Far pairs: the root solves and the interval measure of L(phi) in FP32,
+// everything that fixes the geometry in FP64.  Near the panel the roots
+// w = r + s of the face quadratics are large (~ 2 |x - y|) while the
+// admissible interval is as wide as the panel, so roots computed in FP32
+// about w = 0 would lose |x - y| / diam ulps.  Instead the quadratics are
+// re-centred at the middle w_c of the admissible w-range: with w = w_c + delta,
+//   Q_k(w_c + delta) = e delta^2 + 2 beta delta + gamma,
+//   e = B - a,  beta = B w_c - (a w_c + C),  gamma = B (w_c^2 - d^2)
+//                                               - (a (w_c^2 + d^2) + 2 C w_c),
+// where beta, gamma and the discriminant beta^2 - e gamma (which cancels
+// near a tangency) are formed in FP64 from the FP64 angle and per-pair
+// constants and only then rounded to FP32; the deltas of interest are as
+// large as the panel, so FP32 resolves them to ~1e-7 of the panel.  The r-measure of a gap [delta0, delta1] is
+//   (delta1 - delta0) / 2 * (v0 v1 + |d| (v0 + v1)) / ((|d| + v0)(|d| + v1)),
+// v = w - |d| = (w_c - |d|) + delta >= 0: a product of non-negative terms,
+// free of the cancellation in 1 - d^2 / (w0 w1) near the hyperbola's vertex.
+struct FarConst {
+  double wc, P1;           // centre of the admissible w-range, w_c^2 - d^2
+  double K1[4], K0[4];     // a w_c + C, a (w_c^2 + d^2) + 2 C w_c per face
+  float m, ad;             // w_c - |d|, |d|
+  float dlo, dhi;          // admissible range of delta
+};
+
+STB_HD __forceinline__ FarConst far_const(const ComboL& cb) {
+  FarConst F;
+  const double wc = 0.5 * (cb.wlo + cb.whi), ad = sqrt(cb.d2);
+  F.wc = wc;
+  F.P1 = (wc - ad) * (wc + ad);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    F.K1[k] = fma(cb.fa[k], wc, cb.C[k]);
+    F.K0[k] = fma(cb.fa[k], fma(wc, wc, cb.d2), 2.0 * cb.C[k] * wc);
+  }
+  F.m = (float)(wc - ad);
+  F.ad = (float)ad;
+  F.dlo = (float)(cb.wlo - wc);
+  F.dhi = (float)(cb.whi - wc);
+  return F;
+}
+
+// FP32 reciprocal and square root (hardware, about 1 ulp).
+STB_HD __forceinline__ float rcp32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
+STB_HD __forceinline__ float sqrt32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_sqrtf(x);
+#else
+  return sqrtf(x);
+#endif
+}
+
+STB_HD __forceinline__ void order2f(float& s0, float& e0, float& s1, float& e1) {
+  bool sw = s1 < s0;
+  float ts = s0, te = e0;
+  s0 = sw ? s1 : s0;
+  e0 = sw ? e1 : e0;
+  s1 = sw ? ts : s1;
+  e1 = sw ? te : e1;
+}
+
+// r-measure of the gap [d0, d1] (delta coordinates), see above.
+STB_HD __forceinline__ float rgap32(float d0, float d1, const FarConst& F) {
+  float v0 = fmaxf(F.m + d0, 0.0f), v1 = fmaxf(F.m + d1, 0.0f);
+  float num = fmaf(v0, v1, F.ad * (v0 + v1));
+  float den = (F.ad + v0) * (F.ad + v1);
+  float g = den > 0.0f ? num * rcp32(den) : 1.0f;
+  return 0.5f * (d1 - d0) * g;
+}
+
+// L(phi) of a far pair: same case analysis as L_eval (e > 0: between the
+// roots; e < 0: outside; e = 0: one side of the linear root) in delta.
+// *err receives a first-order bound of the FP32 rounding error: every root
+// is resolved to a few ulps of its own size (beta, gamma and the
+// discriminant come rounded from FP64; one square root, one reciprocal, two
+// products), so a gap [c, g1] contributes at most kE (|c| + |g1| + m) with
+// kE = 4 ulp.
+STB_HD __forceinline__ float L_eval_far(const ComboL& cb, const FarConst& F, double cs,
+                                        double sn, float* err) {
+  const float kNone = 3.0e38f;
+  float lo = F.dlo, hi = F.dhi;
+  bool dead = false;
+  float hs[4], he[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double B = fma(cb.fb[k], cs, cb.fc[k] * sn);
+    const double e64 = B - cb.fa[k];
+    const double be64 = fma(B, F.wc, -F.K1[k]);
+    const double ga64 = fma(B, F.P1, -F.K0[k]);
+    // the discriminant cancels near a tangency: formed in FP64
+    const float D = (float)fma(be64, be64, -e64 * ga64);
+    const float e = (float)e64, be = (float)be64, ga = (float)ga64;
+    const bool two = D > 0.0f;
+    const float q = -(be + copysignf(sqrt32(fmaxf(D, 0.0f)), be));
+    const float r1 = q * rcp32(e), r2 = ga * rcp32(q);
+    const float mn = fminf(r1, r2), mx = fmaxf(r1, r2);
+    const bool pos = e > 0.0f, neg = e < 0.0f, zer = !(pos || neg);
+    const bool cut = pos && two;
+    dead = dead || (pos && !two) || (zer && be == 0.0f && !(ga < 0.0f));
+    lo = cut ? fmaxf(lo, mn) : lo;
+    hi = cut ? fminf(hi, mx) : hi;
+    // e = 0: 2 beta delta + gamma < 0, root r2 = -gamma / (2 beta)
+    lo = (zer && be < 0.0f) ? fmaxf(lo, r2) : lo;
+    hi = (zer && be > 0.0f) ? fminf(hi, r2) : hi;
+    const bool hole = neg && two;
+    hs[k] = hole ? mn : kNone;
+    he[k] = hole ? mx : kNone;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    hs[k] = fminf(fmaxf(hs[k], lo), hi);
+    he[k] = fmaxf(fminf(he[k], hi), hs[k]);
+  }
+  order2f(hs[0], he[0], hs[1], he[1]);
+  order2f(hs[2], he[2], hs[3], he[3]);
+  order2f(hs[0], he[0], hs[2], he[2]);
+  order2f(hs[1], he[1], hs[3], he[3]);
+  order2f(hs[1], he[1], hs[2], he[2]);
+  // gaps whose measure is below 4 FP32 ulps of their delta-coordinates are
+  // rounding artefacts (e.g. where two roots meet at the hyperbola's vertex)
+  const float kWulp32 = 4.76837158203125e-7f;
+  const float kE = 2.384185791015625e-7f;   // 4 ulp
+  // A dropped gap adds its own measure to the bound; an interval that is
+  // empty in FP32 only because its ends crossed by rounding adds the ends'
+  // uncertainty (the decisions on the signs of e and of the discriminant
+  // are the FP64 ones: the casts keep signs).
+  float len = 0.0f, e = 0.0f, c = lo;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float g1 = fmaxf(hs[k], c);
+    float m = rgap32(c, g1, F);
+    bool keep = m > kWulp32 * fmaxf(fabsf(c), fabsf(g1));
+    len += keep ? m : 0.0f;
+    e += keep ? kE * (fabsf(c) + fabsf(g1) + m) : m;
+    c = fmaxf(he[k], c);
+  }
+  float m = rgap32(c, hi, F);
+  bool keep = m > kWulp32 * fmaxf(fabsf(c), fabsf(hi));
+  len += keep ? m : 0.0f;
+  e += keep ? kE * (fabsf(c) + fabsf(hi) + m) : m;
+  const bool empty = dead || !(hi > lo);
+  *err = dead ? 0.0f : (empty ? kE * (fabsf(lo) + fabsf(hi)) : e);
+  return empty ? 0.0f : len;
+}
+
+// A combo is far when the apex's spatial distance from the trial panel's
+// bounding ball exceeds eta times the ball's radius.
+STB_HD __forceinline__ bool apex_far(const TrialRec& T, const double* x4, double eta) {
+  double dx = x4[1] - T.cx, dy = x4[2] - T.cy, dz = x4[3] - T.cz;
+  return sqrt(dx * dx + dy * dy + dz * dz) - T.rad > eta * T.rad;
 }
 
 STB_HD __forceinline__ double L_at(const ComboL& cb, double phi) {

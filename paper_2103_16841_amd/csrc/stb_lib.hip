@@ -343,6 +343,8 @@ static stb_status check_params(stb_ctx* ctx, const stb_quad_params* p) {
   if (p->m_q < 1 || p->m_q > 4) return fail(ctx, STB_E_INVALID_ARG, "m_q must be in [1,4], got %d", p->m_q);
   if (p->n_g < 2 || p->n_g > kMaxNg) return fail(ctx, STB_E_INVALID_ARG, "n_g must be in [2,%d], got %d", kMaxNg, p->n_g);
   if (p->prec != STB_FP64 && p->prec != STB_MIXED) return fail(ctx, STB_E_INVALID_ARG, "bad precision");
+  if (!(p->eta_far >= 0.0) || !std::isfinite(p->eta_far))
+    return fail(ctx, STB_E_INVALID_ARG, "eta_far must be finite and >= 0");
   return STB_OK;
 }
 
@@ -418,7 +420,7 @@ stb_quad_params stb_default_params(void) {
   stb_quad_params p;
   p.m_q = 3;
   p.n_g = 16;
-  p.eta_far = 2.0;
+  p.eta_far = 0.5;
   p.prec = STB_FP64;
   return p;
 }
@@ -608,6 +610,8 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   J.maxq = mesh->maxq;
   J.gl = ctx->d_gl;
   J.ng = p.n_g;
+  J.mixed = p.prec == STB_MIXED;
+  J.eta_far = p.eta_far;
   J.out = M->d_vals;
   unsigned long long causal = 0, work[4];
   J.n_causal = &causal;
@@ -690,6 +694,17 @@ stb_status stb_mat_get(const stb_mat* Mc, int64_t k, const int32_t* row, const i
   return STB_OK;
 }
 
+stb_status stb_mat_export(const stb_mat* M, int64_t* rowptr, int32_t* cols, double* vals) {
+  if (!M) return fail(nullptr, STB_E_INVALID_ARG, "NULL matrix");
+  stb_ctx* ctx = M->ctx;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (rowptr) HIPCHK(ctx, hipMemcpy(rowptr, M->d_rowptr, 8 * (M->n + 1), hipMemcpyDeviceToHost));
+  if (cols && M->nnz) HIPCHK(ctx, hipMemcpy(cols, M->d_cols, 4 * M->nnz, hipMemcpyDeviceToHost));
+  if (vals && M->nnz) HIPCHK(ctx, hipMemcpy(vals, M->d_vals, 8 * M->nnz, hipMemcpyDeviceToHost));
+  return STB_OK;
+}
+
 stb_status stb_apply_dev(stb_ctx* ctx, const stb_mat* M, int32_t nrhs, const double* w, double* y,
                          void* stream) {
   if (!ctx || !M || !w || !y || nrhs < 1) return fail(ctx, STB_E_INVALID_ARG, "bad arguments");
@@ -759,6 +774,7 @@ static stb_status potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_pa
   J.maxq = 1;
   J.gl = ctx->d_gl;
   J.ng = p.n_g;
+  J.mixed = false;   // the potential is a plain sum over panels: always FP64
   J.out = d_I;
   unsigned long long work[4];
   s = stb_run_pairs(ctx, J, work);

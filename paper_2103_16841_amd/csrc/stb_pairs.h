@@ -14,6 +14,8 @@ struct PairJob {
   int maxq = 1;
   const double* gl = nullptr;        // [2 kMaxNg]: Gauss nodes on [0,1], then weights
   int ng = 0;
+  bool mixed = false;                // far combos' Gauss nodes in FP32
+  double eta_far = 2.0;              // far: apex farther than eta_far radii from the panel's ball
   double* out = nullptr;             // [nnz] matrix entry or inner integral
   unsigned long long* n_causal = nullptr;   // host: += candidates with a lit apex
 };

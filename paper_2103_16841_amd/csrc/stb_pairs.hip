@@ -48,8 +48,8 @@ constexpr int kBlk = 256;
 constexpr int kMaxBlocks = 256 * 16;
 
 enum {
-  CNT_COMBO = 0, CNT_PIECE, CNT_JOB, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
-  CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_N
+  CNT_COMBO = 0, CNT_PIECE, CNT_JOB, CNT_JOB32, CNT_REDO, CNT_JOBR, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
+  CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_EVAL_NODES32, CNT_EVAL_REDO, CNT_N
 };
 
 // Block-wide list allocation: every thread of the block calls it (n = 0
@@ -101,17 +101,22 @@ struct Lists {
   uint64_t* mask;        // lit apexes (bit q)
   int32_t* combo0;       // first combo of the candidate
   // per combo
-  uint32_t* key;         // (candidate in chunk) << 8 | q
+  uint32_t* key;         // (candidate in chunk) << 8 | far << 7 | q
   double* cb;            // ComboL fields, structure of arrays: field f at f * cap_combo
   int32_t* p0;           // first piece
   int32_t* np;           // pieces
   double* I;             // inner integral
+  float* Ie;             // its FP32 rounding bound (mixed)
   // per piece
   double* pa;            // start angle (trapezoid half: 0 or 1)
   double* ph;            // length (trapezoid half: -1)
   int32_t* pc;           // owning combo
   double* pv;            // ordered node sum
-  int32_t* job;          // non-empty pieces
+  float* pe;             // FP32 rounding bound of the node sum (far pieces, mixed)
+  int32_t* job;          // non-empty pieces, FP64 nodes
+  int32_t* job32;        // non-empty pieces of far combos, FP32 nodes (mixed)
+  uint8_t* pne;          // per piece: non-empty
+  uint8_t* redo;         // per candidate (mixed): entry recomputed in FP64
   unsigned long long* cnt;
   int64_t cap_cand, cap_combo, cap_piece;
 };
@@ -143,6 +148,8 @@ struct Geo {
   const double* apex_w;  // [rows][maxq] (matrix) or nullptr (potential)
   const int32_t* apex_n; // [rows] or nullptr (one apex)
   int maxq;
+  int mixed;             // far combos' nodes in FP32
+  double eta_far;
 };
 
 __global__ __launch_bounds__(kBlk) void k_lit(Geo g, Lists L, int64_t c0, int64_t nc) {
@@ -194,7 +201,7 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
     if (v) {
       const uint32_t key = L.key[k];
       const int64_t cg = c0 + (key >> 8);
-      const int q = (int)(key & 255u);
+      const int q = (int)(key & 63u);
       const int32_t i = g.rows[cg];
       const TrialRec& T = g.trial[g.cols[cg]];
       const double* xq = g.apex + ((int64_t)i * g.maxq + q) * 4;
@@ -210,6 +217,7 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
         }
         cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
         store_combo(L, k, cb);
+        if (g.mixed && apex_far(T, x4, g.eta_far)) L.key[k] = key | 0x80u;
         nb = breakpoints(T, A, bp);
         sort_bp(bp, nb);
         if (nb == 0) {
@@ -279,6 +287,8 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
         ++ev_mid;
       }
       L.pv[p] = 0.0;
+      L.pe[p] = 0.0f;
+      L.pne[p] = nz ? 1 : 0;
       ne |= (nz ? 1u : 0u) << j;
       if (!nz) s_q[atomicAdd(&s_nq, 1)] = (int32_t)p;
     }
@@ -295,13 +305,32 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
       const double a = L.pa[p], H = L.ph[p];
       bool nz = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
       ev_quarter += 2;
+      if (nz) L.pne[p] = 1;
       qne |= (nz ? 1u : 0u) << m;
     }
-    unsigned long long s = block_alloc(L.cnt + CNT_JOB, (unsigned)(__popc(ne) + __popc(qne)), sh);
+    // route the non-empty pieces: far combos to the FP32 list (mixed mode)
+    unsigned far = 0, qfar = 0;
     for (int j = 0; j < kEmptyPer; ++j)
-      if ((ne >> j) & 1u) L.job[s++] = (int32_t)(base + (int64_t)j * kBlk + threadIdx.x);
+      if ((ne >> j) & 1u) {
+        const int64_t p = base + (int64_t)j * kBlk + threadIdx.x;
+        far |= ((L.key[L.pc[p]] >> 7) & 1u) << j;
+      }
     for (int m = 0; m < kEmptyPer; ++m)
-      if ((qne >> m) & 1u) L.job[s++] = s_q[m * kBlk + threadIdx.x];
+      if ((qne >> m) & 1u) qfar |= ((L.key[L.pc[s_q[m * kBlk + threadIdx.x]]] >> 7) & 1u) << m;
+    const unsigned n64 = __popc(ne & ~far) + __popc(qne & ~qfar);
+    const unsigned n32 = __popc(ne & far) + __popc(qne & qfar);
+    unsigned long long s = block_alloc(L.cnt + CNT_JOB, n64, sh);
+    unsigned long long s32 = block_alloc(L.cnt + CNT_JOB32, n32, sh);
+    for (int j = 0; j < kEmptyPer; ++j) {
+      if (!((ne >> j) & 1u)) continue;
+      const int32_t p = (int32_t)(base + (int64_t)j * kBlk + threadIdx.x);
+      if ((far >> j) & 1u) L.job32[s32++] = p; else L.job[s++] = p;
+    }
+    for (int m = 0; m < kEmptyPer; ++m) {
+      if (!((qne >> m) & 1u)) continue;
+      const int32_t p = s_q[m * kBlk + threadIdx.x];
+      if ((qfar >> m) & 1u) L.job32[s32++] = p; else L.job[s++] = p;
+    }
   }
   block_count(L.cnt + CNT_EVAL_MID, ev_mid);
   block_count(L.cnt + CNT_EVAL_QUARTER, ev_quarter);
@@ -311,14 +340,15 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
 // weight H s'(u_g) w_g with s(u) = 3u^2 - 2u^3.  Trapezoid half h of the
 // period (no breakpoints): phi = (h n_g + g) 2 pi / (2 n_g), weight
 // 2 pi / (2 n_g).
-__global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, int64_t njob, const double* __restrict__ gl,
-                                                int ng) {
+__global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, const int32_t* __restrict__ jobs,
+                                                   int64_t njob, const double* __restrict__ gl,
+                                                   int ng, int ctr) {
   unsigned long long evals = 0;
   const double ht = kTwoPi / (2 * ng);
   for (int64_t base = (int64_t)blockIdx.x * kBlk; base < njob; base += (int64_t)gridDim.x * kBlk) {
     const int64_t k = base + threadIdx.x;
     if (k >= njob) continue;
-    const int32_t p = L.job[k];
+    const int32_t p = jobs[k];
     const double H = L.ph[p], a = L.pa[p];
     const ComboL cb = load_combo(L, L.pc[p]);
     const bool trap = H < 0.0;
@@ -334,7 +364,47 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, int64_t njob, const 
     evals += (unsigned long long)ng;
     L.pv[p] = acc;
   }
-  block_count(L.cnt + CNT_EVAL_NODES, evals);
+  block_count(L.cnt + ctr, evals);
+}
+
+// The n_g nodes of a far piece in mixed precision: node angle, sin/cos and
+// the per-face coefficients in FP64, root solves and interval measure in
+// FP32 (L_eval_far), node sum in FP32 with Kahan compensation.
+__global__ __launch_bounds__(kBlk, 4) void k_nodes32(Lists L, int64_t njob,
+                                                     const double* __restrict__ gl, int ng) {
+  unsigned long long evals = 0;
+  const double ht = kTwoPi / (2 * ng);
+  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < njob; base += (int64_t)gridDim.x * kBlk) {
+    const int64_t k = base + threadIdx.x;
+    if (k >= njob) continue;
+    const int32_t p = L.job32[k];
+    const double H = L.ph[p], a = L.pa[p];
+    const ComboL cb = load_combo(L, L.pc[p]);
+    const FarConst F = far_const(cb);
+    const bool trap = H < 0.0;
+    float acc = 0.0f, comp = 0.0f, eacc = 0.0f;
+    for (int gi = 0; gi < ng; ++gi) {
+      const double u = gl[gi];
+      const double s = u * u * (3.0 - 2.0 * u);
+      const double ds = 6.0 * u * (1.0 - u);
+      const double phi = trap ? (a * ng + gi) * ht : a + H * s;
+      const double wt = trap ? ht : (H * ds) * gl[kMaxNg + gi];
+      double sn, cs;
+      sincos_small(phi, &sn, &cs);
+      float el;
+      const float term = (float)wt * L_eval_far(cb, F, cs, sn, &el);
+      eacc = fmaf((float)wt, el, eacc);
+      const float y = term - comp;
+      const float t = acc + y;
+      comp = (t - acc) - y;
+      acc = t;
+    }
+    evals += (unsigned long long)ng;
+    L.pv[p] = (double)acc;
+    // the bound also covers the summation: Kahan leaves O(ulp) of the sum
+    L.pe[p] = eacc + 1.2e-7f * fabsf(acc);
+  }
+  block_count(L.cnt + CNT_EVAL_NODES32, evals);
 }
 
 __global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo) {
@@ -342,40 +412,95 @@ __global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo) {
   for (; k < ncombo; k += (int64_t)gridDim.x * kBlk) {
     const int32_t p0 = L.p0[k], np = L.np[k];
     double I = 0.0;
-    for (int s = 0; s < np; ++s) I += L.pv[p0 + s];
+    float e = 0.0f;
+    for (int s = 0; s < np; ++s) {
+      I += L.pv[p0 + s];
+      e += L.pe[p0 + s];
+    }
     L.I[k] = I / (4.0 * kPi);
+    L.Ie[k] = e * (float)(1.0 / (4.0 * kPi));
   }
 }
 
 // Matrix: out[c] = sum over lit apexes q (ascending) of w_q I_q, skipping
 // exact zeros; a candidate with any lit apex is a causal pair.  Potential:
 // out[c] = I of the single apex (0 when not lit).
+//
+// Mixed precision (check = 1): the entry is a sum of outer-point terms that
+// can cancel (the energetic form differences the test panel's top and
+// bottom faces), so a small relative error of the far terms can be a large
+// one of the entry.  Each far I_q carries a first-order bound of its FP32
+// rounding error (from the node evaluations, see L_eval_far); when
+// sum_q |w_q| bound_q exceeds kMixedTol |entry|, the candidate is flagged for
+// recomputation with FP64 nodes.  The bound overestimates the error (the
+// largest error/bound ratio seen is 0.32, and the terms' errors partly
+// cancel), so kMixedTol = 5e-6 keeps the entries within 1e-6 of the FP64
+// values.  Causal pairs are counted when check = 0.
+constexpr double kMixedTol = 5e-6;
+
 __global__ __launch_bounds__(kBlk) void k_store(Geo g, Lists L, int64_t c0, int64_t nc,
-                                                double* __restrict__ out) {
-  unsigned long long causal = 0;
+                                                double* __restrict__ out, int check) {
+  unsigned long long causal = 0, redo = 0;
   for (int64_t base = (int64_t)blockIdx.x * kBlk; base < nc; base += (int64_t)gridDim.x * kBlk) {
     const int64_t c = base + threadIdx.x;
     if (c < nc) {
       const uint64_t m = L.mask[c];
       int32_t idx = L.combo0[c];
-      double s = 0.0;
+      double s = 0.0, bound = 0.0;
       if (g.apex_w) {
         const int32_t i = g.rows[c0 + c];
         const double* wq = g.apex_w + (int64_t)i * g.maxq;
         const int nq = g.apex_n ? g.apex_n[i] : 1;
         for (int q = 0; q < nq; ++q) {
           if (!((m >> q) & 1ull)) continue;
-          const double I = L.I[idx++];
+          const int32_t k = idx++;
+          const double I = L.I[k];
           if (I != 0.0) s += wq[q] * I;
+          if (check && ((L.key[k] >> 7) & 1u)) bound += fabs(wq[q]) * (double)L.Ie[k];
         }
       } else if (m) {
         s = L.I[idx];
       }
       out[c0 + c] = s;
-      causal += m ? 1ull : 0ull;
+      if (check) {
+        const bool r = bound > kMixedTol * fabs(s);
+        L.redo[c] = r ? 1 : 0;
+        redo += r ? 1ull : 0ull;
+      } else {
+        causal += m ? 1ull : 0ull;
+      }
     }
   }
   block_count(L.cnt + CNT_CAUSAL, causal);
+  block_count(L.cnt + CNT_REDO, redo);
+}
+
+// Mixed precision: the non-empty pieces of the far combos of every flagged
+// candidate go to the FP64 job list again.
+__global__ __launch_bounds__(kBlk) void k_redo(Geo g, Lists L, int64_t nc) {
+  __shared__ AllocLds sh;
+  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < nc; base += (int64_t)gridDim.x * kBlk) {
+    const int64_t c = base + threadIdx.x;
+    const bool v = c < nc && L.redo[c];
+    unsigned n = 0;
+    int32_t k0 = 0, nk = 0;
+    if (v) {
+      k0 = L.combo0[c];
+      nk = __popcll(L.mask[c]);
+      for (int32_t k = k0; k < k0 + nk; ++k) {
+        if (!((L.key[k] >> 7) & 1u)) continue;
+        for (int32_t p = L.p0[k]; p < L.p0[k] + L.np[k]; ++p) n += L.pne[p];
+      }
+    }
+    unsigned long long s = block_alloc(L.cnt + CNT_JOBR, n, sh);
+    if (v) {
+      for (int32_t k = k0; k < k0 + nk; ++k) {
+        if (!((L.key[k] >> 7) & 1u)) continue;
+        for (int32_t p = L.p0[k]; p < L.p0[k] + L.np[k]; ++p)
+          if (L.pne[p]) L.job[s++] = p;
+      }
+    }
+  }
 }
 
 unsigned grid_for(int64_t n, int per = 1) {
@@ -407,7 +532,8 @@ static size_t ws_bytes(int64_t cc, int64_t cb, int64_t cp) {
   size_t b = 0;
   b += align256(cc * 8) + align256(cc * 4);
   b += align256(cb * 4) + align256(cb * sizeof(ComboL)) + 2 * align256(cb * 4) + align256(cb * 8);
-  b += 2 * align256(cp * 8) + align256(cp * 4) + align256(cp * 8) + align256(cp * 4);
+  b += 2 * align256(cp * 8) + align256(cp * 4) + align256(cp * 8) + 2 * align256(cp * 4);
+  b += align256(cp) + align256(cc) + align256(cb * 4) + align256(cp * 4);
   b += align256(CNT_N * 8);
   return b;
 }
@@ -449,11 +575,16 @@ static stb_status ensure_workspace(stb_ctx* ctx, int64_t want_cand, int64_t want
   L.p0 = (int32_t*)take(want_combo * 4);
   L.np = (int32_t*)take(want_combo * 4);
   L.I = (double*)take(want_combo * 8);
+  L.Ie = (float*)take(want_combo * 4);
   L.pa = (double*)take(want_piece * 8);
   L.ph = (double*)take(want_piece * 8);
   L.pc = (int32_t*)take(want_piece * 4);
   L.pv = (double*)take(want_piece * 8);
+  L.pe = (float*)take(want_piece * 4);
   L.job = (int32_t*)take(want_piece * 4);
+  L.job32 = (int32_t*)take(want_piece * 4);
+  L.pne = (uint8_t*)take(want_piece);
+  L.redo = (uint8_t*)take(want_cand);
   L.cnt = (unsigned long long*)take(CNT_N * 8);
   L.cap_cand = want_cand;
   L.cap_combo = want_combo;
@@ -478,6 +609,8 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
   Geo g;
   g.rows = job.rows; g.cols = job.cols; g.trial = job.trial;
   g.apex = job.apex; g.apex_w = job.apex_w; g.apex_n = job.apex_n; g.maxq = job.maxq;
+  g.mixed = job.mixed ? 1 : 0;
+  g.eta_far = job.eta_far;
   hipStream_t st = ctx->stream;
   unsigned long long h[CNT_N];
   // first guess: ~4 lit apexes and ~4 pieces per lit apex; adapted below
@@ -530,21 +663,56 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       HIPCHK(ctx, t1(2));
     }
     if ((s = rd(CNT_JOB, &njob))) return s;
+    unsigned long long njob32 = 0;
+    if (g.mixed && (s = rd(CNT_JOB32, &njob32))) return s;
     if (njob) {
       HIPCHK(ctx, t0(4));
-      hipLaunchKernelGGL(k_nodes, dim3(grid_for(njob)), dim3(kBlk), 0, st, L, (int64_t)njob, job.gl,
-                         job.ng);
+      hipLaunchKernelGGL(k_nodes, dim3(grid_for(njob)), dim3(kBlk), 0, st, L, L.job, (int64_t)njob,
+                         job.gl, job.ng, (int)CNT_EVAL_NODES);
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(4));
+    }
+    if (njob32) {
+      HIPCHK(ctx, t0(5));
+      hipLaunchKernelGGL(k_nodes32, dim3(grid_for(njob32)), dim3(kBlk), 0, st, L, (int64_t)njob32,
+                         job.gl, job.ng);
+      HIPCHK(ctx, hipGetLastError());
+      HIPCHK(ctx, t1(5));
     }
     HIPCHK(ctx, t0(6));
     if (ncombo) {
       hipLaunchKernelGGL(k_combine, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, L, (int64_t)ncombo);
       HIPCHK(ctx, hipGetLastError());
     }
-    hipLaunchKernelGGL(k_store, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc, job.out);
+    const bool check = g.mixed && g.apex_w && njob32;
+    hipLaunchKernelGGL(k_store, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc, job.out,
+                       check ? 1 : 0);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(6));
+    if (check) {
+      // mixed: entries whose FP32 error bound is too large for their size
+      // are recomputed with FP64 nodes
+      unsigned long long nredo = 0, njr = 0;
+      if ((s = rd(CNT_REDO, &nredo))) return s;
+      if (nredo) {
+        hipLaunchKernelGGL(k_redo, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, nc);
+        HIPCHK(ctx, hipGetLastError());
+        if ((s = rd(CNT_JOBR, &njr))) return s;
+      }
+      if (njr) {
+        HIPCHK(ctx, t0(7));
+        hipLaunchKernelGGL(k_nodes, dim3(grid_for(njr)), dim3(kBlk), 0, st, L, L.job, (int64_t)njr,
+                           job.gl, job.ng, (int)CNT_EVAL_REDO);
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, t1(7));
+      }
+      HIPCHK(ctx, t0(3));
+      if (njr)
+        hipLaunchKernelGGL(k_combine, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, L, (int64_t)ncombo);
+      hipLaunchKernelGGL(k_store, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc, job.out, 0);
+      HIPCHK(ctx, hipGetLastError());
+      HIPCHK(ctx, t1(3));
+    }
     HIPCHK(ctx, hipMemcpyAsync(h, L.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipStreamSynchronize(st));
     for (int k = 0; k < 8; ++k) {
@@ -554,11 +722,15 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       ctx->kern_ms[k] += ms;
       ctx->kern_n[k] += 1;
     }
-    const unsigned long long evals = h[CNT_EVAL_MID] + h[CNT_EVAL_QUARTER] + h[CNT_EVAL_NODES];
+    const unsigned long long evals = h[CNT_EVAL_MID] + h[CNT_EVAL_QUARTER] + h[CNT_EVAL_NODES] +
+                                     h[CNT_EVAL_NODES32] + h[CNT_EVAL_REDO];
     ctx->kern_units[0] += (int64_t)h[CNT_PAIRS];
     ctx->kern_units[1] += (int64_t)ncombo;
     ctx->kern_units[2] += (int64_t)(h[CNT_EVAL_MID] + h[CNT_EVAL_QUARTER]);
     ctx->kern_units[4] += (int64_t)h[CNT_EVAL_NODES];
+    ctx->kern_units[5] += (int64_t)h[CNT_EVAL_NODES32];
+    ctx->kern_units[7] += (int64_t)h[CNT_EVAL_REDO];
+    ctx->kern_units[3] += (int64_t)h[CNT_REDO];
     ctx->kern_units[6] += (int64_t)nc;
     work[0] += evals;
     work[1] += h[CNT_COMBO];

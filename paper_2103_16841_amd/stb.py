@@ -22,10 +22,10 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
            "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
            "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_mesh_create_dev",
-           "stb_last_kernel_times"]
+           "stb_last_kernel_times", "stb_mat_export"]
 
-KERNEL_KINDS = ["lit", "breakpoints", "empty_test", "unused3", "nodes_fp64", "nodes_fp32",
-                "sums_store", "unused7"]
+KERNEL_KINDS = ["lit", "breakpoints", "empty_test", "mixed_restore", "nodes_fp64", "nodes_fp32",
+                "sums_store", "mixed_redo_nodes"]
 
 
 class QuadParams(ctypes.Structure):
@@ -84,6 +84,7 @@ def load():
     L.stb_inner_values.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
     L.stb_last_work.argtypes = [_VP, _I64]
     L.stb_last_kernel_times.argtypes = [_VP, _D, _I64, _I64]
+    L.stb_mat_export.argtypes = [_VP, _I64, _I32, _D]
     L.stb_mesh_create_dev.argtypes = [_VP, i64, _VP, i64, _VP, _VP, ctypes.POINTER(_VP)]
     L.stb_potential_S_dev.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _VP, i64, _VP, _VP,
                                       _VP]
@@ -215,6 +216,15 @@ class Matrix:
         out = np.zeros((self.n, self.n))
         _chk(load().stb_mat_to_dense(self.h, out.ctypes.data_as(_D)), self.ctx.h)
         return out
+
+    def export(self):
+        """(rowptr, cols, vals) of the CSR store (host copies)."""
+        rp = np.zeros(self.n + 1, dtype=np.int64)
+        cols = np.zeros(self.n_stored, dtype=np.int32)
+        vals = np.zeros(self.n_stored)
+        _chk(load().stb_mat_export(self.h, rp.ctypes.data_as(_I64), cols.ctypes.data_as(_I32),
+                                   vals.ctypes.data_as(_D)), self.ctx.h)
+        return rp, cols, vals
 
     def get(self, rows, cols):
         rows = np.ascontiguousarray(rows, dtype=np.int32)
