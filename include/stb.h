@@ -155,6 +155,23 @@ stb_status stb_potential_S_dev(stb_ctx* ctx, const stb_mesh* mesh, const stb_qua
 stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
                             int64_t k, const double* pts, const int32_t* panel, double* out);
 
+/* Batched assembly of nmesh meshes of one context (Exp. 3 style workloads
+ * of many independent scatterers): the candidate sets of all meshes are one
+ * work list of the pair pipeline, so every kernel launch covers the whole
+ * batch.  Meshes are processed in waves of consecutive meshes whose stores
+ * fit hbm_budget bytes of device memory (0: 40% of the free memory).
+ * mats (optional): receives each mesh's matrix, as stb_assemble_V would
+ * return it (then the whole batch forms one wave and must fit).
+ * W_dev, Y_dev (optional, together): per mesh a device array of n_m x nrhs
+ * inputs and outputs, Y_m = A_m W_m computed after the mesh's wave (nrhs = 16:
+ * FP32 matrix cores), so that a batch larger than HBM can be assembled and
+ * applied without keeping its matrices.  At least one of mats and W_dev/Y_dev
+ * must be given.  Results are identical to per-mesh stb_assemble_V calls.
+ * Timings, work and kernel times describe the whole batch. */
+stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* const* meshes,
+                              const stb_quad_params* params, int64_t hbm_budget, stb_mat** mats,
+                              int32_t nrhs, const double* const* W_dev, double* const* Y_dev);
+
 /* Timing of the last stb_assemble_V on ctx, in milliseconds measured with
  * HIP events on the context stream: [0] geometry/outer points, [1] cull and
  * compaction, [2] clip + quadrature + store, [3] total. */

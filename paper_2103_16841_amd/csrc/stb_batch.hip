@@ -1,0 +1,245 @@
+// stb_batch.hip -- many meshes through one pass of the pair pipeline.
+//
+// The meshes of a batch differ in size (here 780 to 245,760 panels) and
+// their pairs in cost; launching one pipeline per mesh would leave the GPU
+// idle on every small mesh and pay one launch chain each.  Instead the
+// candidate sets of all meshes of a wave are concatenated into one work list
+// (panel records, outer points and candidate indices shifted by each mesh's
+// panel offset) and the pipeline runs once over it: every kernel launch
+// covers all meshes, and the flat lists even out the per-pair cost.  Waves
+// group consecutive meshes whose stores fit the HBM budget; after a wave the
+// optional per-mesh products Y_m = A_m W_m run and, unless the caller keeps
+// the matrices, the stores are released.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "stb_internal.h"
+#include "stb_pairs.h"
+
+using namespace stb;
+
+__global__ void k_shift_idx(int64_t n, const int32_t* __restrict__ in, int32_t add,
+                            int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] + add;
+}
+
+namespace {
+
+// Device bytes per candidate held during a wave: the mesh's store (cols,
+// vals), the candidate's row, the concatenated row/column/value copies.
+constexpr int64_t kBytesPerCand = 4 + 8 + 4 + 4 + 4 + 8;
+
+struct WaveMesh {
+  int idx;
+  stb_mesh* mesh;
+  stb_mat* M = nullptr;
+  int32_t* rowof = nullptr;
+  int64_t off_panel = 0, off_cand = 0;
+};
+
+void release(std::vector<WaveMesh>& w, bool keep) {
+  for (auto& x : w) {
+    dfree(x.rowof);
+    x.rowof = nullptr;
+    if (!keep && x.M) {
+      stb_mat_destroy(x.M);
+      x.M = nullptr;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* const* meshes,
+                                         const stb_quad_params* params, int64_t hbm_budget,
+                                         stb_mat** mats, int32_t nrhs, const double* const* W_dev,
+                                         double* const* Y_dev) {
+  if (!ctx || nmesh < 1 || !meshes) return stb_fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  if (!mats && !(W_dev && Y_dev)) return stb_fail(ctx, STB_E_INVALID_ARG, "nothing to return");
+  if ((W_dev || Y_dev) && (!W_dev || !Y_dev || nrhs < 1))
+    return stb_fail(ctx, STB_E_INVALID_ARG, "W and Y need each other and nrhs >= 1");
+  if (hbm_budget < 0) return stb_fail(ctx, STB_E_INVALID_ARG, "negative HBM budget");
+  for (int k = 0; k < nmesh; ++k) {
+    if (!meshes[k]) return stb_fail(ctx, STB_E_INVALID_ARG, "mesh %d is NULL", k);
+    if (meshes[k]->ctx != ctx) return stb_fail(ctx, STB_E_INVALID_ARG, "mesh %d: other context", k);
+    if (W_dev && (!W_dev[k] || !Y_dev[k])) return stb_fail(ctx, STB_E_INVALID_ARG, "W/Y %d NULL", k);
+  }
+  if (mats)
+    for (int k = 0; k < nmesh; ++k) mats[k] = nullptr;
+  stb_quad_params p = params ? *params : stb_default_params();
+  stb_status s = stb_check_params(ctx, &p);
+  if (s) return s;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
+  HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+  for (int k = 0; k < nmesh; ++k)
+    if ((s = stb_ensure_outer(ctx, meshes[k], p.m_q))) return s;
+  const int maxq = meshes[0]->maxq;
+  if (hbm_budget == 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(ctx, hipMemGetInfo(&fr, &tot));
+    hbm_budget = (int64_t)(0.4 * (double)fr);
+  }
+  // candidate counts, for the wave plan
+  std::vector<int64_t> nnz(nmesh, 0);
+  for (int k = 0; k < nmesh; ++k)
+    if ((s = stb_cull_count(ctx, meshes[k]->nt, meshes[k]->d_box, meshes[k], &nnz[k]))) return s;
+  HIPCHK(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+  HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+  unsigned long long work_tot[4] = {0, 0, 0, 0};
+  double kms[8] = {0}, kunits[8] = {0};
+  int64_t kn[8] = {0};
+  int k0 = 0;
+  while (k0 < nmesh) {
+    // wave: consecutive meshes within the budget (at least one); kept
+    // matrices stay resident, so with mats the whole batch must fit
+    int k1 = k0;
+    int64_t bytes = 0, panels = 0, cands = 0;
+    while (k1 < nmesh) {
+      int64_t b = nnz[k1] * kBytesPerCand + meshes[k1]->nt * (int64_t)(sizeof(TrialRec) + 40 * maxq);
+      if (k1 > k0 && bytes + b > hbm_budget && !mats) break;
+      bytes += b;
+      panels += meshes[k1]->nt;
+      cands += nnz[k1];
+      ++k1;
+    }
+    if (panels > (int64_t)INT32_MAX) return stb_fail(ctx, STB_E_INVALID_ARG, "batch wave exceeds 2^31 panels");
+    std::vector<WaveMesh> w;
+    for (int k = k0; k < k1; ++k) {
+      WaveMesh x;
+      x.idx = k;
+      x.mesh = meshes[k];
+      w.push_back(x);
+    }
+    TrialRec* trial_g = nullptr;
+    double *apex_g = nullptr, *apexw_g = nullptr, *vals_g = nullptr;
+    int32_t *apexn_g = nullptr, *rows_g = nullptr, *cols_g = nullptr;
+    int64_t* seg_off = nullptr;
+    unsigned long long* seg_causal = nullptr;
+    auto cleanup = [&](bool keep) {
+      dfree(trial_g); dfree(apex_g); dfree(apexw_g); dfree(apexn_g); dfree(rows_g); dfree(cols_g);
+      dfree(vals_g); dfree(seg_off); dfree(seg_causal);
+      release(w, keep);
+    };
+    bool ok = dalloc(&trial_g, (size_t)panels) == hipSuccess &&
+              dalloc(&apex_g, (size_t)panels * maxq * 4) == hipSuccess &&
+              dalloc(&apexw_g, (size_t)panels * maxq) == hipSuccess &&
+              dalloc(&apexn_g, (size_t)panels) == hipSuccess &&
+              dalloc(&rows_g, (size_t)cands) == hipSuccess &&
+              dalloc(&cols_g, (size_t)cands) == hipSuccess &&
+              dalloc(&vals_g, (size_t)cands) == hipSuccess &&
+              dalloc(&seg_off, w.size() + 1) == hipSuccess &&
+              dalloc(&seg_causal, w.size()) == hipSuccess;
+    if (!ok) {
+      cleanup(false);
+      return stb_fail(ctx, STB_E_NO_MEMORY, "batch wave of %lld candidates does not fit", (long long)cands);
+    }
+    std::vector<int64_t> h_off(w.size() + 1, 0);
+    int64_t op = 0, oc = 0;
+    hipStream_t st = ctx->stream;
+    for (size_t m = 0; m < w.size(); ++m) {
+      WaveMesh& x = w[m];
+      stb_mesh* me = x.mesh;
+      x.M = new stb_mat();
+      x.M->ctx = ctx;
+      x.M->n = me->nt;
+      int64_t nz = 0;
+      s = stb_cull(ctx, me->nt, me->d_box, me, &x.M->d_rowptr, &x.M->d_cols, &x.rowof, &nz);
+      if (s == STB_OK && nz != nnz[x.idx]) s = stb_fail(ctx, STB_E_INTERNAL, "cull count changed");
+      if (s == STB_OK && dalloc(&x.M->d_vals, (size_t)nz) != hipSuccess)
+        s = stb_fail(ctx, STB_E_NO_MEMORY, "store of mesh %d", x.idx);
+      if (s) { cleanup(false); return s; }
+      x.M->nnz = nz;
+      x.off_panel = op;
+      x.off_cand = oc;
+      h_off[m] = oc;
+      hipError_t e = hipMemcpyAsync(trial_g + op, me->d_trial, sizeof(TrialRec) * me->nt,
+                                    hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(apex_g + op * maxq * 4, me->d_opts, sizeof(double) * me->nt * maxq * 4,
+                           hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(apexw_g + op * maxq, me->d_ow, sizeof(double) * me->nt * maxq,
+                           hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(apexn_g + op, me->d_onq, sizeof(int32_t) * me->nt, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess && nz > 0) {
+        unsigned g = (unsigned)((nz + 255) / 256);
+        hipLaunchKernelGGL(k_shift_idx, dim3(g), dim3(256), 0, st, nz, x.rowof, (int32_t)op, rows_g + oc);
+        hipLaunchKernelGGL(k_shift_idx, dim3(g), dim3(256), 0, st, nz, x.M->d_cols, (int32_t)op,
+                           cols_g + oc);
+        e = hipGetLastError();
+      }
+      if (e != hipSuccess) {
+        cleanup(false);
+        return stb_fail(ctx, STB_E_DEVICE, "batch staging: %s", hipGetErrorString(e));
+      }
+      op += me->nt;
+      oc += nz;
+    }
+    h_off[w.size()] = oc;
+    HIPCHK(ctx, hipMemcpyAsync(seg_off, h_off.data(), 8 * h_off.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemsetAsync(seg_causal, 0, 8 * w.size(), st));
+    PairJob J;
+    J.nnz = oc;
+    J.rows = rows_g;
+    J.cols = cols_g;
+    J.trial = trial_g;
+    J.apex = apex_g;
+    J.apex_w = apexw_g;
+    J.apex_n = apexn_g;
+    J.maxq = maxq;
+    J.gl = ctx->d_gl;
+    J.ng = p.n_g;
+    J.mixed = p.prec == STB_MIXED;
+    J.eta_far = p.eta_far;
+    J.out = vals_g;
+    J.nseg = (int)w.size();
+    J.seg_off = seg_off;
+    J.seg_causal = seg_causal;
+    unsigned long long work[4];
+    s = stb_run_pairs(ctx, J, work);
+    if (s) { cleanup(false); return s; }
+    for (int q = 0; q < 4; ++q) work_tot[q] += work[q];
+    for (int q = 0; q < 8; ++q) { kms[q] += ctx->kern_ms[q]; kn[q] += ctx->kern_n[q]; kunits[q] += (double)ctx->kern_units[q]; }
+    std::vector<unsigned long long> h_causal(w.size());
+    HIPCHK(ctx, hipMemcpyAsync(h_causal.data(), seg_causal, 8 * w.size(), hipMemcpyDeviceToHost, st));
+    for (size_t m = 0; m < w.size(); ++m) {
+      WaveMesh& x = w[m];
+      if (x.M->nnz)
+        HIPCHK(ctx, hipMemcpyAsync(x.M->d_vals, vals_g + x.off_cand, 8 * x.M->nnz,
+                                   hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    for (size_t m = 0; m < w.size(); ++m) w[m].M->n_causal = (int64_t)h_causal[m];
+    // products, then release (or hand over) the wave's stores
+    for (size_t m = 0; m < w.size() && W_dev; ++m) {
+      WaveMesh& x = w[m];
+      s = stb_apply_dev(ctx, x.M, nrhs, W_dev[x.idx], Y_dev[x.idx], nullptr);
+      if (s) { cleanup(false); return s; }
+    }
+    if (W_dev) HIPCHK(ctx, hipStreamSynchronize(st));
+    if (mats)
+      for (auto& x : w) mats[x.idx] = x.M;
+    cleanup(mats != nullptr);
+    k0 = k1;
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
+  HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
+  for (int q = 0; q < 4; ++q) ctx->work[q] = (int64_t)work_tot[q];
+  for (int q = 0; q < 8; ++q) {
+    ctx->kern_ms[q] = kms[q];
+    ctx->kern_n[q] = kn[q];
+    ctx->kern_units[q] = (int64_t)kunits[q];
+  }
+  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+  (void)hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
+  (void)hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
+  (void)hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
+  (void)hipEventElapsedTime(&t03, ctx->ev[0], ctx->ev[3]);
+  ctx->timings[0] = t01; ctx->timings[1] = t12; ctx->timings[2] = t23; ctx->timings[3] = t03;
+  return STB_OK;
+}

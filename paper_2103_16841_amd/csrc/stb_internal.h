@@ -84,6 +84,17 @@ static inline void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
+// Shared steps (stb_lib.hip).
+stb_status stb_ensure_gl(stb_ctx* ctx, int ng);
+stb_status stb_check_params(stb_ctx* ctx, const stb_quad_params* p);
+stb_status stb_ensure_outer(stb_ctx* ctx, stb_mesh* m, int mq);
+// Conservative cull of rows (apex boxes) against all panels of m into CSR
+// candidates (rowptr, cols ascending per row) and the row of each candidate.
+stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, const stb_mesh* m,
+                    int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz);
+stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, const stb_mesh* m,
+                          int64_t* nnz);
+
 // 16-RHS product (stb_apply.hip): builds the blocked copy on first use.
 stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y, hipStream_t st);
 void stb_free_blocked(stb_mat* M);

@@ -49,7 +49,6 @@ stb_status stb_fail(stb_ctx* ctx, stb_status s, const char* fmt, ...) {
 }
 #define fail stb_fail
 
-static stb_status ensure_gl(stb_ctx* ctx, int ng);
 
 // ---------------------------------------------------------------- kernels
 
@@ -252,7 +251,7 @@ extern "C" stb_status stb_debug_pair(stb_ctx* ctx, const stb_mesh* mesh, int32_t
   if (!ctx || !mesh || !x4 || !out || panel < 0 || panel >= mesh->nt || ng < 2 || ng > kMaxNg)
     return stb_fail(ctx, STB_E_INVALID_ARG, "bad arguments");
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  stb_status s = ensure_gl(ctx, ng);
+  stb_status s = stb_ensure_gl(ctx, ng);
   if (s) return s;
   double *d_x = nullptr, *d_out = nullptr;
   HIPCHK(ctx, dalloc(&d_x, 4));
@@ -328,7 +327,7 @@ static void gauss_legendre01(int n, double* x, double* w) {
   }
 }
 
-static stb_status ensure_gl(stb_ctx* ctx, int ng) {
+stb_status stb_ensure_gl(stb_ctx* ctx, int ng) {
   if (ctx->gl_n == ng && ctx->d_gl) return STB_OK;
   double h[2 * kMaxNg] = {0};
   gauss_legendre01(ng, h, h + kMaxNg);
@@ -339,7 +338,7 @@ static stb_status ensure_gl(stb_ctx* ctx, int ng) {
   return STB_OK;
 }
 
-static stb_status check_params(stb_ctx* ctx, const stb_quad_params* p) {
+stb_status stb_check_params(stb_ctx* ctx, const stb_quad_params* p) {
   if (p->m_q < 1 || p->m_q > 4) return fail(ctx, STB_E_INVALID_ARG, "m_q must be in [1,4], got %d", p->m_q);
   if (p->n_g < 2 || p->n_g > kMaxNg) return fail(ctx, STB_E_INVALID_ARG, "n_g must be in [2,%d], got %d", kMaxNg, p->n_g);
   if (p->prec != STB_FP64 && p->prec != STB_MIXED) return fail(ctx, STB_E_INVALID_ARG, "bad precision");
@@ -348,7 +347,7 @@ static stb_status check_params(stb_ctx* ctx, const stb_quad_params* p) {
   return STB_OK;
 }
 
-static stb_status ensure_outer(stb_ctx* ctx, stb_mesh* m, int mq) {
+stb_status stb_ensure_outer(stb_ctx* ctx, stb_mesh* m, int mq) {
   if (m->mq == mq && m->d_opts) return STB_OK;
   dfree(m->d_opts); dfree(m->d_ow); dfree(m->d_onq); dfree(m->d_box);
   m->d_opts = nullptr; m->d_ow = nullptr; m->d_onq = nullptr; m->d_box = nullptr;
@@ -387,9 +386,33 @@ static stb_status device_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t
   return stb_exclusive_scan(ctx, in, out, n, ctx->stream);
 }
 
+// Number of candidates the cull would produce for these rows (count pass
+// only).
+stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
+                          int64_t* nnz) {
+  *nnz = 0;
+  if (nrows <= 0) return STB_OK;
+  int64_t *d_cnt = nullptr, *d_scan = nullptr;
+  HIPCHK(ctx, dalloc(&d_cnt, (size_t)nrows));
+  if (dalloc(&d_scan, (size_t)nrows + 1) != hipSuccess) {
+    dfree(d_cnt);
+    return fail(ctx, STB_E_NO_MEMORY, "cull counts");
+  }
+  hipLaunchKernelGGL(k_cull_count, dim3((unsigned)nrows), dim3(kCullThreads), 0, ctx->stream, nrows,
+                     d_rows, m->nt, m->d_trial, d_cnt);
+  hipError_t e = hipGetLastError();
+  stb_status s = e == hipSuccess ? device_exclusive_scan(ctx, d_cnt, d_scan, nrows)
+                                 : fail(ctx, STB_E_DEVICE, "cull count: %s", hipGetErrorString(e));
+  if (s == STB_OK && hipMemcpy(nnz, d_scan + nrows, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+    s = fail(ctx, STB_E_DEVICE, "cull count copy");
+  dfree(d_cnt);
+  dfree(d_scan);
+  return s;
+}
+
 // Cull rows (apex boxes) against all trial panels into CSR candidates, with
 // the row of every candidate alongside.
-static stb_status cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
+stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
                        int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz) {
   int64_t* d_cnt = nullptr;
   HIPCHK(ctx, dalloc(&d_cnt, (size_t)nrows));
@@ -581,18 +604,18 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
   if (mesh->ctx != ctx) return fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
   stb_quad_params p = params ? *params : stb_default_params();
-  stb_status s = check_params(ctx, &p);
+  stb_status s = stb_check_params(ctx, &p);
   if (s) return s;
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  if ((s = ensure_gl(ctx, p.n_g))) return s;
+  if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
   HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
-  if ((s = ensure_outer(ctx, mesh, p.m_q))) return s;
+  if ((s = stb_ensure_outer(ctx, mesh, p.m_q))) return s;
   HIPCHK(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
   stb_mat* M = new stb_mat();
   M->ctx = ctx;
   M->n = mesh->nt;
   int32_t* d_rowof = nullptr;
-  s = cull(ctx, mesh->nt, mesh->d_box, mesh, &M->d_rowptr, &M->d_cols, &d_rowof, &M->nnz);
+  s = stb_cull(ctx, mesh->nt, mesh->d_box, mesh, &M->d_rowptr, &M->d_cols, &d_rowof, &M->nnz);
   if (s) { dfree(d_rowof); stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
   if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess) {
@@ -748,7 +771,7 @@ stb_status stb_apply(stb_ctx* ctx, const stb_mat* M, int32_t nrhs, const double*
 static stb_status potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p,
                                  const double* d_w, int64_t np, const double* d_pts, double* d_out) {
   stb_status s;
-  if ((s = ensure_gl(ctx, p.n_g))) return s;
+  if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
   double* d_I = nullptr;
   ApexBox* d_box = nullptr;
   int64_t* d_rowptr = nullptr;
@@ -760,7 +783,7 @@ static stb_status potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_pa
   hipLaunchKernelGGL(k_point_boxes, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
                      d_pts, d_box);
   int64_t nnz = 0;
-  s = cull(ctx, np, d_box, mesh, &d_rowptr, &d_cols, &d_rowof, &nnz);
+  s = stb_cull(ctx, np, d_box, mesh, &d_rowptr, &d_cols, &d_rowof, &nnz);
   if (s) { cleanup(); return s; }
   if (dalloc(&d_I, (size_t)nnz) != hipSuccess) { cleanup(); return fail(ctx, STB_E_NO_MEMORY, "candidates"); }
   PairJob J;
@@ -795,7 +818,7 @@ stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_
   stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
   if (mesh->ctx != ctx) return fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
   stb_quad_params p = params ? *params : stb_default_params();
-  stb_status s = check_params(ctx, &p);
+  stb_status s = stb_check_params(ctx, &p);
   if (s) return s;
   if (np == 0) return STB_OK;
   for (int64_t i = 0; i < 4 * np; ++i)
@@ -827,7 +850,7 @@ stb_status stb_potential_S_dev(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_q
   stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
   if (mesh->ctx != ctx) return fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
   stb_quad_params p = params ? *params : stb_default_params();
-  stb_status s = check_params(ctx, &p);
+  stb_status s = stb_check_params(ctx, &p);
   if (s) return s;
   if (np == 0) return STB_OK;
   HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -840,14 +863,14 @@ stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_p
   if (!ctx || !mesh || k < 0 || (k > 0 && (!pts || !panel || !out)))
     return fail(ctx, STB_E_INVALID_ARG, "bad arguments");
   stb_quad_params p = params ? *params : stb_default_params();
-  stb_status s = check_params(ctx, &p);
+  stb_status s = stb_check_params(ctx, &p);
   if (s) return s;
   for (int64_t m = 0; m < k; ++m)
     if (panel[m] < 0 || panel[m] >= mesh->nt)
       return fail(ctx, STB_E_INVALID_ARG, "panel index %d out of range", panel[m]);
   if (k == 0) return STB_OK;
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  if ((s = ensure_gl(ctx, p.n_g))) return s;
+  if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
   double *d_pts = nullptr, *d_out = nullptr;
   int32_t* d_pan = nullptr;
   if (dalloc(&d_pts, (size_t)k * 4) != hipSuccess || dalloc(&d_out, (size_t)k) != hipSuccess ||

@@ -18,6 +18,11 @@ struct PairJob {
   double eta_far = 2.0;              // far: apex farther than eta_far radii from the panel's ball
   double* out = nullptr;             // [nnz] matrix entry or inner integral
   unsigned long long* n_causal = nullptr;   // host: += candidates with a lit apex
+  // optional segments of the candidate range (batches of meshes): candidate
+  // offsets [nseg + 1] and per-segment causal counts [nseg], both device
+  int nseg = 0;
+  const int64_t* seg_off = nullptr;
+  unsigned long long* seg_causal = nullptr;
 };
 
 // Runs the pipeline; work[0..3] receive L evaluations, lit combos, apexes

@@ -438,11 +438,24 @@ __global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo) {
 // values.  Causal pairs are counted when check = 0.
 constexpr double kMixedTol = 5e-6;
 
+// Segment of global candidate cg: last s with off[s] <= cg.
+__device__ __forceinline__ int seg_of(const int64_t* off, int nseg, int64_t cg) {
+  int lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= cg) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(kBlk) void k_store(Geo g, Lists L, int64_t c0, int64_t nc,
-                                                double* __restrict__ out, int check) {
+                                                double* __restrict__ out, int check, int nseg,
+                                                const int64_t* __restrict__ seg_off,
+                                                unsigned long long* __restrict__ seg_causal) {
   unsigned long long causal = 0, redo = 0;
   for (int64_t base = (int64_t)blockIdx.x * kBlk; base < nc; base += (int64_t)gridDim.x * kBlk) {
     const int64_t c = base + threadIdx.x;
+    bool is_causal = false;
     if (c < nc) {
       const uint64_t m = L.mask[c];
       int32_t idx = L.combo0[c];
@@ -468,6 +481,23 @@ __global__ __launch_bounds__(kBlk) void k_store(Geo g, Lists L, int64_t c0, int6
         redo += r ? 1ull : 0ull;
       } else {
         causal += m ? 1ull : 0ull;
+        is_causal = m != 0;
+      }
+    }
+    if (seg_off && !check) {
+      // per-segment counts: one atomic per wave unless the wave straddles
+      // a segment boundary (candidates of a wave are consecutive)
+      const int lane = threadIdx.x & 63;
+      const int64_t cf = c0 + base + (threadIdx.x & ~63);
+      const int64_t cl = std::min<int64_t>(cf + 63, c0 + nc - 1);
+      const uint64_t bal = __ballot(is_causal);
+      if (cf <= cl) {
+        const int sa = seg_of(seg_off, nseg, cf), sb = seg_of(seg_off, nseg, cl);
+        if (sa == sb) {
+          if (lane == 0 && bal) atomicAdd(seg_causal + sa, (unsigned long long)__popcll(bal));
+        } else if (is_causal) {
+          atomicAdd(seg_causal + seg_of(seg_off, nseg, c0 + c), 1ull);
+        }
       }
     }
   }
@@ -686,7 +716,7 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     }
     const bool check = g.mixed && g.apex_w && njob32;
     hipLaunchKernelGGL(k_store, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc, job.out,
-                       check ? 1 : 0);
+                       check ? 1 : 0, job.nseg, job.seg_off, job.seg_causal);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(6));
     if (check) {
@@ -709,7 +739,8 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       HIPCHK(ctx, t0(3));
       if (njr)
         hipLaunchKernelGGL(k_combine, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, L, (int64_t)ncombo);
-      hipLaunchKernelGGL(k_store, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc, job.out, 0);
+      hipLaunchKernelGGL(k_store, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc, job.out, 0,
+                         job.nseg, job.seg_off, job.seg_causal);
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(3));
     }

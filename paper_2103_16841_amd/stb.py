@@ -22,7 +22,7 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
            "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
            "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_mesh_create_dev",
-           "stb_last_kernel_times", "stb_mat_export"]
+           "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble"]
 
 KERNEL_KINDS = ["lit", "breakpoints", "empty_test", "mixed_restore", "nodes_fp64", "nodes_fp32",
                 "sums_store", "mixed_redo_nodes"]
@@ -85,6 +85,9 @@ def load():
     L.stb_last_work.argtypes = [_VP, _I64]
     L.stb_last_kernel_times.argtypes = [_VP, _D, _I64, _I64]
     L.stb_mat_export.argtypes = [_VP, _I64, _I32, _D]
+    L.stb_batch_assemble.argtypes = [_VP, i32, ctypes.POINTER(_VP), ctypes.POINTER(QuadParams),
+                                     i64, ctypes.POINTER(_VP), i32, ctypes.POINTER(_VP),
+                                     ctypes.POINTER(_VP)]
     L.stb_mesh_create_dev.argtypes = [_VP, i64, _VP, i64, _VP, _VP, ctypes.POINTER(_VP)]
     L.stb_potential_S_dev.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _VP, i64, _VP, _VP,
                                       _VP]
@@ -246,6 +249,21 @@ class Matrix:
         """Device-pointer product (e.g. torch tensors' data_ptr())."""
         _chk(load().stb_apply_dev(self.ctx.h, self.h, nrhs, _VP(w_ptr), _VP(y_ptr),
                                   _VP(stream) if stream else None), self.ctx.h)
+
+
+def batch_assemble(ctx, meshes, params=None, hbm_budget=0, keep=True, W_ptrs=None, Y_ptrs=None,
+                   nrhs=16):
+    """Assemble several meshes in one pass of the pair pipeline.  keep: return
+    the matrices; W_ptrs/Y_ptrs: device pointers per mesh for Y_m = A_m W_m."""
+    p = params if params is not None else default_params()
+    n = len(meshes)
+    hs = (_VP * n)(*[m.h for m in meshes])
+    outs = (_VP * n)() if keep else None
+    W = (_VP * n)(*[_VP(x) for x in W_ptrs]) if W_ptrs is not None else None
+    Y = (_VP * n)(*[_VP(x) for x in Y_ptrs]) if Y_ptrs is not None else None
+    _chk(load().stb_batch_assemble(ctx.h, n, hs, ctypes.byref(p), hbm_budget, outs, nrhs, W, Y),
+         ctx.h)
+    return [Matrix(ctx, _VP(outs[k])) for k in range(n)] if keep else None
 
 
 def assemble_V(ctx, mesh, params=None):
