@@ -166,11 +166,75 @@ stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_p
  * inputs and outputs, Y_m = A_m W_m computed after the mesh's wave (nrhs = 16:
  * FP32 matrix cores), so that a batch larger than HBM can be assembled and
  * applied without keeping its matrices.  At least one of mats and W_dev/Y_dev
- * must be given.  Results are identical to per-mesh stb_assemble_V calls.
+ * must be given.  n_causal (optional, host, nmesh entries): causal pairs
+ * per mesh.  Results are identical to per-mesh stb_assemble_V calls.
  * Timings, work and kernel times describe the whole batch. */
 stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* const* meshes,
                               const stb_quad_params* params, int64_t hbm_budget, stb_mat** mats,
-                              int32_t nrhs, const double* const* W_dev, double* const* Y_dev);
+                              int32_t nrhs, const double* const* W_dev, double* const* Y_dev,
+                              int64_t* n_causal);
+
+/* Launch-shape autotuner of the pair pipeline: times every stage (lit
+ * test, breakpoints, empty-piece test, FP64 and FP32 Gauss nodes) on a
+ * strided sample of about 2^20 of mesh's (test, trial) candidates for each
+ * threads-per-block in {64, 128, 256} and resident blocks per CU in
+ * {4, 8, 16, 32}, keeps the fastest per stage in ctx (used by every later
+ * assembly, potential and batch on ctx) and, when cfg16 is not NULL, writes
+ * the choice: cfg16[k] threads per block and cfg16[8 + k] blocks per CU of
+ * stage k (numbered as in stb_last_kernel_times).  stb_batch_assemble runs
+ * it on its largest mesh when ctx has not been tuned. */
+stb_status stb_autotune(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                        int32_t* cfg16);
+
+/* Set the launch shapes (cfg16 as written by stb_autotune; block sizes
+ * multiples of 64 in [64, 256], 1..64 blocks per CU), or restore the
+ * defaults (256 threads, 16 blocks per CU) with cfg16 = NULL. */
+stb_status stb_set_tuning(stb_ctx* ctx, const int32_t* cfg16);
+
+/* ------------------------------------------------------------ serving
+ * A server answers matvec and potential requests on meshes (and their
+ * matrices) resident on one device, with continuous batching: nslots worker
+ * slots, each with its own stream and workspace, take requests in arrival
+ * order; a request starts as soon as a slot is free and its device
+ * footprint (inputs, outputs and, for a potential, its exact candidate
+ * arrays) fits hbm_budget_bytes beside the requests in flight (0: half of
+ * the free device memory).  Requests in different slots run concurrently
+ * on the device.  Results do not depend on what else is in flight.
+ * stb_server_submit and stb_server_wait are thread-safe. */
+typedef struct stb_server stb_server;
+
+typedef enum { STB_REQ_MATVEC16 = 0, STB_REQ_POTENTIAL = 1 } stb_request_kind;
+
+/* kind STB_REQ_MATVEC16: out (n x 16, row-major) = A w, w n x 16 row-major,
+ *   A the matrix registered with the mesh (FP32 matrix cores).
+ * kind STB_REQ_POTENTIAL: out[k] = S w (pts[k]) for np points (t, x, y, z),
+ *   w the density (n values), FP64 (default quadrature parameters).
+ * All pointers are host memory owned by the caller and must stay valid until
+ * stb_server_wait for the ticket returns; out is written before that. */
+typedef struct {
+  int32_t kind;
+  int32_t mesh;        /* id from stb_server_add_mesh */
+  int64_t np;
+  const double* w;
+  const double* pts;
+  double* out;
+} stb_request;
+
+stb_status stb_server_create(stb_ctx* ctx, int64_t hbm_budget_bytes, int32_t nslots,
+                             stb_server** out);
+/* Register a mesh of ctx and, for matvec requests, its matrix (both stay
+ * owned by the caller and must outlive the server); *id receives the id. */
+stb_status stb_server_add_mesh(stb_server* server, const stb_mesh* mesh, const stb_mat* mat,
+                               int32_t* id);
+/* Queue a request (the descriptor is copied, the data is not); *ticket
+ * receives its ticket.  STB_E_NOT_FOUND for an unknown mesh id. */
+stb_status stb_server_submit(stb_server* server, const stb_request* req, uint64_t* ticket);
+/* Block until the request completes; returns its status (STB_E_NO_MEMORY if
+ * its footprint exceeds the whole budget) and, if latency_s is not NULL, the
+ * time from submit to completion in seconds.  Wait for each ticket once. */
+stb_status stb_server_wait(stb_server* server, uint64_t ticket, double* latency_s);
+/* Finish the queued and running requests, then release the server. */
+void stb_server_destroy(stb_server* server);
 
 /* Timing of the last stb_assemble_V on ctx, in milliseconds measured with
  * HIP events on the context stream: [0] geometry/outer points, [1] cull and

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t 
     }
 }
 
-static stb_status build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st) {
+stb_status stb_build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st) {
   const int64_t n = M->n;
   if (n > kMaxBlockedN)
     return stb_fail(ctx, STB_E_INVALID_ARG, "16-RHS product supports n <= %lld", (long long)kMaxBlockedN);
@@ -178,7 +178,7 @@ static stb_status build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st) {
 
 stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y, hipStream_t st) {
   if (!M->d_bptr) {
-    stb_status s = build_blocked(ctx, M, st);
+    stb_status s = stb_build_blocked(ctx, M, st);
     if (s) return s;
   }
   float* w32 = nullptr;

@@ -20,10 +20,23 @@
 
 using namespace stb;
 
+extern "C" stb_status stb_autotune(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                                   int32_t* cfg16);
+
 __global__ void k_shift_idx(int64_t n, const int32_t* __restrict__ in, int32_t add,
                             int32_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = in[i] + add;
+}
+
+__global__ void k_gather_stride(int64_t n, int64_t stride, const int32_t* __restrict__ rows,
+                                const int32_t* __restrict__ cols, int32_t* __restrict__ rs,
+                                int32_t* __restrict__ cs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    rs[i] = rows[i * stride];
+    cs[i] = cols[i * stride];
+  }
 }
 
 namespace {
@@ -56,7 +69,7 @@ void release(std::vector<WaveMesh>& w, bool keep) {
 extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* const* meshes,
                                          const stb_quad_params* params, int64_t hbm_budget,
                                          stb_mat** mats, int32_t nrhs, const double* const* W_dev,
-                                         double* const* Y_dev) {
+                                         double* const* Y_dev, int64_t* n_causal) {
   if (!ctx || nmesh < 1 || !meshes) return stb_fail(ctx, STB_E_INVALID_ARG, "bad arguments");
   if (!mats && !(W_dev && Y_dev)) return stb_fail(ctx, STB_E_INVALID_ARG, "nothing to return");
   if ((W_dev || Y_dev) && (!W_dev || !Y_dev || nrhs < 1))
@@ -78,6 +91,12 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
   for (int k = 0; k < nmesh; ++k)
     if ((s = stb_ensure_outer(ctx, meshes[k], p.m_q))) return s;
   const int maxq = meshes[0]->maxq;
+  if (!ctx->tuned) {
+    int big = 0;
+    for (int k = 1; k < nmesh; ++k)
+      if (meshes[k]->nt > meshes[big]->nt) big = k;
+    if ((s = stb_autotune(ctx, meshes[big], &p, nullptr))) return s;
+  }
   if (hbm_budget == 0) {
     size_t fr = 0, tot = 0;
     HIPCHK(ctx, hipMemGetInfo(&fr, &tot));
@@ -214,7 +233,10 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
                                    hipMemcpyDeviceToDevice, st));
     }
     HIPCHK(ctx, hipStreamSynchronize(st));
-    for (size_t m = 0; m < w.size(); ++m) w[m].M->n_causal = (int64_t)h_causal[m];
+    for (size_t m = 0; m < w.size(); ++m) {
+      w[m].M->n_causal = (int64_t)h_causal[m];
+      if (n_causal) n_causal[w[m].idx] = (int64_t)h_causal[m];
+    }
     // products, then release (or hand over) the wave's stores
     for (size_t m = 0; m < w.size() && W_dev; ++m) {
       WaveMesh& x = w[m];
@@ -241,5 +263,78 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
   (void)hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
   (void)hipEventElapsedTime(&t03, ctx->ev[0], ctx->ev[3]);
   ctx->timings[0] = t01; ctx->timings[1] = t12; ctx->timings[2] = t23; ctx->timings[3] = t03;
+  return STB_OK;
+}
+
+// Autotune the pair pipeline on a strided sample (about 2^20 candidates) of
+// one mesh's assembly.
+extern "C" stb_status stb_autotune(stb_ctx* ctx, const stb_mesh* mesh_c,
+                                   const stb_quad_params* params, int32_t* cfg16) {
+  if (!ctx || !mesh_c) return stb_fail(ctx, STB_E_INVALID_ARG, "NULL argument");
+  stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
+  if (mesh->ctx != ctx) return stb_fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
+  stb_quad_params p = params ? *params : stb_default_params();
+  stb_status s = stb_check_params(ctx, &p);
+  if (s) return s;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
+  if ((s = stb_ensure_outer(ctx, mesh, p.m_q))) return s;
+  int64_t *rowptr = nullptr;
+  int32_t *cols = nullptr, *rowof = nullptr, *rs = nullptr, *cs = nullptr;
+  double* out = nullptr;
+  int64_t nnz = 0;
+  auto cleanup = [&]() { dfree(rowptr); dfree(cols); dfree(rowof); dfree(rs); dfree(cs); dfree(out); };
+  s = stb_cull(ctx, mesh->nt, mesh->d_box, mesh, &rowptr, &cols, &rowof, &nnz);
+  if (s) { cleanup(); return s; }
+  const int64_t want = (int64_t)1 << 20;
+  const int64_t stride = std::max<int64_t>(1, nnz / want);
+  const int64_t n = nnz / stride;
+  if (n > 0) {
+    if (dalloc(&rs, (size_t)n) != hipSuccess || dalloc(&cs, (size_t)n) != hipSuccess ||
+        dalloc(&out, (size_t)n) != hipSuccess) {
+      cleanup();
+      return stb_fail(ctx, STB_E_NO_MEMORY, "autotune sample");
+    }
+    hipLaunchKernelGGL(k_gather_stride, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n,
+                       stride, rowof, cols, rs, cs);
+    PairJob J;
+    J.nnz = n;
+    J.rows = rs;
+    J.cols = cs;
+    J.trial = mesh->d_trial;
+    J.apex = mesh->d_opts;
+    J.apex_w = mesh->d_ow;
+    J.apex_n = mesh->d_onq;
+    J.maxq = mesh->maxq;
+    J.gl = ctx->d_gl;
+    J.ng = p.n_g;
+    J.mixed = p.prec == STB_MIXED;
+    J.eta_far = p.eta_far;
+    J.out = out;
+    s = stb_tune_pairs(ctx, J);
+  }
+  cleanup();
+  if (s) return s;
+  ctx->tuned = true;
+  if (cfg16)
+    for (int k = 0; k < 8; ++k) {
+      cfg16[k] = ctx->tune_block[k];
+      cfg16[8 + k] = ctx->tune_per_cu[k];
+    }
+  return STB_OK;
+}
+
+extern "C" stb_status stb_set_tuning(stb_ctx* ctx, const int32_t* cfg16) {
+  if (!ctx) return stb_fail(nullptr, STB_E_INVALID_ARG, "NULL context");
+  for (int k = 0; k < 8; ++k) {
+    int b = cfg16 ? cfg16[k] : 256, pc = cfg16 ? cfg16[8 + k] : 16;
+    if (b < 64 || b > 256 || (b & 63) || pc < 1 || pc > 64)
+      return stb_fail(ctx, STB_E_INVALID_ARG, "stage %d: block %d / blocks per CU %d out of range", k, b, pc);
+  }
+  for (int k = 0; k < 8; ++k) {
+    ctx->tune_block[k] = cfg16 ? cfg16[k] : 256;
+    ctx->tune_per_cu[k] = cfg16 ? cfg16[8 + k] : 16;
+  }
+  ctx->tuned = cfg16 != nullptr;
   return STB_OK;
 }

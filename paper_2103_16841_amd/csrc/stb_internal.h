@@ -21,6 +21,12 @@ struct stb_ctx {
   double kern_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t kern_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t kern_units[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // launch shapes of the pair pipeline's stages (autotuned or defaults):
+  // threads per block and blocks per compute unit, indexed like kern_ms
+  int tune_block[8] = {256, 256, 256, 256, 256, 256, 256, 256};
+  int tune_per_cu[8] = {16, 16, 16, 16, 16, 16, 16, 16};
+  bool tuned = false;
+  int ncu = 0;
   // Gauss-Legendre nodes on [0,1] for the last n_g used (device copy)
   int gl_n = 0;
   double* d_gl = nullptr;   // [2 * kMaxNg]: x then w
@@ -94,8 +100,15 @@ stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, con
                     int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz);
 stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, const stb_mesh* m,
                           int64_t* nnz);
+void stb_point_boxes(stb_ctx* ctx, int64_t np, const double* d_pts, stb::ApexBox* d_box);
+
+// Potential with device inputs/outputs on ctx's stream and workspace (the
+// mesh may belong to another context of the same device).
+stb_status stb_potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p,
+                              const double* d_w, int64_t np, const double* d_pts, double* d_out);
 
 // 16-RHS product (stb_apply.hip): builds the blocked copy on first use.
+stb_status stb_build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st);
 stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y, hipStream_t st);
 void stb_free_blocked(stb_mat* M);
 // Exclusive prefix sum of n counts into out[0..n] (device memory); syncs st.

@@ -386,6 +386,13 @@ static stb_status device_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t
   return stb_exclusive_scan(ctx, in, out, n, ctx->stream);
 }
 
+// Apex boxes of evaluation points (enqueued on ctx's stream).
+void stb_point_boxes(stb_ctx* ctx, int64_t np, const double* d_pts, ApexBox* d_box) {
+  if (np > 0)
+    hipLaunchKernelGGL(k_point_boxes, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
+                       d_pts, d_box);
+}
+
 // Number of candidates the cull would produce for these rows (count pass
 // only).
 stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
@@ -767,9 +774,11 @@ stb_status stb_apply(stb_ctx* ctx, const stb_mat* M, int32_t nrhs, const double*
   return s;
 }
 
+}  // extern "C"
+
 // Potential with device inputs and output, on the context stream.
-static stb_status potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p,
-                                 const double* d_w, int64_t np, const double* d_pts, double* d_out) {
+stb_status stb_potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p,
+                              const double* d_w, int64_t np, const double* d_pts, double* d_out) {
   stb_status s;
   if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
   double* d_I = nullptr;
@@ -811,6 +820,8 @@ static stb_status potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_pa
   return STB_OK;
 }
 
+extern "C" {
+
 stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_params* params,
                            const double* w, int64_t np, const double* pts, double* out) {
   if (!ctx || !mesh_c || !w || (np > 0 && (!pts || !out)) || np < 0)
@@ -832,7 +843,7 @@ stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_
   }
   hipError_t e = hipMemcpyAsync(d_pts, pts, sizeof(double) * 4 * np, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(d_w, w, sizeof(double) * mesh->nt, hipMemcpyHostToDevice, ctx->stream);
-  s = e == hipSuccess ? potential_core(ctx, mesh, p, d_w, np, d_pts, d_out)
+  s = e == hipSuccess ? stb_potential_core(ctx, mesh, p, d_w, np, d_pts, d_out)
                       : fail(ctx, STB_E_DEVICE, "copy failed");
   if (s == STB_OK) {
     e = hipMemcpy(out, d_out, sizeof(double) * np, hipMemcpyDeviceToHost);
@@ -855,7 +866,7 @@ stb_status stb_potential_S_dev(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_q
   if (np == 0) return STB_OK;
   HIPCHK(ctx, hipSetDevice(ctx->device));
   if (stream) HIPCHK(ctx, hipStreamSynchronize((hipStream_t)stream));
-  return potential_core(ctx, mesh, p, w_dev, np, pts_dev, out_dev);
+  return stb_potential_core(ctx, mesh, p, w_dev, np, pts_dev, out_dev);
 }
 
 stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,

@@ -29,3 +29,5 @@ struct PairJob {
 // tested and pieces.  Synchronises the context stream.
 stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long work[4]);
 void stb_free_workspace(stb_ctx* ctx);
+// Chooses the launch shape of every stage on a sample job (see stb_pairs.hip).
+stb_status stb_tune_pairs(stb_ctx* ctx, const PairJob& sample);

@@ -76,7 +76,7 @@ __device__ __forceinline__ unsigned long long block_alloc(unsigned long long* ct
   if (threadIdx.x == 0) {
     unsigned run = 0;
 #pragma unroll
-    for (int w = 0; w < kBlk / 64; ++w) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
       unsigned t = sh.wtot[w];
       sh.wtot[w] = run;
       run += t;
@@ -153,9 +153,10 @@ struct Geo {
 };
 
 __global__ __launch_bounds__(kBlk) void k_lit(Geo g, Lists L, int64_t c0, int64_t nc) {
+  const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
   unsigned long long pairs = 0;
-  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < nc; base += (int64_t)gridDim.x * kBlk) {
+  for (int64_t base = (int64_t)blockIdx.x * B; base < nc; base += (int64_t)gridDim.x * B) {
     const int64_t c = base + threadIdx.x;
     const bool v = c < nc;
     uint64_t m = 0;
@@ -191,8 +192,9 @@ __global__ __launch_bounds__(kBlk) void k_lit(Geo g, Lists L, int64_t c0, int64_
 }
 
 __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t ncombo) {
+  const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
-  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < ncombo; base += (int64_t)gridDim.x * kBlk) {
+  for (int64_t base = (int64_t)blockIdx.x * B; base < ncombo; base += (int64_t)gridDim.x * B) {
     const int64_t k = base + threadIdx.x;
     const bool v = k < ncombo;
     double bp[kMaxBp];
@@ -259,26 +261,27 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
 }
 
 // The empty-piece test, kEmptyPer pieces per thread and pass (coalesced:
-// piece base + j kBlk + tid), so that one list allocation covers
-// kEmptyPer * kBlk pieces.  L at the midpoint first; the pieces where it is
+// piece base + j B + tid, B the block size), so that one list allocation
+// covers kEmptyPer * B pieces.  L at the midpoint first; the pieces where it is
 // zero go to a block-local LDS queue whose quarter-point evaluations are
 // then shared by all lanes of the block (dense, and on combo data the block
 // has just read).
 constexpr int kEmptyPer = 8;
 
 __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
+  const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
   __shared__ int32_t s_q[kEmptyPer * kBlk];
   __shared__ int s_nq;
   unsigned long long ev_mid = 0, ev_quarter = 0;
-  const int64_t step = (int64_t)gridDim.x * kBlk * kEmptyPer;
-  for (int64_t base = (int64_t)blockIdx.x * kBlk * kEmptyPer; base < npiece; base += step) {
+  const int64_t step = (int64_t)gridDim.x * B * kEmptyPer;
+  for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < npiece; base += step) {
     if (threadIdx.x == 0) s_nq = 0;
     __syncthreads();
     unsigned ne = 0;
 #pragma unroll 1
     for (int j = 0; j < kEmptyPer; ++j) {
-      const int64_t p = base + (int64_t)j * kBlk + threadIdx.x;
+      const int64_t p = base + (int64_t)j * B + threadIdx.x;
       if (p >= npiece) break;
       const double H = L.ph[p];
       bool nz = true;   // trapezoid half (H < 0): always evaluated
@@ -294,11 +297,11 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
     }
     __syncthreads();
     const int nq = s_nq;
-    // quarter points of the queued pieces; thread tid owns entries tid + m kBlk
+    // quarter points of the queued pieces; thread tid owns entries tid + m B
     unsigned qne = 0;
 #pragma unroll 1
     for (int m = 0; m < kEmptyPer; ++m) {
-      const int e = m * kBlk + threadIdx.x;
+      const int e = m * B + threadIdx.x;
       if (e >= nq) break;
       const int32_t p = s_q[e];
       const ComboL cb = load_combo(L, L.pc[p]);
@@ -312,23 +315,23 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
     unsigned far = 0, qfar = 0;
     for (int j = 0; j < kEmptyPer; ++j)
       if ((ne >> j) & 1u) {
-        const int64_t p = base + (int64_t)j * kBlk + threadIdx.x;
+        const int64_t p = base + (int64_t)j * B + threadIdx.x;
         far |= ((L.key[L.pc[p]] >> 7) & 1u) << j;
       }
     for (int m = 0; m < kEmptyPer; ++m)
-      if ((qne >> m) & 1u) qfar |= ((L.key[L.pc[s_q[m * kBlk + threadIdx.x]]] >> 7) & 1u) << m;
+      if ((qne >> m) & 1u) qfar |= ((L.key[L.pc[s_q[m * B + threadIdx.x]]] >> 7) & 1u) << m;
     const unsigned n64 = __popc(ne & ~far) + __popc(qne & ~qfar);
     const unsigned n32 = __popc(ne & far) + __popc(qne & qfar);
     unsigned long long s = block_alloc(L.cnt + CNT_JOB, n64, sh);
     unsigned long long s32 = block_alloc(L.cnt + CNT_JOB32, n32, sh);
     for (int j = 0; j < kEmptyPer; ++j) {
       if (!((ne >> j) & 1u)) continue;
-      const int32_t p = (int32_t)(base + (int64_t)j * kBlk + threadIdx.x);
+      const int32_t p = (int32_t)(base + (int64_t)j * B + threadIdx.x);
       if ((far >> j) & 1u) L.job32[s32++] = p; else L.job[s++] = p;
     }
     for (int m = 0; m < kEmptyPer; ++m) {
       if (!((qne >> m) & 1u)) continue;
-      const int32_t p = s_q[m * kBlk + threadIdx.x];
+      const int32_t p = s_q[m * B + threadIdx.x];
       if ((qfar >> m) & 1u) L.job32[s32++] = p; else L.job[s++] = p;
     }
   }
@@ -343,9 +346,10 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
 __global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, const int32_t* __restrict__ jobs,
                                                    int64_t njob, const double* __restrict__ gl,
                                                    int ng, int ctr) {
+  const int B = (int)blockDim.x;
   unsigned long long evals = 0;
   const double ht = kTwoPi / (2 * ng);
-  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < njob; base += (int64_t)gridDim.x * kBlk) {
+  for (int64_t base = (int64_t)blockIdx.x * B; base < njob; base += (int64_t)gridDim.x * B) {
     const int64_t k = base + threadIdx.x;
     if (k >= njob) continue;
     const int32_t p = jobs[k];
@@ -372,9 +376,10 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, const int32_t* __res
 // FP32 (L_eval_far), node sum in FP32 with Kahan compensation.
 __global__ __launch_bounds__(kBlk, 4) void k_nodes32(Lists L, int64_t njob,
                                                      const double* __restrict__ gl, int ng) {
+  const int B = (int)blockDim.x;
   unsigned long long evals = 0;
   const double ht = kTwoPi / (2 * ng);
-  for (int64_t base = (int64_t)blockIdx.x * kBlk; base < njob; base += (int64_t)gridDim.x * kBlk) {
+  for (int64_t base = (int64_t)blockIdx.x * B; base < njob; base += (int64_t)gridDim.x * B) {
     const int64_t k = base + threadIdx.x;
     if (k >= njob) continue;
     const int32_t p = L.job32[k];
@@ -533,9 +538,9 @@ __global__ __launch_bounds__(kBlk) void k_redo(Geo g, Lists L, int64_t nc) {
   }
 }
 
-unsigned grid_for(int64_t n, int per = 1) {
-  int64_t b = (n + (int64_t)kBlk * per - 1) / ((int64_t)kBlk * per);
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, kMaxBlocks));
+unsigned grid_for(int64_t n, int per = 1, int block = kBlk, int64_t max_blocks = kMaxBlocks) {
+  int64_t b = (n + (int64_t)block * per - 1) / ((int64_t)block * per);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, max_blocks));
 }
 
 }  // namespace
@@ -659,13 +664,22 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
   // brackets a launch of kernel kind k with events (per chunk, read after
   // the chunk's synchronisation)
   auto t0 = [&](int k) { used[k] = true; return hipEventRecord(ctx->kev[2 * k], st); };
+  if (!ctx->ncu) {
+    HIPCHK(ctx, hipDeviceGetAttribute(&ctx->ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    if (ctx->ncu < 1) ctx->ncu = 1;
+  }
+  // grid of stage k: enough blocks for n items (per items per thread), at
+  // most the stage's blocks per CU times the CU count
+  auto gfor = [&](int k, unsigned long long n, int per = 1) {
+    return grid_for((int64_t)n, per, ctx->tune_block[k], (int64_t)ctx->tune_per_cu[k] * ctx->ncu);
+  };
   auto t1 = [&](int k) { return hipEventRecord(ctx->kev[2 * k + 1], st); };
   while (c0 < job.nnz) {
     const int64_t nc = std::min<int64_t>(chunk, job.nnz - c0);
     for (auto& u : used) u = false;
     HIPCHK(ctx, hipMemsetAsync(L.cnt, 0, CNT_N * 8, st));
     HIPCHK(ctx, t0(0));
-    hipLaunchKernelGGL(k_lit, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc);
+    hipLaunchKernelGGL(k_lit, dim3(gfor(0, nc)), dim3(ctx->tune_block[0]), 0, st, g, L, c0, nc);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(0));
     unsigned long long ncombo = 0, npiece = 0, njob = 0;
@@ -676,7 +690,8 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       continue;
     }
     HIPCHK(ctx, t0(1));
-    hipLaunchKernelGGL(k_bp, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, g, L, c0, (int64_t)ncombo);
+    hipLaunchKernelGGL(k_bp, dim3(gfor(1, ncombo)), dim3(ctx->tune_block[1]), 0, st, g, L, c0,
+                       (int64_t)ncombo);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(1));
     if ((s = rd(CNT_PIECE, &npiece))) return s;
@@ -687,7 +702,7 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     }
     if (npiece) {
       HIPCHK(ctx, t0(2));
-      hipLaunchKernelGGL(k_empty, dim3(grid_for(npiece, kEmptyPer)), dim3(kBlk), 0, st, L,
+      hipLaunchKernelGGL(k_empty, dim3(gfor(2, npiece, kEmptyPer)), dim3(ctx->tune_block[2]), 0, st, L,
                          (int64_t)npiece);
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(2));
@@ -697,14 +712,16 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     if (g.mixed && (s = rd(CNT_JOB32, &njob32))) return s;
     if (njob) {
       HIPCHK(ctx, t0(4));
-      hipLaunchKernelGGL(k_nodes, dim3(grid_for(njob)), dim3(kBlk), 0, st, L, L.job, (int64_t)njob,
+      hipLaunchKernelGGL(k_nodes, dim3(gfor(4, njob)), dim3(ctx->tune_block[4]), 0, st, L, L.job,
+                         (int64_t)njob,
                          job.gl, job.ng, (int)CNT_EVAL_NODES);
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(4));
     }
     if (njob32) {
       HIPCHK(ctx, t0(5));
-      hipLaunchKernelGGL(k_nodes32, dim3(grid_for(njob32)), dim3(kBlk), 0, st, L, (int64_t)njob32,
+      hipLaunchKernelGGL(k_nodes32, dim3(gfor(5, njob32)), dim3(ctx->tune_block[5]), 0, st, L,
+                         (int64_t)njob32,
                          job.gl, job.ng);
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(5));
@@ -731,7 +748,8 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       }
       if (njr) {
         HIPCHK(ctx, t0(7));
-        hipLaunchKernelGGL(k_nodes, dim3(grid_for(njr)), dim3(kBlk), 0, st, L, L.job, (int64_t)njr,
+        hipLaunchKernelGGL(k_nodes, dim3(gfor(4, njr)), dim3(ctx->tune_block[4]), 0, st, L, L.job,
+                           (int64_t)njr,
                            job.gl, job.ng, (int)CNT_EVAL_REDO);
         HIPCHK(ctx, hipGetLastError());
         HIPCHK(ctx, t1(7));
@@ -775,5 +793,42 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     int64_t next = (int64_t)((double)nc * std::min(fc, fp) * 0.7);
     chunk = std::max<int64_t>(1, std::min<int64_t>(next, w->cap_cand));
   }
+  return STB_OK;
+}
+
+// Launch-shape autotuner.  The flat lists make every stage a loop over
+// items of one cost class (apexes to test, lit combos, pieces, Gauss jobs),
+// so what is left to tune per stage is the launch shape: threads per block
+// (64, 128, 256) and resident blocks per CU (4, 8, 16, 32), which trade
+// latency hiding against tail effects and L2 locality of neighbouring
+// items.  Each stage is timed on the sample (HIP events) for every shape
+// with the other stages at their current choice, in order of their share of
+// the time; the fastest shape is kept in the context.
+stb_status stb_tune_pairs(stb_ctx* ctx, const PairJob& sample) {
+  static const int kStages[] = {4, 5, 2, 1, 0};
+  static const int kBlocks[] = {64, 128, 256};
+  static const int kPerCu[] = {4, 8, 16, 32};
+  unsigned long long work[4];
+  stb_status s = stb_run_pairs(ctx, sample, work);   // warm-up, lists sized
+  if (s) return s;
+  for (int stage : kStages) {
+    if (ctx->kern_n[stage] == 0) continue;   // stage unused on this sample
+    double best = 1e300;
+    int bb = ctx->tune_block[stage], bp = ctx->tune_per_cu[stage];
+    for (int b : kBlocks)
+      for (int pc : kPerCu) {
+        ctx->tune_block[stage] = b;
+        ctx->tune_per_cu[stage] = pc;
+        if ((s = stb_run_pairs(ctx, sample, work))) return s;
+        if (ctx->kern_ms[stage] < best) {
+          best = ctx->kern_ms[stage];
+          bb = b;
+          bp = pc;
+        }
+      }
+    ctx->tune_block[stage] = bb;
+    ctx->tune_per_cu[stage] = bp;
+  }
+  ctx->tuned = true;
   return STB_OK;
 }

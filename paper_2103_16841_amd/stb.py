@@ -22,7 +22,11 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
            "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
            "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_mesh_create_dev",
-           "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble"]
+           "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble", "stb_autotune",
+           "stb_set_tuning", "stb_server_create", "stb_server_add_mesh", "stb_server_submit",
+           "stb_server_wait", "stb_server_destroy"]
+
+STB_REQ_MATVEC16, STB_REQ_POTENTIAL = 0, 1
 
 KERNEL_KINDS = ["lit", "breakpoints", "empty_test", "mixed_restore", "nodes_fp64", "nodes_fp32",
                 "sums_store", "mixed_redo_nodes"]
@@ -31,6 +35,11 @@ KERNEL_KINDS = ["lit", "breakpoints", "empty_test", "mixed_restore", "nodes_fp64
 class QuadParams(ctypes.Structure):
     _fields_ = [("m_q", ctypes.c_int32), ("n_g", ctypes.c_int32), ("eta_far", ctypes.c_double),
                 ("prec", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("mesh", ctypes.c_int32), ("np", ctypes.c_int64),
+                ("w", ctypes.c_void_p), ("pts", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
 class StbError(RuntimeError):
@@ -85,9 +94,17 @@ def load():
     L.stb_last_work.argtypes = [_VP, _I64]
     L.stb_last_kernel_times.argtypes = [_VP, _D, _I64, _I64]
     L.stb_mat_export.argtypes = [_VP, _I64, _I32, _D]
+    L.stb_autotune.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _I32]
+    L.stb_server_create.argtypes = [_VP, i64, i32, ctypes.POINTER(_VP)]
+    L.stb_server_add_mesh.argtypes = [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32)]
+    L.stb_server_submit.argtypes = [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.stb_server_wait.argtypes = [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+    L.stb_server_destroy.argtypes = [_VP]
+    L.stb_server_destroy.restype = None
+    L.stb_set_tuning.argtypes = [_VP, _I32]
     L.stb_batch_assemble.argtypes = [_VP, i32, ctypes.POINTER(_VP), ctypes.POINTER(QuadParams),
                                      i64, ctypes.POINTER(_VP), i32, ctypes.POINTER(_VP),
-                                     ctypes.POINTER(_VP)]
+                                     ctypes.POINTER(_VP), _I64]
     L.stb_mesh_create_dev.argtypes = [_VP, i64, _VP, i64, _VP, _VP, ctypes.POINTER(_VP)]
     L.stb_potential_S_dev.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _VP, i64, _VP, _VP,
                                       _VP]
@@ -251,17 +268,39 @@ class Matrix:
                                   _VP(stream) if stream else None), self.ctx.h)
 
 
+def autotune(ctx, mesh, params=None):
+    """Tune the pipeline's launch shapes on mesh; returns (blocks[8], per_cu[8])."""
+    p = params if params is not None else default_params()
+    cfg = np.zeros(16, dtype=np.int32)
+    _chk(load().stb_autotune(ctx.h, mesh.h, ctypes.byref(p), cfg.ctypes.data_as(_I32)), ctx.h)
+    return cfg[:8].tolist(), cfg[8:].tolist()
+
+
+def set_tuning(ctx, blocks=None, per_cu=None):
+    """Set launch shapes (None: defaults)."""
+    if blocks is None:
+        _chk(load().stb_set_tuning(ctx.h, None), ctx.h)
+        return
+    cfg = np.asarray(list(blocks) + list(per_cu), dtype=np.int32)
+    _chk(load().stb_set_tuning(ctx.h, cfg.ctypes.data_as(_I32)), ctx.h)
+
+
 def batch_assemble(ctx, meshes, params=None, hbm_budget=0, keep=True, W_ptrs=None, Y_ptrs=None,
-                   nrhs=16):
+                   nrhs=16, causal=None):
     """Assemble several meshes in one pass of the pair pipeline.  keep: return
-    the matrices; W_ptrs/Y_ptrs: device pointers per mesh for Y_m = A_m W_m."""
+    the matrices; W_ptrs/Y_ptrs: device pointers per mesh for Y_m = A_m W_m;
+    causal: optional int64 array receiving the causal pairs per mesh."""
     p = params if params is not None else default_params()
     n = len(meshes)
     hs = (_VP * n)(*[m.h for m in meshes])
     outs = (_VP * n)() if keep else None
     W = (_VP * n)(*[_VP(x) for x in W_ptrs]) if W_ptrs is not None else None
     Y = (_VP * n)(*[_VP(x) for x in Y_ptrs]) if Y_ptrs is not None else None
-    _chk(load().stb_batch_assemble(ctx.h, n, hs, ctypes.byref(p), hbm_budget, outs, nrhs, W, Y),
+    nc = None
+    if causal is not None:
+        assert causal.dtype == np.int64 and causal.size == n
+        nc = causal.ctypes.data_as(_I64)
+    _chk(load().stb_batch_assemble(ctx.h, n, hs, ctypes.byref(p), hbm_budget, outs, nrhs, W, Y, nc),
          ctx.h)
     return [Matrix(ctx, _VP(outs[k])) for k in range(n)] if keep else None
 
@@ -299,3 +338,64 @@ def potential_S_dev(ctx, mesh, w_ptr, np_, pts_ptr, out_ptr, params=None, stream
     p = params if params is not None else default_params()
     _chk(load().stb_potential_S_dev(ctx.h, mesh.h, ctypes.byref(p), _VP(w_ptr), np_, _VP(pts_ptr),
                                     _VP(out_ptr), _VP(stream) if stream else None), ctx.h)
+
+
+class Server:
+    """Continuous-batching server on resident meshes (stb_server_*).  The
+    arrays of a request are kept alive here until its ticket is waited on."""
+
+    def __init__(self, ctx, hbm_budget=0, nslots=4):
+        h = _VP()
+        _chk(load().stb_server_create(ctx.h, hbm_budget, nslots, ctypes.byref(h)), ctx.h)
+        self.ctx, self.h = ctx, h
+        self._live = {}
+        self._sizes = {}
+        self._lock = __import__("threading").Lock()
+
+    def add_mesh(self, mesh, mat=None):
+        i = ctypes.c_int32()
+        _chk(load().stb_server_add_mesh(self.h, mesh.h, mat.h if mat is not None else None,
+                                        ctypes.byref(i)), self.ctx.h)
+        self._sizes[i.value] = mesh.nt
+        return i.value
+
+    def _submit(self, req, keep):
+        t = ctypes.c_uint64()
+        _chk(load().stb_server_submit(self.h, ctypes.byref(req), ctypes.byref(t)), None)
+        with self._lock:
+            self._live[t.value] = keep
+        return t.value
+
+    def submit_matvec(self, mesh_id, W):
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        out = np.empty_like(W)
+        req = Request(STB_REQ_MATVEC16, mesh_id, 0, W.ctypes.data, None, out.ctypes.data)
+        return self._submit(req, (W, out))
+
+    def submit_potential(self, mesh_id, w, pts):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 4)
+        out = np.empty(pts.shape[0])
+        req = Request(STB_REQ_POTENTIAL, mesh_id, pts.shape[0], w.ctypes.data, pts.ctypes.data,
+                      out.ctypes.data)
+        return self._submit(req, (w, pts, out))
+
+    def wait(self, ticket):
+        """(result array, latency in seconds)."""
+        lat = ctypes.c_double()
+        st = load().stb_server_wait(self.h, ticket, ctypes.byref(lat))
+        with self._lock:
+            keep = self._live.pop(ticket, None)
+        _chk(st, None)
+        return keep[-1], lat.value
+
+    def close(self):
+        if self.h:
+            load().stb_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -103,3 +103,22 @@ def test_batch_errors(stb, ctx, mix):
         stb.batch_assemble(ctx, [m], keep=False)          # nothing to return
     with pytest.raises(stb.StbError):
         stb.batch_assemble(ctx, [m], hbm_budget=-1)
+
+
+def test_autotune_keeps_results(stb, ctx):
+    """Launch shapes change the schedule, never the values."""
+    mesh = inputs.icosphere_mesh(level=1, S=6, T=4.0, jitter=0.2, seed=4)
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    stb.set_tuning(ctx)                       # defaults
+    ref = stb.assemble_V(ctx, m).export()[2]
+    blocks, per_cu = stb.autotune(ctx, m)
+    print("tuned", blocks, per_cu, flush=True)
+    assert all(b in (64, 128, 256) for b in blocks)
+    assert all(1 <= p <= 64 for p in per_cu)
+    got = stb.assemble_V(ctx, m).export()[2]
+    assert np.array_equal(got, ref)
+    stb.set_tuning(ctx, [64] * 8, [4] * 8)
+    assert np.array_equal(stb.assemble_V(ctx, m).export()[2], ref)
+    with pytest.raises(stb.StbError):
+        stb.set_tuning(ctx, [96] * 8, [4] * 8)
+    stb.set_tuning(ctx)
