@@ -73,14 +73,14 @@ __device__ __forceinline__ void blk_mark(int64_t b, int64_t n, const int64_t* ro
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlkThreads) void k_blk_count(int64_t nblk, int64_t n,
+__global__ __launch_bounds__(kBlkThreads) void k_blk_count(int64_t nblk, int64_t n, int64_t ncols,
                                                            const int64_t* __restrict__ rowptr,
                                                            const int32_t* __restrict__ cols,
                                                            int64_t* __restrict__ nquad) {
   extern __shared__ uint32_t lds[];
   int64_t b = blockIdx.x;
   if (b >= nblk) return;
-  int nw = (int)((n + 31) / 32);
+  int nw = (int)((ncols + 31) / 32);
   blk_mark(b, n, rowptr, cols, lds, nw);
   int c = 0;
   for (int w = threadIdx.x; w < nw; w += kBlkThreads) c += __popc(lds[w]);
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_count(int64_t nblk, int64_t
   if (threadIdx.x == 0) nquad[b] = (red[0] + 3) / 4;
 }
 
-__global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t n,
+__global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t n, int64_t ncols,
                                                           const int64_t* __restrict__ rowptr,
                                                           const int32_t* __restrict__ cols,
                                                           const double* __restrict__ vals,
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t 
   extern __shared__ uint32_t lds[];
   int64_t b = blockIdx.x;
   if (b >= nblk) return;
-  int nw = (int)((n + 31) / 32);
+  int nw = (int)((ncols + 31) / 32);
   uint32_t* bits = lds;
   int* pre = reinterpret_cast<int*>(lds + nw);
   blk_mark(b, n, rowptr, cols, bits, nw);
@@ -149,16 +149,16 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t 
 }
 
 stb_status stb_build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st) {
-  const int64_t n = M->n;
-  if (n > kMaxBlockedN)
+  const int64_t n = M->n, ncols = mat_ncols(M);
+  if (ncols > kMaxBlockedN)
     return stb_fail(ctx, STB_E_INVALID_ARG, "16-RHS product supports n <= %lld", (long long)kMaxBlockedN);
   const int64_t nblk = (n + 15) / 16;
-  size_t lds = sizeof(uint32_t) * 2 * (size_t)((n + 31) / 32);
+  size_t lds = sizeof(uint32_t) * 2 * (size_t)((ncols + 31) / 32);
   int64_t* d_nq = nullptr;
   stb_free_blocked(M);
   HIPCHK(ctx, dalloc(&d_nq, (size_t)nblk));
   HIPCHK(ctx, dalloc(&M->d_bptr, (size_t)nblk + 1));
-  hipLaunchKernelGGL(k_blk_count, dim3((unsigned)nblk), dim3(kBlkThreads), lds / 2, st, nblk, n,
+  hipLaunchKernelGGL(k_blk_count, dim3((unsigned)nblk), dim3(kBlkThreads), lds / 2, st, nblk, n, ncols,
                      M->d_rowptr, M->d_cols, d_nq);
   HIPCHK(ctx, hipGetLastError());
   stb_status s = stb_exclusive_scan(ctx, d_nq, M->d_bptr, nblk, st);
@@ -168,8 +168,8 @@ stb_status stb_build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st) {
   HIPCHK(ctx, hipMemcpy(&nquad, M->d_bptr + nblk, sizeof(int64_t), hipMemcpyDeviceToHost));
   HIPCHK(ctx, dalloc(&M->d_bcol, (size_t)nquad * 4));
   HIPCHK(ctx, dalloc(&M->d_bval, (size_t)nquad * 64));
-  hipLaunchKernelGGL(k_blk_fill, dim3((unsigned)nblk), dim3(kBlkThreads), lds, st, nblk, n, M->d_rowptr,
-                     M->d_cols, M->d_vals, M->d_bptr, M->d_bcol, M->d_bval);
+  hipLaunchKernelGGL(k_blk_fill, dim3((unsigned)nblk), dim3(kBlkThreads), lds, st, nblk, n, ncols,
+                     M->d_rowptr, M->d_cols, M->d_vals, M->d_bptr, M->d_bcol, M->d_bval);
   HIPCHK(ctx, hipGetLastError());
   M->nblk = nblk;
   M->nquad = nquad;
@@ -182,8 +182,8 @@ stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y,
     if (s) return s;
   }
   float* w32 = nullptr;
-  HIPCHK(ctx, dalloc(&w32, (size_t)M->n * 16));
-  int64_t m = M->n * 16;
+  HIPCHK(ctx, dalloc(&w32, (size_t)mat_ncols(M) * 16));
+  int64_t m = mat_ncols(M) * 16;
   if (m > 0) {
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, w, w32);
   }

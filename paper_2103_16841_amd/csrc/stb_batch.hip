@@ -48,6 +48,7 @@ constexpr int64_t kBytesPerCand = 4 + 8 + 4 + 4 + 4 + 8;
 struct WaveMesh {
   int idx;
   stb_mesh* mesh;
+  int64_t r0 = 0, r1 = 0, nnz = 0;   // rows [r0, r1) of the mesh, their candidates
   stb_mat* M = nullptr;
   int32_t* rowof = nullptr;
   int64_t off_panel = 0, off_cand = 0;
@@ -102,35 +103,66 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
     HIPCHK(ctx, hipMemGetInfo(&fr, &tot));
     hbm_budget = (int64_t)(0.4 * (double)fr);
   }
-  // candidate counts, for the wave plan
-  std::vector<int64_t> nnz(nmesh, 0);
-  for (int k = 0; k < nmesh; ++k)
-    if ((s = stb_cull_count(ctx, meshes[k]->nt, meshes[k]->d_box, meshes[k], &nnz[k]))) return s;
+  // candidate counts per row, for the wave plan
+  std::vector<std::vector<int64_t>> rp(nmesh);
+  for (int k = 0; k < nmesh; ++k) {
+    rp[k].resize((size_t)meshes[k]->nt + 1);
+    if ((s = stb_cull_rowptr(ctx, meshes[k]->nt, meshes[k]->d_box, meshes[k], rp[k].data()))) return s;
+  }
   HIPCHK(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+  // units: whole meshes, or (without kept matrices) row blocks of a mesh
+  // whose candidates alone exceed the budget
+  struct Unit { int mesh; int64_t r0, r1, nnz, bytes; };
+  std::vector<Unit> units;
+  for (int k = 0; k < nmesh; ++k) {
+    const int64_t nt = meshes[k]->nt;
+    const int64_t fixed = nt * (int64_t)(sizeof(TrialRec) + 40 * maxq);
+    if (mats) {
+      units.push_back({k, 0, nt, rp[k][nt], rp[k][nt] * kBytesPerCand + fixed});
+      continue;
+    }
+    int64_t r0 = 0;
+    while (r0 < nt) {
+      int64_t r1 = r0 + 1;
+      // largest r1 whose block fits (binary search on the row prefix)
+      int64_t lo = r0 + 1, hi = nt;
+      while (lo < hi) {
+        int64_t mid = (lo + hi + 1) / 2;
+        if ((rp[k][mid] - rp[k][r0]) * kBytesPerCand + fixed <= hbm_budget) lo = mid; else hi = mid - 1;
+      }
+      r1 = lo;
+      int64_t nz = rp[k][r1] - rp[k][r0];
+      units.push_back({k, r0, r1, nz, nz * kBytesPerCand + fixed});
+      r0 = r1;
+    }
+  }
   HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
   unsigned long long work_tot[4] = {0, 0, 0, 0};
   double kms[8] = {0}, kunits[8] = {0};
   int64_t kn[8] = {0};
-  int k0 = 0;
-  while (k0 < nmesh) {
-    // wave: consecutive meshes within the budget (at least one); kept
-    // matrices stay resident, so with mats the whole batch must fit
-    int k1 = k0;
+  std::vector<int64_t> causal(nmesh, 0);
+  size_t u0 = 0;
+  while (u0 < units.size()) {
+    // wave: consecutive units within the budget (at least one); kept
+    // matrices stay resident, so with mats the whole batch is one wave
+    size_t u1 = u0;
     int64_t bytes = 0, panels = 0, cands = 0;
-    while (k1 < nmesh) {
-      int64_t b = nnz[k1] * kBytesPerCand + meshes[k1]->nt * (int64_t)(sizeof(TrialRec) + 40 * maxq);
-      if (k1 > k0 && bytes + b > hbm_budget && !mats) break;
-      bytes += b;
-      panels += meshes[k1]->nt;
-      cands += nnz[k1];
-      ++k1;
+    while (u1 < units.size()) {
+      if (u1 > u0 && bytes + units[u1].bytes > hbm_budget && !mats) break;
+      bytes += units[u1].bytes;
+      panels += meshes[units[u1].mesh]->nt;
+      cands += units[u1].nnz;
+      ++u1;
     }
     if (panels > (int64_t)INT32_MAX) return stb_fail(ctx, STB_E_INVALID_ARG, "batch wave exceeds 2^31 panels");
     std::vector<WaveMesh> w;
-    for (int k = k0; k < k1; ++k) {
+    for (size_t u = u0; u < u1; ++u) {
       WaveMesh x;
-      x.idx = k;
-      x.mesh = meshes[k];
+      x.idx = units[u].mesh;
+      x.mesh = meshes[units[u].mesh];
+      x.r0 = units[u].r0;
+      x.r1 = units[u].r1;
+      x.nnz = units[u].nnz;
       w.push_back(x);
     }
     TrialRec* trial_g = nullptr;
@@ -162,12 +194,14 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
     for (size_t m = 0; m < w.size(); ++m) {
       WaveMesh& x = w[m];
       stb_mesh* me = x.mesh;
+      const bool whole = x.r0 == 0 && x.r1 == me->nt;
       x.M = new stb_mat();
       x.M->ctx = ctx;
-      x.M->n = me->nt;
+      x.M->n = x.r1 - x.r0;
+      x.M->ncols = whole ? 0 : me->nt;
       int64_t nz = 0;
-      s = stb_cull(ctx, me->nt, me->d_box, me, &x.M->d_rowptr, &x.M->d_cols, &x.rowof, &nz);
-      if (s == STB_OK && nz != nnz[x.idx]) s = stb_fail(ctx, STB_E_INTERNAL, "cull count changed");
+      s = stb_cull(ctx, x.r1 - x.r0, me->d_box + x.r0, me, &x.M->d_rowptr, &x.M->d_cols, &x.rowof, &nz);
+      if (s == STB_OK && nz != x.nnz) s = stb_fail(ctx, STB_E_INTERNAL, "cull count changed");
       if (s == STB_OK && dalloc(&x.M->d_vals, (size_t)nz) != hipSuccess)
         s = stb_fail(ctx, STB_E_NO_MEMORY, "store of mesh %d", x.idx);
       if (s) { cleanup(false); return s; }
@@ -187,7 +221,8 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
         e = hipMemcpyAsync(apexn_g + op, me->d_onq, sizeof(int32_t) * me->nt, hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess && nz > 0) {
         unsigned g = (unsigned)((nz + 255) / 256);
-        hipLaunchKernelGGL(k_shift_idx, dim3(g), dim3(256), 0, st, nz, x.rowof, (int32_t)op, rows_g + oc);
+        hipLaunchKernelGGL(k_shift_idx, dim3(g), dim3(256), 0, st, nz, x.rowof, (int32_t)(op + x.r0),
+                           rows_g + oc);
         hipLaunchKernelGGL(k_shift_idx, dim3(g), dim3(256), 0, st, nz, x.M->d_cols, (int32_t)op,
                            cols_g + oc);
         e = hipGetLastError();
@@ -235,20 +270,22 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
     HIPCHK(ctx, hipStreamSynchronize(st));
     for (size_t m = 0; m < w.size(); ++m) {
       w[m].M->n_causal = (int64_t)h_causal[m];
-      if (n_causal) n_causal[w[m].idx] = (int64_t)h_causal[m];
+      causal[(size_t)w[m].idx] += (int64_t)h_causal[m];
     }
-    // products, then release (or hand over) the wave's stores
+    // products of the wave's row blocks, then release (or hand over) the stores
     for (size_t m = 0; m < w.size() && W_dev; ++m) {
       WaveMesh& x = w[m];
-      s = stb_apply_dev(ctx, x.M, nrhs, W_dev[x.idx], Y_dev[x.idx], nullptr);
+      s = stb_apply_dev(ctx, x.M, nrhs, W_dev[x.idx], Y_dev[x.idx] + x.r0 * nrhs, nullptr);
       if (s) { cleanup(false); return s; }
     }
     if (W_dev) HIPCHK(ctx, hipStreamSynchronize(st));
     if (mats)
       for (auto& x : w) mats[x.idx] = x.M;
     cleanup(mats != nullptr);
-    k0 = k1;
+    u0 = u1;
   }
+  if (n_causal)
+    for (int k = 0; k < nmesh; ++k) n_causal[k] = causal[(size_t)k];
   HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
   HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
   for (int q = 0; q < 4; ++q) ctx->work[q] = (int64_t)work_tot[q];

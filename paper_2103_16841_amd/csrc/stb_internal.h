@@ -50,6 +50,7 @@ struct stb_mesh {
 struct stb_mat {
   stb_ctx* ctx = nullptr;
   int64_t n = 0, nnz = 0, n_causal = 0;
+  int64_t ncols = 0;             // columns (0: n; a row block of a batch: the mesh's panels)
   int64_t* d_rowptr = nullptr;
   int32_t* d_cols = nullptr;
   double* d_vals = nullptr;
@@ -79,6 +80,8 @@ extern "C" stb_status stb_mirror_host(stb_mat* M);
                       "%s failed: %s", #call, hipGetErrorString(e_));                        \
   } while (0)
 
+static inline int64_t mat_ncols(const stb_mat* M) { return M->ncols ? M->ncols : M->n; }
+
 template <typename T>
 static inline hipError_t dalloc(T** p, size_t count) {
   *p = nullptr;
@@ -100,6 +103,9 @@ stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, con
                     int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz);
 stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, const stb_mesh* m,
                           int64_t* nnz);
+// Exclusive prefix of the per-row candidate counts (nrows + 1 entries, host).
+stb_status stb_cull_rowptr(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, const stb_mesh* m,
+                           int64_t* rowptr_host);
 void stb_point_boxes(stb_ctx* ctx, int64_t np, const double* d_pts, stb::ApexBox* d_box);
 
 // Potential with device inputs/outputs on ctx's stream and workspace (the

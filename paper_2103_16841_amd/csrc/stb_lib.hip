@@ -393,11 +393,11 @@ void stb_point_boxes(stb_ctx* ctx, int64_t np, const double* d_pts, ApexBox* d_b
                        d_pts, d_box);
 }
 
-// Number of candidates the cull would produce for these rows (count pass
-// only).
-stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
-                          int64_t* nnz) {
-  *nnz = 0;
+// Exclusive prefix of the candidate counts of these rows (count pass only),
+// copied to the host.
+stb_status stb_cull_rowptr(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
+                           int64_t* rowptr_host) {
+  rowptr_host[0] = 0;
   if (nrows <= 0) return STB_OK;
   int64_t *d_cnt = nullptr, *d_scan = nullptr;
   HIPCHK(ctx, dalloc(&d_cnt, (size_t)nrows));
@@ -410,10 +410,20 @@ stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, co
   hipError_t e = hipGetLastError();
   stb_status s = e == hipSuccess ? device_exclusive_scan(ctx, d_cnt, d_scan, nrows)
                                  : fail(ctx, STB_E_DEVICE, "cull count: %s", hipGetErrorString(e));
-  if (s == STB_OK && hipMemcpy(nnz, d_scan + nrows, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+  if (s == STB_OK &&
+      hipMemcpy(rowptr_host, d_scan, sizeof(int64_t) * (nrows + 1), hipMemcpyDeviceToHost) != hipSuccess)
     s = fail(ctx, STB_E_DEVICE, "cull count copy");
   dfree(d_cnt);
   dfree(d_scan);
+  return s;
+}
+
+// Number of candidates the cull would produce for these rows.
+stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
+                          int64_t* nnz) {
+  std::vector<int64_t> rp((size_t)std::max<int64_t>(nrows, 0) + 1);
+  stb_status s = stb_cull_rowptr(ctx, nrows, d_rows, m, rp.data());
+  *nnz = rp.back();
   return s;
 }
 
