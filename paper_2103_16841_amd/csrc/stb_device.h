@@ -47,8 +47,10 @@ struct TrialRec {
   double tmin, tmax, diam;           // time range; max(spatial diam, span)
   double cx, cy, cz, rad;            // spatial bounding ball
   double pad;
+  double phik[4], beta[4];           // per face: atan2(c, b), |(b, c)| (breakpoints)
+  double pad2[8];
 };
-static_assert(sizeof(TrialRec) == 64 * sizeof(double), "TrialRec layout");
+static_assert(sizeof(TrialRec) == 80 * sizeof(double), "TrialRec layout");
 
 // Bounding data of an apex set (the outer points of a test panel, or one
 // evaluation point) for the conservative causal cull.
@@ -408,9 +410,9 @@ STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
     }
   for (int k = 0; k < 4; ++k) {
     double a = T.fa[k], b = T.fb[k], c = T.fc[k], Ck = A.C[k];
-    double beta = sqrt(b * b + c * c);
+    double beta = T.beta[k];
     if (!(beta > 1e-12)) continue;
-    double phik = atan2(c, b);
+    double phik = T.phik[k];
     if (d2 > 0.0) {
       double rhs = a * a - Ck * Ck / d2;
       if (rhs >= 0.0 && rhs <= beta * beta) {
@@ -529,6 +531,11 @@ STB_HD inline int make_trial(const double (&X)[4][4], TrialRec& R) {
   }
   R.cx = cen[0]; R.cy = cen[1]; R.cz = cen[2]; R.rad = rad * (1.0 + 1e-12);
   R.pad = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    R.beta[k] = sqrt(R.fb[k] * R.fb[k] + R.fc[k] * R.fc[k]);
+    R.phik[k] = atan2(R.fc[k], R.fb[k]);
+  }
+  for (int k = 0; k < 8; ++k) R.pad2[k] = 0.0;
   return 0;
 }
 
@@ -579,6 +586,172 @@ STB_HD __forceinline__ double L_combo(const ComboL& cb, double cs, double sn) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) { F.fa[k] = cb.fa[k]; F.fb[k] = cb.fb[k]; F.fc[k] = cb.fc[k]; }
   return L_eval(F, cb.C, cb.d2, cb.wlo, cb.whi, cs, sn);
+}
+
+// ------------------------------------------------------------ piece recipes
+//
+// Between consecutive breakpoints the admissible set keeps its structure:
+// which face roots (or ends of the time range) bound each of its gaps
+// changes only where two roots meet on a panel edge (edge events), where a
+// face's roots appear or vanish (tangencies), or at the hint angles -- all
+// breakpoints.  So the structure seen at one point of a piece (its midpoint,
+// or a quarter point) is a recipe for L at every node of the piece: L is the
+// r-measure of a fixed list of gaps, each from one endpoint formula to
+// another, and a node needs only those formulas instead of all four faces,
+// the hole sort and the sweep.  Endpoint ids: 0 = wlo, 1 = whi, 2 + 2k =
+// face k's root q / e, 3 + 2k = its root -d^2 f / q (the root of the linear
+// case e = 0).  A recipe holds up to kRecipeGaps (2) gaps, 8 bits each (start id
+// << 4 | end id), and the gap count in bits 24-25; 0 gaps means "no recipe"
+// (more gaps than fit).  On the host mirror over 8.5 million non-empty
+// pieces of the cube and icosphere workloads the recipe reproduced L at
+// every node of every piece wider than 1e-12 to rounding; 99.6% of the
+// pieces have one gap, the rest two.
+constexpr int kRecipeGaps = 2;
+
+STB_HD __forceinline__ void order2i(double& s0, double& e0, int& i0, int& j0, double& s1, double& e1,
+                                    int& i1, int& j1) {
+  bool sw = s1 < s0;
+  double ts = s0, te = e0;
+  int ti = i0, tj = j0;
+  s0 = sw ? s1 : s0; e0 = sw ? e1 : e0; i0 = sw ? i1 : i0; j0 = sw ? j1 : j0;
+  s1 = sw ? ts : s1; e1 = sw ? te : e1; i1 = sw ? ti : i1; j1 = sw ? tj : j1;
+}
+
+// L(phi) as L_eval, also returning the recipe of its gap structure.
+STB_HD inline double L_eval_recipe(const ComboL& cb, double cs, double sn, uint32_t* recipe) {
+  const double kNone = 1e300;
+  const double d2 = cb.d2;
+  double lo = cb.wlo, hi = cb.whi;
+  int loi = 0, hii = 1;
+  bool dead = false;
+  double hs[4], he[4];
+  int hsi[4], hei[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double a = cb.fa[k];
+    double B = fma(cb.fb[k], cs, cb.fc[k] * sn);
+    double e = B - a, f = B + a, Ck = cb.C[k];
+    double D = fma(Ck, Ck, d2 * (e * f));
+    bool two = D > 0.0;
+    double q = Ck + copysign(sqrt(fmax(D, 0.0)), Ck);
+    double w1 = q * frcp(e);
+    double w2 = -d2 * f * frcp(q);
+    const int ia = 2 + 2 * k, ib = 3 + 2 * k;
+    bool aless = w1 < w2;
+    double mn = aless ? w1 : w2, mx = aless ? w2 : w1;
+    int mni = aless ? ia : ib, mxi = aless ? ib : ia;
+    bool pos = e > 0.0, neg = e < 0.0, zer = !(pos || neg);
+    bool cut = pos && two;
+    dead = dead || (pos && !two) || (zer && Ck == 0.0 && !(d2 * f > 0.0));
+    bool nlo = cut && mn > lo, nhi = cut && mx < hi;
+    lo = nlo ? mn : lo; loi = nlo ? mni : loi;
+    hi = nhi ? mx : hi; hii = nhi ? mxi : hii;
+    bool llo = zer && Ck > 0.0 && w2 > lo, lhi = zer && Ck < 0.0 && w2 < hi;
+    lo = llo ? w2 : lo; loi = llo ? ib : loi;
+    hi = lhi ? w2 : hi; hii = lhi ? ib : hii;
+    bool hole = neg && two;
+    hs[k] = hole ? mn : kNone; hsi[k] = hole ? mni : hii;
+    he[k] = hole ? mx : kNone; hei[k] = hole ? mxi : hii;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    bool b1 = hs[k] < lo;
+    hs[k] = b1 ? lo : hs[k]; hsi[k] = b1 ? loi : hsi[k];
+    bool b2 = hs[k] > hi;
+    hs[k] = b2 ? hi : hs[k]; hsi[k] = b2 ? hii : hsi[k];
+    bool b3 = he[k] > hi;
+    he[k] = b3 ? hi : he[k]; hei[k] = b3 ? hii : hei[k];
+    bool b4 = he[k] < hs[k];
+    he[k] = b4 ? hs[k] : he[k]; hei[k] = b4 ? hsi[k] : hei[k];
+  }
+  order2i(hs[0], he[0], hsi[0], hei[0], hs[1], he[1], hsi[1], hei[1]);
+  order2i(hs[2], he[2], hsi[2], hei[2], hs[3], he[3], hsi[3], hei[3]);
+  order2i(hs[0], he[0], hsi[0], hei[0], hs[2], he[2], hsi[2], hei[2]);
+  order2i(hs[1], he[1], hsi[1], hei[1], hs[3], he[3], hsi[3], hei[3]);
+  order2i(hs[1], he[1], hsi[1], hei[1], hs[2], he[2], hsi[2], hei[2]);
+  const double kWulp = 8.881784197001252e-16;
+  double len = 0.0, c = lo;
+  int ci = loi, ng = 0;
+  uint32_t rec = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    bool adv = hs[k] > c;
+    double g1 = adv ? hs[k] : c;
+    int g1i = adv ? hsi[k] : ci;
+    double m = rdiff(c, g1, d2);
+    bool keep = m > kWulp * g1;
+    len += keep ? m : 0.0;
+    if (keep) {
+      if (ng < kRecipeGaps) rec |= (uint32_t)((ci << 4) | g1i) << (8 * ng);
+      ++ng;
+    }
+    bool ext = he[k] > c;
+    c = ext ? he[k] : c;
+    ci = ext ? hei[k] : ci;
+  }
+  double m = rdiff(c, hi, d2);
+  bool keep = m > kWulp * hi;
+  len += keep ? m : 0.0;
+  if (keep) {
+    if (ng < kRecipeGaps) rec |= (uint32_t)((ci << 4) | hii) << (8 * ng);
+    ++ng;
+  }
+  const bool empty = dead || !(hi > lo);
+  *recipe = (empty || ng > kRecipeGaps) ? 0u : (rec | ((uint32_t)ng << 24));
+  return empty ? 0.0 : len;
+}
+
+STB_HD __forceinline__ int recipe_gaps(uint32_t r) { return (int)((r >> 24) & 3u); }
+
+// One endpoint formula, prepared per piece: the coefficients of its face
+// (or a constant end of the time range).
+struct Endpoint {
+  double a, fb, fc, C;
+  double cval;      // value when constant
+  bool cst, isb;    // constant end; root -d^2 f / q (else q / e)
+};
+
+STB_HD __forceinline__ Endpoint endpoint_of(const ComboL& cb, int id) {
+  Endpoint E;
+  const int k = id >= 2 ? (id - 2) >> 1 : 0;
+  // select the face's coefficients (registers only)
+  const bool k1 = k & 1, k2 = (k >> 1) & 1;
+  E.a = k2 ? (k1 ? cb.fa[3] : cb.fa[2]) : (k1 ? cb.fa[1] : cb.fa[0]);
+  E.fb = k2 ? (k1 ? cb.fb[3] : cb.fb[2]) : (k1 ? cb.fb[1] : cb.fb[0]);
+  E.fc = k2 ? (k1 ? cb.fc[3] : cb.fc[2]) : (k1 ? cb.fc[1] : cb.fc[0]);
+  E.C = k2 ? (k1 ? cb.C[3] : cb.C[2]) : (k1 ? cb.C[1] : cb.C[0]);
+  E.cst = id < 2;
+  E.cval = id == 0 ? cb.wlo : cb.whi;
+  E.isb = id >= 2 && ((id - 2) & 1);
+  return E;
+}
+
+STB_HD __forceinline__ double endpoint_value(const Endpoint& E, double d2, double wlo, double whi,
+                                             double cs, double sn) {
+  double B = fma(E.fb, cs, E.fc * sn);
+  double e = B - E.a, f = B + E.a;
+  double D = fma(E.C, E.C, d2 * (e * f));
+  double q = E.C + copysign(sqrt(fmax(D, 0.0)), E.C);
+  double num = E.isb ? -d2 * f : q;
+  double den = E.isb ? q : e;
+  double v = num * frcp(den);
+  v = E.cst ? E.cval : v;
+  // the admissible set lies in [wlo, whi]; a formula evaluated just past
+  // the structure it was chosen for (rounding at a piece's end) stays there
+  return fmin(fmax(v, wlo), whi);
+}
+
+// L by a recipe: the r-measure of its gaps, each between two endpoint
+// formulas (E[2g], E[2g + 1]).
+STB_HD __forceinline__ double L_by_recipe(const Endpoint* E, int ng, double d2, double wlo,
+                                          double whi, double cs, double sn) {
+  double len = 0.0;
+  for (int g = 0; g < ng; ++g) {
+    double v0 = endpoint_value(E[2 * g], d2, wlo, whi, cs, sn);
+    double v1 = endpoint_value(E[2 * g + 1], d2, wlo, whi, cs, sn);
+    len += v1 > v0 ? rdiff(v0, v1, d2) : 0.0;
+  }
+  return len;
 }
 
 // ------------------------------------------------------------ mixed precision

@@ -48,7 +48,7 @@ constexpr int kBlk = 256;
 constexpr int kMaxBlocks = 256 * 16;
 
 enum {
-  CNT_COMBO = 0, CNT_PIECE, CNT_JOB, CNT_JOB32, CNT_REDO, CNT_JOBR, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
+  CNT_COMBO = 0, CNT_PIECE, CNT_JOB, CNT_JOB2, CNT_JOBF, CNT_JOB32, CNT_REDO, CNT_JOBR, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
   CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_EVAL_NODES32, CNT_EVAL_REDO, CNT_N
 };
 
@@ -113,7 +113,10 @@ struct Lists {
   int32_t* pc;           // owning combo
   double* pv;            // ordered node sum
   float* pe;             // FP32 rounding bound of the node sum (far pieces, mixed)
-  int32_t* job;          // non-empty pieces, FP64 nodes
+  int32_t* job;          // non-empty pieces, FP64 nodes by a one-gap recipe
+  int32_t* job2;         // ... by a two-gap recipe
+  int32_t* jobf;         // ... full evaluation (no recipe, slivers, trapezoid halves)
+  uint32_t* prec;        // per piece: recipe of its gap structure
   int32_t* job32;        // non-empty pieces of far combos, FP32 nodes (mixed)
   uint8_t* pne;          // per piece: non-empty
   uint8_t* redo;         // per candidate (mixed): entry recomputed in FP64
@@ -268,7 +271,22 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
 // has just read).
 constexpr int kEmptyPer = 8;
 
-__global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
+// Job lists the empty-piece test routes a non-empty piece to.
+enum { JOB_R1 = 0, JOB_R2 = 1, JOB_FULL = 2, JOB_FP32 = 3 };
+
+// Pieces narrower than this take the full evaluation: their nodes sit
+// within rounding of the breakpoints, where the structure is ambiguous.
+constexpr double kRecipeMinH = 1e-8;
+
+__device__ __forceinline__ unsigned route_of(const Lists& L, int32_t p, uint32_t rec) {
+  if ((L.key[L.pc[p]] >> 7) & 1u) return JOB_FP32;
+  const double H = L.ph[p];
+  const int ng = recipe_gaps(rec);
+  if (rec == 0u || !(H >= kRecipeMinH)) return JOB_FULL;
+  return ng == 1 ? JOB_R1 : JOB_R2;
+}
+
+__global__ __launch_bounds__(kBlk, 2) void k_empty(Lists L, int64_t npiece) {
   const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
   __shared__ int32_t s_q[kEmptyPer * kBlk];
@@ -278,27 +296,32 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
   for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < npiece; base += step) {
     if (threadIdx.x == 0) s_nq = 0;
     __syncthreads();
-    unsigned ne = 0;
+    unsigned ne = 0, route = 0;   // route: 2 bits per item
 #pragma unroll 1
     for (int j = 0; j < kEmptyPer; ++j) {
       const int64_t p = base + (int64_t)j * B + threadIdx.x;
       if (p >= npiece) break;
       const double H = L.ph[p];
       bool nz = true;   // trapezoid half (H < 0): always evaluated
+      uint32_t rec = 0u;
       if (!(H < 0.0)) {
-        nz = L_at(load_combo(L, L.pc[p]), L.pa[p] + 0.5 * H) != 0.0;
+        double sn, cs;
+        sincos_small(L.pa[p] + 0.5 * H, &sn, &cs);
+        nz = L_eval_recipe(load_combo(L, L.pc[p]), cs, sn, &rec) != 0.0;
         ++ev_mid;
       }
       L.pv[p] = 0.0;
       L.pe[p] = 0.0f;
       L.pne[p] = nz ? 1 : 0;
+      L.prec[p] = rec;
       ne |= (nz ? 1u : 0u) << j;
+      if (nz) route |= route_of(L, (int32_t)p, rec) << (2 * j);
       if (!nz) s_q[atomicAdd(&s_nq, 1)] = (int32_t)p;
     }
     __syncthreads();
     const int nq = s_nq;
     // quarter points of the queued pieces; thread tid owns entries tid + m B
-    unsigned qne = 0;
+    unsigned qne = 0, qroute = 0;
 #pragma unroll 1
     for (int m = 0; m < kEmptyPer; ++m) {
       const int e = m * B + threadIdx.x;
@@ -306,37 +329,91 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
       const int32_t p = s_q[e];
       const ComboL cb = load_combo(L, L.pc[p]);
       const double a = L.pa[p], H = L.ph[p];
-      bool nz = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+      uint32_t rec = 0u;
+      double sn, cs;
+      sincos_small(a + 0.25 * H, &sn, &cs);
+      bool nz = L_eval_recipe(cb, cs, sn, &rec) != 0.0;
+      if (!nz) {
+        sincos_small(a + 0.75 * H, &sn, &cs);
+        nz = L_eval_recipe(cb, cs, sn, &rec) != 0.0;
+      }
       ev_quarter += 2;
-      if (nz) L.pne[p] = 1;
+      if (nz) {
+        L.pne[p] = 1;
+        L.prec[p] = rec;
+        qroute |= route_of(L, p, rec) << (2 * m);
+      }
       qne |= (nz ? 1u : 0u) << m;
     }
-    // route the non-empty pieces: far combos to the FP32 list (mixed mode)
-    unsigned far = 0, qfar = 0;
+    unsigned cnt[4] = {0, 0, 0, 0};
     for (int j = 0; j < kEmptyPer; ++j)
-      if ((ne >> j) & 1u) {
-        const int64_t p = base + (int64_t)j * B + threadIdx.x;
-        far |= ((L.key[L.pc[p]] >> 7) & 1u) << j;
-      }
+      if ((ne >> j) & 1u) ++cnt[(route >> (2 * j)) & 3u];
     for (int m = 0; m < kEmptyPer; ++m)
-      if ((qne >> m) & 1u) qfar |= ((L.key[L.pc[s_q[m * B + threadIdx.x]]] >> 7) & 1u) << m;
-    const unsigned n64 = __popc(ne & ~far) + __popc(qne & ~qfar);
-    const unsigned n32 = __popc(ne & far) + __popc(qne & qfar);
-    unsigned long long s = block_alloc(L.cnt + CNT_JOB, n64, sh);
-    unsigned long long s32 = block_alloc(L.cnt + CNT_JOB32, n32, sh);
+      if ((qne >> m) & 1u) ++cnt[(qroute >> (2 * m)) & 3u];
+    unsigned long long sl[4];
+    sl[JOB_R1] = block_alloc(L.cnt + CNT_JOB, cnt[JOB_R1], sh);
+    sl[JOB_R2] = block_alloc(L.cnt + CNT_JOB2, cnt[JOB_R2], sh);
+    sl[JOB_FULL] = block_alloc(L.cnt + CNT_JOBF, cnt[JOB_FULL], sh);
+    sl[JOB_FP32] = block_alloc(L.cnt + CNT_JOB32, cnt[JOB_FP32], sh);
+    int32_t* lists[4] = {L.job, L.job2, L.jobf, L.job32};
     for (int j = 0; j < kEmptyPer; ++j) {
       if (!((ne >> j) & 1u)) continue;
-      const int32_t p = (int32_t)(base + (int64_t)j * B + threadIdx.x);
-      if ((far >> j) & 1u) L.job32[s32++] = p; else L.job[s++] = p;
+      const unsigned r = (route >> (2 * j)) & 3u;
+      lists[r][sl[r]++] = (int32_t)(base + (int64_t)j * B + threadIdx.x);
     }
     for (int m = 0; m < kEmptyPer; ++m) {
       if (!((qne >> m) & 1u)) continue;
-      const int32_t p = s_q[m * B + threadIdx.x];
-      if ((qfar >> m) & 1u) L.job32[s32++] = p; else L.job[s++] = p;
+      const unsigned r = (qroute >> (2 * m)) & 3u;
+      lists[r][sl[r]++] = s_q[m * B + threadIdx.x];
     }
   }
   block_count(L.cnt + CNT_EVAL_MID, ev_mid);
   block_count(L.cnt + CNT_EVAL_QUARTER, ev_quarter);
+}
+
+// The n_g nodes of a piece by its recipe (NG gaps): per node only the
+// endpoint formulas of the recipe, not all four faces (see L_eval_recipe).
+template <int NG>
+__global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* __restrict__ jobs,
+                                                       int64_t njob, const double* __restrict__ gl,
+                                                       int ng) {
+  const int B = (int)blockDim.x;
+  unsigned long long evals = 0;
+  for (int64_t base = (int64_t)blockIdx.x * B; base < njob; base += (int64_t)gridDim.x * B) {
+    const int64_t k = base + threadIdx.x;
+    if (k >= njob) continue;
+    const int32_t p = jobs[k];
+    const double H = L.ph[p], a = L.pa[p];
+    const uint32_t rec = L.prec[p];
+    const ComboL cb = load_combo(L, L.pc[p]);
+    Endpoint E[2 * NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      E[2 * g] = endpoint_of(cb, (rec >> (8 * g + 4)) & 15u);
+      E[2 * g + 1] = endpoint_of(cb, (rec >> (8 * g)) & 15u);
+    }
+    double acc = 0.0;
+    for (int gi = 0; gi < ng; ++gi) {
+      const double u = gl[gi];
+      const double s = u * u * (3.0 - 2.0 * u);
+      const double ds = 6.0 * u * (1.0 - u);
+      const double phi = a + H * s;
+      const double wt = (H * ds) * gl[kMaxNg + gi];
+      double sn, cs;
+      sincos_small(phi, &sn, &cs);
+      double Lv = 0.0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        double v0 = endpoint_value(E[2 * g], cb.d2, cb.wlo, cb.whi, cs, sn);
+        double v1 = endpoint_value(E[2 * g + 1], cb.d2, cb.wlo, cb.whi, cs, sn);
+        Lv += v1 > v0 ? rdiff(v0, v1, cb.d2) : 0.0;
+      }
+      acc += wt * Lv;
+    }
+    evals += (unsigned long long)ng;
+    L.pv[p] = acc;
+  }
+  block_count(L.cnt + CNT_EVAL_NODES, evals);
 }
 
 // The n_g nodes of one piece.  Gauss piece [a, a + H]: phi = a + H s(u_g),
@@ -569,6 +646,7 @@ static size_t ws_bytes(int64_t cc, int64_t cb, int64_t cp) {
   b += align256(cb * 4) + align256(cb * sizeof(ComboL)) + 2 * align256(cb * 4) + align256(cb * 8);
   b += 2 * align256(cp * 8) + align256(cp * 4) + align256(cp * 8) + 2 * align256(cp * 4);
   b += align256(cp) + align256(cc) + align256(cb * 4) + align256(cp * 4);
+  b += 3 * align256(cp * 4);
   b += align256(CNT_N * 8);
   return b;
 }
@@ -617,6 +695,9 @@ static stb_status ensure_workspace(stb_ctx* ctx, int64_t want_cand, int64_t want
   L.pv = (double*)take(want_piece * 8);
   L.pe = (float*)take(want_piece * 4);
   L.job = (int32_t*)take(want_piece * 4);
+  L.job2 = (int32_t*)take(want_piece * 4);
+  L.jobf = (int32_t*)take(want_piece * 4);
+  L.prec = (uint32_t*)take(want_piece * 4);
   L.job32 = (int32_t*)take(want_piece * 4);
   L.pne = (uint8_t*)take(want_piece);
   L.redo = (uint8_t*)take(want_cand);
@@ -707,14 +788,25 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(2));
     }
-    if ((s = rd(CNT_JOB, &njob))) return s;
-    unsigned long long njob32 = 0;
-    if (g.mixed && (s = rd(CNT_JOB32, &njob32))) return s;
-    if (njob) {
+    unsigned long long njob32 = 0, njob2 = 0, njobf = 0, hc[CNT_N];
+    HIPCHK(ctx, hipMemcpyAsync(hc, L.cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    njob = hc[CNT_JOB];
+    njob2 = hc[CNT_JOB2];
+    njobf = hc[CNT_JOBF];
+    njob32 = hc[CNT_JOB32];
+    if (njob + njob2 + njobf) {
+      // FP64 nodes: one-gap recipes, two-gap recipes, full evaluations
       HIPCHK(ctx, t0(4));
-      hipLaunchKernelGGL(k_nodes, dim3(gfor(4, njob)), dim3(ctx->tune_block[4]), 0, st, L, L.job,
-                         (int64_t)njob,
-                         job.gl, job.ng, (int)CNT_EVAL_NODES);
+      if (njob)
+        hipLaunchKernelGGL(k_nodes_rec<1>, dim3(gfor(4, njob)), dim3(ctx->tune_block[4]), 0, st, L,
+                           L.job, (int64_t)njob, job.gl, job.ng);
+      if (njob2)
+        hipLaunchKernelGGL(k_nodes_rec<2>, dim3(gfor(4, njob2)), dim3(ctx->tune_block[4]), 0, st, L,
+                           L.job2, (int64_t)njob2, job.gl, job.ng);
+      if (njobf)
+        hipLaunchKernelGGL(k_nodes, dim3(gfor(4, njobf)), dim3(ctx->tune_block[4]), 0, st, L, L.jobf,
+                           (int64_t)njobf, job.gl, job.ng, (int)CNT_EVAL_NODES);
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(4));
     }
