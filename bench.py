@@ -28,11 +28,11 @@ FP64_VECTOR_PEAK = 78.6e12      # MI355X dense FP64 vector FLOP/s
 # B, e, f, D, sqrt D, q and the two roots 14 (x 4 faces = 56), r-measure of
 # the admissible interval 6, interval bookkeeping 4.
 FLOP_PER_L = 80.0
-# HBM bytes per k_nodes launch on this workload: rocprofv3 FETCH_SIZE x 2.0 +
-# WRITE_SIZE x 1.0 (factors from a plain 1 GiB copy), averaged over the 16
-# assembly launches (profiles/k_nodes_icosphere_L2_S32.md).  Must be reset to
-# None whenever k_nodes changes, until it is profiled again.
-K_NODES_TRAFFIC_BYTES = 28.45e9
+# HBM bytes per launch group of the FP64 node stage on this workload:
+# rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a plain 1 GiB
+# copy), per assembly chunk (profiles/).  None whenever the node kernels have
+# changed since they were profiled.
+K_NODES_TRAFFIC_BYTES = None
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -351,7 +351,7 @@ def main():
         "phase_ms": rec["timings"],
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt_acc.items() if v[1]},
         "roofline": {
-            "bound": "alu", "kernel": "k_nodes",
+            "bound": "alu", "kernel": "FP64 node stage (k_nodes_rec<1>, k_nodes_rec<2>, k_nodes)",
             "achieved": achieved, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": K_NODES_TRAFFIC_BYTES,
             "flop_per_L": FLOP_PER_L, "L_evals_per_launch": k_units / max(k_n, 1),

@@ -47,10 +47,9 @@ struct TrialRec {
   double tmin, tmax, diam;           // time range; max(spatial diam, span)
   double cx, cy, cz, rad;            // spatial bounding ball
   double pad;
-  double phik[4], beta[4];           // per face: atan2(c, b), |(b, c)| (breakpoints)
-  double pad2[8];
 };
-static_assert(sizeof(TrialRec) == 80 * sizeof(double), "TrialRec layout");
+// 512 bytes: every candidate's lane reads one record, so it is kept small
+static_assert(sizeof(TrialRec) == 64 * sizeof(double), "TrialRec layout");
 
 // Bounding data of an apex set (the outer points of a test panel, or one
 // evaluation point) for the conservative causal cull.
@@ -410,9 +409,9 @@ STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
     }
   for (int k = 0; k < 4; ++k) {
     double a = T.fa[k], b = T.fb[k], c = T.fc[k], Ck = A.C[k];
-    double beta = T.beta[k];
+    double beta = sqrt(b * b + c * c);
     if (!(beta > 1e-12)) continue;
-    double phik = T.phik[k];
+    double phik = atan2(c, b);
     if (d2 > 0.0) {
       double rhs = a * a - Ck * Ck / d2;
       if (rhs >= 0.0 && rhs <= beta * beta) {
@@ -531,11 +530,6 @@ STB_HD inline int make_trial(const double (&X)[4][4], TrialRec& R) {
   }
   R.cx = cen[0]; R.cy = cen[1]; R.cz = cen[2]; R.rad = rad * (1.0 + 1e-12);
   R.pad = 0.0;
-  for (int k = 0; k < 4; ++k) {
-    R.beta[k] = sqrt(R.fb[k] * R.fb[k] + R.fc[k] * R.fc[k]);
-    R.phik[k] = atan2(R.fc[k], R.fb[k]);
-  }
-  for (int k = 0; k < 8; ++k) R.pad2[k] = 0.0;
   return 0;
 }
 

@@ -286,7 +286,7 @@ __device__ __forceinline__ unsigned route_of(const Lists& L, int32_t p, uint32_t
   return ng == 1 ? JOB_R1 : JOB_R2;
 }
 
-__global__ __launch_bounds__(kBlk, 2) void k_empty(Lists L, int64_t npiece) {
+__global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
   const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
   __shared__ int32_t s_q[kEmptyPer * kBlk];
@@ -329,15 +329,21 @@ __global__ __launch_bounds__(kBlk, 2) void k_empty(Lists L, int64_t npiece) {
       const int32_t p = s_q[e];
       const ComboL cb = load_combo(L, L.pc[p]);
       const double a = L.pa[p], H = L.ph[p];
+      // the test in plain arithmetic; the recipe only for the (few) pieces
+      // it finds non-empty, at the point that decided
       uint32_t rec = 0u;
-      double sn, cs;
-      sincos_small(a + 0.25 * H, &sn, &cs);
-      bool nz = L_eval_recipe(cb, cs, sn, &rec) != 0.0;
+      double phq = a + 0.25 * H;
+      bool nz = L_at(cb, phq) != 0.0;
       if (!nz) {
-        sincos_small(a + 0.75 * H, &sn, &cs);
-        nz = L_eval_recipe(cb, cs, sn, &rec) != 0.0;
+        phq = a + 0.75 * H;
+        nz = L_at(cb, phq) != 0.0;
       }
       ev_quarter += 2;
+      if (nz) {
+        double sn, cs;
+        sincos_small(phq, &sn, &cs);
+        (void)L_eval_recipe(cb, cs, sn, &rec);
+      }
       if (nz) {
         L.pne[p] = 1;
         L.prec[p] = rec;
