@@ -263,6 +263,12 @@ STB_HD __forceinline__ double L_eval(const FaceSet& F, const double* C, double d
 // max at a vertex; min among vertices, stationary points on the 6 edges and
 // in the non-vertical faces.  Returns the lit decision with the relative
 // dead zone kLitDead * (|t - tmin| + diam).
+// The cheap part of the lit decision: 0 = not lit (cone misses the panel's
+// time slab, bounding-ball rejection, or every vertex inside the cone),
+// 1 = lit (a vertex strictly inside and one strictly outside), 2 = the
+// vertices do not decide (lit_test's edge and face minima must).
+STB_HD inline int lit_quick(const TrialRec& T, const double* x4, const Apex& A);
+
 STB_HD inline bool lit_test(const TrialRec& T, const double* x4, const Apex& A) {
   double mn = 1e300, mx = -1e300;
 #pragma unroll
@@ -327,6 +333,25 @@ STB_HD inline bool lit_test(const TrialRec& T, const double* x4, const Apex& A) 
     mn = fmin(mn, f);
   }
   return mn < -dead;
+}
+
+STB_HD __forceinline__ bool ball_rejects(const TrialRec& T, const double* x4);
+
+STB_HD inline int lit_quick(const TrialRec& T, const double* x4, const Apex& A) {
+  if (!(A.t - T.tmin > fabs(A.d))) return 0;
+  if (ball_rejects(T, x4)) return 0;
+  double mn = 1e300, mx = -1e300;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double dx = x4[1] - T.X[k][1], dy = x4[2] - T.X[k][2], dz = x4[3] - T.X[k][3];
+    double f = sqrt(dx * dx + dy * dy + dz * dz) - (x4[0] - T.X[k][0]);
+    mn = fmin(mn, f);
+    mx = fmax(mx, f);
+  }
+  double dead = kLitDead * (fabs(A.t - T.tmin) + T.diam);
+  if (!(mx > dead)) return 0;
+  if (mn < -dead) return 1;
+  return 2;
 }
 
 // Quick rejection by the bounding 4-ball of the panel (Theorem

@@ -48,7 +48,7 @@ constexpr int kBlk = 256;
 constexpr int kMaxBlocks = 256 * 16;
 
 enum {
-  CNT_COMBO = 0, CNT_PIECE, CNT_JOB, CNT_JOB2, CNT_JOBF, CNT_JOB32, CNT_REDO, CNT_JOBR, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
+  CNT_COMBO = 0, CNT_DEEP, CNT_PIECE, CNT_JOB, CNT_JOB2, CNT_JOBF, CNT_JOB32, CNT_REDO, CNT_JOBR, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
   CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_EVAL_NODES32, CNT_EVAL_REDO, CNT_N
 };
 
@@ -102,6 +102,7 @@ struct Lists {
   int32_t* combo0;       // first combo of the candidate
   // per combo
   uint32_t* key;         // (candidate in chunk) << 8 | far << 7 | q
+  uint32_t* deep;        // (candidate in chunk) << 8 | q of lit tests the vertices left open
   double* cb;            // ComboL fields, structure of arrays: field f at f * cap_combo
   int32_t* p0;           // first piece
   int32_t* np;           // pieces
@@ -155,6 +156,10 @@ struct Geo {
   double eta_far;
 };
 
+// Lit test in two passes: the cheap part (slab, bounding ball, vertices)
+// for every (candidate, apex), then the edge and face minima only for the
+// few apexes the vertices leave open, densely -- a wave that ran them
+// inline would pay the long path whenever one of its 64 lanes needs it.
 __global__ __launch_bounds__(kBlk) void k_lit(Geo g, Lists L, int64_t c0, int64_t nc) {
   const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(kBlk) void k_lit(Geo g, Lists L, int64_t c0, int64_
   for (int64_t base = (int64_t)blockIdx.x * B; base < nc; base += (int64_t)gridDim.x * B) {
     const int64_t c = base + threadIdx.x;
     const bool v = c < nc;
-    uint64_t m = 0;
+    uint64_t m = 0, und = 0;
     int nq = 0;
     if (v) {
       const int64_t cg = c0 + c;
@@ -174,24 +179,62 @@ __global__ __launch_bounds__(kBlk) void k_lit(Geo g, Lists L, int64_t c0, int64_
         double x4[4] = {xr[4 * q], xr[4 * q + 1], xr[4 * q + 2], xr[4 * q + 3]};
         Apex A;
         apex_of(T, x4, A);
-        bool lit = A.t - T.tmin > fabs(A.d) && !ball_rejects(T, x4) && lit_test(T, x4, A);
-        m |= (uint64_t)lit << q;
+        const int r = lit_quick(T, x4, A);
+        m |= (uint64_t)(r == 1) << q;
+        und |= (uint64_t)(r == 2) << q;
       }
       pairs += (unsigned long long)nq;
+      L.mask[c] = m;
     }
+    const unsigned n = (unsigned)__popcll(und);
+    unsigned long long k = block_alloc(L.cnt + CNT_DEEP, n, sh);
+    if (v && k + n <= (unsigned long long)L.cap_combo)
+      for (int q = 0; q < nq; ++q)
+        if ((und >> q) & 1ull) L.deep[k++] = ((uint32_t)c << 8) | (uint32_t)q;
+  }
+  block_count(L.cnt + CNT_PAIRS, pairs);
+}
+
+__global__ __launch_bounds__(kBlk) void k_lit_deep(Geo g, Lists L, int64_t c0, int64_t ndeep) {
+  const int B = (int)blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * B + threadIdx.x; k < ndeep; k += (int64_t)gridDim.x * B) {
+    const uint32_t key = L.deep[k];
+    const int64_t c = key >> 8;
+    const int q = (int)(key & 255u);
+    const int64_t cg = c0 + c;
+    const int32_t i = g.rows[cg];
+    const TrialRec& T = g.trial[g.cols[cg]];
+    const double* xq = g.apex + ((int64_t)i * g.maxq + q) * 4;
+    double x4[4] = {xq[0], xq[1], xq[2], xq[3]};
+    Apex A;
+    apex_of(T, x4, A);
+    if (lit_test(T, x4, A)) atomicOr(reinterpret_cast<unsigned long long*>(L.mask + c), 1ull << q);
+  }
+}
+
+// Lit combos appended contiguously per candidate, in apex order.
+__global__ __launch_bounds__(kBlk) void k_emit(Geo g, Lists L, int64_t c0, int64_t nc) {
+  const int B = (int)blockDim.x;
+  __shared__ AllocLds sh;
+  for (int64_t base = (int64_t)blockIdx.x * B; base < nc; base += (int64_t)gridDim.x * B) {
+    const int64_t c = base + threadIdx.x;
+    const bool v = c < nc;
+    const uint64_t m = v ? L.mask[c] : 0ull;
     const unsigned n = (unsigned)__popcll(m);
     const unsigned long long b = block_alloc(L.cnt + CNT_COMBO, n, sh);
     if (v) {
-      L.mask[c] = m;
       L.combo0[c] = (int32_t)std::min<unsigned long long>(b, 0x7fffffffull);
       if (b + n <= (unsigned long long)L.cap_combo) {
         unsigned long long k = b;
-        for (int q = 0; q < nq; ++q)
-          if ((m >> q) & 1ull) L.key[k++] = ((uint32_t)c << 8) | (uint32_t)q;
+        uint64_t mm = m;
+        while (mm) {
+          const int q = __ffsll((long long)mm) - 1;
+          L.key[k++] = ((uint32_t)c << 8) | (uint32_t)q;
+          mm &= mm - 1;
+        }
       }
     }
   }
-  block_count(L.cnt + CNT_PAIRS, pairs);
 }
 
 __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t ncombo) {
@@ -649,7 +692,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 static size_t ws_bytes(int64_t cc, int64_t cb, int64_t cp) {
   size_t b = 0;
   b += align256(cc * 8) + align256(cc * 4);
-  b += align256(cb * 4) + align256(cb * sizeof(ComboL)) + 2 * align256(cb * 4) + align256(cb * 8);
+  b += 2 * align256(cb * 4) + align256(cb * sizeof(ComboL)) + 2 * align256(cb * 4) + align256(cb * 8);
   b += 2 * align256(cp * 8) + align256(cp * 4) + align256(cp * 8) + 2 * align256(cp * 4);
   b += align256(cp) + align256(cc) + align256(cb * 4) + align256(cp * 4);
   b += 3 * align256(cp * 4);
@@ -690,6 +733,7 @@ static stb_status ensure_workspace(stb_ctx* ctx, int64_t want_cand, int64_t want
   L.mask = (uint64_t*)take(want_cand * 8);
   L.combo0 = (int32_t*)take(want_cand * 4);
   L.key = (uint32_t*)take(want_combo * 4);
+  L.deep = (uint32_t*)take(want_combo * 4);
   L.cb = (double*)take(want_combo * sizeof(ComboL));
   L.p0 = (int32_t*)take(want_combo * 4);
   L.np = (int32_t*)take(want_combo * 4);
@@ -767,6 +811,18 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     HIPCHK(ctx, hipMemsetAsync(L.cnt, 0, CNT_N * 8, st));
     HIPCHK(ctx, t0(0));
     hipLaunchKernelGGL(k_lit, dim3(gfor(0, nc)), dim3(ctx->tune_block[0]), 0, st, g, L, c0, nc);
+    HIPCHK(ctx, hipGetLastError());
+    unsigned long long ndeep = 0;
+    if ((s = rd(CNT_DEEP, &ndeep))) return s;
+    if (ndeep > (unsigned long long)w->cap_combo) {
+      if (nc == 1) return stb_fail(ctx, STB_E_INTERNAL, "pair lists too small for one candidate");
+      chunk = std::max<int64_t>(1, (int64_t)((double)nc * w->cap_combo / ndeep * 0.8));
+      continue;
+    }
+    if (ndeep)
+      hipLaunchKernelGGL(k_lit_deep, dim3(gfor(0, ndeep)), dim3(ctx->tune_block[0]), 0, st, g, L, c0,
+                         (int64_t)ndeep);
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(0));
     unsigned long long ncombo = 0, npiece = 0, njob = 0;
