@@ -23,11 +23,20 @@ if ROOT not in sys.path:
 
 METRIC = "causal element-pairs/s, FP64 vs mixed at rel.err≤1e-6; serving p50/p99 latency"
 FP64_VECTOR_PEAK = 78.6e12      # MI355X dense FP64 vector FLOP/s
-# Algorithmic FLOPs of one L(phi) evaluation, counted from the formulas
-# (FMA = 2, divide / sqrt / sin / cos = 1): node map 12, sin + cos 2, per face
-# B, e, f, D, sqrt D, q and the two roots 14 (x 4 faces = 56), r-measure of
-# the admissible interval 6, interval bookkeeping 4.
-FLOP_PER_L = 80.0
+# FP64 operations of one evaluation of L(phi) at a Gauss node, by the path
+# that evaluates it, counted from the formulas (FMA = 2, add / mul = 1,
+# divide / sqrt / sin / cos = 1; min, max, compares and selects not counted):
+#   node map, weight and accumulation 12, sin + cos 2;
+#   one endpoint root (B, e, f, D, sqrt D, q, one quotient) 14;
+#   one face with both roots 16;  r-measure of one gap 6.
+# One-gap recipe: 12 + 2 + 2 x 14 + 6 = 48.  Two-gap recipe: 12 + 2 + 4 x 14
+# + 2 x 6 = 82.  Full evaluation: 12 + 2 + 4 x 16 + 5 x 6 (the gaps between
+# up to four holes) = 108.
+FLOP_PER_L = {"recipe1": 48.0, "recipe2": 82.0, "full": 108.0}
+
+
+def node_flops(counts):
+    return sum(FLOP_PER_L[k] * counts.get(k, 0) for k in FLOP_PER_L)
 # HBM bytes per launch group of the FP64 node stage on this workload:
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a plain 1 GiB
 # copy), per assembly chunk (profiles/).  None whenever the node kernels have
@@ -215,7 +224,7 @@ def batch_main(args):
     print("tuned on mesh %d: blocks %s per CU %s" % (big, blocks, per_cu), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     causal = np.zeros(len(mix), dtype=np.int64)
-    kt_acc = {}
+    kt_acc, ev_acc = {}, {}
     t0 = time.perf_counter()
     g = args.batch_group
     for k0 in range(0, len(mix), g):
@@ -227,13 +236,15 @@ def batch_main(args):
         for kk, (ms_k, n_k, u_k) in ctx.kernel_times().items():
             a = kt_acc.setdefault(kk, [0.0, 0, 0])
             a[0] += ms_k; a[1] += n_k; a[2] += u_k
+        for kk, v in ctx.path_counts().items():
+            ev_acc[kk] = ev_acc.get(kk, 0) + v
         print("meshes %d..%d done, %.1f s, causal pairs so far %d" %
               (k0, k0 + len(c) - 1, time.perf_counter() - t0, causal.sum()), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     k_ms, k_n, k_units = kt_acc.get("nodes_fp64", [0.0, 0, 0])
     avg_ms = k_ms / max(k_n, 1)
-    achieved = FLOP_PER_L * k_units / max(k_n, 1) / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    achieved = node_flops(ev_acc) / max(k_n, 1) / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     out = {
         "metric": METRIC, "value": float(causal.sum()) / dt, "unit": "causal element-pairs/s",
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": dt * 1e3, "higher_is_better": True,
@@ -244,10 +255,11 @@ def batch_main(args):
                                (len(mix), sum(m.nt for m in mix), g),
                    "causal_pairs": int(causal.sum())},
         "kernel_ms": {k: v[0] for k, v in kt_acc.items() if v[1]},
-        "roofline": {"bound": "alu", "kernel": "k_nodes", "achieved": achieved,
-                     "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+        "roofline": {"bound": "alu",
+                     "kernel": "FP64 node stage (k_nodes_rec<1>, k_nodes_rec<2>, k_nodes)",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": None,
-                     "avg_launch_ms": avg_ms, "launches": k_n},
+                     "avg_launch_ms": avg_ms, "launches": k_n, "path_counts": ev_acc},
     }
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -291,7 +303,7 @@ def main():
     ctx = stb.Context(0)
     rec = {}
 
-    kt_acc = {}
+    kt_acc, ev_acc = {}, {}
     params64 = stb.default_params()
     paramsmx = stb.default_params(prec=stb.STB_MIXED)
 
@@ -306,6 +318,9 @@ def main():
             for k, (ms_k, n_k, u_k) in ctx.kernel_times().items():
                 a = acc.setdefault(k, [0.0, 0, 0])
                 a[0] += ms_k; a[1] += n_k; a[2] += u_k
+            if acc is kt_acc:
+                for k, v in ctx.path_counts().items():
+                    ev_acc[k] = ev_acc.get(k, 0) + v
         A.apply_dev(w_d.data_ptr(), y_d.data_ptr(), 1)
         A.apply_dev(W_d.data_ptr(), Y_d.data_ptr(), 16)
         stb.potential_S_dev(ctx, m, wp_d.data_ptr(), args.points, pts_d.data_ptr(), u_d.data_ptr())
@@ -326,7 +341,7 @@ def main():
     # with HIP events on the library's stream during the timed steps
     k_ms, k_n, k_units = kt_acc.get("nodes_fp64", [0.0, 0, 0])
     avg_ms = k_ms / max(k_n, 1)
-    flops_per_launch = FLOP_PER_L * k_units / max(k_n, 1)
+    flops_per_launch = node_flops(ev_acc) / max(k_n, 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     out = {
         "metric": METRIC,
@@ -355,6 +370,8 @@ def main():
             "achieved": achieved, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": K_NODES_TRAFFIC_BYTES,
             "flop_per_L": FLOP_PER_L, "L_evals_per_launch": k_units / max(k_n, 1),
+            "node_evals_per_launch": {k: ev_acc.get(k, 0) / max(k_n, 1) for k in FLOP_PER_L},
+            "ray_empty_pieces": ev_acc.get("ray_empty_pieces", 0) // args.steps,
             "algorithmic_flops_per_launch": flops_per_launch, "avg_launch_ms": avg_ms,
             "launches": k_n, "work": rec["work"],
         },

@@ -241,6 +241,17 @@ void stb_server_destroy(stb_server* server);
  * compaction, [2] clip + quadrature + store, [3] total. */
 stb_status stb_last_timings(const stb_ctx* ctx, double* ms4);
 
+/* Path counts of the last assembly or batch on ctx.  [0..2]: evaluations of
+ * L(phi) in the FP64 Gauss-node launches (kernel kind 4 of
+ * stb_last_kernel_times) by the path that evaluated them: [0] pieces with
+ * one gap of a fixed endpoint structure (two endpoint formulas per node),
+ * [1] two gaps (four formulas), [2] the full evaluation over the four faces
+ * (Sec. 3.2, the (r, phi) rule).  [3]: phi pieces found empty without
+ * evaluating L, because the rays of all three test points (midpoint and
+ * quarter points) miss the panel's spatial shadow (each would otherwise
+ * cost three evaluations). */
+stb_status stb_last_path_counts(const stb_ctx* ctx, int64_t* counts4);
+
 /* Work of the last stb_assemble_V on ctx: [0] evaluations of L(phi)
  * (empty-piece tests and Gauss nodes), [1] lit (outer point, trial panel)
  * pairs, [2] candidate (outer point, trial panel) pairs examined, [3] phi

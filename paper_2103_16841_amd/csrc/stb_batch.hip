@@ -139,6 +139,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
   HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
   unsigned long long work_tot[4] = {0, 0, 0, 0};
   double kms[8] = {0}, kunits[8] = {0};
+  int64_t npath[4] = {0, 0, 0, 0};
   int64_t kn[8] = {0};
   std::vector<int64_t> causal(nmesh, 0);
   size_t u0 = 0;
@@ -259,6 +260,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
     if (s) { cleanup(false); return s; }
     for (int q = 0; q < 4; ++q) work_tot[q] += work[q];
     for (int q = 0; q < 8; ++q) { kms[q] += ctx->kern_ms[q]; kn[q] += ctx->kern_n[q]; kunits[q] += (double)ctx->kern_units[q]; }
+    for (int q = 0; q < 4; ++q) npath[q] += ctx->path_counts[q];
     std::vector<unsigned long long> h_causal(w.size());
     HIPCHK(ctx, hipMemcpyAsync(h_causal.data(), seg_causal, 8 * w.size(), hipMemcpyDeviceToHost, st));
     for (size_t m = 0; m < w.size(); ++m) {
@@ -289,6 +291,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
   HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
   HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
   for (int q = 0; q < 4; ++q) ctx->work[q] = (int64_t)work_tot[q];
+  for (int q = 0; q < 4; ++q) ctx->path_counts[q] = npath[q];
   for (int q = 0; q < 8; ++q) {
     ctx->kern_ms[q] = kms[q];
     ctx->kern_n[q] = kn[q];

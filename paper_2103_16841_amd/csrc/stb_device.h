@@ -473,6 +473,33 @@ STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
   return nb;
 }
 
+// A direction whose ray from the apex's projection (pu, pv) misses the
+// panel's spatial shadow (the hull of its vertices' (u, v)) carries no part
+// of the panel, so L = 0 there.  Sufficient test with a margin tol: every
+// vertex strictly on one side of the ray's line, or strictly behind it.
+STB_HD __forceinline__ bool ray_misses(const TrialRec& T, const Apex& A, double phi, double tol) {
+  double sn, cs;
+  sincos_small(phi, &sn, &cs);
+  bool left = true, right = true, behind = true;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double du = T.V[k][1] - A.pu, dv = T.V[k][2] - A.pv;
+    double cr = cs * dv - sn * du, dt = cs * du + sn * dv;
+    left = left && cr > tol;
+    right = right && cr < -tol;
+    behind = behind && dt < -tol;
+  }
+  return left || right || behind;
+}
+
+// The empty-piece test's three points (mid, then the quarter points) all
+// on rays that miss the panel: the piece is empty without evaluating L.
+STB_HD __forceinline__ bool piece_misses(const TrialRec& T, const Apex& A, double a, double H) {
+  const double tol = 1e-10 * (fabs(A.t - T.tmin) + T.diam);
+  return ray_misses(T, A, a + 0.5 * H, tol) && ray_misses(T, A, a + 0.25 * H, tol) &&
+         ray_misses(T, A, a + 0.75 * H, tol);
+}
+
 STB_HD __forceinline__ void sort_bp(double* a, int n) {
   for (int i = 1; i < n; ++i) {
     double v = a[i];
@@ -729,21 +756,6 @@ struct Endpoint {
   double cval;      // value when constant
   bool cst, isb;    // constant end; root -d^2 f / q (else q / e)
 };
-
-STB_HD __forceinline__ Endpoint endpoint_of(const ComboL& cb, int id) {
-  Endpoint E;
-  const int k = id >= 2 ? (id - 2) >> 1 : 0;
-  // select the face's coefficients (registers only)
-  const bool k1 = k & 1, k2 = (k >> 1) & 1;
-  E.a = k2 ? (k1 ? cb.fa[3] : cb.fa[2]) : (k1 ? cb.fa[1] : cb.fa[0]);
-  E.fb = k2 ? (k1 ? cb.fb[3] : cb.fb[2]) : (k1 ? cb.fb[1] : cb.fb[0]);
-  E.fc = k2 ? (k1 ? cb.fc[3] : cb.fc[2]) : (k1 ? cb.fc[1] : cb.fc[0]);
-  E.C = k2 ? (k1 ? cb.C[3] : cb.C[2]) : (k1 ? cb.C[1] : cb.C[0]);
-  E.cst = id < 2;
-  E.cval = id == 0 ? cb.wlo : cb.whi;
-  E.isb = id >= 2 && ((id - 2) & 1);
-  return E;
-}
 
 STB_HD __forceinline__ double endpoint_value(const Endpoint& E, double d2, double wlo, double whi,
                                              double cs, double sn) {

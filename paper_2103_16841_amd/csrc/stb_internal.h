@@ -21,6 +21,10 @@ struct stb_ctx {
   double kern_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t kern_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t kern_units[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // evaluations of L in the FP64 node launches (kind 4) by path: one-gap
+  // recipe, two-gap recipe, full evaluation; [3] pieces found empty by the
+  // ray test (no evaluation of L)
+  int64_t path_counts[4] = {0, 0, 0, 0};
   // launch shapes of the pair pipeline's stages (autotuned or defaults):
   // threads per block and blocks per compute unit, indexed like kern_ms
   int tune_block[8] = {256, 256, 256, 256, 256, 256, 256, 256};

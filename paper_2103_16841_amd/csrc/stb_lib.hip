@@ -930,6 +930,12 @@ stb_status stb_last_kernel_times(const stb_ctx* ctx, double* ms8, int64_t* launc
   return STB_OK;
 }
 
+stb_status stb_last_path_counts(const stb_ctx* ctx, int64_t* counts4) {
+  if (!ctx || !counts4) return fail(nullptr, STB_E_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 4; ++k) counts4[k] = ctx->path_counts[k];
+  return STB_OK;
+}
+
 stb_status stb_last_work(const stb_ctx* ctx, int64_t* counts4) {
   if (!ctx || !counts4) return fail(nullptr, STB_E_INVALID_ARG, "NULL argument");
   for (int k = 0; k < 4; ++k) counts4[k] = ctx->work[k];

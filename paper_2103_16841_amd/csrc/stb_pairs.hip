@@ -16,6 +16,8 @@
 //             phi-breakpoints (sorted) and the pieces between them, appended
 //             to the piece list, contiguous per combo in phi order; a combo
 //             without breakpoints gets two half-periods of the trapezoid rule.
+//             A piece whose three test points all lie on rays that miss the
+//             panel's spatial shadow is empty and is not listed.
 //   k_empty   one lane per piece: L at the midpoint, then, for the pieces where
 //             it is zero, at the quarter points (block-local queue); the
 //             non-empty pieces go to the job list.
@@ -36,6 +38,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 
 #include "stb_internal.h"
 #include "stb_pairs.h"
@@ -49,7 +52,7 @@ constexpr int kMaxBlocks = 256 * 16;
 
 enum {
   CNT_COMBO = 0, CNT_DEEP, CNT_PIECE, CNT_JOB, CNT_JOB2, CNT_JOBF, CNT_JOB32, CNT_REDO, CNT_JOBR, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
-  CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_EVAL_NODES32, CNT_EVAL_REDO, CNT_N
+  CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_EVAL_NODES32, CNT_EVAL_REDO, CNT_MISS, CNT_N
 };
 
 // Block-wide list allocation: every thread of the block calls it (n = 0
@@ -134,6 +137,35 @@ __device__ __forceinline__ void store_combo(const Lists& L, int64_t k, const Com
   const double* src = reinterpret_cast<const double*>(&cb);
 #pragma unroll
   for (int f = 0; f < kComboF; ++f) L.cb[(int64_t)f * L.cap_combo + k] = src[f];
+}
+
+// Field positions of ComboL in the combo list.
+constexpr int64_t kCbC = offsetof(ComboL, C) / sizeof(double);
+constexpr int64_t kCbD2 = offsetof(ComboL, d2) / sizeof(double);
+constexpr int64_t kCbWlo = offsetof(ComboL, wlo) / sizeof(double);
+constexpr int64_t kCbWhi = offsetof(ComboL, whi) / sizeof(double);
+constexpr int64_t kCbFa = offsetof(ComboL, fa) / sizeof(double);
+constexpr int64_t kCbFb = offsetof(ComboL, fb) / sizeof(double);
+constexpr int64_t kCbFc = offsetof(ComboL, fc) / sizeof(double);
+
+// One endpoint formula of a recipe read straight from the combo list: only
+// the selected face's four coefficients.  (Selecting the face among all four
+// in registers lets the compiler turn the selects into an indexed load from
+// a private copy of the arrays: 128 bytes of scratch traffic per piece.)
+__device__ __forceinline__ Endpoint endpoint_load(const Lists& L, int64_t c, int id, double wlo,
+                                                  double whi) {
+  const int64_t cap = L.cap_combo;
+  const int64_t k = id >= 2 ? (id - 2) >> 1 : 0;
+  const double* p = L.cb + c + k * cap;
+  Endpoint E;
+  E.C = p[kCbC * cap];
+  E.a = p[kCbFa * cap];
+  E.fb = p[kCbFb * cap];
+  E.fc = p[kCbFc * cap];
+  E.cst = id < 2;
+  E.cval = id == 0 ? wlo : whi;
+  E.isb = id >= 2 && ((id - 2) & 1);
+  return E;
 }
 
 __device__ __forceinline__ ComboL load_combo(const Lists& L, int64_t k) {
@@ -240,12 +272,14 @@ __global__ __launch_bounds__(kBlk) void k_emit(Geo g, Lists L, int64_t c0, int64
 __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t ncombo) {
   const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
+  unsigned long long nmiss = 0;
   for (int64_t base = (int64_t)blockIdx.x * B; base < ncombo; base += (int64_t)gridDim.x * B) {
     const int64_t k = base + threadIdx.x;
     const bool v = k < ncombo;
     double bp[kMaxBp];
     int nb = 0;
     unsigned np = 0;
+    unsigned long long miss = 0;   // pieces (by start breakpoint) found empty by the ray test
     if (v) {
       const uint32_t key = L.key[k];
       const int64_t cg = c0 + (key >> 8);
@@ -273,7 +307,13 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
         } else {
           for (int m = 0; m < nb; ++m) {
             double e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
-            np += (e - bp[m] > 0.0) ? 1u : 0u;
+            if (!(e - bp[m] > 0.0)) continue;
+            if (piece_misses(T, A, bp[m], e - bp[m])) {
+              miss |= 1ull << m;
+              ++nmiss;
+            } else {
+              ++np;
+            }
           }
         }
       }
@@ -294,7 +334,7 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
           for (int m = 0; m < nb; ++m) {
             double a = bp[m];
             double e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
-            if (!(e - a > 0.0)) continue;
+            if (!(e - a > 0.0) || ((miss >> m) & 1ull)) continue;
             L.pa[s] = a;
             L.ph[s] = e - a;
             L.pc[s] = (int32_t)k;
@@ -304,6 +344,7 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
       }
     }
   }
+  block_count(L.cnt + CNT_MISS, nmiss);
 }
 
 // The empty-piece test, kEmptyPer pieces per thread and pass (coalesced:
@@ -434,12 +475,15 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
     const int32_t p = jobs[k];
     const double H = L.ph[p], a = L.pa[p];
     const uint32_t rec = L.prec[p];
-    const ComboL cb = load_combo(L, L.pc[p]);
+    const int64_t c = L.pc[p];
+    const int64_t cap = L.cap_combo;
+    const double d2 = L.cb[kCbD2 * cap + c], wlo = L.cb[kCbWlo * cap + c],
+                 whi = L.cb[kCbWhi * cap + c];
     Endpoint E[2 * NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      E[2 * g] = endpoint_of(cb, (rec >> (8 * g + 4)) & 15u);
-      E[2 * g + 1] = endpoint_of(cb, (rec >> (8 * g)) & 15u);
+      E[2 * g] = endpoint_load(L, c, (rec >> (8 * g + 4)) & 15u, wlo, whi);
+      E[2 * g + 1] = endpoint_load(L, c, (rec >> (8 * g)) & 15u, wlo, whi);
     }
     double acc = 0.0;
     for (int gi = 0; gi < ng; ++gi) {
@@ -453,9 +497,9 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
       double Lv = 0.0;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        double v0 = endpoint_value(E[2 * g], cb.d2, cb.wlo, cb.whi, cs, sn);
-        double v1 = endpoint_value(E[2 * g + 1], cb.d2, cb.wlo, cb.whi, cs, sn);
-        Lv += v1 > v0 ? rdiff(v0, v1, cb.d2) : 0.0;
+        double v0 = endpoint_value(E[2 * g], d2, wlo, whi, cs, sn);
+        double v1 = endpoint_value(E[2 * g + 1], d2, wlo, whi, cs, sn);
+        Lv += v1 > v0 ? rdiff(v0, v1, d2) : 0.0;
       }
       acc += wt * Lv;
     }
@@ -789,6 +833,7 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     return STB_OK;
   };
   for (int k = 0; k < 8; ++k) { ctx->kern_ms[k] = 0.0; ctx->kern_n[k] = 0; ctx->kern_units[k] = 0; }
+  for (int k = 0; k < 4; ++k) ctx->path_counts[k] = 0;
   for (auto& e : ctx->kev)
     if (!e) HIPCHK(ctx, hipEventCreate(&e));
   bool used[8] = {false, false, false, false, false, false, false, false};
@@ -931,6 +976,10 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     ctx->kern_units[1] += (int64_t)ncombo;
     ctx->kern_units[2] += (int64_t)(h[CNT_EVAL_MID] + h[CNT_EVAL_QUARTER]);
     ctx->kern_units[4] += (int64_t)h[CNT_EVAL_NODES];
+    ctx->path_counts[0] += (int64_t)njob * job.ng;
+    ctx->path_counts[1] += (int64_t)njob2 * job.ng;
+    ctx->path_counts[2] += (int64_t)h[CNT_EVAL_NODES] - (int64_t)(njob + njob2) * job.ng;
+    ctx->path_counts[3] += (int64_t)h[CNT_MISS];
     ctx->kern_units[5] += (int64_t)h[CNT_EVAL_NODES32];
     ctx->kern_units[7] += (int64_t)h[CNT_EVAL_REDO];
     ctx->kern_units[3] += (int64_t)h[CNT_REDO];

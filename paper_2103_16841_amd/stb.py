@@ -21,7 +21,7 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_last_error", "stb_mesh_create", "stb_mesh_destroy", "stb_mesh_size",
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
            "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
-           "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_mesh_create_dev",
+           "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_last_path_counts", "stb_mesh_create_dev",
            "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble", "stb_autotune",
            "stb_set_tuning", "stb_server_create", "stb_server_add_mesh", "stb_server_submit",
            "stb_server_wait", "stb_server_destroy"]
@@ -92,6 +92,7 @@ def load():
     L.stb_last_timings.argtypes = [_VP, _D]
     L.stb_inner_values.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
     L.stb_last_work.argtypes = [_VP, _I64]
+    L.stb_last_path_counts.argtypes = [_VP, _I64]
     L.stb_last_kernel_times.argtypes = [_VP, _D, _I64, _I64]
     L.stb_mat_export.argtypes = [_VP, _I64, _I32, _D]
     L.stb_autotune.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _I32]
@@ -175,6 +176,15 @@ class Context:
         _chk(load().stb_last_work(self.h, out.ctypes.data_as(_I64)), self.h)
         return dict(L_evals=int(out[0]), lit_pairs=int(out[1]), apex_pairs=int(out[2]),
                     pieces=int(out[3]))
+
+    def path_counts(self):
+        """Evaluations of L in the FP64 Gauss-node launches of the last run by
+        path (recipe1, recipe2, full), and the pieces found empty by the ray
+        test without evaluating L (ray_empty_pieces)."""
+        out = np.zeros(4, dtype=np.int64)
+        _chk(load().stb_last_path_counts(self.h, out.ctypes.data_as(_I64)), self.h)
+        return dict(recipe1=int(out[0]), recipe2=int(out[1]), full=int(out[2]),
+                    ray_empty_pieces=int(out[3]))
 
 
 class Mesh:

@@ -310,5 +310,10 @@ def test_work_counters(stb, ctx, cube):
     # sliver piece between two nearly coincident breakpoints where L is
     # rounding noise (~1e-17) on one side and exactly 0 on the other costs
     # n_g node evaluations that contribute nothing
+    # pieces the ray test finds empty skip the three evaluations of the
+    # empty-piece test
+    pc = ctx.path_counts()
+    assert pc["ray_empty_pieces"] > 0
     assert abs(w["lit_pairs"] - st.n_lit) <= 0.01 * st.n_lit
-    assert abs(w["L_evals"] - st.n_eval) <= 0.03 * st.n_eval
+    evals = w["L_evals"] + 3 * pc["ray_empty_pieces"]
+    assert abs(evals - st.n_eval) <= 0.03 * st.n_eval
