@@ -167,16 +167,18 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
       w.push_back(x);
     }
     TrialRec* trial_g = nullptr;
+    FaceAng* fang_g = nullptr;
     double *apex_g = nullptr, *apexw_g = nullptr, *vals_g = nullptr;
     int32_t *apexn_g = nullptr, *rows_g = nullptr, *cols_g = nullptr;
     int64_t* seg_off = nullptr;
     unsigned long long* seg_causal = nullptr;
     auto cleanup = [&](bool keep) {
-      dfree(trial_g); dfree(apex_g); dfree(apexw_g); dfree(apexn_g); dfree(rows_g); dfree(cols_g);
+      dfree(trial_g); dfree(fang_g); dfree(apex_g); dfree(apexw_g); dfree(apexn_g); dfree(rows_g); dfree(cols_g);
       dfree(vals_g); dfree(seg_off); dfree(seg_causal);
       release(w, keep);
     };
     bool ok = dalloc(&trial_g, (size_t)panels) == hipSuccess &&
+              dalloc(&fang_g, (size_t)panels) == hipSuccess &&
               dalloc(&apex_g, (size_t)panels * maxq * 4) == hipSuccess &&
               dalloc(&apexw_g, (size_t)panels * maxq) == hipSuccess &&
               dalloc(&apexn_g, (size_t)panels) == hipSuccess &&
@@ -213,6 +215,8 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
       hipError_t e = hipMemcpyAsync(trial_g + op, me->d_trial, sizeof(TrialRec) * me->nt,
                                     hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess)
+        e = hipMemcpyAsync(fang_g + op, me->d_fang, sizeof(FaceAng) * me->nt, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess)
         e = hipMemcpyAsync(apex_g + op * maxq * 4, me->d_opts, sizeof(double) * me->nt * maxq * 4,
                            hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess)
@@ -243,6 +247,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
     J.rows = rows_g;
     J.cols = cols_g;
     J.trial = trial_g;
+    J.fang = fang_g;
     J.apex = apex_g;
     J.apex_w = apexw_g;
     J.apex_n = apexn_g;
@@ -342,6 +347,7 @@ extern "C" stb_status stb_autotune(stb_ctx* ctx, const stb_mesh* mesh_c,
     J.rows = rs;
     J.cols = cs;
     J.trial = mesh->d_trial;
+    J.fang = mesh->d_fang;
     J.apex = mesh->d_opts;
     J.apex_w = mesh->d_ow;
     J.apex_n = mesh->d_onq;

@@ -53,6 +53,13 @@ static_assert(sizeof(TrialRec) == 64 * sizeof(double), "TrialRec layout");
 
 // Bounding data of an apex set (the outer points of a test panel, or one
 // evaluation point) for the conservative causal cull.
+// Polar form of each face's spatial normal (b_k, c_k) = beta_k (cos phi_k,
+// sin phi_k): B_k(phi) = beta_k cos(phi - phi_k).  Per panel, used by the
+// breakpoints.
+struct FaceAng {
+  double phi[4], beta[4];
+};
+
 struct ApexBox {
   double tlo, thi;   // apex time range
   double cx, cy, cz; // centre of the spatial bounding ball
@@ -372,26 +379,75 @@ STB_HD __forceinline__ bool ball_rejects(const TrialRec& T, const double* x4) {
   return (phi + r * s2 < -margin) || (phi - dr > margin);
 }
 
-// Stable roots of qa l^2 + qb l + qc = 0; returns count.
+// atan2 for breakpoint angles (range (-pi, pi]).  With t = min/max of |x|,
+// |y| in [0, 1] and c the multiple of 1/4 nearest to t,
+//   atan t = atan c + atan u,  u = (t - c) / (1 + t c) = (min - c max) / (max + c min),
+// |u| <= 1/8, and atan u is its odd Taylor series to u^17 (remainder below
+// u^19 / 19 < 4e-19).  atan c is a table of three values in two parts
+// each; the octant follows from |y| > |x|, x < 0 and the sign of y.
+// Absolute error about 2e-16; one quotient instead of the library's range
+// reduction with several.
+STB_HD __forceinline__ double atan2_bp(double y, double x) {
+  const double ax = fabs(x), ay = fabs(y);
+  const double mx = fmax(ax, ay), mn = fmin(ax, ay);
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double tq = mn * __builtin_amdgcn_rcp(mx);   // only picks c
+#else
+  const double tq = mn / mx;
+#endif
+  const double i = rint(4.0 * tq);
+  const double c = 0.25 * i;
+  const double u = fma(-c, mx, mn) * frcp(fma(c, mn, mx));
+  const double u2 = u * u;
+  double p = 1.0 / 17.0;
+  p = fma(p, u2, -1.0 / 15.0);
+  p = fma(p, u2, 1.0 / 13.0);
+  p = fma(p, u2, -1.0 / 11.0);
+  p = fma(p, u2, 1.0 / 9.0);
+  p = fma(p, u2, -1.0 / 7.0);
+  p = fma(p, u2, 1.0 / 5.0);
+  p = fma(p, u2, -1.0 / 3.0);
+  const double au = fma(u * u2, p, u);
+  // atan(i / 4), high and low parts
+  const double th_hi = i < 0.5 ? 0.0 : i < 1.5 ? 0.24497866312686414 : i < 2.5 ? 0.4636476090008061
+                     : i < 3.5 ? 0.6435011087932844 : 0.7853981633974483;
+  const double th_lo = i < 0.5 ? 0.0 : i < 1.5 ? 1.0699e-17 : i < 2.5 ? 2.2699e-17
+                     : i < 3.5 ? 1.5835e-17 : 3.0616e-17;
+  double th = th_hi + (au + th_lo);                        // atan(mn / mx), [0, pi/4]
+  th = ay > ax ? (1.5707963267948966 - th) + 6.123233995736766e-17 : th;
+  th = x < 0.0 ? (3.141592653589793 - th) + 1.2246467991473532e-16 : th;
+  th = copysign(th, y);
+  return mx > 0.0 ? th : 0.0;
+}
+
+// acos x = atan2(sqrt((1 - x)(1 + x)), x) for x in [-1, 1].
+STB_HD __forceinline__ double acos_bp(double x) {
+  return atan2_bp(sqrt(fmax((1.0 - x) * (1.0 + x), 0.0)), x);
+}
+
+// Stable roots of qa l^2 + qb l + qc = 0; returns count.  Quotients by the
+// refined reciprocal (within an ulp; the correctly rounded division costs
+// registers that limit the breakpoint kernel's occupancy).
 STB_HD __forceinline__ int roots2(double qa, double qb, double qc, double* r) {
   if (qa == 0.0) {
     if (qb == 0.0) return 0;
-    r[0] = -qc / qb;
+    r[0] = -qc * frcp(qb);
     return 1;
   }
   double disc = qb * qb - 4.0 * qa * qc;
+  double rqa = frcp(qa);
   if (disc < 0.0) {
     // the cone touching an edge: a double root lost to rounding
     if (disc >= -1e-12 * (qb * qb + fabs(4.0 * qa * qc))) {
-      r[0] = -qb / (2.0 * qa);
+      r[0] = -0.5 * qb * rqa;
       return 1;
     }
     return 0;
   }
   double q = -0.5 * (qb + copysign(sqrt(disc), qb));
   if (q == 0.0) { r[0] = 0.0; return 1; }
-  r[0] = q / qa;
-  r[1] = qc / q;
+  r[0] = q * rqa;
+  r[1] = qc * frcp(q);
   return 2;
 }
 
@@ -400,7 +456,15 @@ STB_HD __forceinline__ int roots2(double qa, double qb, double qc, double* r) {
 // closed panel; B_k = 0 where the hyperboloid vertex is within kVtxHint of
 // face k's plane; B_k = a_k for an apex on face k's plane inside the
 // panel's hyperplane (d = 0, C_k = 0).
-STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
+STB_HD inline void face_angles(const TrialRec& T, FaceAng& F) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    F.beta[k] = sqrt(T.fb[k] * T.fb[k] + T.fc[k] * T.fc[k]);
+    F.phi[k] = atan2(T.fc[k], T.fb[k]);
+  }
+}
+
+STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& A, double* bp) {
   int nb = 0;
   double d2 = A.d * A.d, ad = fabs(A.d);
   double sc = fabs(A.t - T.tmin) + T.diam;
@@ -412,6 +476,9 @@ STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
     fv[k] = sqrt(du * du + dv * dv + d2) - (A.t - T.V[k][0]);
   }
   const double inside = -1e-9 * sc;
+  // edge events (at most 12): the in-plane offsets (ou, ov) first, kept in
+  // bp[m] and bp[16 + m], then their angles in one loop
+  int nh = 0;
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j) {
       if (fv[i] < inside && fv[j] < inside) continue;
@@ -429,19 +496,23 @@ STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
         if (a0 + a1 * l < 0.0) continue;
         double ou = bu + l * du, ov = bv + l * dv;
         if (ou * ou + ov * ov <= 1e-20 * sc * sc) continue;
-        bp[nb++] = wrap_2pi(atan2(ov, ou));
+        bp[nh] = ou;
+        bp[16 + nh] = ov;
+        ++nh;
       }
     }
+  for (int m = 0; m < nh; ++m) bp[m] = wrap_2pi(atan2_bp(bp[16 + m], bp[m]));
+  nb = nh;
   for (int k = 0; k < 4; ++k) {
     double a = T.fa[k], b = T.fb[k], c = T.fc[k], Ck = A.C[k];
-    double beta = sqrt(b * b + c * c);
+    double beta = FA.beta[k];
     if (!(beta > 1e-12)) continue;
-    double phik = atan2(c, b);
+    double phik = FA.phi[k];
     if (d2 > 0.0) {
       double rhs = a * a - Ck * Ck / d2;
       if (rhs >= 0.0 && rhs <= beta * beta) {
         double cv = fmin(sqrt(rhs) / beta, 1.0);
-        double g = acos(cv);
+        double g = acos_bp(cv);
         double cand[4] = {phik + g, phik - g, phik + kPi - g, phik + kPi + g};
         for (int m = 0; m < 4; ++m) {
           double sn, cs;
@@ -465,7 +536,7 @@ STB_HD inline int breakpoints(const TrialRec& T, const Apex& A, double* bp) {
       bp[nb++] = wrap_2pi(phik - 0.5 * kPi);
     }
     if (ad <= kFlatTol * sc && fabs(Ck) <= kFlatTol * sc && fabs(a) <= beta) {
-      double g = acos(fmax(-1.0, fmin(1.0, a / beta)));
+      double g = acos_bp(fmax(-1.0, fmin(1.0, a / beta)));
       bp[nb++] = wrap_2pi(phik + g);
       bp[nb++] = wrap_2pi(phik - g);
     }
@@ -500,7 +571,34 @@ STB_HD __forceinline__ bool piece_misses(const TrialRec& T, const Apex& A, doubl
          ray_misses(T, A, a + 0.75 * H, tol);
 }
 
+// Sorts a[0..n).  Up to 16 values (nearly every (apex, panel) pair): into
+// registers (padded with +inf), Batcher's odd-even merge network, back --
+// independent loads and stores instead of the insertion sort's dependent
+// chain through private memory.
 STB_HD __forceinline__ void sort_bp(double* a, int n) {
+  if (n <= 16) {
+    double r[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) r[j] = j < n ? a[j] : HUGE_VAL;
+#pragma unroll
+    for (int p = 1; p < 16; p <<= 1)
+#pragma unroll
+      for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+        for (int j = k % p; j + k < 16; j += 2 * k)
+#pragma unroll
+          for (int i = 0; i < k && i + j + k < 16; ++i)
+            if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+              const double lo = fmin(r[i + j], r[i + j + k]);
+              const double hi = fmax(r[i + j], r[i + j + k]);
+              r[i + j] = lo;
+              r[i + j + k] = hi;
+            }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j < n) a[j] = r[j];
+    return;
+  }
   for (int i = 1; i < n; ++i) {
     double v = a[i];
     int j = i - 1;
@@ -981,7 +1079,9 @@ STB_HD inline double inner_serial(const TrialRec& T, const double* x4, int ng, c
   }
   cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
   double bp[kMaxBp];
-  int nb = breakpoints(T, A, bp);
+  FaceAng FA;
+  face_angles(T, FA);
+  int nb = breakpoints(T, FA, A, bp);
   sort_bp(bp, nb);
   double I = 0.0;
   if (nb == 0) {

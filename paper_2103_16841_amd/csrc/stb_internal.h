@@ -42,6 +42,7 @@ struct stb_mesh {
   double* d_vtx = nullptr;
   int32_t* d_tet = nullptr;
   stb::TrialRec* d_trial = nullptr;
+  stb::FaceAng* d_fang = nullptr;   // [nt] polar form of the face normals
   // outer points for one m_q (recomputed when m_q changes)
   int mq = 0;
   int maxq = 0;

@@ -65,7 +65,7 @@ __global__ void k_check_index(int64_t nt, int64_t nv, const int32_t* __restrict_
 // Panel geometry.  status[j]: 0 ok, 1 non-finite, else as make_trial.
 __global__ void k_geometry(int64_t nt, const double* __restrict__ vtx,
                            const int32_t* __restrict__ tet, TrialRec* __restrict__ out,
-                           int32_t* __restrict__ status) {
+                           FaceAng* __restrict__ fang, int32_t* __restrict__ status) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nt) return;
   double X[4][4];
@@ -80,7 +80,12 @@ __global__ void k_geometry(int64_t nt, const double* __restrict__ vtx,
   if (st == 0) {
     TrialRec R;
     st = make_trial(X, R);
-    if (st == 0) out[j] = R;
+    if (st == 0) {
+      out[j] = R;
+      FaceAng F;
+      face_angles(R, F);
+      fang[j] = F;
+    }
   }
   status[j] = st;
 }
@@ -215,7 +220,9 @@ __global__ void k_debug_pair(const TrialRec* __restrict__ trial, const double* _
   Apex A;
   apex_of(T, x4, A);
   double bp[kMaxBp];
-  int nb = breakpoints(T, A, bp);
+  FaceAng FA;
+  face_angles(T, FA);
+  int nb = breakpoints(T, FA, A, bp);
   sort_bp(bp, nb);
   out[0] = nb;
   for (int k = 0; k < nb; ++k) out[1 + k] = bp[k];
@@ -547,7 +554,8 @@ static stb_status mesh_create_impl(stb_ctx* ctx, int64_t nv, const double* vtx, 
     stb_mesh_destroy(m);
   };
   if (dalloc(&m->d_vtx, (size_t)nv * 4) != hipSuccess || dalloc(&m->d_tet, (size_t)nt * 4) != hipSuccess ||
-      dalloc(&m->d_trial, (size_t)nt) != hipSuccess || dalloc(&d_status, (size_t)nt) != hipSuccess) {
+      dalloc(&m->d_trial, (size_t)nt) != hipSuccess || dalloc(&m->d_fang, (size_t)nt) != hipSuccess ||
+      dalloc(&d_status, (size_t)nt) != hipSuccess) {
     cleanup();
     return fail(ctx, STB_E_NO_MEMORY, "device allocation for %lld panels failed", (long long)nt);
   }
@@ -572,7 +580,7 @@ static stb_status mesh_create_impl(stb_ctx* ctx, int64_t nv, const double* vtx, 
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_geometry, dim3((unsigned)((nt + 127) / 128)), dim3(128), 0, ctx->stream, nt,
-                       m->d_vtx, m->d_tet, m->d_trial, d_status);
+                       m->d_vtx, m->d_tet, m->d_trial, m->d_fang, d_status);
     e = hipGetLastError();
   }
   if (e == hipSuccess)
@@ -607,7 +615,7 @@ stb_status stb_mesh_create_dev(stb_ctx* ctx, int64_t nv, const double* vtx_dev, 
 
 void stb_mesh_destroy(stb_mesh* m) {
   if (!m) return;
-  dfree(m->d_vtx); dfree(m->d_tet); dfree(m->d_trial);
+  dfree(m->d_vtx); dfree(m->d_tet); dfree(m->d_trial); dfree(m->d_fang);
   dfree(m->d_opts); dfree(m->d_ow); dfree(m->d_onq); dfree(m->d_box);
   delete m;
 }
@@ -644,6 +652,7 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   J.rows = d_rowof;
   J.cols = M->d_cols;
   J.trial = mesh->d_trial;
+  J.fang = mesh->d_fang;
   J.apex = mesh->d_opts;
   J.apex_w = mesh->d_ow;
   J.apex_n = mesh->d_onq;
@@ -810,6 +819,7 @@ stb_status stb_potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_param
   J.rows = d_rowof;
   J.cols = d_cols;
   J.trial = mesh->d_trial;
+  J.fang = mesh->d_fang;
   J.apex = d_pts;
   J.apex_w = nullptr;
   J.apex_n = nullptr;

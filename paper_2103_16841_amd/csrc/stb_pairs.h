@@ -8,6 +8,7 @@ struct PairJob {
   const int32_t* rows = nullptr;     // [nnz] row of each candidate
   const int32_t* cols = nullptr;     // [nnz] trial panel of each candidate
   const stb::TrialRec* trial = nullptr;
+  const stb::FaceAng* fang = nullptr;  // [panels]
   const double* apex = nullptr;      // [rows][maxq][4] (t, x, y, z)
   const double* apex_w = nullptr;    // [rows][maxq] outer weights; nullptr: potential
   const int32_t* apex_n = nullptr;   // [rows] apexes per row; nullptr: one

@@ -180,6 +180,7 @@ struct Geo {
   const int32_t* rows;   // row of each candidate (global index)
   const int32_t* cols;   // trial panel of each candidate
   const TrialRec* trial;
+  const FaceAng* fang;   // per trial panel
   const double* apex;    // [rows][maxq][4]
   const double* apex_w;  // [rows][maxq] (matrix) or nullptr (potential)
   const int32_t* apex_n; // [rows] or nullptr (one apex)
@@ -285,7 +286,8 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
       const int64_t cg = c0 + (key >> 8);
       const int q = (int)(key & 63u);
       const int32_t i = g.rows[cg];
-      const TrialRec& T = g.trial[g.cols[cg]];
+      const int32_t col = g.cols[cg];
+      const TrialRec& T = g.trial[col];
       const double* xq = g.apex + ((int64_t)i * g.maxq + q) * 4;
       double x4[4] = {xq[0], xq[1], xq[2], xq[3]};
       Apex A;
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
         cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
         store_combo(L, k, cb);
         if (g.mixed && apex_far(T, x4, g.eta_far)) L.key[k] = key | 0x80u;
-        nb = breakpoints(T, A, bp);
+        nb = breakpoints(T, g.fang[col], A, bp);
         sort_bp(bp, nb);
         if (nb == 0) {
           np = 2;
@@ -817,7 +819,7 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
   PairWorkspace* w = ctx->ws;
   Lists L = w->L;
   Geo g;
-  g.rows = job.rows; g.cols = job.cols; g.trial = job.trial;
+  g.rows = job.rows; g.cols = job.cols; g.trial = job.trial; g.fang = job.fang;
   g.apex = job.apex; g.apex_w = job.apex_w; g.apex_n = job.apex_n; g.maxq = job.maxq;
   g.mixed = job.mixed ? 1 : 0;
   g.eta_far = job.eta_far;
