@@ -168,6 +168,27 @@ STB_HD __forceinline__ double frcp(double x) {
   return fma(r, e, r);
 }
 
+// sqrt(max(D, 0)) of a face discriminant: v_rsq_f64, one Goldschmidt and
+// one Newton step (about an ulp; the library's square root adds a second
+// Newton step, range scaling and special-value selects).  D below 2^-900
+// gives 0: its root, below 2^-450, is far under an ulp of the C_k it is
+// added to.
+STB_HD __forceinline__ double sqrt_disc(double D) {
+  const bool pos = D > 0x1p-900;
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double x = pos ? D : 1.0;
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  g = fma(fma(-g, g, x), h, g);
+  return pos ? g : 0.0;
+#else
+  return pos ? sqrt(D) : 0.0;
+#endif
+}
+
 // r(w1) - r(w0) = (w1 - w0) (1 - d^2 / (w0 w1)) / 2 for w1 >= w0 > 0 (or
 // d^2 = 0, where w0 may be 0).
 STB_HD __forceinline__ double rdiff(double w0, double w1, double d2) {
@@ -219,7 +240,7 @@ STB_HD __forceinline__ double L_eval(const FaceSet& F, const double* C, double d
     double e = B - a, f = B + a, Ck = C[k];
     double D = fma(Ck, Ck, d2 * (e * f));
     bool two = D > 0.0;
-    double q = Ck + copysign(sqrt(fmax(D, 0.0)), Ck);
+    double q = Ck + copysign(sqrt_disc(D), Ck);
     double w1 = q * frcp(e);
     double w2 = -d2 * f * frcp(q);
     double mn = fmin(w1, w2), mx = fmax(w1, w2);
@@ -777,7 +798,7 @@ STB_HD inline double L_eval_recipe(const ComboL& cb, double cs, double sn, uint3
     double e = B - a, f = B + a, Ck = cb.C[k];
     double D = fma(Ck, Ck, d2 * (e * f));
     bool two = D > 0.0;
-    double q = Ck + copysign(sqrt(fmax(D, 0.0)), Ck);
+    double q = Ck + copysign(sqrt_disc(D), Ck);
     double w1 = q * frcp(e);
     double w2 = -d2 * f * frcp(q);
     const int ia = 2 + 2 * k, ib = 3 + 2 * k;
@@ -860,13 +881,25 @@ STB_HD __forceinline__ double endpoint_value(const Endpoint& E, double d2, doubl
   double B = fma(E.fb, cs, E.fc * sn);
   double e = B - E.a, f = B + E.a;
   double D = fma(E.C, E.C, d2 * (e * f));
-  double q = E.C + copysign(sqrt(fmax(D, 0.0)), E.C);
+  double q = E.C + copysign(sqrt_disc(D), E.C);
   double num = E.isb ? -d2 * f : q;
   double den = E.isb ? q : e;
   double v = num * frcp(den);
   v = E.cst ? E.cval : v;
   // the admissible set lies in [wlo, whi]; a formula evaluated just past
   // the structure it was chosen for (rounding at a piece's end) stays there
+  return fmin(fmax(v, wlo), whi);
+}
+
+// endpoint_value for a q / e root (not a constant, not the -d^2 f / q root):
+// the same operations without the selects.
+STB_HD __forceinline__ double endpoint_value_qe(const Endpoint& E, double d2, double wlo, double whi,
+                                                double cs, double sn) {
+  double B = fma(E.fb, cs, E.fc * sn);
+  double e = B - E.a, f = B + E.a;
+  double D = fma(E.C, E.C, d2 * (e * f));
+  double q = E.C + copysign(sqrt_disc(D), E.C);
+  double v = q * frcp(e);
   return fmin(fmax(v, wlo), whi);
 }
 

@@ -51,7 +51,7 @@ constexpr int kBlk = 256;
 constexpr int kMaxBlocks = 256 * 16;
 
 enum {
-  CNT_COMBO = 0, CNT_DEEP, CNT_PIECE, CNT_JOB, CNT_JOB2, CNT_JOBF, CNT_JOB32, CNT_REDO, CNT_JOBR, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
+  CNT_COMBO = 0, CNT_DEEP, CNT_PIECE, CNT_JOB, CNT_JOB1X, CNT_JOB2, CNT_JOBF, CNT_JOB32, CNT_REDO, CNT_JOBR, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
   CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_EVAL_NODES32, CNT_EVAL_REDO, CNT_MISS, CNT_N
 };
 
@@ -358,7 +358,10 @@ __global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t
 constexpr int kEmptyPer = 8;
 
 // Job lists the empty-piece test routes a non-empty piece to.
-enum { JOB_R1 = 0, JOB_R2 = 1, JOB_FULL = 2, JOB_FP32 = 3 };
+// One-gap recipes whose two endpoints are both q / e roots (nearly all of
+// them) go to the front of the one-gap list, the other one-gap recipes to
+// its back (filled downward from the end).
+enum { JOB_R1Q = 0, JOB_R2 = 1, JOB_FULL = 2, JOB_FP32 = 3, JOB_R1X = 4 };
 
 // Pieces narrower than this take the full evaluation: their nodes sit
 // within rounding of the breakpoints, where the structure is ambiguous.
@@ -369,7 +372,10 @@ __device__ __forceinline__ unsigned route_of(const Lists& L, int32_t p, uint32_t
   const double H = L.ph[p];
   const int ng = recipe_gaps(rec);
   if (rec == 0u || !(H >= kRecipeMinH)) return JOB_FULL;
-  return ng == 1 ? JOB_R1 : JOB_R2;
+  if (ng != 1) return JOB_R2;
+  const uint32_t i0 = (rec >> 4) & 15u, i1 = rec & 15u;
+  const bool qe = i0 >= 2 && i1 >= 2 && !((i0 - 2) & 1u) && !((i1 - 2) & 1u);
+  return qe ? JOB_R1Q : JOB_R1X;
 }
 
 __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
@@ -382,7 +388,7 @@ __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
   for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < npiece; base += step) {
     if (threadIdx.x == 0) s_nq = 0;
     __syncthreads();
-    unsigned ne = 0, route = 0;   // route: 2 bits per item
+    unsigned ne = 0, route = 0;   // route: 3 bits per item
 #pragma unroll 1
     for (int j = 0; j < kEmptyPer; ++j) {
       const int64_t p = base + (int64_t)j * B + threadIdx.x;
@@ -401,7 +407,7 @@ __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
       L.pne[p] = nz ? 1 : 0;
       L.prec[p] = rec;
       ne |= (nz ? 1u : 0u) << j;
-      if (nz) route |= route_of(L, (int32_t)p, rec) << (2 * j);
+      if (nz) route |= route_of(L, (int32_t)p, rec) << (3 * j);
       if (!nz) s_q[atomicAdd(&s_nq, 1)] = (int32_t)p;
     }
     __syncthreads();
@@ -433,31 +439,30 @@ __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
       if (nz) {
         L.pne[p] = 1;
         L.prec[p] = rec;
-        qroute |= route_of(L, p, rec) << (2 * m);
+        qroute |= route_of(L, p, rec) << (3 * m);
       }
       qne |= (nz ? 1u : 0u) << m;
     }
-    unsigned cnt[4] = {0, 0, 0, 0};
+    unsigned cnt[5] = {0, 0, 0, 0, 0};
     for (int j = 0; j < kEmptyPer; ++j)
-      if ((ne >> j) & 1u) ++cnt[(route >> (2 * j)) & 3u];
+      if ((ne >> j) & 1u) ++cnt[(route >> (3 * j)) & 7u];
     for (int m = 0; m < kEmptyPer; ++m)
-      if ((qne >> m) & 1u) ++cnt[(qroute >> (2 * m)) & 3u];
-    unsigned long long sl[4];
-    sl[JOB_R1] = block_alloc(L.cnt + CNT_JOB, cnt[JOB_R1], sh);
+      if ((qne >> m) & 1u) ++cnt[(qroute >> (3 * m)) & 7u];
+    unsigned long long sl[5];
+    sl[JOB_R1Q] = block_alloc(L.cnt + CNT_JOB, cnt[JOB_R1Q], sh);
     sl[JOB_R2] = block_alloc(L.cnt + CNT_JOB2, cnt[JOB_R2], sh);
     sl[JOB_FULL] = block_alloc(L.cnt + CNT_JOBF, cnt[JOB_FULL], sh);
     sl[JOB_FP32] = block_alloc(L.cnt + CNT_JOB32, cnt[JOB_FP32], sh);
+    sl[JOB_R1X] = block_alloc(L.cnt + CNT_JOB1X, cnt[JOB_R1X], sh);
     int32_t* lists[4] = {L.job, L.job2, L.jobf, L.job32};
-    for (int j = 0; j < kEmptyPer; ++j) {
-      if (!((ne >> j) & 1u)) continue;
-      const unsigned r = (route >> (2 * j)) & 3u;
-      lists[r][sl[r]++] = (int32_t)(base + (int64_t)j * B + threadIdx.x);
-    }
-    for (int m = 0; m < kEmptyPer; ++m) {
-      if (!((qne >> m) & 1u)) continue;
-      const unsigned r = (qroute >> (2 * m)) & 3u;
-      lists[r][sl[r]++] = s_q[m * B + threadIdx.x];
-    }
+    auto put = [&](unsigned r, int32_t p) {
+      if (r == JOB_R1X) L.job[L.cap_piece - 1 - (int64_t)(sl[r]++)] = p;
+      else lists[r][sl[r]++] = p;
+    };
+    for (int j = 0; j < kEmptyPer; ++j)
+      if ((ne >> j) & 1u) put((route >> (3 * j)) & 7u, (int32_t)(base + (int64_t)j * B + threadIdx.x));
+    for (int m = 0; m < kEmptyPer; ++m)
+      if ((qne >> m) & 1u) put((qroute >> (3 * m)) & 7u, s_q[m * B + threadIdx.x]);
   }
   block_count(L.cnt + CNT_EVAL_MID, ev_mid);
   block_count(L.cnt + CNT_EVAL_QUARTER, ev_quarter);
@@ -465,7 +470,7 @@ __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
 
 // The n_g nodes of a piece by its recipe (NG gaps): per node only the
 // endpoint formulas of the recipe, not all four faces (see L_eval_recipe).
-template <int NG>
+template <int NG, bool QE>
 __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* __restrict__ jobs,
                                                        int64_t njob, const double* __restrict__ gl,
                                                        int ng) {
@@ -499,8 +504,10 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
       double Lv = 0.0;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        double v0 = endpoint_value(E[2 * g], d2, wlo, whi, cs, sn);
-        double v1 = endpoint_value(E[2 * g + 1], d2, wlo, whi, cs, sn);
+        double v0 = QE ? endpoint_value_qe(E[2 * g], d2, wlo, whi, cs, sn)
+                       : endpoint_value(E[2 * g], d2, wlo, whi, cs, sn);
+        double v1 = QE ? endpoint_value_qe(E[2 * g + 1], d2, wlo, whi, cs, sn)
+                       : endpoint_value(E[2 * g + 1], d2, wlo, whi, cs, sn);
         Lv += v1 > v0 ? rdiff(v0, v1, d2) : 0.0;
       }
       acc += wt * Lv;
@@ -897,22 +904,27 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(2));
     }
-    unsigned long long njob32 = 0, njob2 = 0, njobf = 0, hc[CNT_N];
+    unsigned long long njob32 = 0, njob2 = 0, njobf = 0, njob1x = 0, hc[CNT_N];
     HIPCHK(ctx, hipMemcpyAsync(hc, L.cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipStreamSynchronize(st));
     njob = hc[CNT_JOB];
     njob2 = hc[CNT_JOB2];
+    njob1x = hc[CNT_JOB1X];
     njobf = hc[CNT_JOBF];
     njob32 = hc[CNT_JOB32];
-    if (njob + njob2 + njobf) {
+    if (njob + njob1x + njob2 + njobf) {
       // FP64 nodes: one-gap recipes, two-gap recipes, full evaluations
       HIPCHK(ctx, t0(4));
       if (njob)
-        hipLaunchKernelGGL(k_nodes_rec<1>, dim3(gfor(4, njob)), dim3(ctx->tune_block[4]), 0, st, L,
-                           L.job, (int64_t)njob, job.gl, job.ng);
+        hipLaunchKernelGGL((k_nodes_rec<1, true>), dim3(gfor(4, njob)), dim3(ctx->tune_block[4]), 0, st,
+                           L, L.job, (int64_t)njob, job.gl, job.ng);
+      if (njob1x)
+        hipLaunchKernelGGL((k_nodes_rec<1, false>), dim3(gfor(4, njob1x)), dim3(ctx->tune_block[4]), 0,
+                           st, L, L.job + (L.cap_piece - (int64_t)njob1x), (int64_t)njob1x, job.gl,
+                           job.ng);
       if (njob2)
-        hipLaunchKernelGGL(k_nodes_rec<2>, dim3(gfor(4, njob2)), dim3(ctx->tune_block[4]), 0, st, L,
-                           L.job2, (int64_t)njob2, job.gl, job.ng);
+        hipLaunchKernelGGL((k_nodes_rec<2, false>), dim3(gfor(4, njob2)), dim3(ctx->tune_block[4]), 0,
+                           st, L, L.job2, (int64_t)njob2, job.gl, job.ng);
       if (njobf)
         hipLaunchKernelGGL(k_nodes, dim3(gfor(4, njobf)), dim3(ctx->tune_block[4]), 0, st, L, L.jobf,
                            (int64_t)njobf, job.gl, job.ng, (int)CNT_EVAL_NODES);
@@ -978,9 +990,9 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     ctx->kern_units[1] += (int64_t)ncombo;
     ctx->kern_units[2] += (int64_t)(h[CNT_EVAL_MID] + h[CNT_EVAL_QUARTER]);
     ctx->kern_units[4] += (int64_t)h[CNT_EVAL_NODES];
-    ctx->path_counts[0] += (int64_t)njob * job.ng;
+    ctx->path_counts[0] += (int64_t)(njob + njob1x) * job.ng;
     ctx->path_counts[1] += (int64_t)njob2 * job.ng;
-    ctx->path_counts[2] += (int64_t)h[CNT_EVAL_NODES] - (int64_t)(njob + njob2) * job.ng;
+    ctx->path_counts[2] += (int64_t)h[CNT_EVAL_NODES] - (int64_t)(njob + njob1x + njob2) * job.ng;
     ctx->path_counts[3] += (int64_t)h[CNT_MISS];
     ctx->kern_units[5] += (int64_t)h[CNT_EVAL_NODES32];
     ctx->kern_units[7] += (int64_t)h[CNT_EVAL_REDO];
