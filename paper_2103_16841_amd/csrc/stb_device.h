@@ -80,6 +80,19 @@ STB_HD __forceinline__ double dot3(const double* a, const double* b) {
 // [0, 4 pi)): Cody-Waite reduction by pi/2 with a two-part pi/2, then the
 // Taylor polynomials of sin (to x^17) and cos (to x^18) on [-pi/4, pi/4],
 // whose truncation errors there are below 1e-17.
+// a * b + c as one v_fma_f64 with the addend in a register that stays
+// live (a polynomial coefficient): the compiler otherwise copies the
+// coefficient and uses the two-address v_fmac_f64, two instructions.
+STB_HD __forceinline__ double fma_keep(double a, double b, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+#else
+  return fma(a, b, c);
+#endif
+}
+
 STB_HD __forceinline__ void sincos_small(double x, double* s, double* c) {
   const double kInvPio2 = 0.63661977236758134308;
   const double kPio2Hi = 1.5707963267948966192e+00;   // nearest double to pi/2
@@ -90,23 +103,23 @@ STB_HD __forceinline__ void sincos_small(double x, double* s, double* c) {
   double r2 = r * r;
   // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
   double ps = -1.0 / 355687428096000.0;                 // -1/17!
-  ps = fma(ps, r2, 1.0 / 1307674368000.0);              //  1/15!
-  ps = fma(ps, r2, -1.0 / 6227020800.0);                // -1/13!
-  ps = fma(ps, r2, 1.0 / 39916800.0);                   //  1/11!
-  ps = fma(ps, r2, -1.0 / 362880.0);                    // -1/9!
-  ps = fma(ps, r2, 1.0 / 5040.0);                       //  1/7!
-  ps = fma(ps, r2, -1.0 / 120.0);                       // -1/5!
-  ps = fma(ps, r2, 1.0 / 6.0);                          //  1/3! (sign below)
+  ps = fma_keep(ps, r2, 1.0 / 1307674368000.0);              //  1/15!
+  ps = fma_keep(ps, r2, -1.0 / 6227020800.0);                // -1/13!
+  ps = fma_keep(ps, r2, 1.0 / 39916800.0);                   //  1/11!
+  ps = fma_keep(ps, r2, -1.0 / 362880.0);                    // -1/9!
+  ps = fma_keep(ps, r2, 1.0 / 5040.0);                       //  1/7!
+  ps = fma_keep(ps, r2, -1.0 / 120.0);                       // -1/5!
+  ps = fma_keep(ps, r2, 1.0 / 6.0);                          //  1/3! (sign below)
   double sr = fma(-r * r2, ps, r);
   double pc = 1.0 / 6402373705728000.0;                 //  1/18!
-  pc = fma(pc, r2, -1.0 / 20922789888000.0);            // -1/16!
-  pc = fma(pc, r2, 1.0 / 87178291200.0);                //  1/14!
-  pc = fma(pc, r2, -1.0 / 479001600.0);                 // -1/12!
-  pc = fma(pc, r2, 1.0 / 3628800.0);                    //  1/10!
-  pc = fma(pc, r2, -1.0 / 40320.0);                     // -1/8!
-  pc = fma(pc, r2, 1.0 / 720.0);                        //  1/6!
-  pc = fma(pc, r2, -1.0 / 24.0);                        // -1/4!
-  pc = fma(pc, r2, 0.5);                                //  1/2! (sign below)
+  pc = fma_keep(pc, r2, -1.0 / 20922789888000.0);            // -1/16!
+  pc = fma_keep(pc, r2, 1.0 / 87178291200.0);                //  1/14!
+  pc = fma_keep(pc, r2, -1.0 / 479001600.0);                 // -1/12!
+  pc = fma_keep(pc, r2, 1.0 / 3628800.0);                    //  1/10!
+  pc = fma_keep(pc, r2, -1.0 / 40320.0);                     // -1/8!
+  pc = fma_keep(pc, r2, 1.0 / 720.0);                        //  1/6!
+  pc = fma_keep(pc, r2, -1.0 / 24.0);                        // -1/4!
+  pc = fma_keep(pc, r2, 0.5);                                //  1/2! (sign below)
   double cr = fma(-r2, pc, 1.0);
   int q = ((int)k) & 3;
   double ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
@@ -421,13 +434,13 @@ STB_HD __forceinline__ double atan2_bp(double y, double x) {
   const double u = fma(-c, mx, mn) * frcp(fma(c, mn, mx));
   const double u2 = u * u;
   double p = 1.0 / 17.0;
-  p = fma(p, u2, -1.0 / 15.0);
-  p = fma(p, u2, 1.0 / 13.0);
-  p = fma(p, u2, -1.0 / 11.0);
-  p = fma(p, u2, 1.0 / 9.0);
-  p = fma(p, u2, -1.0 / 7.0);
-  p = fma(p, u2, 1.0 / 5.0);
-  p = fma(p, u2, -1.0 / 3.0);
+  p = fma_keep(p, u2, -1.0 / 15.0);
+  p = fma_keep(p, u2, 1.0 / 13.0);
+  p = fma_keep(p, u2, -1.0 / 11.0);
+  p = fma_keep(p, u2, 1.0 / 9.0);
+  p = fma_keep(p, u2, -1.0 / 7.0);
+  p = fma_keep(p, u2, 1.0 / 5.0);
+  p = fma_keep(p, u2, -1.0 / 3.0);
   const double au = fma(u * u2, p, u);
   // atan(i / 4), high and low parts
   const double th_hi = i < 0.5 ? 0.0 : i < 1.5 ? 0.24497866312686414 : i < 2.5 ? 0.4636476090008061
