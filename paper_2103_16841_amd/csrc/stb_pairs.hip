@@ -492,15 +492,7 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
       E[2 * g] = endpoint_load(L, c, (rec >> (8 * g + 4)) & 15u, wlo, whi);
       E[2 * g + 1] = endpoint_load(L, c, (rec >> (8 * g)) & 15u, wlo, whi);
     }
-    double acc = 0.0;
-    for (int gi = 0; gi < ng; ++gi) {
-      const double u = gl[gi];
-      const double s = u * u * (3.0 - 2.0 * u);
-      const double ds = 6.0 * u * (1.0 - u);
-      const double phi = a + H * s;
-      const double wt = (H * ds) * gl[kMaxNg + gi];
-      double sn, cs;
-      sincos_small(phi, &sn, &cs);
+    auto L_node = [&](double cs, double sn) {
       double Lv = 0.0;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
@@ -510,8 +502,28 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
                        : endpoint_value(E[2 * g + 1], d2, wlo, whi, cs, sn);
         Lv += v1 > v0 ? rdiff(v0, v1, d2) : 0.0;
       }
-      acc += wt * Lv;
+      return Lv;
+    };
+    // The nodes come in mirror pairs about the piece's midpoint m:
+    // phi = m -+ delta with delta = H (1/2 - s(u_g)) (the Gauss nodes are
+    // symmetric and s(1 - u) = 1 - s(u)), sharing one weight; the pair's
+    // cosines and sines follow from those of m and delta by the addition
+    // theorems, one sin/cos evaluation per pair instead of two.
+    const double m = a + 0.5 * H;
+    double sm, cm;
+    sincos_small(m, &sm, &cm);
+    double acc = 0.0;
+    for (int gi = 0; gi < (ng >> 1); ++gi) {
+      const double u = gl[gi];
+      const double s = u * u * (3.0 - 2.0 * u);
+      const double ds = 6.0 * u * (1.0 - u);
+      const double wt = (H * ds) * gl[kMaxNg + gi];
+      double sd, cd;
+      sincos_small(H * (0.5 - s), &sd, &cd);
+      const double cc = cm * cd, ss = sm * sd, sc = sm * cd, cs = cm * sd;
+      acc += wt * (L_node(cc + ss, sc - cs) + L_node(cc - ss, sc + cs));
     }
+    if (ng & 1) acc += (H * 1.5) * gl[kMaxNg + (ng >> 1)] * L_node(cm, sm);   // u = 1/2
     evals += (unsigned long long)ng;
     L.pv[p] = acc;
   }
