@@ -39,9 +39,10 @@ def node_flops(counts):
     return sum(FLOP_PER_L[k] * counts.get(k, 0) for k in FLOP_PER_L)
 # HBM bytes per launch group of the FP64 node stage on this workload:
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a plain 1 GiB
-# copy), per assembly chunk (profiles/).  None whenever the node kernels have
-# changed since they were profiled.
-K_NODES_TRAFFIC_BYTES = None
+# copy), average over the 16 assembly chunks
+# (profiles/node_stage_icosphere_L2_S32.md).  Set to None whenever the node
+# kernels change until they are profiled again.
+K_NODES_TRAFFIC_BYTES = 3.421e10
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -49,7 +50,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--points", type=int, default=1000)
-    ap.add_argument("--cpu-rows", type=int, default=384)
+    ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--workload", choices=["icosphere", "batch"], default="icosphere",
@@ -256,7 +257,8 @@ def batch_main(args):
                    "causal_pairs": int(causal.sum())},
         "kernel_ms": {k: v[0] for k, v in kt_acc.items() if v[1]},
         "roofline": {"bound": "alu",
-                     "kernel": "FP64 node stage (k_nodes_rec<1>, k_nodes_rec<2>, k_nodes)",
+                     "kernel": "FP64 node stage (k_nodes_rec<1, true>, k_nodes_rec<1, false>, "
+                               "k_nodes_rec<2, false>, k_nodes)",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": None,
                      "avg_launch_ms": avg_ms, "launches": k_n, "path_counts": ev_acc},
@@ -366,7 +368,9 @@ def main():
         "phase_ms": rec["timings"],
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt_acc.items() if v[1]},
         "roofline": {
-            "bound": "alu", "kernel": "FP64 node stage (k_nodes_rec<1>, k_nodes_rec<2>, k_nodes)",
+            "bound": "alu",
+            "kernel": "FP64 node stage (k_nodes_rec<1, true>, k_nodes_rec<1, false>, "
+                      "k_nodes_rec<2, false>, k_nodes)",
             "achieved": achieved, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": K_NODES_TRAFFIC_BYTES,
             "flop_per_L": FLOP_PER_L, "L_evals_per_launch": k_units / max(k_n, 1),
