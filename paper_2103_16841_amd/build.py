@@ -8,7 +8,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstb.so")
 SOURCES = [os.path.join(CSRC, "stb_lib.hip"), os.path.join(CSRC, "stb_pairs.hip"),
            os.path.join(CSRC, "stb_batch.hip"), os.path.join(CSRC, "stb_server.hip"),
-           os.path.join(CSRC, "stb_apply.hip")]
+           os.path.join(CSRC, "stb_apply.hip"),
+           os.path.join(CSRC, "stb_faces.hip")]
 HEADERS = [os.path.join(CSRC, "stb_device.h"), os.path.join(CSRC, "stb_internal.h"),
            os.path.join(CSRC, "stb_pairs.h"), os.path.join(ROOT, "include", "stb.h")]
 

@@ -177,16 +177,19 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
       dfree(vals_g); dfree(seg_off); dfree(seg_causal);
       release(w, keep);
     };
-    bool ok = dalloc(&trial_g, (size_t)panels) == hipSuccess &&
-              dalloc(&fang_g, (size_t)panels) == hipSuccess &&
-              dalloc(&apex_g, (size_t)panels * maxq * 4) == hipSuccess &&
-              dalloc(&apexw_g, (size_t)panels * maxq) == hipSuccess &&
-              dalloc(&apexn_g, (size_t)panels) == hipSuccess &&
-              dalloc(&rows_g, (size_t)cands) == hipSuccess &&
-              dalloc(&cols_g, (size_t)cands) == hipSuccess &&
-              dalloc(&vals_g, (size_t)cands) == hipSuccess &&
-              dalloc(&seg_off, w.size() + 1) == hipSuccess &&
-              dalloc(&seg_causal, w.size()) == hipSuccess;
+    // FP64: through the shared faces (stb_faces.hip), which stages its own
+    // lists; mixed precision: the panels' outer points, staged here
+    const bool faces = p.prec == STB_FP64;
+    bool ok = faces || (dalloc(&trial_g, (size_t)panels) == hipSuccess &&
+                        dalloc(&fang_g, (size_t)panels) == hipSuccess &&
+                        dalloc(&apex_g, (size_t)panels * maxq * 4) == hipSuccess &&
+                        dalloc(&apexw_g, (size_t)panels * maxq) == hipSuccess &&
+                        dalloc(&apexn_g, (size_t)panels) == hipSuccess &&
+                        dalloc(&rows_g, (size_t)cands) == hipSuccess &&
+                        dalloc(&cols_g, (size_t)cands) == hipSuccess &&
+                        dalloc(&vals_g, (size_t)cands) == hipSuccess &&
+                        dalloc(&seg_off, w.size() + 1) == hipSuccess &&
+                        dalloc(&seg_causal, w.size()) == hipSuccess);
     if (!ok) {
       cleanup(false);
       return stb_fail(ctx, STB_E_NO_MEMORY, "batch wave of %lld candidates does not fit", (long long)cands);
@@ -212,6 +215,11 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
       x.off_panel = op;
       x.off_cand = oc;
       h_off[m] = oc;
+      if (faces) {
+        op += me->nt;
+        oc += nz;
+        continue;
+      }
       hipError_t e = hipMemcpyAsync(trial_g + op, me->d_trial, sizeof(TrialRec) * me->nt,
                                     hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess)
@@ -240,6 +248,28 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
       oc += nz;
     }
     h_off[w.size()] = oc;
+    if (faces) {
+      std::vector<FaceUnit> fu(w.size());
+      for (size_t m = 0; m < w.size(); ++m) {
+        fu[m].mesh = w[m].mesh;
+        fu[m].r0 = w[m].r0;
+        fu[m].r1 = w[m].r1;
+        fu[m].rowof = w[m].rowof;
+        fu[m].cols = w[m].M->d_cols;
+        fu[m].nnz = w[m].M->nnz;
+        fu[m].vals = w[m].M->d_vals;
+      }
+      unsigned long long work[4];
+      s = stb_face_assemble(ctx, p, fu.data(), (int)fu.size(), work);
+      if (s) { cleanup(false); return s; }
+      for (int q = 0; q < 4; ++q) work_tot[q] += work[q];
+      for (int q = 0; q < 8; ++q) { kms[q] += ctx->kern_ms[q]; kn[q] += ctx->kern_n[q]; kunits[q] += (double)ctx->kern_units[q]; }
+      for (int q = 0; q < 4; ++q) npath[q] += ctx->path_counts[q];
+      for (size_t m = 0; m < w.size(); ++m) {
+        w[m].M->n_causal = fu[m].n_causal;
+        causal[(size_t)w[m].idx] += fu[m].n_causal;
+      }
+    } else {
     HIPCHK(ctx, hipMemcpyAsync(seg_off, h_off.data(), 8 * h_off.size(), hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipMemsetAsync(seg_causal, 0, 8 * w.size(), st));
     PairJob J;
@@ -278,6 +308,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
     for (size_t m = 0; m < w.size(); ++m) {
       w[m].M->n_causal = (int64_t)h_causal[m];
       causal[(size_t)w[m].idx] += (int64_t)h_causal[m];
+    }
     }
     // products of the wave's row blocks, then release (or hand over) the stores
     for (size_t m = 0; m < w.size() && W_dev; ++m) {

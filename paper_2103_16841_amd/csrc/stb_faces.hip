@@ -1,0 +1,394 @@
+// stb_faces.hip -- FP64 assembly through the outer points of shared faces.
+//
+// The outer rule of eq. int_bform puts its points on the faces of the test
+// panel with nu_t != 0, and in a conforming space-time mesh each such face
+// is shared by two panels (the slab above or below, or the neighbouring
+// tetrahedron of the same prism), with outward time normals of opposite
+// sign.  The inner integrals Vphi_j(x_{F,q}) at a face's points are
+// therefore the same numbers for both panels.  Here the pair pipeline runs
+// once per unique face F and trial panel j and returns
+//   S(F, j) = sum_q Vphi_j(x_{F,q})          (fixed order in q),
+// and every matrix entry is
+//   A_ij = sum over the active faces F of panel i of w_{i,F} S(F, j),
+//   w_{i,F} = -nu_{F,t} |F| / m_q^2          (nu outward for panel i),
+// exactly +0.0 unless some point of one of its faces is lit (Sec. 3.3).
+//
+// Faces are identified by their sorted global vertex ids; a face's points
+// are computed once from its vertices in that order (the set of sub-triangle
+// centroids does not depend on the vertex order).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <unordered_map>
+#include <vector>
+
+#include "stb_device.h"
+
+using namespace stb;
+
+#include "stb_internal.h"
+#include "stb_pairs.h"
+
+namespace {
+
+// Outer weight of each face slot k of every panel (the face opposite local
+// vertex k): -nu_t |F| / m^2 with the panel's outward normal, 0 for a
+// vertical face.  Same arithmetic as the per-panel outer points.
+__global__ void k_slot_weights(int64_t nt, const TrialRec* __restrict__ rec, int m,
+                               double* __restrict__ pw) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const TrialRec& R = rec[i];
+  for (int k = 0; k < 4; ++k) {
+    const int i0 = k == 0 ? 1 : 0, i1 = k <= 1 ? 2 : 1, i2 = k <= 2 ? 3 : 2;
+    double u1[3], u2[3], tk[3];
+    for (int c = 0; c < 3; ++c) {
+      u1[c] = R.V[i1][c] - R.V[i0][c];
+      u2[c] = R.V[i2][c] - R.V[i0][c];
+      tk[c] = R.V[k][c] - R.V[i0][c];
+    }
+    const double N[3] = {u1[1] * u2[2] - u1[2] * u2[1], u1[2] * u2[0] - u1[0] * u2[2],
+                         u1[0] * u2[1] - u1[1] * u2[0]};
+    const double sg = dot3(N, tk) > 0.0 ? -1.0 : 1.0;
+    const double nut_area = sg * N[0] * 0.5;
+    pw[4 * i + k] = nut_area == 0.0 ? 0.0 : -nut_area / (double)(m * m);
+  }
+}
+
+// Outer points of each face from its sorted vertices: centroids of the m^2
+// congruent sub-triangles (Fig. int_tri_mid), in the per-panel order of
+// (a, b, up); unit weights (the sums S are unweighted); apex box.
+__global__ void k_face_points(int64_t nf, const double* __restrict__ vtx,
+                              const int32_t* __restrict__ fv, int m, int maxq,
+                              double* __restrict__ pts, double* __restrict__ ones,
+                              int32_t* __restrict__ nq, ApexBox* __restrict__ box) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const double* X0 = vtx + 4 * (int64_t)fv[3 * f];
+  const double* X1 = vtx + 4 * (int64_t)fv[3 * f + 1];
+  const double* X2 = vtx + 4 * (int64_t)fv[3 * f + 2];
+  double* P = pts + f * maxq * 4;
+  const double inv = 1.0 / m;
+  int cnt = 0;
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; a + b < m; ++b)
+      for (int up = 0; up < 2; ++up) {
+        double al, be;
+        if (up == 0) {
+          al = (a + 1.0 / 3.0) * inv;
+          be = (b + 1.0 / 3.0) * inv;
+        } else {
+          if (a + b > m - 2) continue;
+          al = (a + 2.0 / 3.0) * inv;
+          be = (b + 2.0 / 3.0) * inv;
+        }
+        for (int c = 0; c < 4; ++c) P[4 * cnt + c] = X0[c] + al * (X1[c] - X0[c]) + be * (X2[c] - X0[c]);
+        ones[f * maxq + cnt] = 1.0;
+        ++cnt;
+      }
+  nq[f] = cnt;
+  ApexBox B;
+  B.tlo = 1e300;
+  B.thi = -1e300;
+  double c3[3] = {0, 0, 0};
+  for (int q = 0; q < cnt; ++q) {
+    B.tlo = fmin(B.tlo, P[4 * q]);
+    B.thi = fmax(B.thi, P[4 * q]);
+    for (int d = 0; d < 3; ++d) c3[d] += P[4 * q + 1 + d] / cnt;
+  }
+  double rho = 0.0;
+  for (int q = 0; q < cnt; ++q) {
+    const double dx = P[4 * q + 1] - c3[0], dy = P[4 * q + 2] - c3[1], dz = P[4 * q + 3] - c3[2];
+    rho = fmax(rho, sqrt(dx * dx + dy * dy + dz * dz));
+  }
+  B.cx = c3[0];
+  B.cy = c3[1];
+  B.cz = c3[2];
+  B.rho = rho * (1.0 + 1e-12);
+  B.pad[0] = B.pad[1] = 0.0;
+  box[f] = B;
+}
+
+__global__ void k_face_shift(int64_t n, const int32_t* __restrict__ in, int32_t add,
+                             int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] + add;
+}
+
+// Matrix entries of panel rows r0 .. r0 + nrow from the face sums, one lane
+// per candidate: per active face slot of the row's panel (slot order), the
+// candidate's column is looked up among the face's candidate columns
+// (ascending) by bisection.
+__global__ void k_face_combine(int64_t nnz, int64_t r0, const int32_t* __restrict__ rowof,
+                               const int32_t* __restrict__ cols, const int32_t* __restrict__ pf,
+                               const double* __restrict__ pw, int64_t f0, int64_t nfu,
+                               const int64_t* __restrict__ frowptr,
+                               const int32_t* __restrict__ fcols, const double* __restrict__ S,
+                               const uint8_t* __restrict__ lit, double* __restrict__ vals,
+                               unsigned long long* __restrict__ causal) {
+  unsigned long long n = 0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nnz;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = r0 + rowof[c];
+    const int32_t j = cols[c];
+    double acc = 0.0;
+    bool any = false;
+    for (int s = 0; s < 4; ++s) {
+      const int64_t lf = (int64_t)pf[4 * i + s] - f0;
+      if (pf[4 * i + s] < 0 || lf < 0 || lf >= nfu) continue;
+      int64_t lo = frowptr[lf], hi = frowptr[lf + 1];
+      while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (fcols[mid] < j) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < frowptr[lf + 1] && fcols[lo] == j) {
+        acc += pw[4 * i + s] * S[lo];
+        any = any || lit[lo] != 0;
+      }
+    }
+    vals[c] = any ? acc : 0.0;
+    n += any ? 1ull : 0ull;
+  }
+  for (int off = 32; off > 0; off >>= 1) n += __shfl_down(n, off, 64);
+  if ((threadIdx.x & 63) == 0 && n) atomicAdd(causal, n);
+}
+
+struct Key3Hash {
+  size_t operator()(const std::array<int32_t, 3>& k) const {
+    uint64_t h = (uint64_t)(uint32_t)k[0] * 0x9E3779B97F4A7C15ull;
+    h ^= (uint64_t)(uint32_t)k[1] + 0x7F4A7C159E3779B9ull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)(uint32_t)k[2] + 0x94D049BB133111EBull + (h << 6) + (h >> 2);
+    return (size_t)h;
+  }
+};
+
+}  // namespace
+
+void stb_free_faces(stb_mesh* m) {
+  dfree(m->d_fpts); dfree(m->d_fones); dfree(m->d_fnq); dfree(m->d_fbox);
+  dfree(m->d_pf); dfree(m->d_pw);
+  m->d_fpts = m->d_fones = nullptr;
+  m->d_fnq = nullptr;
+  m->d_fbox = nullptr;
+  m->d_pf = nullptr;
+  m->d_pw = nullptr;
+  m->h_pf.clear();
+  m->nf = 0;
+  m->face_mq = 0;
+}
+
+stb_status stb_ensure_faces(stb_ctx* ctx, stb_mesh* m, int mq) {
+  if (m->face_mq == mq && m->d_pf) return STB_OK;
+  stb_free_faces(m);
+  const int64_t nt = m->nt;
+  const int fq = mq * mq;
+  std::vector<double> pw((size_t)nt * 4);
+  std::vector<int32_t> tet((size_t)nt * 4);
+  HIPCHK(ctx, dalloc(&m->d_pw, (size_t)nt * 4));
+  if (nt > 0) {
+    hipLaunchKernelGGL(k_slot_weights, dim3((unsigned)((nt + 127) / 128)), dim3(128), 0, ctx->stream, nt,
+                       m->d_trial, mq, m->d_pw);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipMemcpyAsync(pw.data(), m->d_pw, sizeof(double) * 4 * nt, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(tet.data(), m->d_tet, sizeof(int32_t) * 4 * nt, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  // unique active faces by sorted vertex ids, numbered in order of first
+  // appearance (panel, slot)
+  std::unordered_map<std::array<int32_t, 3>, int32_t, Key3Hash> id;
+  id.reserve((size_t)nt * 2);
+  std::vector<int32_t> fv;
+  fv.reserve((size_t)nt * 6);
+  m->h_pf.assign((size_t)nt * 4, -1);
+  for (int64_t i = 0; i < nt; ++i)
+    for (int k = 0; k < 4; ++k) {
+      if (pw[4 * i + k] == 0.0) continue;
+      std::array<int32_t, 3> key;
+      int c = 0;
+      for (int v = 0; v < 4; ++v)
+        if (v != k) key[c++] = tet[4 * i + v];
+      std::sort(key.begin(), key.end());
+      auto it = id.find(key);
+      int32_t f;
+      if (it == id.end()) {
+        f = (int32_t)(fv.size() / 3);
+        id.emplace(key, f);
+        fv.insert(fv.end(), key.begin(), key.end());
+      } else {
+        f = it->second;
+      }
+      m->h_pf[4 * i + k] = f;
+    }
+  const int64_t nf = (int64_t)(fv.size() / 3);
+  int32_t* d_fv = nullptr;
+  HIPCHK(ctx, dalloc(&m->d_pf, (size_t)nt * 4));
+  HIPCHK(ctx, dalloc(&m->d_fpts, (size_t)std::max<int64_t>(nf, 1) * fq * 4));
+  HIPCHK(ctx, dalloc(&m->d_fones, (size_t)std::max<int64_t>(nf, 1) * fq));
+  HIPCHK(ctx, dalloc(&m->d_fnq, (size_t)std::max<int64_t>(nf, 1)));
+  HIPCHK(ctx, dalloc(&m->d_fbox, (size_t)std::max<int64_t>(nf, 1)));
+  HIPCHK(ctx, dalloc(&d_fv, (size_t)std::max<int64_t>(nf, 1) * 3));
+  hipError_t e = hipSuccess;
+  if (nt > 0)
+    e = hipMemcpyAsync(m->d_pf, m->h_pf.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && nf > 0)
+    e = hipMemcpyAsync(d_fv, fv.data(), sizeof(int32_t) * 3 * nf, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && nf > 0) {
+    hipLaunchKernelGGL(k_face_points, dim3((unsigned)((nf + 127) / 128)), dim3(128), 0, ctx->stream, nf,
+                       m->d_vtx, d_fv, mq, fq, m->d_fpts, m->d_fones, m->d_fnq, m->d_fbox);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(d_fv);
+  if (e != hipSuccess) {
+    stb_free_faces(m);
+    return stb_fail(ctx, STB_E_DEVICE, "face table: %s", hipGetErrorString(e));
+  }
+  m->nf = nf;
+  m->face_mq = mq;
+  return STB_OK;
+}
+
+// Face range [f0, f1) referenced by panel rows [r0, r1) (host table).
+static void face_range(const stb_mesh* m, int64_t r0, int64_t r1, int64_t* f0, int64_t* f1) {
+  int64_t lo = m->nf, hi = 0;
+  for (int64_t i = r0; i < r1; ++i)
+    for (int k = 0; k < 4; ++k) {
+      const int32_t f = m->h_pf[4 * i + k];
+      if (f < 0) continue;
+      lo = std::min<int64_t>(lo, f);
+      hi = std::max<int64_t>(hi, (int64_t)f + 1);
+    }
+  if (hi <= lo) lo = hi = 0;
+  *f0 = lo;
+  *f1 = hi;
+}
+
+stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* units, int nunit,
+                             unsigned long long work[4]) {
+  for (int k = 0; k < 4; ++k) work[k] = 0;
+  hipStream_t st = ctx->stream;
+  const int fq = p.m_q * p.m_q;
+  struct U {
+    int64_t f0 = 0, f1 = 0, fnnz = 0, of = 0, op = 0, oc = 0;
+    int64_t* frowptr = nullptr;
+    int32_t *fcols = nullptr, *frowof = nullptr;
+  };
+  std::vector<U> u((size_t)nunit);
+  TrialRec* trial_g = nullptr;
+  FaceAng* fang_g = nullptr;
+  double *apex_g = nullptr, *ones_g = nullptr, *S_g = nullptr;
+  int32_t *apexn_g = nullptr, *rows_g = nullptr, *cols_g = nullptr;
+  uint8_t* lit_g = nullptr;
+  unsigned long long* d_causal = nullptr;
+  auto cleanup = [&]() {
+    for (auto& x : u) { dfree(x.frowptr); dfree(x.fcols); dfree(x.frowof); }
+    dfree(trial_g); dfree(fang_g); dfree(apex_g); dfree(ones_g); dfree(S_g);
+    dfree(apexn_g); dfree(rows_g); dfree(cols_g); dfree(lit_g); dfree(d_causal);
+  };
+  stb_status s = STB_OK;
+  int64_t F = 0, C = 0, P = 0;
+  for (int k = 0; k < nunit; ++k) {
+    FaceUnit& fu = units[k];
+    U& x = u[(size_t)k];
+    if ((s = stb_ensure_faces(ctx, fu.mesh, p.m_q))) { cleanup(); return s; }
+    face_range(fu.mesh, fu.r0, fu.r1, &x.f0, &x.f1);
+    s = stb_cull(ctx, x.f1 - x.f0, fu.mesh->d_fbox + x.f0, fu.mesh, &x.frowptr, &x.fcols, &x.frowof,
+                 &x.fnnz);
+    if (s) { cleanup(); return s; }
+    x.of = F;
+    x.oc = C;
+    x.op = P;
+    F += x.f1 - x.f0;
+    C += x.fnnz;
+    P += fu.mesh->nt;
+  }
+  if (F > 0x7fffffffll || P > 0x7fffffffll) {
+    cleanup();
+    return stb_fail(ctx, STB_E_INVALID_ARG, "face batch too large");
+  }
+  bool ok = dalloc(&trial_g, (size_t)std::max<int64_t>(P, 1)) == hipSuccess &&
+            dalloc(&fang_g, (size_t)std::max<int64_t>(P, 1)) == hipSuccess &&
+            dalloc(&apex_g, (size_t)std::max<int64_t>(F, 1) * fq * 4) == hipSuccess &&
+            dalloc(&ones_g, (size_t)std::max<int64_t>(F, 1) * fq) == hipSuccess &&
+            dalloc(&apexn_g, (size_t)std::max<int64_t>(F, 1)) == hipSuccess &&
+            dalloc(&rows_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
+            dalloc(&cols_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
+            dalloc(&S_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
+            dalloc(&lit_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
+            dalloc(&d_causal, (size_t)nunit) == hipSuccess;
+  if (!ok) {
+    cleanup();
+    return stb_fail(ctx, STB_E_NO_MEMORY, "face lists of %lld candidates do not fit", (long long)C);
+  }
+  hipError_t e = hipMemsetAsync(d_causal, 0, sizeof(unsigned long long) * nunit, st);
+  for (int k = 0; k < nunit && e == hipSuccess; ++k) {
+    const FaceUnit& fu = units[k];
+    const U& x = u[(size_t)k];
+    const stb_mesh* me = fu.mesh;
+    const int64_t nfu = x.f1 - x.f0;
+    e = hipMemcpyAsync(trial_g + x.op, me->d_trial, sizeof(TrialRec) * me->nt, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(fang_g + x.op, me->d_fang, sizeof(FaceAng) * me->nt, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && nfu > 0)
+      e = hipMemcpyAsync(apex_g + x.of * fq * 4, me->d_fpts + x.f0 * fq * 4, sizeof(double) * nfu * fq * 4,
+                         hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && nfu > 0)
+      e = hipMemcpyAsync(ones_g + x.of * fq, me->d_fones + x.f0 * fq, sizeof(double) * nfu * fq,
+                         hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && nfu > 0)
+      e = hipMemcpyAsync(apexn_g + x.of, me->d_fnq + x.f0, sizeof(int32_t) * nfu, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && x.fnnz > 0) {
+      const unsigned g = (unsigned)((x.fnnz + 255) / 256);
+      hipLaunchKernelGGL(k_face_shift, dim3(g), dim3(256), 0, st, x.fnnz, x.frowof, (int32_t)x.of,
+                         rows_g + x.oc);
+      hipLaunchKernelGGL(k_face_shift, dim3(g), dim3(256), 0, st, x.fnnz, x.fcols, (int32_t)x.op,
+                         cols_g + x.oc);
+      e = hipGetLastError();
+    }
+  }
+  if (e != hipSuccess) {
+    cleanup();
+    return stb_fail(ctx, STB_E_DEVICE, "face staging: %s", hipGetErrorString(e));
+  }
+  PairJob J;
+  J.nnz = C;
+  J.rows = rows_g;
+  J.cols = cols_g;
+  J.trial = trial_g;
+  J.fang = fang_g;
+  J.apex = apex_g;
+  J.apex_w = ones_g;
+  J.apex_n = apexn_g;
+  J.maxq = fq;
+  J.gl = ctx->d_gl;
+  J.ng = p.n_g;
+  J.mixed = false;
+  J.eta_far = p.eta_far;
+  J.out = S_g;
+  J.lit_out = lit_g;
+  s = stb_run_pairs(ctx, J, work);
+  if (s) { cleanup(); return s; }
+  for (int k = 0; k < nunit; ++k) {
+    const FaceUnit& fu = units[k];
+    const U& x = u[(size_t)k];
+    if (fu.nnz <= 0) continue;
+    const int64_t blocks = std::min<int64_t>((fu.nnz + 255) / 256, (int64_t)std::max(ctx->ncu, 1) * 32);
+    hipLaunchKernelGGL(k_face_combine, dim3((unsigned)blocks), dim3(256), 0, st, fu.nnz, fu.r0, fu.rowof,
+                       fu.cols, fu.mesh->d_pf, fu.mesh->d_pw, x.f0, x.f1 - x.f0, x.frowptr, x.fcols,
+                       S_g + x.oc, lit_g + x.oc, fu.vals, d_causal + k);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+  }
+  std::vector<unsigned long long> hc((size_t)nunit, 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hc.data(), d_causal, sizeof(unsigned long long) * nunit, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) return stb_fail(ctx, STB_E_DEVICE, "face combine: %s", hipGetErrorString(e));
+  for (int k = 0; k < nunit; ++k) units[k].n_causal = (int64_t)hc[(size_t)k];
+  return STB_OK;
+}

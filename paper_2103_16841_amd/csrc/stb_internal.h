@@ -50,6 +50,16 @@ struct stb_mesh {
   double* d_ow = nullptr;     // [nt][4*mq*mq]
   int32_t* d_onq = nullptr;   // [nt]
   stb::ApexBox* d_box = nullptr;   // [nt]
+  // unique faces with nu_t != 0 and their outer points (for one m_q)
+  int face_mq = 0;
+  int64_t nf = 0;
+  double* d_fpts = nullptr;        // [nf][mq*mq][4], from the sorted vertex ids
+  double* d_fones = nullptr;       // [nf][mq*mq] unit weights
+  int32_t* d_fnq = nullptr;        // [nf] points per face
+  stb::ApexBox* d_fbox = nullptr;  // [nf]
+  int32_t* d_pf = nullptr;         // [nt][4] face of each slot (-1: vertical), device
+  double* d_pw = nullptr;          // [nt][4] outer weight of the slot for this panel
+  std::vector<int32_t> h_pf;       // host copy of d_pf
 };
 
 struct stb_mat {
@@ -112,6 +122,24 @@ stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_row
 stb_status stb_cull_rowptr(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, const stb_mesh* m,
                            int64_t* rowptr_host);
 void stb_point_boxes(stb_ctx* ctx, int64_t np, const double* d_pts, stb::ApexBox* d_box);
+
+// FP64 assembly through shared faces (stb_faces.hip).  A unit is a range
+// of panel rows of one mesh with its candidate CSR (rows local to r0).
+struct FaceUnit {
+  stb_mesh* mesh = nullptr;
+  int64_t r0 = 0, r1 = 0;
+  const int32_t* rowof = nullptr;   // [nnz] local row of each candidate
+  const int32_t* cols = nullptr;    // [nnz] trial panel (mesh-local)
+  int64_t nnz = 0;
+  double* vals = nullptr;           // [nnz] out
+  int64_t n_causal = 0;             // out
+};
+stb_status stb_ensure_faces(stb_ctx* ctx, stb_mesh* m, int mq);
+void stb_free_faces(stb_mesh* m);
+// One pass of the pair pipeline over the faces of all units; writes each
+// unit's values and causal count; work as stb_run_pairs.
+stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* units, int nunit,
+                             unsigned long long work[4]);
 
 // Potential with device inputs/outputs on ctx's stream and workspace (the
 // mesh may belong to another context of the same device).

@@ -617,6 +617,7 @@ void stb_mesh_destroy(stb_mesh* m) {
   if (!m) return;
   dfree(m->d_vtx); dfree(m->d_tet); dfree(m->d_trial); dfree(m->d_fang);
   dfree(m->d_opts); dfree(m->d_ow); dfree(m->d_onq); dfree(m->d_box);
+  stb_free_faces(m);
   delete m;
 }
 
@@ -647,24 +648,38 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
     dfree(d_rowof); stb_mat_destroy(M);
     return fail(ctx, STB_E_NO_MEMORY, "store of %lld entries does not fit", (long long)M->nnz);
   }
-  PairJob J;
-  J.nnz = M->nnz;
-  J.rows = d_rowof;
-  J.cols = M->d_cols;
-  J.trial = mesh->d_trial;
-  J.fang = mesh->d_fang;
-  J.apex = mesh->d_opts;
-  J.apex_w = mesh->d_ow;
-  J.apex_n = mesh->d_onq;
-  J.maxq = mesh->maxq;
-  J.gl = ctx->d_gl;
-  J.ng = p.n_g;
-  J.mixed = p.prec == STB_MIXED;
-  J.eta_far = p.eta_far;
-  J.out = M->d_vals;
   unsigned long long causal = 0, work[4];
-  J.n_causal = &causal;
-  s = stb_run_pairs(ctx, J, work);
+  if (p.prec == STB_FP64) {
+    // through the shared faces' outer points
+    FaceUnit U;
+    U.mesh = mesh;
+    U.r0 = 0;
+    U.r1 = mesh->nt;
+    U.rowof = d_rowof;
+    U.cols = M->d_cols;
+    U.nnz = M->nnz;
+    U.vals = M->d_vals;
+    s = stb_face_assemble(ctx, p, &U, 1, work);
+    causal = (unsigned long long)U.n_causal;
+  } else {
+    PairJob J;
+    J.nnz = M->nnz;
+    J.rows = d_rowof;
+    J.cols = M->d_cols;
+    J.trial = mesh->d_trial;
+    J.fang = mesh->d_fang;
+    J.apex = mesh->d_opts;
+    J.apex_w = mesh->d_ow;
+    J.apex_n = mesh->d_onq;
+    J.maxq = mesh->maxq;
+    J.gl = ctx->d_gl;
+    J.ng = p.n_g;
+    J.mixed = true;
+    J.eta_far = p.eta_far;
+    J.out = M->d_vals;
+    J.n_causal = &causal;
+    s = stb_run_pairs(ctx, J, work);
+  }
   dfree(d_rowof);
   if (s) { stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));

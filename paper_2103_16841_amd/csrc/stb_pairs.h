@@ -18,6 +18,7 @@ struct PairJob {
   bool mixed = false;                // far combos' Gauss nodes in FP32
   double eta_far = 2.0;              // far: apex farther than eta_far radii from the panel's ball
   double* out = nullptr;             // [nnz] matrix entry or inner integral
+  uint8_t* lit_out = nullptr;        // optional [nnz]: 1 where some apex is lit
   unsigned long long* n_causal = nullptr;   // host: += candidates with a lit apex
   // optional segments of the candidate range (batches of meshes): candidate
   // offsets [nseg + 1] and per-segment causal counts [nseg], both device

@@ -183,6 +183,7 @@ struct Geo {
   const FaceAng* fang;   // per trial panel
   const double* apex;    // [rows][maxq][4]
   const double* apex_w;  // [rows][maxq] (matrix) or nullptr (potential)
+  uint8_t* lit_out;      // optional per candidate: some apex lit
   const int32_t* apex_n; // [rows] or nullptr (one apex)
   int maxq;
   int mixed;             // far combos' nodes in FP32
@@ -671,6 +672,7 @@ __global__ __launch_bounds__(kBlk) void k_store(Geo g, Lists L, int64_t c0, int6
         s = L.I[idx];
       }
       out[c0 + c] = s;
+      if (g.lit_out) g.lit_out[c0 + c] = m ? 1 : 0;
       if (check) {
         const bool r = bound > kMixedTol * fabs(s);
         L.redo[c] = r ? 1 : 0;
@@ -839,6 +841,7 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
   Lists L = w->L;
   Geo g;
   g.rows = job.rows; g.cols = job.cols; g.trial = job.trial; g.fang = job.fang;
+  g.lit_out = job.lit_out;
   g.apex = job.apex; g.apex_w = job.apex_w; g.apex_n = job.apex_n; g.maxq = job.maxq;
   g.mixed = job.mixed ? 1 : 0;
   g.eta_far = job.eta_far;

@@ -299,12 +299,34 @@ def test_device_pointer_paths(stb, ctx):
     assert e.value.status == 2
 
 
+def _unique_outer_points(mesh):
+    """The outer points of every panel (oracle), each shared point once: a
+    face with nu_t != 0 belongs to two panels, which evaluate the same
+    points (up to rounding)."""
+    seen, pts = set(), []
+    for i in range(mesh.nt):
+        P, _ = oracle.outer_points(mesh.vtx[mesh.tets[i]])
+        for x in P:
+            key = tuple(np.round(x, 9))
+            if key not in seen:
+                seen.add(key)
+                pts.append(x)
+    return np.array(pts)
+
+
 def test_work_counters(stb, ctx, cube):
+    """FP64 work per distinct (outer point, panel) pair against the oracle
+    run on the same pairs: each face's points are evaluated once for the
+    two panels that share the face."""
     m = stb.Mesh(ctx, cube.vtx, cube.tets)
     stb.assemble_V(ctx, m)
     w = ctx.work()
+    pts = _unique_outer_points(cube)
     st = oracle.Stats()
-    oracle.assemble_rows(cube.vtx, cube.tets, stats=st)
+    for x in pts:
+        for j in range(cube.nt):
+            oracle.inner(x, cube.vtx[cube.tets[j]], stats=st)
+    print("case: cube, %d distinct outer points" % len(pts), w, st.as_dict(), flush=True)
     # the same rule: lit (outer point, panel) pairs and L evaluations (piece
     # tests and Gauss nodes) agree up to decisions taken within rounding: a
     # sliver piece between two nearly coincident breakpoints where L is
