@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kBlk) void k_emit(Geo g, Lists L, int64_t c0, int64
   }
 }
 
-__global__ __launch_bounds__(kBlk) void k_bp(Geo g, Lists L, int64_t c0, int64_t ncombo) {
+__global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int64_t ncombo) {
   const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
   unsigned long long nmiss = 0;
