@@ -254,6 +254,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
         fu[m].mesh = w[m].mesh;
         fu[m].r0 = w[m].r0;
         fu[m].r1 = w[m].r1;
+        fu[m].rowptr = w[m].M->d_rowptr;
         fu[m].rowof = w[m].rowof;
         fu[m].cols = w[m].M->d_cols;
         fu[m].nnz = w[m].M->nnz;

@@ -15,7 +15,8 @@
 //
 // Faces are identified by their sorted global vertex ids; a face's points
 // are computed once from its vertices in that order (the set of sub-triangle
-// centroids does not depend on the vertex order).
+// centroids does not depend on the vertex order).  A face's candidate trial
+// panels are those of the first panel row of the unit that has it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,11 +59,11 @@ __global__ void k_slot_weights(int64_t nt, const TrialRec* __restrict__ rec, int
 
 // Outer points of each face from its sorted vertices: centroids of the m^2
 // congruent sub-triangles (Fig. int_tri_mid), in the per-panel order of
-// (a, b, up); unit weights (the sums S are unweighted); apex box.
+// (a, b, up); unit weights (the sums S are unweighted).
 __global__ void k_face_points(int64_t nf, const double* __restrict__ vtx,
                               const int32_t* __restrict__ fv, int m, int maxq,
                               double* __restrict__ pts, double* __restrict__ ones,
-                              int32_t* __restrict__ nq, ApexBox* __restrict__ box) {
+                              int32_t* __restrict__ nq) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
   const double* X0 = vtx + 4 * (int64_t)fv[3 * f];
@@ -88,26 +89,33 @@ __global__ void k_face_points(int64_t nf, const double* __restrict__ vtx,
         ++cnt;
       }
   nq[f] = cnt;
-  ApexBox B;
-  B.tlo = 1e300;
-  B.thi = -1e300;
-  double c3[3] = {0, 0, 0};
-  for (int q = 0; q < cnt; ++q) {
-    B.tlo = fmin(B.tlo, P[4 * q]);
-    B.thi = fmax(B.thi, P[4 * q]);
-    for (int d = 0; d < 3; ++d) c3[d] += P[4 * q + 1 + d] / cnt;
+}
+
+// Candidates of each face: those of its primary panel row (the first row of
+// the unit that has the face; the panel's apex box contains the face's
+// points, so its cull is a superset of the face's).  -1: no such row.
+__global__ void k_face_rows_count(int64_t nfu, const int32_t* __restrict__ prim,
+                                  const int64_t* __restrict__ rowptr, int64_t* __restrict__ cnt) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nfu) return;
+  const int32_t r = prim[f];
+  cnt[f] = r < 0 ? 0 : rowptr[r + 1] - rowptr[r];
+}
+
+// One block per face row: copy the primary row's columns.
+__global__ void k_face_rows_fill(int64_t nfu, const int32_t* __restrict__ prim,
+                                 const int64_t* __restrict__ rowptr, const int32_t* __restrict__ cols,
+                                 const int64_t* __restrict__ frowptr, int32_t* __restrict__ fcols,
+                                 int32_t* __restrict__ frowof) {
+  const int64_t f = blockIdx.x;
+  if (f >= nfu) return;
+  const int32_t r = prim[f];
+  if (r < 0) return;
+  const int64_t src = rowptr[r], n = rowptr[r + 1] - src, dst = frowptr[f];
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    fcols[dst + k] = cols[src + k];
+    frowof[dst + k] = (int32_t)f;
   }
-  double rho = 0.0;
-  for (int q = 0; q < cnt; ++q) {
-    const double dx = P[4 * q + 1] - c3[0], dy = P[4 * q + 2] - c3[1], dz = P[4 * q + 3] - c3[2];
-    rho = fmax(rho, sqrt(dx * dx + dy * dy + dz * dz));
-  }
-  B.cx = c3[0];
-  B.cy = c3[1];
-  B.cz = c3[2];
-  B.rho = rho * (1.0 + 1e-12);
-  B.pad[0] = B.pad[1] = 0.0;
-  box[f] = B;
 }
 
 __global__ void k_face_shift(int64_t n, const int32_t* __restrict__ in, int32_t add,
@@ -167,11 +175,10 @@ struct Key3Hash {
 }  // namespace
 
 void stb_free_faces(stb_mesh* m) {
-  dfree(m->d_fpts); dfree(m->d_fones); dfree(m->d_fnq); dfree(m->d_fbox);
+  dfree(m->d_fpts); dfree(m->d_fones); dfree(m->d_fnq);
   dfree(m->d_pf); dfree(m->d_pw);
   m->d_fpts = m->d_fones = nullptr;
   m->d_fnq = nullptr;
-  m->d_fbox = nullptr;
   m->d_pf = nullptr;
   m->d_pw = nullptr;
   m->h_pf.clear();
@@ -229,7 +236,6 @@ stb_status stb_ensure_faces(stb_ctx* ctx, stb_mesh* m, int mq) {
   HIPCHK(ctx, dalloc(&m->d_fpts, (size_t)std::max<int64_t>(nf, 1) * fq * 4));
   HIPCHK(ctx, dalloc(&m->d_fones, (size_t)std::max<int64_t>(nf, 1) * fq));
   HIPCHK(ctx, dalloc(&m->d_fnq, (size_t)std::max<int64_t>(nf, 1)));
-  HIPCHK(ctx, dalloc(&m->d_fbox, (size_t)std::max<int64_t>(nf, 1)));
   HIPCHK(ctx, dalloc(&d_fv, (size_t)std::max<int64_t>(nf, 1) * 3));
   hipError_t e = hipSuccess;
   if (nt > 0)
@@ -238,7 +244,7 @@ stb_status stb_ensure_faces(stb_ctx* ctx, stb_mesh* m, int mq) {
     e = hipMemcpyAsync(d_fv, fv.data(), sizeof(int32_t) * 3 * nf, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess && nf > 0) {
     hipLaunchKernelGGL(k_face_points, dim3((unsigned)((nf + 127) / 128)), dim3(128), 0, ctx->stream, nf,
-                       m->d_vtx, d_fv, mq, fq, m->d_fpts, m->d_fones, m->d_fnq, m->d_fbox);
+                       m->d_vtx, d_fv, mq, fq, m->d_fpts, m->d_fones, m->d_fnq);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -265,6 +271,58 @@ static void face_range(const stb_mesh* m, int64_t r0, int64_t r1, int64_t* f0, i
   if (hi <= lo) lo = hi = 0;
   *f0 = lo;
   *f1 = hi;
+}
+
+// Face CSR of a unit (faces f0 .. f1, local rows): each face's row is its
+// primary panel's candidate row.
+static stb_status face_rows(stb_ctx* ctx, const FaceUnit& fu, int64_t f0, int64_t f1,
+                            int64_t** frowptr, int32_t** fcols, int32_t** frowof, int64_t* fnnz) {
+  const int64_t nfu = f1 - f0;
+  std::vector<int32_t> prim((size_t)std::max<int64_t>(nfu, 1), -1);
+  for (int64_t i = fu.r0; i < fu.r1; ++i)
+    for (int k = 0; k < 4; ++k) {
+      const int32_t f = fu.mesh->h_pf[4 * i + k];
+      if (f < 0 || f < f0 || f >= f1) continue;
+      if (prim[(size_t)(f - f0)] < 0) prim[(size_t)(f - f0)] = (int32_t)(i - fu.r0);
+    }
+  int32_t* d_prim = nullptr;
+  int64_t* d_cnt = nullptr;
+  *fnnz = 0;
+  HIPCHK(ctx, dalloc(frowptr, (size_t)nfu + 1));
+  if (dalloc(&d_prim, (size_t)nfu) != hipSuccess || dalloc(&d_cnt, (size_t)nfu) != hipSuccess) {
+    dfree(d_prim);
+    dfree(d_cnt);
+    return stb_fail(ctx, STB_E_NO_MEMORY, "face rows");
+  }
+  hipStream_t st = ctx->stream;
+  hipError_t e = hipSuccess;
+  if (nfu > 0) {
+    e = hipMemcpyAsync(d_prim, prim.data(), sizeof(int32_t) * nfu, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_face_rows_count, dim3((unsigned)((nfu + 255) / 256)), dim3(256), 0, st, nfu,
+                         d_prim, fu.rowptr, d_cnt);
+      e = hipGetLastError();
+    }
+  }
+  stb_status s = e == hipSuccess ? stb_exclusive_scan(ctx, d_cnt, *frowptr, nfu, st)
+                                 : stb_fail(ctx, STB_E_DEVICE, "face rows: %s", hipGetErrorString(e));
+  if (s == STB_OK && hipMemcpy(fnnz, *frowptr + nfu, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+    s = stb_fail(ctx, STB_E_DEVICE, "face rows copy");
+  if (s == STB_OK && (dalloc(fcols, (size_t)*fnnz) != hipSuccess || dalloc(frowof, (size_t)*fnnz) != hipSuccess))
+    s = stb_fail(ctx, STB_E_NO_MEMORY, "face candidates (%lld)", (long long)*fnnz);
+  if (s == STB_OK && nfu > 0) {
+    hipLaunchKernelGGL(k_face_rows_fill, dim3((unsigned)nfu), dim3(256), 0, st, nfu, d_prim, fu.rowptr,
+                       fu.cols, *frowptr, *fcols, *frowof);
+    e = hipGetLastError();
+    if (e != hipSuccess) s = stb_fail(ctx, STB_E_DEVICE, "face rows: %s", hipGetErrorString(e));
+  }
+  if (s == STB_OK) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = stb_fail(ctx, STB_E_DEVICE, "face rows: %s", hipGetErrorString(e));
+  }
+  dfree(d_prim);
+  dfree(d_cnt);
+  return s;
 }
 
 stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* units, int nunit,
@@ -296,9 +354,10 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
     U& x = u[(size_t)k];
     if ((s = stb_ensure_faces(ctx, fu.mesh, p.m_q))) { cleanup(); return s; }
     face_range(fu.mesh, fu.r0, fu.r1, &x.f0, &x.f1);
-    s = stb_cull(ctx, x.f1 - x.f0, fu.mesh->d_fbox + x.f0, fu.mesh, &x.frowptr, &x.fcols, &x.frowof,
-                 &x.fnnz);
-    if (s) { cleanup(); return s; }
+    if ((s = face_rows(ctx, fu, x.f0, x.f1, &x.frowptr, &x.fcols, &x.frowof, &x.fnnz))) {
+      cleanup();
+      return s;
+    }
     x.of = F;
     x.oc = C;
     x.op = P;

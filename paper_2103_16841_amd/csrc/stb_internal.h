@@ -56,7 +56,6 @@ struct stb_mesh {
   double* d_fpts = nullptr;        // [nf][mq*mq][4], from the sorted vertex ids
   double* d_fones = nullptr;       // [nf][mq*mq] unit weights
   int32_t* d_fnq = nullptr;        // [nf] points per face
-  stb::ApexBox* d_fbox = nullptr;  // [nf]
   int32_t* d_pf = nullptr;         // [nt][4] face of each slot (-1: vertical), device
   double* d_pw = nullptr;          // [nt][4] outer weight of the slot for this panel
   std::vector<int32_t> h_pf;       // host copy of d_pf
@@ -128,6 +127,7 @@ void stb_point_boxes(stb_ctx* ctx, int64_t np, const double* d_pts, stb::ApexBox
 struct FaceUnit {
   stb_mesh* mesh = nullptr;
   int64_t r0 = 0, r1 = 0;
+  const int64_t* rowptr = nullptr;  // [r1 - r0 + 1] candidate rows (local)
   const int32_t* rowof = nullptr;   // [nnz] local row of each candidate
   const int32_t* cols = nullptr;    // [nnz] trial panel (mesh-local)
   int64_t nnz = 0;

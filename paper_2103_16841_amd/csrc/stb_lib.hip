@@ -655,6 +655,7 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
     U.mesh = mesh;
     U.r0 = 0;
     U.r1 = mesh->nt;
+    U.rowptr = M->d_rowptr;
     U.rowof = d_rowof;
     U.cols = M->d_cols;
     U.nnz = M->nnz;
