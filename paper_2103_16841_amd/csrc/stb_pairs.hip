@@ -106,7 +106,8 @@ struct Lists {
   // per combo
   uint32_t* key;         // (candidate in chunk) << 8 | far << 7 | q
   uint32_t* deep;        // (candidate in chunk) << 8 | q of lit tests the vertices left open
-  double* cb;            // ComboL fields, structure of arrays: field f at f * cap_combo
+  double* cb;            // C_k, d^2, w-range: structure of arrays, field f at f * cap_combo
+  int32_t* ccol;         // trial panel of the combo (its face normals are read from there)
   int32_t* p0;           // first piece
   int32_t* np;           // pieces
   double* I;             // inner integral
@@ -126,42 +127,45 @@ struct Lists {
   uint8_t* redo;         // per candidate (mixed): entry recomputed in FP64
   unsigned long long* cnt;
   int64_t cap_cand, cap_combo, cap_piece;
+  const TrialRec* trial; // panel records of the run
 };
 
-constexpr int kComboF = (int)(sizeof(ComboL) / sizeof(double));
-static_assert(sizeof(ComboL) == kComboF * sizeof(double), "ComboL holds doubles only");
-
-// Combo data in structure-of-arrays form: lanes reading neighbouring combos
-// touch neighbouring addresses of each field.
-__device__ __forceinline__ void store_combo(const Lists& L, int64_t k, const ComboL& cb) {
-  const double* src = reinterpret_cast<const double*>(&cb);
-#pragma unroll
-  for (int f = 0; f < kComboF; ++f) L.cb[(int64_t)f * L.cap_combo + k] = src[f];
-}
-
-// Field positions of ComboL in the combo list.
+// Field positions of ComboL's apex-dependent part in the combo list; the
+// face normals (fa, fb, fc) are the trial panel's and are read from its
+// record, not stored per combo.
 constexpr int64_t kCbC = offsetof(ComboL, C) / sizeof(double);
 constexpr int64_t kCbD2 = offsetof(ComboL, d2) / sizeof(double);
 constexpr int64_t kCbWlo = offsetof(ComboL, wlo) / sizeof(double);
 constexpr int64_t kCbWhi = offsetof(ComboL, whi) / sizeof(double);
-constexpr int64_t kCbFa = offsetof(ComboL, fa) / sizeof(double);
-constexpr int64_t kCbFb = offsetof(ComboL, fb) / sizeof(double);
-constexpr int64_t kCbFc = offsetof(ComboL, fc) / sizeof(double);
+constexpr int kComboStored = 7;
+static_assert(kCbC == 0 && kCbD2 == 4 && kCbWlo == 5 && kCbWhi == 6, "ComboL layout");
 
-// One endpoint formula of a recipe read straight from the combo list: only
-// the selected face's four coefficients.  (Selecting the face among all four
-// in registers lets the compiler turn the selects into an indexed load from
-// a private copy of the arrays: 128 bytes of scratch traffic per piece.)
+// Combo data in structure-of-arrays form: lanes reading neighbouring combos
+// touch neighbouring addresses of each field.
+__device__ __forceinline__ void store_combo(const Lists& L, int64_t k, const ComboL& cb, int32_t col) {
+  const int64_t cap = L.cap_combo;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) L.cb[(kCbC + f) * cap + k] = cb.C[f];
+  L.cb[kCbD2 * cap + k] = cb.d2;
+  L.cb[kCbWlo * cap + k] = cb.wlo;
+  L.cb[kCbWhi * cap + k] = cb.whi;
+  L.ccol[k] = col;
+}
+
+// One endpoint formula of a recipe: only the selected face's coefficients,
+// C_k from the combo list and (a, b, c)_k from the panel record.  (Selecting
+// the face among all four in registers lets the compiler turn the selects
+// into an indexed load from a private copy of the arrays.)
 __device__ __forceinline__ Endpoint endpoint_load(const Lists& L, int64_t c, int id, double wlo,
                                                   double whi) {
   const int64_t cap = L.cap_combo;
-  const int64_t k = id >= 2 ? (id - 2) >> 1 : 0;
-  const double* p = L.cb + c + k * cap;
+  const int k = id >= 2 ? (id - 2) >> 1 : 0;
+  const TrialRec* T = L.trial + L.ccol[c];
   Endpoint E;
-  E.C = p[kCbC * cap];
-  E.a = p[kCbFa * cap];
-  E.fb = p[kCbFb * cap];
-  E.fc = p[kCbFc * cap];
+  E.C = L.cb[(kCbC + k) * cap + c];
+  E.a = T->fa[k];
+  E.fb = T->fb[k];
+  E.fc = T->fc[k];
   E.cst = id < 2;
   E.cval = id == 0 ? wlo : whi;
   E.isb = id >= 2 && ((id - 2) & 1);
@@ -169,10 +173,19 @@ __device__ __forceinline__ Endpoint endpoint_load(const Lists& L, int64_t c, int
 }
 
 __device__ __forceinline__ ComboL load_combo(const Lists& L, int64_t k) {
+  const int64_t cap = L.cap_combo;
+  const TrialRec& T = L.trial[L.ccol[k]];
   ComboL cb;
-  double* dst = reinterpret_cast<double*>(&cb);
 #pragma unroll
-  for (int f = 0; f < kComboF; ++f) dst[f] = L.cb[(int64_t)f * L.cap_combo + k];
+  for (int f = 0; f < 4; ++f) {
+    cb.C[f] = L.cb[(kCbC + f) * cap + k];
+    cb.fa[f] = T.fa[f];
+    cb.fb[f] = T.fb[f];
+    cb.fc[f] = T.fc[f];
+  }
+  cb.d2 = L.cb[kCbD2 * cap + k];
+  cb.wlo = L.cb[kCbWlo * cap + k];
+  cb.whi = L.cb[kCbWhi * cap + k];
   return cb;
 }
 
@@ -301,7 +314,7 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
           cb.C[f] = A.C[f]; cb.fa[f] = T.fa[f]; cb.fb[f] = T.fb[f]; cb.fc[f] = T.fc[f];
         }
         cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
-        store_combo(L, k, cb);
+        store_combo(L, k, cb, col);
         if (g.mixed && apex_far(T, x4, g.eta_far)) L.key[k] = key | 0x80u;
         nb = breakpoints(T, g.fang[col], A, bp);
         sort_bp(bp, nb);
@@ -759,7 +772,8 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 static size_t ws_bytes(int64_t cc, int64_t cb, int64_t cp) {
   size_t b = 0;
   b += align256(cc * 8) + align256(cc * 4);
-  b += 2 * align256(cb * 4) + align256(cb * sizeof(ComboL)) + 2 * align256(cb * 4) + align256(cb * 8);
+  b += 2 * align256(cb * 4) + align256(cb * kComboStored * 8) + align256(cb * 4) + 2 * align256(cb * 4) +
+       align256(cb * 8);
   b += 2 * align256(cp * 8) + align256(cp * 4) + align256(cp * 8) + 2 * align256(cp * 4);
   b += align256(cp) + align256(cc) + align256(cb * 4) + align256(cp * 4);
   b += 3 * align256(cp * 4);
@@ -801,7 +815,8 @@ static stb_status ensure_workspace(stb_ctx* ctx, int64_t want_cand, int64_t want
   L.combo0 = (int32_t*)take(want_cand * 4);
   L.key = (uint32_t*)take(want_combo * 4);
   L.deep = (uint32_t*)take(want_combo * 4);
-  L.cb = (double*)take(want_combo * sizeof(ComboL));
+  L.cb = (double*)take(want_combo * kComboStored * 8);
+  L.ccol = (int32_t*)take(want_combo * 4);
   L.p0 = (int32_t*)take(want_combo * 4);
   L.np = (int32_t*)take(want_combo * 4);
   L.I = (double*)take(want_combo * 8);
@@ -839,6 +854,7 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
   if (s) return s;
   PairWorkspace* w = ctx->ws;
   Lists L = w->L;
+  L.trial = job.trial;
   Geo g;
   g.rows = job.rows; g.cols = job.cols; g.trial = job.trial; g.fang = job.fang;
   g.lit_out = job.lit_out;
