@@ -21,7 +21,6 @@
 
 #include <algorithm>
 #include <array>
-#include <unordered_map>
 #include <vector>
 
 #include "stb_device.h"
@@ -163,14 +162,12 @@ __global__ void k_face_combine(int64_t nnz, int64_t r0, const int32_t* __restric
   if ((threadIdx.x & 63) == 0 && n) atomicAdd(causal, n);
 }
 
-struct Key3Hash {
-  size_t operator()(const std::array<int32_t, 3>& k) const {
-    uint64_t h = (uint64_t)(uint32_t)k[0] * 0x9E3779B97F4A7C15ull;
-    h ^= (uint64_t)(uint32_t)k[1] + 0x7F4A7C159E3779B9ull + (h << 6) + (h >> 2);
-    h ^= (uint64_t)(uint32_t)k[2] + 0x94D049BB133111EBull + (h << 6) + (h >> 2);
-    return (size_t)h;
-  }
-};
+inline uint64_t hash3(const int32_t* k) {
+  uint64_t h = (uint64_t)(uint32_t)k[0] * 0x9E3779B97F4A7C15ull;
+  h ^= (uint64_t)(uint32_t)k[1] + 0x7F4A7C159E3779B9ull + (h << 6) + (h >> 2);
+  h ^= (uint64_t)(uint32_t)k[2] + 0x94D049BB133111EBull + (h << 6) + (h >> 2);
+  return h ^ (h >> 29);
+}
 
 }  // namespace
 
@@ -205,9 +202,12 @@ stb_status stb_ensure_faces(stb_ctx* ctx, stb_mesh* m, int mq) {
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   }
   // unique active faces by sorted vertex ids, numbered in order of first
-  // appearance (panel, slot)
-  std::unordered_map<std::array<int32_t, 3>, int32_t, Key3Hash> id;
-  id.reserve((size_t)nt * 2);
+  // appearance (panel, slot); open addressing in a power-of-two table at
+  // most one-eighth full
+  size_t tcap = 16;
+  while (tcap < (size_t)nt * 32) tcap <<= 1;
+  std::vector<int32_t> table(tcap, -1);
+  const size_t tmask = tcap - 1;
   std::vector<int32_t> fv;
   fv.reserve((size_t)nt * 6);
   m->h_pf.assign((size_t)nt * 4, -1);
@@ -219,14 +219,21 @@ stb_status stb_ensure_faces(stb_ctx* ctx, stb_mesh* m, int mq) {
       for (int v = 0; v < 4; ++v)
         if (v != k) key[c++] = tet[4 * i + v];
       std::sort(key.begin(), key.end());
-      auto it = id.find(key);
+      size_t h = (size_t)hash3(key.data()) & tmask;
       int32_t f;
-      if (it == id.end()) {
-        f = (int32_t)(fv.size() / 3);
-        id.emplace(key, f);
-        fv.insert(fv.end(), key.begin(), key.end());
-      } else {
-        f = it->second;
+      for (;;) {
+        const int32_t t = table[h];
+        if (t < 0) {
+          f = (int32_t)(fv.size() / 3);
+          table[h] = f;
+          fv.insert(fv.end(), key.begin(), key.end());
+          break;
+        }
+        if (fv[3 * (size_t)t] == key[0] && fv[3 * (size_t)t + 1] == key[1] && fv[3 * (size_t)t + 2] == key[2]) {
+          f = t;
+          break;
+        }
+        h = (h + 1) & tmask;
       }
       m->h_pf[4 * i + k] = f;
     }
