@@ -501,6 +501,7 @@ STB_HD inline void face_angles(const TrialRec& T, FaceAng& F) {
 STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& A, double* bp) {
   int nb = 0;
   double d2 = A.d * A.d, ad = fabs(A.d);
+  const double rd2 = d2 > 0.0 ? frcp(d2) : 0.0;   // for the tangency test
   double sc = fabs(A.t - T.tmin) + T.diam;
   // cone function at the vertices: an edge with both ends strictly inside
   // the backward cone (a convex set) cannot meet it
@@ -543,7 +544,7 @@ STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& 
     if (!(beta > 1e-12)) continue;
     double phik = FA.phi[k];
     if (d2 > 0.0) {
-      double rhs = a * a - Ck * Ck / d2;
+      double rhs = a * a - Ck * Ck * rd2;
       if (rhs >= 0.0 && rhs <= beta * beta) {
         double cv = fmin(sqrt(rhs) / beta, 1.0);
         double g = acos_bp(cv);
@@ -582,9 +583,8 @@ STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& 
 // panel's spatial shadow (the hull of its vertices' (u, v)) carries no part
 // of the panel, so L = 0 there.  Sufficient test with a margin tol: every
 // vertex strictly on one side of the ray's line, or strictly behind it.
-STB_HD __forceinline__ bool ray_misses(const TrialRec& T, const Apex& A, double phi, double tol) {
-  double sn, cs;
-  sincos_small(phi, &sn, &cs);
+STB_HD __forceinline__ bool ray_misses(const TrialRec& T, const Apex& A, double cs, double sn,
+                                       double tol) {
   bool left = true, right = true, behind = true;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -599,10 +599,16 @@ STB_HD __forceinline__ bool ray_misses(const TrialRec& T, const Apex& A, double 
 
 // The empty-piece test's three points (mid, then the quarter points) all
 // on rays that miss the panel: the piece is empty without evaluating L.
+// The quarter points' directions are the midpoint's turned by -+ H/4.
 STB_HD __forceinline__ bool piece_misses(const TrialRec& T, const Apex& A, double a, double H) {
   const double tol = 1e-10 * (fabs(A.t - T.tmin) + T.diam);
-  return ray_misses(T, A, a + 0.5 * H, tol) && ray_misses(T, A, a + 0.25 * H, tol) &&
-         ray_misses(T, A, a + 0.75 * H, tol);
+  double sm, cm;
+  sincos_small(a + 0.5 * H, &sm, &cm);
+  if (!ray_misses(T, A, cm, sm, tol)) return false;
+  double sh, ch;
+  sincos_small(0.25 * H, &sh, &ch);
+  const double cc = cm * ch, ss = sm * sh, sc = sm * ch, cs = cm * sh;
+  return ray_misses(T, A, cc + ss, sc - cs, tol) && ray_misses(T, A, cc - ss, sc + cs, tol);
 }
 
 // Sorts a[0..n).  Up to 16 values (nearly every (apex, panel) pair): into

@@ -416,8 +416,6 @@ __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
         nz = L_eval_recipe(load_combo(L, L.pc[p]), cs, sn, &rec) != 0.0;
         ++ev_mid;
       }
-      L.pv[p] = 0.0;
-      L.pe[p] = 0.0f;
       L.pne[p] = nz ? 1 : 0;
       L.prec[p] = rec;
       ne |= (nz ? 1u : 0u) << j;
@@ -621,11 +619,15 @@ __global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo) {
   int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x;
   for (; k < ncombo; k += (int64_t)gridDim.x * kBlk) {
     const int32_t p0 = L.p0[k], np = L.np[k];
+    // empty pieces have no node sum (not written); far combos' non-empty
+    // pieces went through the FP32 nodes and carry a rounding bound
+    const bool far = (L.key[k] >> 7) & 1u;
     double I = 0.0;
     float e = 0.0f;
     for (int s = 0; s < np; ++s) {
+      if (!L.pne[p0 + s]) continue;
       I += L.pv[p0 + s];
-      e += L.pe[p0 + s];
+      if (far) e += L.pe[p0 + s];
     }
     L.I[k] = I / (4.0 * kPi);
     L.Ie[k] = e * (float)(1.0 / (4.0 * kPi));
