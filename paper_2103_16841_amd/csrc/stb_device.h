@@ -22,6 +22,7 @@
 // [w(r_lo), w(r_hi)] cut by the intervals, minus the holes.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #define STB_HD __host__ __device__
@@ -40,16 +41,18 @@ constexpr double kLitDead = 1e-12;
 
 // Per-panel record used when the panel is the trial panel (64 doubles).
 struct TrialRec {
+  // first 256 bytes: all the lit test's first pass reads
   double o[3], e1[3], e2[3], n[3];   // spatial frame of the panel plane
-  double fa[4], fb[4], fc[4], fh[4]; // unit outward face normals, offsets
   double V[4][3];                    // vertices in local (tau, u, v)
-  double X[4][4];                    // vertices (t, x, y, z)
   double tmin, tmax, diam;           // time range; max(spatial diam, span)
   double cx, cy, cz, rad;            // spatial bounding ball
   double pad;
+  double fa[4], fb[4], fc[4], fh[4]; // unit outward face normals, offsets
+  double X[4][4];                    // vertices (t, x, y, z)
 };
 // 512 bytes: every candidate's lane reads one record, so it is kept small
 static_assert(sizeof(TrialRec) == 64 * sizeof(double), "TrialRec layout");
+static_assert(offsetof(TrialRec, pad) == 31 * sizeof(double), "lit-test fields in two 128-byte lines");
 
 // Bounding data of an apex set (the outer points of a test panel, or one
 // evaluation point) for the conservative causal cull.
@@ -135,7 +138,8 @@ STB_HD __forceinline__ double wrap_2pi(double a) {
   return a;
 }
 
-STB_HD __forceinline__ void apex_of(const TrialRec& T, const double* x4, Apex& A) {
+// The apex in the panel's frame (t, p_u, p_v, d), without the C_k.
+STB_HD __forceinline__ void apex_frame(const TrialRec& T, const double* x4, Apex& A) {
   double v[3] = {x4[1] - T.o[0], x4[2] - T.o[1], x4[3] - T.o[2]};
   A.t = x4[0];
   A.pu = dot3(v, T.e1);
@@ -144,6 +148,10 @@ STB_HD __forceinline__ void apex_of(const TrialRec& T, const double* x4, Apex& A
   // an apex in the panel's hyperplane up to rounding is taken exactly in it:
   // d of order 1e-17 would make C_k / d (tangency) meaningless
   if (fabs(A.d) <= kFlatTol * (fabs(A.t - T.tmin) + T.diam)) A.d = 0.0;
+}
+
+STB_HD __forceinline__ void apex_of(const TrialRec& T, const double* x4, Apex& A) {
+  apex_frame(T, x4, A);
 #pragma unroll
   for (int k = 0; k < 4; ++k) A.C[k] = T.fh[k] - T.fa[k] * A.t - T.fb[k] * A.pu - T.fc[k] * A.pv;
 }
@@ -378,14 +386,17 @@ STB_HD inline bool lit_test(const TrialRec& T, const double* x4, const Apex& A) 
 
 STB_HD __forceinline__ bool ball_rejects(const TrialRec& T, const double* x4);
 
+// First pass of the lit test from the apex's frame (apex_frame) and the
+// panel's local vertices: the record's first 256 bytes only.
 STB_HD inline int lit_quick(const TrialRec& T, const double* x4, const Apex& A) {
   if (!(A.t - T.tmin > fabs(A.d))) return 0;
   if (ball_rejects(T, x4)) return 0;
   double mn = 1e300, mx = -1e300;
+  const double d2 = A.d * A.d;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    double dx = x4[1] - T.X[k][1], dy = x4[2] - T.X[k][2], dz = x4[3] - T.X[k][3];
-    double f = sqrt(dx * dx + dy * dy + dz * dz) - (x4[0] - T.X[k][0]);
+    double du = A.pu - T.V[k][1], dv = A.pv - T.V[k][2];
+    double f = sqrt(du * du + dv * dv + d2) - (A.t - T.V[k][0]);
     mn = fmin(mn, f);
     mx = fmax(mx, f);
   }

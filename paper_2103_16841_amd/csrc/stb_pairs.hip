@@ -207,7 +207,7 @@ struct Geo {
 // for every (candidate, apex), then the edge and face minima only for the
 // few apexes the vertices leave open, densely -- a wave that ran them
 // inline would pay the long path whenever one of its 64 lanes needs it.
-__global__ __launch_bounds__(kBlk) void k_lit(Geo g, Lists L, int64_t c0, int64_t nc) {
+__global__ __launch_bounds__(kBlk, 5) void k_lit(Geo g, Lists L, int64_t c0, int64_t nc) {
   const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
   unsigned long long pairs = 0;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBlk) void k_lit(Geo g, Lists L, int64_t c0, int64_
       for (int q = 0; q < nq; ++q) {
         double x4[4] = {xr[4 * q], xr[4 * q + 1], xr[4 * q + 2], xr[4 * q + 3]};
         Apex A;
-        apex_of(T, x4, A);
+        apex_frame(T, x4, A);
         const int r = lit_quick(T, x4, A);
         m |= (uint64_t)(r == 1) << q;
         und |= (uint64_t)(r == 2) << q;
