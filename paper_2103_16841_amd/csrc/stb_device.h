@@ -559,21 +559,30 @@ STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& 
       if (rhs >= 0.0 && rhs <= beta * beta) {
         double cv = fmin(sqrt(rhs) / beta, 1.0);
         double g = acos_bp(cv);
-        double cand[4] = {phik + g, phik - g, phik + kPi - g, phik + kPi + g};
+        // candidates phi_k + g, phi_k - g, phi_k + pi - g, phi_k + pi + g;
+        // their directions from (cos, sin) of phi_k = (b, c) / beta and of
+        // g = (cv, sqrt(1 - cv^2)) by the addition theorems
+        const double rb = frcp(beta);
+        const double cp = b * rb, sp = c * rb, sg = sqrt(fmax((1.0 - cv) * (1.0 + cv), 0.0));
+        const double c1 = cp * cv - sp * sg, s1 = sp * cv + cp * sg;   // phi_k + g
+        const double c2 = cp * cv + sp * sg, s2 = sp * cv - cp * sg;   // phi_k - g
+#pragma unroll 1
         for (int m = 0; m < 4; ++m) {
-          double sn, cs;
-          sincos_small(cand[m], &sn, &cs);
+          const bool pg = m == 0 || m == 3;             // + g
+          const double sgn = m < 2 ? 1.0 : -1.0;        // + pi: opposite direction
+          const double cs = sgn * (pg ? c1 : c2), sn = sgn * (pg ? s1 : s2);
+          const double cand = (m < 2 ? phik : phik + kPi) + (pg ? g : -g);
           double e = b * cs + c * sn - a;
           if (e == 0.0) continue;
-          double wt = Ck / e;                 // double root of Q_k
+          double wt = Ck * frcp(e);           // double root of Q_k
           if (!(wt >= ad) || !(wt > 0.0)) continue;
-          double rt = r_of_w(wt, d2), st = 0.5 * (wt - d2 / wt);
+          double rt = r_of_w(wt, d2), st = 0.5 * (wt - d2 * frcp(wt));
           double y0 = A.t - rt, y1 = A.pu + st * cs, y2 = A.pv + st * sn;
           double worst = -1e300;
 #pragma unroll
           for (int m2 = 0; m2 < 4; ++m2)
             worst = fmax(worst, T.fa[m2] * y0 + T.fb[m2] * y1 + T.fc[m2] * y2 - T.fh[m2]);
-          if (worst <= kTangHint * sc) bp[nb++] = wrap_2pi(cand[m]);
+          if (worst <= kTangHint * sc) bp[nb++] = wrap_2pi(cand);
         }
       }
     }
