@@ -247,6 +247,28 @@ def test_errors(stb, ctx):
     assert e.value.status == 1
 
 
+def test_unshared_faces_equal_shared(stb, ctx):
+    """The FP64 assembly evaluates each face shared by two panels once.  The
+    same mesh with every panel on vertices of its own shares no face, so
+    each face is evaluated per panel: the matrices agree to rounding, with
+    the same causal pairs, and both match the oracle."""
+    mesh = inputs.icosphere_mesh(level=0, S=4, T=2.5, jitter=0.2, seed=7)
+    vtx_split = mesh.vtx[mesh.tets].reshape(-1, 4).copy()
+    tets_split = np.arange(4 * mesh.nt, dtype=np.int32).reshape(mesh.nt, 4)
+    print("case: icosphere L0 S4 shared vs unshared faces", flush=True)
+    A1 = stb.assemble_V(ctx, stb.Mesh(ctx, mesh.vtx, mesh.tets))
+    A2 = stb.assemble_V(ctx, stb.Mesh(ctx, vtx_split, tets_split))
+    D1, D2 = A1.to_dense(), A2.to_dense()
+    assert A1.n_causal == A2.n_causal
+    assert np.array_equal(D1 != 0.0, D2 != 0.0)
+    scale = np.abs(D1).max()
+    assert np.all(np.abs(D1 - D2) <= RTOL * np.maximum(np.abs(D1), FLOOR * scale))
+    ref = oracle.assemble_rows(mesh.vtx, mesh.tets, rows=np.arange(0, mesh.nt, 7))
+    for k, i in enumerate(range(0, mesh.nt, 7)):
+        err = np.abs(D1[i] - ref[k]) / np.maximum(np.abs(ref[k]), FLOOR * scale)
+        assert err.max() <= RTOL
+
+
 def test_single_panel_and_empty_points(stb, ctx):
     vtx = np.array([[0, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [1, 0, 0, 0]], float)
     tets = np.array([[0, 1, 2, 3]])
