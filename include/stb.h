@@ -236,6 +236,30 @@ stb_status stb_server_wait(stb_server* server, uint64_t ticket, double* latency_
 /* Finish the queued and running requests, then release the server. */
 void stb_server_destroy(stb_server* server);
 
+/* The outer rule of eq. int_bform for every panel of mesh, the points the
+ * matrix rows are built from: pts [nt][4 m_q^2][4] (t, x, y, z), weights
+ * [nt][4 m_q^2] (-nu_{F,t} |F| / m_q^2 for the panel's faces with nu_t != 0,
+ * Fig. int_tri_mid), counts [nt]; host arrays owned by the caller; entries
+ * past a panel's count are zero.  With g sampled at these points,
+ * b_i = sum_q w_iq g(x_q) is the right-hand side b(g, phi_i) of the discrete
+ * indirect system (eq. df_ind, the same integration by parts as
+ * eq. int_bform with g in place of V w). */
+stb_status stb_outer_points(stb_ctx* ctx, const stb_mesh* mesh, int32_t m_q, double* pts,
+                            double* weights, int32_t* counts);
+
+/* Solves the discrete indirect system A x = b (eq. df_ind) for the square
+ * matrix of one whole mesh by restarted GMRES(restart) on the device: FP64
+ * products with the stored matrix, classical Gram-Schmidt with one
+ * re-orthogonalisation, Givens rotations on the host.  x_host holds the
+ * initial guess and receives the solution (n doubles each, host).  Stops
+ * when the true residual |b - A x| <= rtol |b| (checked at each restart) or
+ * after maxit products; iters (optional) receives the products used,
+ * relres (optional) the last true relative residual.  STB_E_INVALID_ARG for
+ * a row block (not square), restart outside [1, 512], maxit < 1 or
+ * rtol <= 0. */
+stb_status stb_solve_gmres(stb_ctx* ctx, const stb_mat* A, const double* b_host, double* x_host,
+                           int32_t restart, int32_t maxit, double rtol, int32_t* iters, double* relres);
+
 /* Timing of the last stb_assemble_V on ctx, in milliseconds measured with
  * HIP events on the context stream: [0] geometry/outer points, [1] cull and
  * compaction, [2] clip + quadrature + store, [3] total. */

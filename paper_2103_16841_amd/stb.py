@@ -22,6 +22,7 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
            "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
            "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_last_path_counts", "stb_mesh_create_dev",
+           "stb_outer_points", "stb_solve_gmres",
            "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble", "stb_autotune",
            "stb_set_tuning", "stb_server_create", "stb_server_add_mesh", "stb_server_submit",
            "stb_server_wait", "stb_server_destroy"]
@@ -93,6 +94,9 @@ def load():
     L.stb_inner_values.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
     L.stb_last_work.argtypes = [_VP, _I64]
     L.stb_last_path_counts.argtypes = [_VP, _I64]
+    L.stb_outer_points.argtypes = [_VP, _VP, i32, _D, _D, _I32]
+    L.stb_solve_gmres.argtypes = [_VP, _VP, _D, _D, i32, i32, ctypes.c_double, _I32,
+                                  ctypes.POINTER(ctypes.c_double)]
     L.stb_last_kernel_times.argtypes = [_VP, _D, _I64, _I64]
     L.stb_mat_export.argtypes = [_VP, _I64, _I32, _D]
     L.stb_autotune.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _I32]
@@ -330,6 +334,38 @@ def potential_S(ctx, mesh, w, pts, params=None):
     _chk(load().stb_potential_S(ctx.h, mesh.h, ctypes.byref(p), pw, pts.shape[0], pp,
                                 out.ctypes.data_as(_D)), ctx.h)
     return out
+
+
+def outer_points(ctx, mesh, m_q=3):
+    """The outer rule of every panel: points [nt][4 m_q^2][4], weights
+    [nt][4 m_q^2], counts [nt] (entries past a panel's count are zero)."""
+    maxq = 4 * m_q * m_q
+    pts = np.zeros((mesh.nt, maxq, 4))
+    w = np.zeros((mesh.nt, maxq))
+    n = np.zeros(mesh.nt, dtype=np.int32)
+    _chk(load().stb_outer_points(ctx.h, mesh.h, m_q, pts.ctypes.data_as(_D), w.ctypes.data_as(_D),
+                                 n.ctypes.data_as(_I32)), ctx.h)
+    return pts, w, n
+
+
+def energetic_rhs(ctx, mesh, g, m_q=3):
+    """b_i = sum_q w_iq g(x_q): the right-hand side of the indirect system
+    for boundary data g (a function of an array [k][4] of points (t,x,y,z))."""
+    pts, w, n = outer_points(ctx, mesh, m_q)
+    vals = np.asarray(g(pts.reshape(-1, 4)), dtype=np.float64).reshape(w.shape)
+    return (w * vals).sum(axis=1)
+
+
+def solve_gmres(ctx, A, b, x0=None, restart=100, maxit=2000, rtol=1e-10):
+    """x with A x = b by restarted GMRES on the device; returns (x, products,
+    relative residual)."""
+    b, pb = _d(b)
+    x = np.zeros(b.shape[0]) if x0 is None else np.array(x0, dtype=np.float64)
+    it = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    _chk(load().stb_solve_gmres(ctx.h, A.h, pb, x.ctypes.data_as(_D), restart, maxit, rtol,
+                                ctypes.byref(it), ctypes.byref(rr)), ctx.h)
+    return x, it.value, rr.value
 
 
 def inner_values(ctx, mesh, pts, panels, params=None):
