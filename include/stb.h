@@ -276,7 +276,7 @@ stb_status stb_last_timings(const stb_ctx* ctx, double* ms4);
  * cost three evaluations). */
 stb_status stb_last_path_counts(const stb_ctx* ctx, int64_t* counts4);
 
-/* Work of the last stb_assemble_V on ctx: [0] evaluations of L(phi)
+/* Work of the last stb_assemble_V or potential on ctx: [0] evaluations of L(phi)
  * (empty-piece tests and Gauss nodes), [1] lit (outer point, trial panel)
  * pairs, [2] candidate (outer point, trial panel) pairs examined, [3] phi
  * pieces. */

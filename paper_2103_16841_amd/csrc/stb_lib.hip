@@ -847,6 +847,7 @@ stb_status stb_potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_param
   unsigned long long work[4];
   s = stb_run_pairs(ctx, J, work);
   if (s) { cleanup(); return s; }
+  for (int k = 0; k < 4; ++k) ctx->work[k] = (int64_t)work[k];
   hipLaunchKernelGGL(k_point_sum, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
                      d_rowptr, d_cols, d_I, d_w, d_out);
   hipError_t e = hipGetLastError();

@@ -1,0 +1,65 @@
+"""Lit-set sizes of single points (the culling study of Sec. 3.3 / Exp. 1,
+on this build's own meshes): for a point x at time t = T, the lit set
+Sigma_N(x) is the set of panels its backward light cone meets, a
+two-dimensional slice of the three-dimensional space-time boundary, so
+|Sigma_N(x)| grows like N^(2/3) under uniform refinement in space and time;
+the cull's candidate set X_N(x) (bounding-ball tests) stays within a
+bounded factor of it.
+
+Meshes: the unit sphere (icosphere levels 0-3) with T = 5 and about one slab
+per spatial mesh width (S = 5, 10, 20, 40), N = 300 ... 153,600.  Points at
+t = T: the centre, a point on the sphere, (1, 1, 1)/sqrt 3, and the outside
+point (-1, -sqrt(2)/2, -1/pi).
+"""
+import numpy as np
+import pytest
+
+from paper_2103_16841_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+POINTS = {"x_A": (0.0, 0.0, 0.0), "x_B": tuple(np.ones(3) / np.sqrt(3.0)),
+          "x_C": (-1.0, -np.sqrt(2.0) / 2.0, -1.0 / np.pi)}
+
+
+@pytest.fixture(scope="module")
+def stb():
+    import torch
+    torch.cuda.init()
+    from paper_2103_16841_amd import stb as s
+    s.load()
+    return s
+
+
+@pytest.fixture(scope="module")
+def ctx(stb):
+    c = stb.Context(0)
+    yield c
+    c.close()
+
+
+def test_lit_set_growth(stb, ctx):
+    T = 5.0
+    rows = []
+    for level, S in ((0, 5), (1, 10), (2, 20), (3, 40)):
+        mesh = inputs.icosphere_mesh(level=level, S=S, T=T, jitter=0.0, seed=0)
+        m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+        w = np.ones(mesh.nt)
+        row = [mesh.nt]
+        for name, x in POINTS.items():
+            stb.potential_S(ctx, m, w, np.array([[T, *x]]))
+            wk = ctx.work()
+            row += [wk["lit_pairs"], wk["apex_pairs"]]
+        rows.append(row)
+        print("case: level %d S %d N %d: (lit, candidates) per point %s"
+              % (level, S, mesh.nt, row[1:]), flush=True)
+    rows = np.array(rows, dtype=np.float64)
+    logn = np.log(rows[:, 0])
+    for k, name in enumerate(POINTS):
+        lit, cand = rows[:, 1 + 2 * k], rows[:, 2 + 2 * k]
+        slope = np.polyfit(logn[1:], np.log(lit[1:]), 1)[0]
+        ratio = cand / lit
+        print("%s: |Sigma_N| slope %.3f (2/3 expected), |X_N|/|Sigma_N| %s"
+              % (name, slope, np.round(ratio, 2)), flush=True)
+        assert 0.6 <= slope <= 0.73
+        assert ratio.max() <= 2.0 * ratio[1:].min()
