@@ -135,7 +135,16 @@ __global__ void k_point_boxes(int64_t np, const double* __restrict__ pts, ApexBo
 // Conservative causal test: some apex of the box and some point of the
 // panel with |x - y| = t - tau requires t - tau >= dist >= lower bound, and a
 // crossing needs a point outside the cone: t - tau < dist <= upper bound.
-__device__ __forceinline__ bool maybe_lit(const ApexBox& b, const TrialRec& T) {
+// The panel fields the cull reads.
+struct CullPanel {
+  double cx, cy, cz, rad, tmin, tmax, diam;
+};
+
+__device__ __forceinline__ CullPanel cull_panel(const TrialRec& T) {
+  return CullPanel{T.cx, T.cy, T.cz, T.rad, T.tmin, T.tmax, T.diam};
+}
+
+__device__ __forceinline__ bool maybe_lit(const ApexBox& b, const CullPanel& T) {
   double dx = b.cx - T.cx, dy = b.cy - T.cy, dz = b.cz - T.cz;
   double dc = sqrt(dx * dx + dy * dy + dz * dz);
   double lb = dc - b.rho - T.rad, ub = dc + b.rho + T.rad;
@@ -144,26 +153,46 @@ __device__ __forceinline__ bool maybe_lit(const ApexBox& b, const TrialRec& T) {
 }
 
 constexpr int kCullThreads = 256;
+// Rows per block: each panel record read from L2 serves this many rows.
+constexpr int kCullRows = 8;
 
 __global__ __launch_bounds__(kCullThreads) void k_cull_count(int64_t nrows,
                                                              const ApexBox* __restrict__ rows,
                                                              int64_t nt,
                                                              const TrialRec* __restrict__ T,
                                                              int64_t* __restrict__ cnt) {
-  int64_t i = blockIdx.x;
-  if (i >= nrows) return;
-  ApexBox b = rows[i];
-  int c = 0;
-  for (int64_t j = threadIdx.x; j < nt; j += kCullThreads) c += maybe_lit(b, T[j]) ? 1 : 0;
-  typedef hipcub::BlockReduce<int, kCullThreads> BR;
-  __shared__ typename BR::TempStorage tmp;
-  int s = BR(tmp).Sum(c);
-  if (threadIdx.x == 0) cnt[i] = s;
+  const int64_t i0 = (int64_t)blockIdx.x * kCullRows;
+  if (i0 >= nrows) return;
+  const int nr = (int)std::min<int64_t>(kCullRows, nrows - i0);
+  __shared__ ApexBox s_b[kCullRows];
+  __shared__ int red[kCullRows][kCullThreads];
+  if ((int)threadIdx.x < nr) s_b[threadIdx.x] = rows[i0 + threadIdx.x];
+  __syncthreads();
+  int c[kCullRows];
+#pragma unroll
+  for (int r = 0; r < kCullRows; ++r) c[r] = 0;
+  for (int64_t j = threadIdx.x; j < nt; j += kCullThreads) {
+    const CullPanel P = cull_panel(T[j]);
+#pragma unroll
+    for (int r = 0; r < kCullRows; ++r)
+      if (r < nr) c[r] += maybe_lit(s_b[r], P) ? 1 : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < kCullRows; ++r) red[r][threadIdx.x] = c[r];
+  __syncthreads();
+  for (int off = kCullThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+#pragma unroll
+      for (int r = 0; r < kCullRows; ++r) red[r][threadIdx.x] += red[r][threadIdx.x + off];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < nr) cnt[i0 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Fill the candidate columns of each row in ascending order: per 256-wide
-// chunk, a wavefront ballot + mbcnt gives each lane its rank inside the
-// wave; an LDS prefix over the four waves orders the chunk.
+// chunk of panels (read once for the block's rows), a wavefront ballot +
+// mbcnt gives each lane its rank inside the wave per row; an LDS prefix
+// over the four waves orders the chunk.
 __global__ __launch_bounds__(kCullThreads) void k_cull_fill(int64_t nrows,
                                                             const ApexBox* __restrict__ rows,
                                                             int64_t nt,
@@ -171,29 +200,46 @@ __global__ __launch_bounds__(kCullThreads) void k_cull_fill(int64_t nrows,
                                                             const int64_t* __restrict__ rowptr,
                                                             int32_t* __restrict__ cols,
                                                             int32_t* __restrict__ rowof) {
-  int64_t i = blockIdx.x;
-  if (i >= nrows) return;
-  __shared__ int wave_cnt[kCullThreads / 64];
-  ApexBox b = rows[i];
-  int64_t base = rowptr[i];
-  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * kCullRows;
+  if (i0 >= nrows) return;
+  const int nr = (int)std::min<int64_t>(kCullRows, nrows - i0);
+  constexpr int kWaves = kCullThreads / 64;
+  __shared__ ApexBox s_b[kCullRows];
+  __shared__ int wave_cnt[kCullRows][kWaves];
+  if ((int)threadIdx.x < nr) s_b[threadIdx.x] = rows[i0 + threadIdx.x];
+  __syncthreads();
+  int64_t base[kCullRows];
+#pragma unroll
+  for (int r = 0; r < kCullRows; ++r) base[r] = r < nr ? rowptr[i0 + r] : 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t j0 = 0; j0 < nt; j0 += kCullThreads) {
-    int64_t j = j0 + threadIdx.x;
-    bool p = j < nt && maybe_lit(b, T[j]);
-    uint64_t bal = __ballot(p);
-    int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-    if (lane == 0) wave_cnt[wave] = __popcll(bal);
-    __syncthreads();
-    int off = 0;
-    for (int w = 0; w < wave; ++w) off += wave_cnt[w];
-    int tot = 0;
-    for (int w = 0; w < kCullThreads / 64; ++w) tot += wave_cnt[w];
-    if (p) {
-      cols[base + off + rank] = (int32_t)j;
-      rowof[base + off + rank] = (int32_t)i;
+    const int64_t j = j0 + threadIdx.x;
+    CullPanel P{};
+    if (j < nt) P = cull_panel(T[j]);
+    uint32_t pm = 0;   // rows for which panel j is a candidate
+    int rank[kCullRows];
+#pragma unroll
+    for (int r = 0; r < kCullRows; ++r) {
+      const bool p = r < nr && j < nt && maybe_lit(s_b[r], P);
+      const uint64_t bal = __ballot(p);
+      rank[r] = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+      if (lane == 0) wave_cnt[r][wave] = __popcll(bal);
+      pm |= (p ? 1u : 0u) << r;
     }
-    base += tot;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kCullRows; ++r) {
+      int off = 0, tot = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        off += w < wave ? wave_cnt[r][w] : 0;
+        tot += wave_cnt[r][w];
+      }
+      if ((pm >> r) & 1u) {
+        cols[base[r] + off + rank[r]] = (int32_t)j;
+        rowof[base[r] + off + rank[r]] = (int32_t)(i0 + r);
+      }
+      base[r] += tot;
+    }
     __syncthreads();
   }
 }
@@ -412,7 +458,8 @@ stb_status stb_cull_rowptr(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, c
     dfree(d_cnt);
     return fail(ctx, STB_E_NO_MEMORY, "cull counts");
   }
-  hipLaunchKernelGGL(k_cull_count, dim3((unsigned)nrows), dim3(kCullThreads), 0, ctx->stream, nrows,
+  hipLaunchKernelGGL(k_cull_count, dim3((unsigned)((nrows + kCullRows - 1) / kCullRows)), dim3(kCullThreads), 0,
+                     ctx->stream, nrows,
                      d_rows, m->nt, m->d_trial, d_cnt);
   hipError_t e = hipGetLastError();
   stb_status s = e == hipSuccess ? device_exclusive_scan(ctx, d_cnt, d_scan, nrows)
@@ -442,7 +489,8 @@ stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const st
   HIPCHK(ctx, dalloc(&d_cnt, (size_t)nrows));
   HIPCHK(ctx, dalloc(d_rowptr, (size_t)nrows + 1));
   if (nrows > 0) {
-    hipLaunchKernelGGL(k_cull_count, dim3((unsigned)nrows), dim3(kCullThreads), 0, ctx->stream,
+    hipLaunchKernelGGL(k_cull_count, dim3((unsigned)((nrows + kCullRows - 1) / kCullRows)), dim3(kCullThreads),
+                       0, ctx->stream,
                        nrows, d_rows, m->nt, m->d_trial, d_cnt);
     HIPCHK(ctx, hipGetLastError());
   }
@@ -453,7 +501,8 @@ stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const st
   HIPCHK(ctx, dalloc(d_cols, (size_t)*nnz));
   HIPCHK(ctx, dalloc(d_rowof, (size_t)*nnz));
   if (nrows > 0) {
-    hipLaunchKernelGGL(k_cull_fill, dim3((unsigned)nrows), dim3(kCullThreads), 0, ctx->stream,
+    hipLaunchKernelGGL(k_cull_fill, dim3((unsigned)((nrows + kCullRows - 1) / kCullRows)), dim3(kCullThreads),
+                       0, ctx->stream,
                        nrows, d_rows, m->nt, m->d_trial, *d_rowptr, *d_cols, *d_rowof);
     HIPCHK(ctx, hipGetLastError());
   }
