@@ -35,6 +35,7 @@
 // percent of what the FP64 arithmetic takes, while each stage runs at full
 // lane occupancy with its own register budget.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -103,6 +104,10 @@ struct Lists {
   // per candidate of the chunk
   uint64_t* mask;        // lit apexes (bit q)
   int32_t* combo0;       // first combo of the candidate
+  int32_t* ccnt;         // [cap_cand + 1] lit apexes per candidate, then ...
+  int32_t* coff;         // [cap_cand + 1] ... their exclusive prefix
+  void* scan_tmp;        // prefix-sum scratch
+  size_t scan_bytes;
   // per combo
   uint32_t* key;         // (candidate in chunk) << 8 | far << 7 | q
   uint32_t* deep;        // (candidate in chunk) << 8 | q of lit tests the vertices left open
@@ -259,27 +264,28 @@ __global__ __launch_bounds__(kBlk) void k_lit_deep(Geo g, Lists L, int64_t c0, i
   }
 }
 
-// Lit combos appended contiguously per candidate, in apex order.
-__global__ __launch_bounds__(kBlk) void k_emit(Geo g, Lists L, int64_t c0, int64_t nc) {
-  const int B = (int)blockDim.x;
-  __shared__ AllocLds sh;
-  for (int64_t base = (int64_t)blockIdx.x * B; base < nc; base += (int64_t)gridDim.x * B) {
-    const int64_t c = base + threadIdx.x;
-    const bool v = c < nc;
-    const uint64_t m = v ? L.mask[c] : 0ull;
-    const unsigned n = (unsigned)__popcll(m);
-    const unsigned long long b = block_alloc(L.cnt + CNT_COMBO, n, sh);
-    if (v) {
-      L.combo0[c] = (int32_t)std::min<unsigned long long>(b, 0x7fffffffull);
-      if (b + n <= (unsigned long long)L.cap_combo) {
-        unsigned long long k = b;
-        uint64_t mm = m;
-        while (mm) {
-          const int q = __ffsll((long long)mm) - 1;
-          L.key[k++] = ((uint32_t)c << 8) | (uint32_t)q;
-          mm &= mm - 1;
-        }
-      }
+// Lit combos contiguous per candidate, in apex order, candidates in order:
+// counts, an exclusive prefix sum (hipcub), then the keys.
+__global__ void k_emit_count(Lists L, int64_t nc) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nc) L.ccnt[c] = __popcll(L.mask[c]);
+  else if (c == nc) L.ccnt[nc] = 0;
+}
+
+__global__ __launch_bounds__(kBlk) void k_emit(Lists L, int64_t nc) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) L.cnt[CNT_COMBO] = (unsigned long long)L.coff[nc];
+  if (c >= nc) return;
+  const uint64_t m = L.mask[c];
+  const int32_t b = L.coff[c];
+  L.combo0[c] = b;
+  if ((int64_t)b + __popcll(m) <= L.cap_combo) {
+    int64_t k = b;
+    uint64_t mm = m;
+    while (mm) {
+      const int q = __ffsll((long long)mm) - 1;
+      L.key[k++] = ((uint32_t)c << 8) | (uint32_t)q;
+      mm &= mm - 1;
     }
   }
 }
@@ -771,8 +777,16 @@ void stb_free_workspace(stb_ctx* ctx) {
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Lay the lists out in one allocation.
+static size_t scan_bytes_for(int64_t cc) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (const int32_t*)nullptr, (int32_t*)nullptr,
+                                         (int)(cc + 1));
+  return bytes;
+}
+
 static size_t ws_bytes(int64_t cc, int64_t cb, int64_t cp) {
   size_t b = 0;
+  b += 2 * align256((cc + 1) * 4) + align256(scan_bytes_for(cc));
   b += align256(cc * 8) + align256(cc * 4);
   b += 2 * align256(cb * 4) + align256(cb * kComboStored * 8) + align256(cb * 4) + 2 * align256(cb * 4) +
        align256(cb * 8);
@@ -813,6 +827,10 @@ static stb_status ensure_workspace(stb_ctx* ctx, int64_t want_cand, int64_t want
   char* p = (char*)base;
   auto take = [&](size_t bytes) { char* r = p; p += align256(bytes); return (void*)r; };
   Lists& L = w->L;
+  L.scan_bytes = scan_bytes_for(want_cand);
+  L.ccnt = (int32_t*)take((want_cand + 1) * 4);
+  L.coff = (int32_t*)take((want_cand + 1) * 4);
+  L.scan_tmp = take(L.scan_bytes);
   L.mask = (uint64_t*)take(want_cand * 8);
   L.combo0 = (int32_t*)take(want_cand * 4);
   L.key = (uint32_t*)take(want_combo * 4);
@@ -909,7 +927,13 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     if (ndeep)
       hipLaunchKernelGGL(k_lit_deep, dim3(gfor(0, ndeep)), dim3(ctx->tune_block[0]), 0, st, g, L, c0,
                          (int64_t)ndeep);
-    hipLaunchKernelGGL(k_emit, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc);
+    hipLaunchKernelGGL(k_emit_count, dim3((unsigned)((nc + 1 + 255) / 256)), dim3(256), 0, st, L, nc);
+    HIPCHK(ctx, hipGetLastError());
+    {
+      size_t sb = L.scan_bytes;
+      HIPCHK(ctx, hipcub::DeviceScan::ExclusiveSum(L.scan_tmp, sb, L.ccnt, L.coff, (int)(nc + 1), st));
+    }
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, L, nc);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(0));
     unsigned long long ncombo = 0, npiece = 0, njob = 0;
