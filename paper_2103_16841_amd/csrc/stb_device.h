@@ -509,7 +509,16 @@ STB_HD inline void face_angles(const TrialRec& T, FaceAng& F) {
   }
 }
 
-STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& A, double* bp) {
+// Breakpoint storage: a plain array, or (the breakpoint kernel) slots in
+// LDS with the rare overflow in private memory.  put/get by slot index.
+struct BpArray {
+  double* a;
+  STB_HD __forceinline__ void put(int i, double v) { a[i] = v; }
+  STB_HD __forceinline__ double get(int i) const { return a[i]; }
+};
+
+template <class BP>
+STB_HD inline int breakpoints_t(const TrialRec& T, const FaceAng& FA, const Apex& A, BP& bp) {
   int nb = 0;
   double d2 = A.d * A.d, ad = fabs(A.d);
   const double rd2 = d2 > 0.0 ? frcp(d2) : 0.0;   // for the tangency test
@@ -523,7 +532,7 @@ STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& 
   }
   const double inside = -1e-9 * sc;
   // edge events (at most 12): the in-plane offsets (ou, ov) first, kept in
-  // bp[m] and bp[16 + m], then their angles in one loop
+  // slots m and 12 + m, then their angles in one loop
   int nh = 0;
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j) {
@@ -542,12 +551,12 @@ STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& 
         if (a0 + a1 * l < 0.0) continue;
         double ou = bu + l * du, ov = bv + l * dv;
         if (ou * ou + ov * ov <= 1e-20 * sc * sc) continue;
-        bp[nh] = ou;
-        bp[16 + nh] = ov;
+        bp.put(nh, ou);
+        bp.put(12 + nh, ov);
         ++nh;
       }
     }
-  for (int m = 0; m < nh; ++m) bp[m] = wrap_2pi(atan2_bp(bp[16 + m], bp[m]));
+  for (int m = 0; m < nh; ++m) bp.put(m, wrap_2pi(atan2_bp(bp.get(12 + m), bp.get(m))));
   nb = nh;
   for (int k = 0; k < 4; ++k) {
     double a = T.fa[k], b = T.fb[k], c = T.fc[k], Ck = A.C[k];
@@ -582,21 +591,26 @@ STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& 
 #pragma unroll
           for (int m2 = 0; m2 < 4; ++m2)
             worst = fmax(worst, T.fa[m2] * y0 + T.fb[m2] * y1 + T.fc[m2] * y2 - T.fh[m2]);
-          if (worst <= kTangHint * sc) bp[nb++] = wrap_2pi(cand);
+          if (worst <= kTangHint * sc) bp.put(nb++, wrap_2pi(cand));
         }
       }
     }
     if (fabs(a * ad + Ck) <= kVtxHint * sc) {
-      bp[nb++] = wrap_2pi(phik + 0.5 * kPi);
-      bp[nb++] = wrap_2pi(phik - 0.5 * kPi);
+      bp.put(nb++, wrap_2pi(phik + 0.5 * kPi));
+      bp.put(nb++, wrap_2pi(phik - 0.5 * kPi));
     }
     if (ad <= kFlatTol * sc && fabs(Ck) <= kFlatTol * sc && fabs(a) <= beta) {
       double g = acos_bp(fmax(-1.0, fmin(1.0, a / beta)));
-      bp[nb++] = wrap_2pi(phik + g);
-      bp[nb++] = wrap_2pi(phik - g);
+      bp.put(nb++, wrap_2pi(phik + g));
+      bp.put(nb++, wrap_2pi(phik - g));
     }
   }
   return nb;
+}
+
+STB_HD inline int breakpoints(const TrialRec& T, const FaceAng& FA, const Apex& A, double* bp) {
+  BpArray a{bp};
+  return breakpoints_t(T, FA, A, a);
 }
 
 // A direction whose ray from the apex's projection (pu, pv) misses the
@@ -635,11 +649,12 @@ STB_HD __forceinline__ bool piece_misses(const TrialRec& T, const Apex& A, doubl
 // registers (padded with +inf), Batcher's odd-even merge network, back --
 // independent loads and stores instead of the insertion sort's dependent
 // chain through private memory.
-STB_HD __forceinline__ void sort_bp(double* a, int n) {
+template <class BP>
+STB_HD __forceinline__ void sort_bp_t(BP& a, int n) {
   if (n <= 16) {
     double r[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) r[j] = j < n ? a[j] : HUGE_VAL;
+    for (int j = 0; j < 16; ++j) r[j] = j < n ? a.get(j) : HUGE_VAL;
 #pragma unroll
     for (int p = 1; p < 16; p <<= 1)
 #pragma unroll
@@ -656,15 +671,20 @@ STB_HD __forceinline__ void sort_bp(double* a, int n) {
             }
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-      if (j < n) a[j] = r[j];
+      if (j < n) a.put(j, r[j]);
     return;
   }
   for (int i = 1; i < n; ++i) {
-    double v = a[i];
+    double v = a.get(i);
     int j = i - 1;
-    while (j >= 0 && a[j] > v) { a[j + 1] = a[j]; --j; }
-    a[j + 1] = v;
+    while (j >= 0 && a.get(j) > v) { a.put(j + 1, a.get(j)); --j; }
+    a.put(j + 1, v);
   }
+}
+
+STB_HD __forceinline__ void sort_bp(double* a, int n) {
+  BpArray b{a};
+  sort_bp_t(b, n);
 }
 
 // Panel geometry from its 4 vertices (t, x, y, z).  Returns 0, or 2 for a

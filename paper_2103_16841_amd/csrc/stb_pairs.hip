@@ -290,14 +290,35 @@ __global__ __launch_bounds__(kBlk) void k_emit(Lists L, int64_t nc) {
   }
 }
 
+// Breakpoints of a lane: the first kBpLds slots in LDS (slot s of lane t at
+// s * B + t: neighbouring lanes, neighbouring banks), the rest (nearly never
+// used) in private memory.  Private memory of every resident lane is tens of
+// MB, past the L2 caches: keeping the lists there cost most of the kernel's
+// memory traffic.
+constexpr int kBpLds = 24;
+struct BpLds {
+  double* lds;
+  int stride;
+  double* spill;
+  __device__ __forceinline__ void put(int i, double v) {
+    if (i < kBpLds) lds[i * stride] = v;
+    else spill[i - kBpLds] = v;
+  }
+  __device__ __forceinline__ double get(int i) const {
+    return i < kBpLds ? lds[i * stride] : spill[i - kBpLds];
+  }
+};
+
 __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int64_t ncombo) {
   const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
+  __shared__ double s_bp[kBpLds * kBlk];
   unsigned long long nmiss = 0;
+  double spill[kMaxBp - kBpLds];
+  BpLds bp{s_bp + threadIdx.x, B, spill};
   for (int64_t base = (int64_t)blockIdx.x * B; base < ncombo; base += (int64_t)gridDim.x * B) {
     const int64_t k = base + threadIdx.x;
     const bool v = k < ncombo;
-    double bp[kMaxBp];
     int nb = 0;
     unsigned np = 0;
     unsigned long long miss = 0;   // pieces (by start breakpoint) found empty by the ray test
@@ -322,15 +343,16 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
         cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
         store_combo(L, k, cb, col);
         if (g.mixed && apex_far(T, x4, g.eta_far)) L.key[k] = key | 0x80u;
-        nb = breakpoints(T, g.fang[col], A, bp);
-        sort_bp(bp, nb);
+        nb = breakpoints_t(T, g.fang[col], A, bp);
+        sort_bp_t(bp, nb);
         if (nb == 0) {
           np = 2;
         } else {
           for (int m = 0; m < nb; ++m) {
-            double e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
-            if (!(e - bp[m] > 0.0)) continue;
-            if (piece_misses(T, A, bp[m], e - bp[m])) {
+            const double a = bp.get(m);
+            double e = (m + 1 < nb) ? bp.get(m + 1) : bp.get(0) + kTwoPi;
+            if (!(e - a > 0.0)) continue;
+            if (piece_misses(T, A, a, e - a)) {
               miss |= 1ull << m;
               ++nmiss;
             } else {
@@ -354,8 +376,8 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
         } else {
           unsigned long long s = p0;
           for (int m = 0; m < nb; ++m) {
-            double a = bp[m];
-            double e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
+            double a = bp.get(m);
+            double e = (m + 1 < nb) ? bp.get(m + 1) : bp.get(0) + kTwoPi;
             if (!(e - a > 0.0) || ((miss >> m) & 1ull)) continue;
             L.pa[s] = a;
             L.ph[s] = e - a;
