@@ -39,10 +39,10 @@ def node_flops(counts):
     return sum(FLOP_PER_L[k] * counts.get(k, 0) for k in FLOP_PER_L)
 # HBM bytes per launch group of the FP64 node stage on this workload:
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a plain 1 GiB
-# copy), average over the 16 assembly chunks
+# copy), average over the 18 assembly launch groups of one profiled run
 # (profiles/node_stage_icosphere_L2_S32.md).  Set to None whenever the node
 # kernels change until they are profiled again.
-K_NODES_TRAFFIC_BYTES = 1.454e10
+K_NODES_TRAFFIC_BYTES = 1.49e10
 
 def parse():
     ap = argparse.ArgumentParser()
