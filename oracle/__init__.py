@@ -68,6 +68,8 @@ def lib():
         L.orc_count_causal_per_row.argtypes = [i64, _D, i64, _I32, i64, _I64, c_int, _I64]
         L.orc_num_threads.argtypes = []
         L.orc_breakpoints.argtypes = [_D, _D, _D, c_int]
+        L.orc_inner_dl.argtypes = [_D, _D, _D, _D, c_int, _D]
+        L.orc_potential_dl.argtypes = [i64, _D, i64, _I32, _D, _D, i64, _D, c_int, _D]
         _lib = L
     return _lib
 
@@ -220,3 +222,30 @@ def breakpoints(x4, tet):
     out = np.zeros(64)
     n = _check(lib().orc_breakpoints(px, pt, out.ctypes.data_as(_D), 64), "breakpoints")
     return out[:n].copy()
+
+
+def inner_dl(x4, tet, nrm, vv, n_g=DEFAULT_NG):
+    """Retarded double-layer potential (eq. dlp) at x = (t,x,y,z) of the
+    density that is linear on the panel tet (4x4) with values vv at its 4
+    vertices; nrm = the outward spatial normal of the panel (any length)."""
+    x4, px = _d(x4)
+    tet, pt = _d(tet)
+    nrm, pn = _d(nrm)
+    vv, pvv = _d(vv)
+    out = ctypes.c_double()
+    _check(lib().orc_inner_dl(px, pt, pn, pvv, n_g, ctypes.byref(out)), "inner_dl")
+    return out.value
+
+
+def potential_dl(vtx, tets, nrm, v, pts, n_g=DEFAULT_NG):
+    """u(p) = D v (p) for v in V_h^1 given by its vertex values v (eq. dlp);
+    nrm = per-panel outward spatial normals (nt x 3)."""
+    vtx, pv = _d(vtx)
+    tets, pt = _i32(tets)
+    nrm, pn = _d(np.asarray(nrm).reshape(-1, 3))
+    v, pvv = _d(v)
+    pts, pp = _d(np.asarray(pts).reshape(-1, 4))
+    out = np.zeros(pts.shape[0])
+    _check(lib().orc_potential_dl(vtx.shape[0], pv, tets.shape[0], pt, pn, pvv, pts.shape[0], pp,
+                                  n_g, out.ctypes.data_as(_D)), "potential_dl")
+    return out

@@ -275,12 +275,14 @@ static int face_roots(double B, double a, double C, double d2, double* r) {
   return 2;
 }
 
-/* L(phi): measure of the admissible r-set (see header comment). */
-static double L_phi(const orc_panel* P, const orc_apex* A, double phi) {
+/* The admissible r-set at angle phi as sub-intervals [seg[2m], seg[2m+1]]
+ * in increasing order (see header comment); returns their number.  Adjacent
+ * kept sub-intervals are not merged. */
+static int r_segments(const orc_panel* P, const orc_apex* A, double phi, double* seg) {
   double rlo = fabs(A->d);
   if (A->t - P->tmax > rlo) rlo = A->t - P->tmax;
   double rhi = A->t - P->tmin;
-  if (!(rhi > rlo)) return 0.0;
+  if (!(rhi > rlo)) return 0;
   double cs = cos(phi), sn = sin(phi);
   double B[4], cand[16];
   int nc = 0;
@@ -296,7 +298,7 @@ static double L_phi(const orc_panel* P, const orc_apex* A, double phi) {
       if (r[m] > rlo && r[m] < rhi) cand[nc++] = r[m];
   }
   sort_small(cand, nc);
-  double len = 0.0;
+  int ns = 0;
   for (int m = 0; m + 1 < nc; ++m) {
     double r1 = cand[m], r2 = cand[m + 1];
     if (!(r2 > r1)) continue;
@@ -306,8 +308,17 @@ static double L_phi(const orc_panel* P, const orc_apex* A, double phi) {
     int inside = 1;
     for (int k = 0; k < 4 && inside; ++k)
       if (!(B[k] * s - P->fa[k] * rm - A->C[k] < 0.0)) inside = 0;
-    if (inside) len += r2 - r1;
+    if (inside) { seg[2 * ns] = r1; seg[2 * ns + 1] = r2; ++ns; }
   }
+  return ns;
+}
+
+/* L(phi): measure of the admissible r-set (see header comment). */
+static double L_phi(const orc_panel* P, const orc_apex* A, double phi) {
+  double seg[32];
+  int ns = r_segments(P, A, phi, seg);
+  double len = 0.0;
+  for (int m = 0; m < ns; ++m) len += seg[2 * m + 1] - seg[2 * m];
   return len;
 }
 
@@ -589,6 +600,139 @@ int orc_inner(const double* x4, const double* tet, int n_g, double* out, orc_sta
   return ORC_OK;
 }
 
+/* ---------------- double layer (eq. dlp) ----------------
+ *
+ * For a density v linear on the panel, eq. dlp restricted to the panel
+ * reads, after the delta fixes tau = t - |x - y| and with the polar
+ * coordinates of the single layer (dA = r dr dphi, r = |x - y|,
+ * s = sqrt(r^2 - d^2)):
+ *
+ *   D v (x) = (d_n / 4 pi) int dphi int_{R(phi)} [ v(t - r, y) / r^2
+ *                                                  + dv/dtau / r ] dr,
+ *
+ * with d_n = <n_Gamma, x - y> the distance of x from the panel's plane
+ * along the outward normal (constant on the plane), so that k3 = d_n /
+ * (4 pi r^3) and k2 = d_n / (4 pi r^2) (eq. kfunc).  Writing
+ * v = c0 + c_tau tau + c_u u + c_v v in the local frame, the retarded
+ * value is v(t - r, p + s e(phi)) = alpha - c_tau r + s gamma(phi) with
+ * alpha = v(t, p) and gamma = c_u cos phi + c_v sin phi, so the c_tau terms
+ * cancel and the r-integrand is alpha / r^2 + gamma s / r^2, integrated in
+ * closed form over every sub-interval [r0, r1] of R(phi):
+ *
+ *   alpha (1/r0 - 1/r1) + gamma (H(r1) - H(r0)),  H(r) = ln(r + s) - s / r.
+ *
+ * The phi-rule (breakpoints, empty-piece test on L, smoothstep Gauss) is
+ * the single layer's: the r-set is the same. */
+
+/* v = c[0] + c[1] tau + c[2] u + c[3] v from its values at the 4 local
+ * vertices (Gaussian elimination with partial pivoting). */
+static int linear_coeffs(const orc_panel* P, const double* vv, double* c) {
+  double M[4][5];
+  for (int k = 0; k < 4; ++k) {
+    M[k][0] = 1.0; M[k][1] = P->V[k][0]; M[k][2] = P->V[k][1]; M[k][3] = P->V[k][2];
+    M[k][4] = vv[k];
+  }
+  for (int col = 0; col < 4; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 4; ++r)
+      if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+    if (M[piv][col] == 0.0) return ORC_E_PANEL;
+    for (int q = 0; q < 5; ++q) { double t = M[col][q]; M[col][q] = M[piv][q]; M[piv][q] = t; }
+    for (int r = col + 1; r < 4; ++r) {
+      double f = M[r][col] / M[col][col];
+      for (int q = col; q < 5; ++q) M[r][q] -= f * M[col][q];
+    }
+  }
+  for (int r = 3; r >= 0; --r) {
+    double x = M[r][4];
+    for (int q = r + 1; q < 4; ++q) x -= M[r][q] * c[q];
+    c[r] = x / M[r][r];
+  }
+  return ORC_OK;
+}
+
+static double H_dl(double r, double d2) {
+  double s2 = r * r - d2;
+  double s = s2 > 0.0 ? sqrt(s2) : 0.0;
+  return log(r + s) - s / r;
+}
+
+/* The double-layer r-integral at angle phi (without the factor d_n). */
+static double F_phi(const orc_panel* P, const orc_apex* A, double phi, double alpha,
+                    double cu, double cv) {
+  double seg[32];
+  int ns = r_segments(P, A, phi, seg);
+  double d2 = A->d * A->d, gam = cu * cos(phi) + cv * sin(phi);
+  double f = 0.0;
+  for (int m = 0; m < ns; ++m) {
+    double r0 = seg[2 * m], r1 = seg[2 * m + 1];
+    f += alpha * (1.0 / r0 - 1.0 / r1) + gam * (H_dl(r1, d2) - H_dl(r0, d2));
+  }
+  return f;
+}
+
+/* D v_j (x) for the outward-normal sign sgn (+1 when the outward normal is
+ * the frame normal P->n) and vertex values vv. */
+static double inner_panel_dl(const orc_panel* P, const double* tet, const double* x4, double sgn,
+                             const double* vv, int n_g, const double* gx, const double* gw) {
+  orc_apex A;
+  apex_setup(P, x4, &A);
+  if (A.d == 0.0) return 0.0;                     /* k2 = k3 = 0 in the plane */
+  if (!(A.t - P->tmin > fabs(A.d))) return 0.0;
+  double mn, mx;
+  lit_extrema(x4, tet, P, &mn, &mx);
+  if (!lit_decide(mn, mx, A.t, P)) return 0.0;
+  double c[4];
+  if (linear_coeffs(P, vv, c)) return 0.0;
+  double alpha = c[0] + c[1] * A.t + c[2] * A.pu + c[3] * A.pv;
+  double bp[ORC_MAX_BP];
+  int nb = breakpoints(P, &A, bp);
+  double sum = 0.0;
+  if (nb == 0) {
+    int m = 2 * n_g;
+    double h = ORC_TWO_PI / m;
+    for (int k = 0; k < m; ++k) sum += h * F_phi(P, &A, k * h, alpha, c[2], c[3]);
+  } else {
+    for (int k = 0; k < nb; ++k) {
+      double a = bp[k];
+      double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + ORC_TWO_PI;
+      double H = b - a;
+      if (!(H > 0.0)) continue;
+      if (L_phi(P, &A, a + 0.5 * H) == 0.0 && L_phi(P, &A, a + 0.25 * H) == 0.0 &&
+          L_phi(P, &A, a + 0.75 * H) == 0.0)
+        continue;
+      for (int g = 0; g < n_g; ++g) {
+        double u = gx[g];
+        double s = u * u * (3.0 - 2.0 * u);
+        double ds = 6.0 * u * (1.0 - u);
+        sum += H * ds * gw[g] * F_phi(P, &A, a + H * s, alpha, c[2], c[3]);
+      }
+    }
+  }
+  return sgn * A.d * sum / (4.0 * ORC_PI);
+}
+
+static int normal_sign(const orc_panel* P, const double* nrm, double* sgn) {
+  double l = sqrt(dot3(nrm, nrm)), c = dot3(nrm, P->n);
+  if (!(l > 0.0) || !isfinite(l) || !(fabs(c) >= 0.5 * l)) return ORC_E_ARG;
+  *sgn = c > 0.0 ? 1.0 : -1.0;
+  return ORC_OK;
+}
+
+int orc_inner_dl(const double* x4, const double* tet, const double* nrm, const double* vv,
+                 int n_g, double* out) {
+  if (n_g < 1 || n_g > ORC_MAX_NG) return ORC_E_ARG;
+  orc_panel P;
+  int rc = panel_setup(tet, &P);
+  if (rc) return rc;
+  double sgn;
+  if ((rc = normal_sign(&P, nrm, &sgn))) return rc;
+  double gx[ORC_MAX_NG], gw[ORC_MAX_NG];
+  orc_gauss_legendre01(n_g, gx, gw);
+  *out = inner_panel_dl(&P, tet, x4, sgn, vv, n_g, gx, gw);
+  return ORC_OK;
+}
+
 /* ---------------- outer rule ---------------- */
 int orc_outer_points(const double* tet, int m_q, double* pts, double* w) {
   if (m_q < 1 || m_q > 16) return ORC_E_ARG;
@@ -756,6 +900,44 @@ int orc_potential(int64_t nv, const double* vtx, int64_t nt, const int32_t* tets
   }
   free(panels);
   free(tetc);
+  return ORC_OK;
+}
+
+int orc_potential_dl(int64_t nv, const double* vtx, int64_t nt, const int32_t* tets,
+                     const double* nrm, const double* v, int64_t np, const double* pts, int n_g,
+                     double* out) {
+  int rc = check_mesh(nv, vtx, nt, tets);
+  if (rc) return rc;
+  if (n_g < 1 || n_g > ORC_MAX_NG) return ORC_E_ARG;
+  orc_panel* panels = (orc_panel*)malloc(sizeof(orc_panel) * (size_t)(nt > 0 ? nt : 1));
+  double* tetc = (double*)malloc(sizeof(double) * 16 * (size_t)(nt > 0 ? nt : 1));
+  double* sg = (double*)malloc(sizeof(double) * (size_t)(nt > 0 ? nt : 1));
+  for (int64_t j = 0; j < nt; ++j) {
+    gather_tet(vtx, tets, j, tetc + 16 * j);
+    rc = panel_setup(tetc + 16 * j, panels + j);
+    if (!rc) rc = normal_sign(panels + j, nrm + 3 * j, sg + j);
+    if (rc) { free(panels); free(tetc); free(sg); return rc; }
+  }
+  double gx[ORC_MAX_NG], gw[ORC_MAX_NG];
+  orc_gauss_legendre01(n_g, gx, gw);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t p = 0; p < np; ++p) {
+    double s = 0.0, comp = 0.0;
+    for (int64_t j = 0; j < nt; ++j) {
+      double vv[4];
+      for (int k = 0; k < 4; ++k) vv[k] = v[tets[4 * j + k]];
+      double I = inner_panel_dl(panels + j, tetc + 16 * j, pts + 4 * p, sg[j], vv, n_g, gx, gw);
+      if (I == 0.0) continue;
+      double yk = I - comp;
+      double tk = s + yk;
+      comp = (tk - s) - yk;
+      s = tk;
+    }
+    out[p] = s;
+  }
+  free(panels);
+  free(tetc);
+  free(sg);
   return ORC_OK;
 }
 

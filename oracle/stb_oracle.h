@@ -76,6 +76,18 @@ int orc_potential(int64_t nv, const double* vtx, int64_t nt,
                   const int32_t* tets, const double* w, int64_t np,
                   const double* pts, int n_g, double* out);
 
+/* Retarded double-layer potential (eq. dlp, kernels k2, k3 of eq. kfunc)
+ * at x4 of the density that is linear on the panel tet with values vv[4]
+ * at its vertices; nrm[3] = the panel's outward spatial normal (its sign
+ * is what matters; it must not be tangent to the panel).  Same phi-rule as
+ * orc_inner; the r-integral is closed-form. */
+int orc_inner_dl(const double* x4, const double* tet, const double* nrm,
+                 const double* vv, int n_g, double* out);
+/* u(p) = D v (p) at np points for v in V_h^1 (vertex values v[nv]); nrm =
+ * per-panel outward spatial normals [nt][3]. */
+int orc_potential_dl(int64_t nv, const double* vtx, int64_t nt,
+                     const int32_t* tets, const double* nrm, const double* v,
+                     int64_t np, const double* pts, int n_g, double* out);
 /* Exact lit predicate of Sec. 3.3: 1 iff the backward cone of x meets the
  * open panel, i.e. min < 0 < max of phi_Xi(x - y) over the closed panel
  * (eq. sgn_dist_cone).  Also returns min and max when non-NULL. */

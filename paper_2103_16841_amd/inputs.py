@@ -51,6 +51,21 @@ class Mesh:
     def centroid_times(self):
         return self.vtx[self.tets][:, :, 0].mean(axis=1)
 
+    def outward_normals(self):
+        """Unit spatial normal of every panel pointing away from the origin
+        (the outward normal of Gamma for the cube and the icospheres, which
+        are star-shaped about the origin): float64 [N, 3]."""
+        X = self.vtx[self.tets][:, :, 1:]            # [N, 4, 3] spatial points
+        best = np.zeros((self.nt, 3))
+        for a, b, c in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)):
+            v = np.cross(X[:, b] - X[:, a], X[:, c] - X[:, a])
+            take = np.einsum("ij,ij->i", v, v) > np.einsum("ij,ij->i", best, best)
+            best[take] = v[take]
+        n = best / np.linalg.norm(best, axis=1, keepdims=True)
+        flip = np.einsum("ij,ij->i", n, X.mean(axis=1)) < 0.0
+        n[flip] = -n[flip]
+        return n
+
     def __repr__(self):
         return "Mesh(%s, N=%d, V=%d, S=%d, T=%g)" % (self.name, self.nt, self.nv, self.S, self.T)
 

@@ -278,3 +278,35 @@ def random_rotation(rng):
     if np.linalg.det(q) < 0:
         q[:, 0] = -q[:, 0]
     return q
+
+
+# --- a wave from a point source (Kirchhoff's formula checks) ---------------
+
+POINT_SOURCE = np.array([0.0, 0.0, 2.5])
+
+
+def _pulse(t):
+    """sin^2(pi t / 2) on (0, 2), zero outside (C^1)."""
+    return np.where((t > 0.0) & (t < 2.0), np.sin(0.5 * np.pi * t) ** 2, 0.0)
+
+
+def _pulse_dt(t):
+    return np.where((t > 0.0) & (t < 2.0), 0.5 * np.pi * np.sin(np.pi * t), 0.0)
+
+
+def point_source_wave(p):
+    """u(t, x) = f(t - |x - x0|) / (4 pi |x - x0|) with x0 = (0, 0, 2.5): a
+    solution of the wave equation away from x0 (inside the unit sphere),
+    zero at times t <= |x - x0|.  p: [..., 4] points (t, x, y, z)."""
+    r = np.linalg.norm(p[..., 1:] - POINT_SOURCE, axis=-1)
+    return _pulse(p[..., 0] - r) / (4.0 * np.pi * r)
+
+
+def point_source_wave_dn(p, n):
+    """Normal derivative <grad_x u, n> of point_source_wave at points p."""
+    y = p[..., 1:]
+    r = np.linalg.norm(y - POINT_SOURCE, axis=-1)
+    tr = p[..., 0] - r
+    g = (-_pulse_dt(tr) / (4.0 * np.pi * r) - _pulse(tr) / (4.0 * np.pi * r * r))[..., None] \
+        * (y - POINT_SOURCE) / r[..., None]
+    return np.einsum("...i,...i->...", g, n)
