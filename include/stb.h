@@ -155,6 +155,37 @@ stb_status stb_potential_S_dev(stb_ctx* ctx, const stb_mesh* mesh, const stb_qua
 stb_status stb_inner_values(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
                             int64_t k, const double* pts, const int32_t* panel, double* out);
 
+/* Outward spatial normals of the panels, needed by the double layer (its
+ * kernels k2, k3 of eq. kfunc contain <n_Gamma(y), x - y>): nrm is nt x 3
+ * (host, any length); only the side matters: each normal must be finite
+ * and within 60 degrees of the panel's plane normal (STB_E_INVALID_ARG
+ * otherwise, and the mesh is left without normals).  The mesh keeps one
+ * sign per panel. */
+stb_status stb_mesh_set_normals(stb_ctx* ctx, stb_mesh* mesh, const double* nrm);
+
+/* Retarded double-layer potential u(p) = D v (p) (eq. dlp: kernels k3 v +
+ * k2 dv/dtau of eq. kfunc, behind the light cone) of the density v in
+ * V_h^1 (def. st_be: continuous, linear on every panel) given by its nv
+ * vertex values, at np points pts (np x 4, (t, x, y, z), host).  Needs the
+ * mesh's outward normals (stb_mesh_set_normals; STB_E_INVALID_ARG
+ * otherwise).  Panels whose plane contains the point contribute 0 (k2 = k3
+ * = 0 there), so points on the surface get the direct value of the
+ * integral.  Same phi-rule as the single layer, closed-form r-integrals;
+ * FP64. */
+stb_status stb_potential_D(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                           const double* v, int64_t np, const double* pts, double* out);
+/* Same with v, pts and out in device memory; returns after the result is
+ * written (the call synchronises its stream). */
+stb_status stb_potential_D_dev(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                               const double* v_dev, int64_t np, const double* pts_dev,
+                               double* out_dev, void* stream);
+/* Double-layer potentials of the four hat functions of one panel at one
+ * point: out[4 m + q] = D lambda_q (pts[m]) for panel[m], lambda_q the
+ * linear function that is 1 at the panel's vertex q (its q-th index in the
+ * tetrahedra array) and 0 at the other three.  For checks. */
+stb_status stb_inner_values_D(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                              int64_t k, const double* pts, const int32_t* panel, double* out);
+
 /* Batched assembly of nmesh meshes of one context (Exp. 3 style workloads
  * of many independent scatterers): the candidate sets of all meshes are one
  * work list of the pair pipeline, so every kernel launch covers the whole

@@ -308,6 +308,72 @@ STB_HD __forceinline__ double L_eval(const FaceSet& F, const double* C, double d
   return empty ? 0.0 : len;
 }
 
+// The double layer's r-integrals at one angle, over the same admissible set
+// as L_eval: for every gap [w0, w1] of it (r0 = r(w0), r1 = r(w1)),
+//   sa += 1/r0 - 1/r1 = 2 w0 / (w0^2 + d^2) - 2 w1 / (w1^2 + d^2),
+//   sh += H(r1) - H(r0),  H(r) = ln(r + s) - s / r = ln w - 1 + 2 d^2 / (w^2 + d^2),
+// the integrals of 1/r^2 and of s/r^2 over r (s = sqrt(r^2 - d^2), so that
+// r + s = w and s / r = (w^2 - d^2) / (w^2 + d^2)).  Needs d^2 > 0.  Same
+// holes, clipping, sort and gap threshold as L_eval, so that both see the
+// same set.
+STB_HD inline void dl_eval(const FaceSet& F, const double* C, double d2, double wlo, double whi,
+                           double cs, double sn, double& sa, double& sh) {
+  const double kNone = 1e300;
+  double lo = wlo, hi = whi;
+  bool dead = false;
+  double hs[4], he[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double a = F.fa[k];
+    double B = fma(F.fb[k], cs, F.fc[k] * sn);
+    double e = B - a, f = B + a, Ck = C[k];
+    double D = fma(Ck, Ck, d2 * (e * f));
+    bool two = D > 0.0;
+    double q = Ck + copysign(sqrt_disc(D), Ck);
+    double w1 = q * frcp(e);
+    double w2 = -d2 * f * frcp(q);
+    double mn = fmin(w1, w2), mx = fmax(w1, w2);
+    bool pos = e > 0.0, neg = e < 0.0, zer = !(pos || neg);
+    bool cut = pos && two;
+    dead = dead || (pos && !two) || (zer && Ck == 0.0 && !(d2 * f > 0.0));
+    lo = cut ? fmax(lo, mn) : lo;
+    hi = cut ? fmin(hi, mx) : hi;
+    lo = (zer && Ck > 0.0) ? fmax(lo, w2) : lo;
+    hi = (zer && Ck < 0.0) ? fmin(hi, w2) : hi;
+    bool hole = neg && two;
+    hs[k] = hole ? mn : kNone;
+    he[k] = hole ? mx : kNone;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    hs[k] = fmin(fmax(hs[k], lo), hi);
+    he[k] = fmax(fmin(he[k], hi), hs[k]);
+  }
+  order2(hs[0], he[0], hs[1], he[1]);
+  order2(hs[2], he[2], hs[3], he[3]);
+  order2(hs[0], he[0], hs[2], he[2]);
+  order2(hs[1], he[1], hs[3], he[3]);
+  order2(hs[1], he[1], hs[2], he[2]);
+  const double kWulp = 8.881784197001252e-16;
+  sa = 0.0;
+  sh = 0.0;
+  if (dead || !(hi > lo)) return;
+  auto gap = [&](double w0, double w1) {
+    double m = rdiff(w0, w1, d2);
+    if (!(m > kWulp * w1)) return;
+    double q0 = 1.0 / fma(w0, w0, d2), q1 = 1.0 / fma(w1, w1, d2);
+    sa += 2.0 * (w0 * q0 - w1 * q1);
+    sh += log(w1 / w0) + 2.0 * d2 * (q1 - q0);
+  };
+  double c = lo;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    gap(c, fmax(hs[k], c));
+    c = fmax(he[k], c);
+  }
+  gap(c, hi);
+}
+
 // Exact extrema of f(y) = |x - y| - (t - tau) over the closed panel:
 // max at a vertex; min among vertices, stationary points on the 6 edges and
 // in the non-vertical faces.  Returns the lit decision with the relative
@@ -1195,6 +1261,76 @@ STB_HD inline double inner_serial(const TrialRec& T, const double* x4, int ng, c
     I += acc;
   }
   return I / (4.0 * kPi);
+}
+
+// Retarded double-layer potential (eq. dlp) of the four hat functions of a
+// panel at x4, out[m] for the density that is 1 at local vertex m and 0 at
+// the others.  With k3 = d_n / (4 pi r^3), k2 = d_n / (4 pi r^2) (eq. kfunc;
+// d_n = nsign d, the distance along the outward normal) and dA = r dr dphi,
+// the k2 term of a linear density cancels the time part of the k3 term:
+// the r-integrand is d_n (lambda(t, p) + grad_uv lambda . e(phi) s) / r^2.
+// The hat of vertex m is lambda_m = (h_m - a_m tau - b_m u - c_m v) / D_m
+// over face m (opposite vertex m), D_m its value at vertex m: at (t, p) it
+// is C_m / D_m, its in-plane gradient -(b_m, c_m) / D_m.  Three integrals
+// over phi (of sa, sh cos, sh sin from dl_eval) give all four hats; the
+// phi-rule (breakpoints, empty-piece test on L, smoothstep Gauss) is the
+// single layer's.
+STB_HD inline void inner_dl_serial(const TrialRec& T, const FaceAng& FA, const double* x4,
+                                   double nsign, int ng, const double* glx, const double* glw,
+                                   double* out) {
+  for (int m = 0; m < 4; ++m) out[m] = 0.0;
+  Apex A;
+  apex_of(T, x4, A);
+  double wlo = 0.0, whi = 0.0;
+  if (A.d == 0.0) return;   // k2 = k3 = 0 in the panel's plane
+  bool lit = A.t - T.tmin > fabs(A.d) && !ball_rejects(T, x4) && lit_test(T, x4, A);
+  if (!lit || !w_range(T, A, wlo, whi)) return;
+  ComboL cb;
+  FaceSet F;
+  for (int k = 0; k < 4; ++k) {
+    cb.C[k] = A.C[k]; cb.fa[k] = T.fa[k]; cb.fb[k] = T.fb[k]; cb.fc[k] = T.fc[k];
+    F.fa[k] = T.fa[k]; F.fb[k] = T.fb[k]; F.fc[k] = T.fc[k];
+  }
+  const double d2 = A.d * A.d;
+  cb.d2 = d2; cb.wlo = wlo; cb.whi = whi;
+  double bp[kMaxBp];
+  int nb = breakpoints(T, FA, A, bp);
+  sort_bp(bp, nb);
+  double ia = 0.0, ic = 0.0, is = 0.0;
+  auto node = [&](double phi, double wt) {
+    double sn, cs, sa, sh;
+    sincos_small(phi, &sn, &cs);
+    dl_eval(F, A.C, d2, wlo, whi, cs, sn, sa, sh);
+    ia += wt * sa;
+    ic += (wt * sh) * cs;
+    is += (wt * sh) * sn;
+  };
+  if (nb == 0) {
+    const int m = 2 * ng;
+    const double h = kTwoPi / m;
+    for (int k = 0; k < m; ++k) node(k * h, h);
+  } else {
+    for (int k = 0; k < nb; ++k) {
+      const double a = bp[k];
+      const double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
+      const double H = b - a;
+      if (!(H > 0.0)) continue;
+      bool ne = L_at(cb, a + 0.5 * H) != 0.0;
+      if (!ne) ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
+      if (!ne) continue;
+      for (int g = 0; g < ng; ++g) {
+        const double u = glx[g];
+        const double sm = u * u * (3.0 - 2.0 * u);
+        const double ds = 6.0 * u * (1.0 - u);
+        node(a + H * sm, H * ds * glw[g]);
+      }
+    }
+  }
+  const double f = nsign * A.d / (4.0 * kPi);
+  for (int m = 0; m < 4; ++m) {
+    const double Dm = T.fh[m] - T.fa[m] * T.V[m][0] - T.fb[m] * T.V[m][1] - T.fc[m] * T.V[m][2];
+    out[m] = f * (A.C[m] * ia - T.fb[m] * ic - T.fc[m] * is) / Dm;
+  }
 }
 
 }  // namespace stb

@@ -1,0 +1,258 @@
+// stb_dl.hip -- retarded double-layer potential (eq. dlp, kernels k2 and k3
+// of eq. kfunc) of a density in V_h^1 (continuous, linear on every panel;
+// def. st_be), at points off or on the surface.
+//
+// The candidates (point, panel) come from the single layer's cull; one lane
+// evaluates one candidate completely (inner_dl_serial: lit test,
+// breakpoints, the empty-piece test and the Gauss nodes of every piece) and
+// writes the potentials of the panel's four hat functions; a second kernel
+// sums them per point against the vertex values in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "stb_internal.h"
+
+using namespace stb;
+
+namespace {
+
+// nsign[j] = +1 where the given outward normal has a positive component along
+// the frame normal n of panel j, -1 where negative; status 1 where the given
+// normal is not finite or is within 60 degrees of the panel's plane.
+__global__ void k_normal_sign(int64_t nt, const TrialRec* __restrict__ trial,
+                              const double* __restrict__ nrm, double* __restrict__ nsign,
+                              int32_t* __restrict__ status) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nt) return;
+  const double* g = nrm + 3 * j;
+  const TrialRec& T = trial[j];
+  double l = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  double c = g[0] * T.n[0] + g[1] * T.n[1] + g[2] * T.n[2];
+  bool ok = l > 0.0 && isfinite(l) && fabs(c) >= 0.5 * l;
+  nsign[j] = c > 0.0 ? 1.0 : -1.0;
+  status[j] = ok ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void k_dl_hats(int64_t nnz, const int32_t* __restrict__ rowof,
+                                                 const int32_t* __restrict__ cols,
+                                                 const TrialRec* __restrict__ trial,
+                                                 const FaceAng* __restrict__ fang,
+                                                 const double* __restrict__ nsign,
+                                                 const double* __restrict__ pts,
+                                                 const double* __restrict__ gl, int ng,
+                                                 double* __restrict__ out4) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nnz) return;
+  const int32_t j = cols[c];
+  const double* xp = pts + 4 * (int64_t)rowof[c];
+  double x4[4] = {xp[0], xp[1], xp[2], xp[3]};
+  double h[4];
+  inner_dl_serial(trial[j], fang[j], x4, nsign[j], ng, gl, gl + kMaxNg, h);
+  for (int m = 0; m < 4; ++m) out4[4 * c + m] = h[m];
+}
+
+// u(p) = sum over p's candidates (ascending panel) and the panel's vertices
+// of v(vertex) * hat potential.
+__global__ void k_dl_point_sum(int64_t np, const int64_t* __restrict__ rowptr,
+                               const int32_t* __restrict__ cols, const int32_t* __restrict__ tet,
+                               const double* __restrict__ v, const double* __restrict__ h4,
+                               double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  double s = 0.0;
+  for (int64_t c = rowptr[i]; c < rowptr[i + 1]; ++c) {
+    const int32_t* tv = tet + 4 * (int64_t)cols[c];
+    const double* h = h4 + 4 * c;
+    s += ((v[tv[0]] * h[0] + v[tv[1]] * h[1]) + v[tv[2]] * h[2]) + v[tv[3]] * h[3];
+  }
+  out[i] = s;
+}
+
+__global__ void k_dl_pairs(int64_t k, const TrialRec* __restrict__ trial,
+                           const FaceAng* __restrict__ fang, const double* __restrict__ nsign,
+                           const double* __restrict__ pts, const int32_t* __restrict__ panel,
+                           const double* __restrict__ gl, int ng, double* __restrict__ out4) {
+  int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= k) return;
+  const int32_t j = panel[m];
+  double x4[4] = {pts[4 * m], pts[4 * m + 1], pts[4 * m + 2], pts[4 * m + 3]};
+  double h[4];
+  inner_dl_serial(trial[j], fang[j], x4, nsign[j], ng, gl, gl + kMaxNg, h);
+  for (int q = 0; q < 4; ++q) out4[4 * m + q] = h[q];
+}
+
+unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// Double-layer potential with device inputs and output on the context stream.
+static stb_status dl_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p, const double* d_v,
+                          int64_t np, const double* d_pts, double* d_out) {
+  stb_status s;
+  if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
+  double* d_h = nullptr;
+  ApexBox* d_box = nullptr;
+  int64_t* d_rowptr = nullptr;
+  int32_t *d_cols = nullptr, *d_rowof = nullptr;
+  auto cleanup = [&]() {
+    dfree(d_h); dfree(d_box); dfree(d_rowptr); dfree(d_cols); dfree(d_rowof);
+  };
+  if (dalloc(&d_box, (size_t)np) != hipSuccess)
+    return stb_fail(ctx, STB_E_NO_MEMORY, "double-layer buffers");
+  stb_point_boxes(ctx, np, d_pts, d_box);
+  int64_t nnz = 0;
+  s = stb_cull(ctx, np, d_box, mesh, &d_rowptr, &d_cols, &d_rowof, &nnz);
+  if (s) { cleanup(); return s; }
+  if (dalloc(&d_h, (size_t)nnz * 4) != hipSuccess) {
+    cleanup();
+    return stb_fail(ctx, STB_E_NO_MEMORY, "double-layer candidates");
+  }
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_dl_hats, dim3(grid_for(nnz, 256)), dim3(256), 0, ctx->stream, nnz, d_rowof,
+                       d_cols, mesh->d_trial, mesh->d_fang, mesh->d_nsign, d_pts, ctx->d_gl, p.n_g, d_h);
+  hipLaunchKernelGGL(k_dl_point_sum, dim3(grid_for(np, 256)), dim3(256), 0, ctx->stream, np, d_rowptr,
+                     d_cols, mesh->d_tet, d_v, d_h, d_out);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  cleanup();
+  ctx->work[0] = 0;
+  ctx->work[1] = 0;
+  ctx->work[2] = nnz;
+  ctx->work[3] = 0;
+  if (e != hipSuccess) return stb_fail(ctx, STB_E_DEVICE, "double layer failed: %s", hipGetErrorString(e));
+  return STB_OK;
+}
+
+static stb_status dl_check(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                           stb_quad_params* p) {
+  if (mesh->ctx != ctx) return stb_fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
+  if (!mesh->d_nsign)
+    return stb_fail(ctx, STB_E_INVALID_ARG, "the mesh has no outward normals (stb_mesh_set_normals)");
+  *p = params ? *params : stb_default_params();
+  return stb_check_params(ctx, p);
+}
+
+extern "C" {
+
+stb_status stb_mesh_set_normals(stb_ctx* ctx, stb_mesh* mesh, const double* nrm) {
+  if (!ctx || !mesh || !nrm) return stb_fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  if (mesh->ctx != ctx) return stb_fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
+  const int64_t nt = mesh->nt;
+  if (nt == 0) return STB_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  double* d_n = nullptr;
+  int32_t* d_st = nullptr;
+  if (!mesh->d_nsign && dalloc(&mesh->d_nsign, (size_t)nt) != hipSuccess)
+    return stb_fail(ctx, STB_E_NO_MEMORY, "normal signs");
+  if (dalloc(&d_n, (size_t)nt * 3) != hipSuccess || dalloc(&d_st, (size_t)nt) != hipSuccess) {
+    dfree(d_n); dfree(d_st);
+    return stb_fail(ctx, STB_E_NO_MEMORY, "normals");
+  }
+  std::vector<int32_t> st((size_t)nt);
+  hipError_t e = hipMemcpyAsync(d_n, nrm, sizeof(double) * 3 * nt, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_normal_sign, dim3(grid_for(nt, 256)), dim3(256), 0, ctx->stream, nt,
+                       mesh->d_trial, d_n, mesh->d_nsign, d_st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(st.data(), d_st, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(d_n);
+  dfree(d_st);
+  if (e != hipSuccess) return stb_fail(ctx, STB_E_DEVICE, "normals failed: %s", hipGetErrorString(e));
+  for (int64_t j = 0; j < nt; ++j)
+    if (st[j]) {
+      dfree(mesh->d_nsign);
+      mesh->d_nsign = nullptr;
+      return stb_fail(ctx, STB_E_INVALID_ARG,
+                      "normal of panel %lld is not finite or not transversal to the panel's plane",
+                      (long long)j);
+    }
+  return STB_OK;
+}
+
+stb_status stb_potential_D(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_params* params,
+                           const double* v, int64_t np, const double* pts, double* out) {
+  if (!ctx || !mesh_c || !v || (np > 0 && (!pts || !out)) || np < 0)
+    return stb_fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
+  stb_quad_params p;
+  stb_status s = dl_check(ctx, mesh, params, &p);
+  if (s) return s;
+  if (np == 0) return STB_OK;
+  for (int64_t i = 0; i < 4 * np; ++i)
+    if (!std::isfinite(pts[i]))
+      return stb_fail(ctx, STB_E_INVALID_ARG, "non-finite point %lld", (long long)(i / 4));
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  double *d_pts = nullptr, *d_v = nullptr, *d_out = nullptr;
+  if (dalloc(&d_pts, (size_t)np * 4) != hipSuccess || dalloc(&d_v, (size_t)mesh->nv) != hipSuccess ||
+      dalloc(&d_out, (size_t)np) != hipSuccess) {
+    dfree(d_pts); dfree(d_v); dfree(d_out);
+    return stb_fail(ctx, STB_E_NO_MEMORY, "double-layer buffers");
+  }
+  hipError_t e = hipMemcpyAsync(d_pts, pts, sizeof(double) * 4 * np, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_v, v, sizeof(double) * mesh->nv, hipMemcpyHostToDevice, ctx->stream);
+  s = e == hipSuccess ? dl_core(ctx, mesh, p, d_v, np, d_pts, d_out)
+                      : stb_fail(ctx, STB_E_DEVICE, "copy failed");
+  if (s == STB_OK) {
+    e = hipMemcpy(out, d_out, sizeof(double) * np, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) s = stb_fail(ctx, STB_E_DEVICE, "copy back failed: %s", hipGetErrorString(e));
+  }
+  dfree(d_pts); dfree(d_v); dfree(d_out);
+  return s;
+}
+
+stb_status stb_potential_D_dev(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_params* params,
+                               const double* v_dev, int64_t np, const double* pts_dev, double* out_dev,
+                               void* stream) {
+  if (!ctx || !mesh_c || !v_dev || (np > 0 && (!pts_dev || !out_dev)) || np < 0)
+    return stb_fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
+  stb_quad_params p;
+  stb_status s = dl_check(ctx, mesh, params, &p);
+  if (s) return s;
+  if (np == 0) return STB_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (stream) HIPCHK(ctx, hipStreamSynchronize((hipStream_t)stream));
+  return dl_core(ctx, mesh, p, v_dev, np, pts_dev, out_dev);
+}
+
+stb_status stb_inner_values_D(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                              int64_t k, const double* pts, const int32_t* panel, double* out) {
+  if (!ctx || !mesh || k < 0 || (k > 0 && (!pts || !panel || !out)))
+    return stb_fail(ctx, STB_E_INVALID_ARG, "bad arguments");
+  stb_quad_params p;
+  stb_status s = dl_check(ctx, mesh, params, &p);
+  if (s) return s;
+  for (int64_t m = 0; m < k; ++m)
+    if (panel[m] < 0 || panel[m] >= mesh->nt)
+      return stb_fail(ctx, STB_E_INVALID_ARG, "panel index %d out of range", panel[m]);
+  if (k == 0) return STB_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
+  double *d_pts = nullptr, *d_out = nullptr;
+  int32_t* d_pan = nullptr;
+  if (dalloc(&d_pts, (size_t)k * 4) != hipSuccess || dalloc(&d_out, (size_t)k * 4) != hipSuccess ||
+      dalloc(&d_pan, (size_t)k) != hipSuccess) {
+    dfree(d_pts); dfree(d_out); dfree(d_pan);
+    return stb_fail(ctx, STB_E_NO_MEMORY, "buffers");
+  }
+  hipError_t e = hipMemcpyAsync(d_pts, pts, 32 * k, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_pan, panel, 4 * k, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_dl_pairs, dim3(grid_for(k, 128)), dim3(128), 0, ctx->stream, k, mesh->d_trial,
+                       mesh->d_fang, mesh->d_nsign, d_pts, d_pan, ctx->d_gl, p.n_g, d_out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, 32 * k, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(d_pts); dfree(d_out); dfree(d_pan);
+  if (e != hipSuccess)
+    return stb_fail(ctx, STB_E_DEVICE, "double-layer values failed: %s", hipGetErrorString(e));
+  return STB_OK;
+}
+
+}  // extern "C"

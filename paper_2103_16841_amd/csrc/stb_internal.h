@@ -43,6 +43,9 @@ struct stb_mesh {
   int32_t* d_tet = nullptr;
   stb::TrialRec* d_trial = nullptr;
   stb::FaceAng* d_fang = nullptr;   // [nt] polar form of the face normals
+  // double layer: +1 where the outward normal of Gamma is the panel frame's
+  // normal n, else -1 (set by stb_mesh_set_normals)
+  double* d_nsign = nullptr;        // [nt]
   // outer points for one m_q (recomputed when m_q changes)
   int mq = 0;
   int maxq = 0;

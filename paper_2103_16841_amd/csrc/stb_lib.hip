@@ -665,6 +665,7 @@ stb_status stb_mesh_create_dev(stb_ctx* ctx, int64_t nv, const double* vtx_dev, 
 void stb_mesh_destroy(stb_mesh* m) {
   if (!m) return;
   dfree(m->d_vtx); dfree(m->d_tet); dfree(m->d_trial); dfree(m->d_fang);
+  dfree(m->d_nsign);
   dfree(m->d_opts); dfree(m->d_ow); dfree(m->d_onq); dfree(m->d_box);
   stb_free_faces(m);
   delete m;

@@ -22,7 +22,8 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
            "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
            "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_last_path_counts", "stb_mesh_create_dev",
-           "stb_outer_points", "stb_solve_gmres",
+           "stb_outer_points", "stb_solve_gmres", "stb_mesh_set_normals", "stb_potential_D",
+           "stb_potential_D_dev", "stb_inner_values_D",
            "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble", "stb_autotune",
            "stb_set_tuning", "stb_server_create", "stb_server_add_mesh", "stb_server_submit",
            "stb_server_wait", "stb_server_destroy"]
@@ -92,6 +93,10 @@ def load():
     L.stb_potential_S.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _D, i64, _D, _D]
     L.stb_last_timings.argtypes = [_VP, _D]
     L.stb_inner_values.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
+    L.stb_mesh_set_normals.argtypes = [_VP, _VP, _D]
+    L.stb_potential_D.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _D, i64, _D, _D]
+    L.stb_potential_D_dev.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _VP, i64, _VP, _VP, _VP]
+    L.stb_inner_values_D.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
     L.stb_last_work.argtypes = [_VP, _I64]
     L.stb_last_path_counts.argtypes = [_VP, _I64]
     L.stb_outer_points.argtypes = [_VP, _VP, i32, _D, _D, _I32]
@@ -213,6 +218,13 @@ class Mesh:
         _chk(load().stb_mesh_create_dev(ctx.h, nv, _VP(vtx_ptr), nt, _VP(tet_ptr),
                                         _VP(stream) if stream else None, ctypes.byref(h)), ctx.h)
         return cls(ctx, None, None, _handle=h, _nt=int(nt))
+
+    def set_normals(self, nrm):
+        """Outward spatial normals of the panels (nt x 3), for the double layer."""
+        nrm, pn = _d(nrm, (-1, 3))
+        if nrm.shape[0] != self.nt:
+            raise ValueError("need one normal per panel")
+        _chk(load().stb_mesh_set_normals(self.ctx.h, self.h, pn), self.ctx.h)
 
     def close(self):
         if self.h:
@@ -376,6 +388,37 @@ def inner_values(ctx, mesh, pts, panels, params=None):
     out = np.zeros(pts.shape[0])
     _chk(load().stb_inner_values(ctx.h, mesh.h, ctypes.byref(p), pts.shape[0], pp,
                                  panels.ctypes.data_as(_I32), out.ctypes.data_as(_D)), ctx.h)
+    return out
+
+
+def potential_D(ctx, mesh, v, pts, params=None):
+    """Retarded double-layer potential of the V_h^1 density with vertex
+    values v at points (t,x,y,z); the mesh needs its outward normals."""
+    p = params if params is not None else default_params()
+    v, pv = _d(v)
+    pts, pp = _d(pts, (-1, 4))
+    out = np.zeros(pts.shape[0])
+    _chk(load().stb_potential_D(ctx.h, mesh.h, ctypes.byref(p), pv, pts.shape[0], pp,
+                                out.ctypes.data_as(_D)), ctx.h)
+    return out
+
+
+def potential_D_dev(ctx, mesh, v_ptr, np_, pts_ptr, out_ptr, params=None, stream=None):
+    """Double-layer potential with device pointers (vertex values, points, output)."""
+    p = params if params is not None else default_params()
+    _chk(load().stb_potential_D_dev(ctx.h, mesh.h, ctypes.byref(p), _VP(v_ptr), np_, _VP(pts_ptr),
+                                    _VP(out_ptr), _VP(stream) if stream else None), ctx.h)
+
+
+def inner_values_D(ctx, mesh, pts, panels, params=None):
+    """Double-layer potentials of the 4 hat functions of each panel at each
+    point: [k, 4], column q for the panel's q-th vertex."""
+    p = params if params is not None else default_params()
+    pts, pp = _d(pts, (-1, 4))
+    panels = np.ascontiguousarray(panels, dtype=np.int32)
+    out = np.zeros((pts.shape[0], 4))
+    _chk(load().stb_inner_values_D(ctx.h, mesh.h, ctypes.byref(p), pts.shape[0], pp,
+                                   panels.ctypes.data_as(_I32), out.ctypes.data_as(_D)), ctx.h)
     return out
 
 

@@ -1,0 +1,161 @@
+"""The double-layer potential (eq. dlp) on the GPU, through the C ABI,
+against the FP64 oracle (same phi-rule; tolerances as for the single
+layer: relative 1e-10 above 1e-5 of the largest value), and against what
+the mathematics fixes: Gauss's law on closed surfaces and Kirchhoff's
+representation of a wave from an outside point source.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_16841_amd import inputs
+from _pins import point_source_wave, point_source_wave_dn
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+FLOOR = 1e-5
+
+
+@pytest.fixture(scope="module")
+def stb():
+    import torch
+    torch.cuda.init()
+    from paper_2103_16841_amd import stb as s
+    s.load()
+    return s
+
+
+@pytest.fixture(scope="module")
+def ctx(stb):
+    c = stb.Context(0)
+    yield c
+    c.close()
+
+
+def _mesh(stb, ctx, mesh):
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    m.set_normals(mesh.outward_normals())
+    return m
+
+
+def _check(a, ref, what):
+    scale = np.abs(ref).max()
+    err = np.abs(a - ref) / np.maximum(np.abs(ref), FLOOR * scale)
+    k = int(np.argmax(err))
+    print("%s: %d values, max |ref| %.3e, worst rel err %.3e (gpu %.17g oracle %.17g)"
+          % (what, ref.size, scale, err.flat[k], a.flat[k], ref.flat[k]), flush=True)
+    assert err.max() <= RTOL
+
+
+def test_hat_values_vs_oracle(stb, ctx):
+    mesh = inputs.icosphere_mesh(level=1, S=4, T=3.0, jitter=0.2, seed=7)
+    m = _mesh(stb, ctx, mesh)
+    nrm = mesh.outward_normals()
+    rng = np.random.default_rng(11)
+    opts, _, _ = stb.outer_points(ctx, m)
+    # outer points of random panels (on the surface), near-surface and shell points
+    k = 400
+    src = rng.integers(0, mesh.nt, k)
+    on = opts[src, rng.integers(0, 18, k)]
+    d = rng.standard_normal((k, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    near = np.concatenate([rng.uniform(0.5, 3.0, (k, 1)), d * rng.uniform(0.9, 1.1, (k, 1))], axis=1)
+    shell = inputs.shell_points(k, mesh.T, rmin=1.2, rmax=2.0, seed=12)
+    pts = np.concatenate([on, near, shell])
+    # pair every point with panels its light cone reaches (and some it does not)
+    pan = rng.integers(0, mesh.nt, pts.shape[0])
+    got = stb.inner_values_D(ctx, m, pts, pan)
+    ref = np.zeros_like(got)
+    eye = np.eye(4)
+    for i in range(pts.shape[0]):
+        T = mesh.vtx[mesh.tets[pan[i]]]
+        for q in range(4):
+            ref[i, q] = oracle.inner_dl(pts[i], T, nrm[pan[i]], eye[q])
+    assert np.count_nonzero(ref) > 400
+    assert np.all((got == 0.0) == (ref == 0.0))
+    _check(got, ref, "hat values")
+
+
+def test_potential_vs_oracle(stb, ctx):
+    mesh = inputs.icosphere_mesh(level=1, S=8, T=4.0, jitter=0.2, seed=5)
+    m = _mesh(stb, ctx, mesh)
+    v = inputs.density_normal(mesh.nv, seed=3)
+    rng = np.random.default_rng(8)
+    d = rng.standard_normal((100, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    near = np.concatenate([rng.uniform(0.5, 4.0, (100, 1)), d * rng.uniform(0.3, 1.2, (100, 1))], axis=1)
+    pts = np.concatenate([inputs.shell_points(200, mesh.T, seed=4), near])
+    u = stb.potential_D(ctx, m, v, pts)
+    uo = oracle.potential_dl(mesh.vtx, mesh.tets, mesh.outward_normals(), v, pts)
+    _check(u, uo, "potential")
+
+
+def test_gauss_closed_surface(stb, ctx):
+    mesh = inputs.icosphere_mesh(level=2, S=4, T=6.0, jitter=0.2, seed=4)
+    m = _mesh(stb, ctx, mesh)
+    ones = np.ones(mesh.nv)
+    inside = np.array([[5.0, 0.0, 0.0, 0.0], [5.0, 0.3, -0.2, 0.4], [4.8, -0.5, 0.1, 0.2]])
+    outside = np.array([[5.0, 1.6, 0.0, 0.3], [5.5, -0.9, 1.3, -0.8]])
+    for n_g, tol in ((64, 1e-10), (16, 2e-7)):
+        p = stb.default_params(n_g=n_g)
+        u_in = stb.potential_D(ctx, m, ones, inside, params=p)
+        u_out = stb.potential_D(ctx, m, ones, outside, params=p)
+        print("n_g %d: D1 inside + 1 = %s, outside = %s" % (n_g, u_in + 1.0, u_out), flush=True)
+        assert np.all(np.abs(u_in + 1.0) <= tol)
+        assert np.all(np.abs(u_out) <= tol)
+
+
+def test_kirchhoff_representation(stb, ctx):
+    """Inside the sphere u = S(du/dn) - D(u) (Kirchhoff's formula for the
+    interior with the outward normal): D of the vertex interpolant of u
+    (V_h^1) and S of du/dn at the panel centroids (S_h^0)."""
+    pts = np.array([[3.5, 0.0, 0.0, 0.3], [3.2, 0.2, -0.3, 0.0], [3.8, -0.2, 0.1, -0.4]])
+    exact = point_source_wave(pts)
+    errs = []
+    for level, S in ((2, 16), (3, 32)):
+        mesh = inputs.icosphere_mesh(level=level, S=S, T=4.0, jitter=0.0, seed=0)
+        m = _mesh(stb, ctx, mesh)
+        nrm = mesh.outward_normals()
+        cen = mesh.vtx[mesh.tets].mean(axis=1)
+        rep = (stb.potential_S(ctx, m, point_source_wave_dn(cen, nrm), pts)
+               - stb.potential_D(ctx, m, point_source_wave(mesh.vtx), pts))
+        err = np.abs(rep - exact).max() / np.abs(exact).max()
+        print("case: sphere level %d S %d N %d: representation error %.3e" % (level, S, mesh.nt, err),
+              flush=True)
+        errs.append(err)
+    assert errs[1] < 0.01 and errs[1] < 0.3 * errs[0]
+
+
+def test_bench_workload_sampled(stb, ctx):
+    """The bench's double-layer leg (icosphere level 2, 32 slabs, 1,000 shell
+    points in one launch) against the oracle on a sample of the points."""
+    mesh = inputs.icosphere_mesh()
+    m = _mesh(stb, ctx, mesh)
+    v = inputs.density_normal(mesh.nv, seed=9)
+    pts = inputs.shell_points(1000, mesh.T, seed=1)
+    u = stb.potential_D(ctx, m, v, pts)
+    idx = np.arange(0, 1000, 125)
+    uo = oracle.potential_dl(mesh.vtx, mesh.tets, mesh.outward_normals(), v, pts[idx])
+    _check(u[idx], uo, "bench workload sample")
+
+
+def test_arguments(stb, ctx):
+    mesh = inputs.icosphere_mesh(level=0, S=2, T=2.0, jitter=0.0, seed=0)
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    pts = np.array([[1.5, 0.0, 0.0, 0.0]])
+    with pytest.raises(stb.StbError):
+        stb.potential_D(ctx, m, np.ones(mesh.nv), pts)        # no normals yet
+    nrm = mesh.outward_normals()
+    bad = nrm.copy()
+    bad[5] = np.cross(bad[5], [0.3, 0.1, 0.9])               # in the panel's plane
+    with pytest.raises(stb.StbError):
+        m.set_normals(bad)
+    with pytest.raises(ValueError):
+        m.set_normals(nrm[:-1])
+    m.set_normals(nrm)
+    assert stb.potential_D(ctx, m, np.ones(mesh.nv), np.zeros((0, 4))).shape == (0,)
+    u1 = stb.potential_D(ctx, m, np.ones(mesh.nv), pts)
+    m.set_normals(-nrm)
+    u2 = stb.potential_D(ctx, m, np.ones(mesh.nv), pts)
+    assert u1[0] == -u2[0] and u1[0] < -0.9
