@@ -200,6 +200,37 @@ def solve_leg(ctx, stb, mesh):
             "rel_l2_error_vs_exact_density": float(np.linalg.norm(x - f) / np.linalg.norm(f))}
 
 
+def double_layer_leg(ctx, stb, mesh, npts, reps=3):
+    """The retarded double-layer potential (eq. dlp) of a V_h^1 density with
+    N(0,1) vertex values (seed 9) at the step's shell points, beside the
+    single layer's potential at the same points; median of reps runs after
+    one warm-up."""
+    import numpy as np
+    import torch
+    from paper_2103_16841_amd import inputs
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    m.set_normals(mesh.outward_normals())
+    v = inputs.density_normal(mesh.nv, seed=9)
+    w = inputs.density_normal(mesh.nt, seed=5)
+    pts = inputs.shell_points(npts, mesh.T, seed=4)
+    res = {}
+    for name, fn, dens in (("double_layer", stb.potential_D, v), ("single_layer", stb.potential_S, w)):
+        fn(ctx, m, dens, pts)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn(ctx, m, dens, pts)
+            ts.append((time.perf_counter() - t0) * 1e3)
+        res[name + "_ms"] = float(np.median(ts))
+        res[name + "_candidates"] = ctx.work()["apex_pairs"]
+    m.close()
+    res["points"] = npts
+    res["candidate_pairs_per_s"] = res["double_layer_candidates"] / (res["double_layer_ms"] * 1e-3)
+    res["note"] = "host-to-device copies of points and densities included in both timings"
+    return res
+
+
 def mixed_leg(args, ctx, stb, step, paramsmx, vtx_d, tet_d, nv, nt, rec):
     """The same step with the mixed-precision assembly; its entries compared
     with the FP64 assembly's (which match the oracle to 1e-10)."""
@@ -422,6 +453,7 @@ def main():
         },
     }
     out["solve"] = solve_leg(ctx, stb, mesh)
+    out["double_layer"] = double_layer_leg(ctx, stb, mesh, args.points)
     if not args.no_mixed:
         out["mixed"] = mixed_leg(args, ctx, stb, step, paramsmx, vtx_d, tet_d, nv, nt, rec)
     if not args.no_serving:

@@ -53,21 +53,26 @@ __global__ __launch_bounds__(256) void k_dl_hats(int64_t nnz, const int32_t* __r
   for (int m = 0; m < 4; ++m) out4[4 * c + m] = h[m];
 }
 
-// u(p) = sum over p's candidates (ascending panel) and the panel's vertices
-// of v(vertex) * hat potential.
-__global__ void k_dl_point_sum(int64_t np, const int64_t* __restrict__ rowptr,
-                               const int32_t* __restrict__ cols, const int32_t* __restrict__ tet,
-                               const double* __restrict__ v, const double* __restrict__ h4,
-                               double* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// u(p) = sum over p's candidates and the panel's vertices of v(vertex) *
+// hat potential: one wavefront per point, lane-strided partial sums and a
+// fixed-order shuffle reduction.
+__global__ __launch_bounds__(256) void k_dl_point_sum(int64_t np, const int64_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ cols,
+                                                      const int32_t* __restrict__ tet,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ h4,
+                                                      double* __restrict__ out) {
+  int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
   if (i >= np) return;
   double s = 0.0;
-  for (int64_t c = rowptr[i]; c < rowptr[i + 1]; ++c) {
+  for (int64_t c = rowptr[i] + lane; c < rowptr[i + 1]; c += 64) {
     const int32_t* tv = tet + 4 * (int64_t)cols[c];
     const double* h = h4 + 4 * c;
     s += ((v[tv[0]] * h[0] + v[tv[1]] * h[1]) + v[tv[2]] * h[2]) + v[tv[3]] * h[3];
   }
-  out[i] = s;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) out[i] = s;
 }
 
 __global__ void k_dl_pairs(int64_t k, const TrialRec* __restrict__ trial,
@@ -112,7 +117,7 @@ static stb_status dl_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p
   if (nnz > 0)
     hipLaunchKernelGGL(k_dl_hats, dim3(grid_for(nnz, 256)), dim3(256), 0, ctx->stream, nnz, d_rowof,
                        d_cols, mesh->d_trial, mesh->d_fang, mesh->d_nsign, d_pts, ctx->d_gl, p.n_g, d_h);
-  hipLaunchKernelGGL(k_dl_point_sum, dim3(grid_for(np, 256)), dim3(256), 0, ctx->stream, np, d_rowptr,
+  hipLaunchKernelGGL(k_dl_point_sum, dim3(grid_for(np * 64, 256)), dim3(256), 0, ctx->stream, np, d_rowptr,
                      d_cols, mesh->d_tet, d_v, d_h, d_out);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);

@@ -321,15 +321,21 @@ extern "C" stb_status stb_debug_pair(stb_ctx* ctx, const stb_mesh* mesh, int32_t
 
 // Potential per evaluation point: ordered sum over its candidates of
 // w_j I_j (exact zeros skipped).
-__global__ void k_point_sum(int64_t np, const int64_t* __restrict__ rowptr,
-                            const int32_t* __restrict__ cols, const double* __restrict__ I,
-                            const double* __restrict__ w, double* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// u(p) = sum_j w_j I_pj over the point's candidates: one wavefront per
+// point, lane-strided partial sums and a fixed-order shuffle reduction.
+__global__ __launch_bounds__(256) void k_point_sum(int64_t np, const int64_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ cols,
+                                                   const double* __restrict__ I,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ out) {
+  int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
   if (i >= np) return;
   double s = 0.0;
-  for (int64_t c = rowptr[i]; c < rowptr[i + 1]; ++c)
+  for (int64_t c = rowptr[i] + lane; c < rowptr[i + 1]; c += 64)
     if (I[c] != 0.0) s += w[cols[c]] * I[c];
-  out[i] = s;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) out[i] = s;
 }
 
 // y = A w (FP64 CSR), one wavefront per row, fixed-order reduction.
@@ -898,7 +904,7 @@ stb_status stb_potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_param
   s = stb_run_pairs(ctx, J, work);
   if (s) { cleanup(); return s; }
   for (int k = 0; k < 4; ++k) ctx->work[k] = (int64_t)work[k];
-  hipLaunchKernelGGL(k_point_sum, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
+  hipLaunchKernelGGL(k_point_sum, dim3((unsigned)((np * 64 + 255) / 256)), dim3(256), 0, ctx->stream, np,
                      d_rowptr, d_cols, d_I, d_w, d_out);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
