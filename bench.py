@@ -231,6 +231,54 @@ def double_layer_leg(ctx, stb, mesh, npts, reps=3):
     return res
 
 
+def direct_leg(ctx, stb):
+    """The direct method (eq. df_dir) on the exterior of the unit sphere
+    (icosphere level 2 x 16 slabs, T = 4) for the spherical wave
+    mu(t - |x - y_S|) / |x - y_S|, mu(t) = t^3 e^-t, y_S = (-0.1, -0.2, -0.3):
+    right-hand side -1/2 b_I(g) + b_K(g) from the vertex values of g, GMRES
+    for the Neumann trace, Kirchhoff's formula u_h = D g - S w_h at three
+    outside points at t = T."""
+    import numpy as np
+    import torch
+    from paper_2103_16841_amd import inputs
+    ys = np.array([-0.1, -0.2, -0.3])
+
+    def mu(t, d=False):
+        tp = np.maximum(t, 0.0)
+        f = (3.0 * tp ** 2 - tp ** 3) if d else tp ** 3
+        return np.where(t > 0.0, f * np.exp(-tp), 0.0)
+
+    def u(p):
+        r = np.linalg.norm(p[..., 1:] - ys, axis=-1)
+        return mu(p[..., 0] - r) / r
+    mesh = inputs.icosphere_mesh(level=2, S=16, T=4.0, jitter=0.0, seed=0)
+    nrm = mesh.outward_normals()
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    m.set_normals(nrm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A = stb.assemble_V(ctx, m)
+    t1 = time.perf_counter()
+    g = u(mesh.vtx)
+    b = stb.dl_energetic(ctx, m, g, c_id=-0.5)
+    t2 = time.perf_counter()
+    x, its, rr = stb.solve_gmres(ctx, A, b, restart=100, maxit=20000, rtol=1e-10)
+    t3 = time.perf_counter()
+    cen = mesh.vtx[mesh.tets].mean(axis=1)
+    y = cen[:, 1:]
+    r = np.linalg.norm(y - ys, axis=1)
+    tr = cen[:, 0] - r
+    dn = np.einsum("ij,ij->i", ((-mu(tr, True) / r - mu(tr) / (r * r))[:, None] * (y - ys) / r[:, None]), nrm)
+    far = np.array([[4.0, 1.5, 0.0, 0.3], [4.0, 0.2, -1.6, 0.0], [4.0, -1.2, 0.9, -0.6]])
+    uh = stb.potential_D(ctx, m, g, far) - stb.potential_S(ctx, m, x, far)
+    A.close()
+    m.close()
+    return {"mesh": "icosphere level 2 x 16 slabs, T=4 (N=%d)" % mesh.nt, "assemble_ms": (t1 - t0) * 1e3,
+            "rhs_ms": (t2 - t1) * 1e3, "gmres_ms": (t3 - t2) * 1e3, "products": its, "relres": rr,
+            "neumann_rel_l2_error": float(np.linalg.norm(x - dn) / np.linalg.norm(dn)),
+            "field_rel_error_max": float(np.max(np.abs(uh - u(far)) / np.abs(u(far))))}
+
+
 def mixed_leg(args, ctx, stb, step, paramsmx, vtx_d, tet_d, nv, nt, rec):
     """The same step with the mixed-precision assembly; its entries compared
     with the FP64 assembly's (which match the oracle to 1e-10)."""
@@ -454,6 +502,7 @@ def main():
     }
     out["solve"] = solve_leg(ctx, stb, mesh)
     out["double_layer"] = double_layer_leg(ctx, stb, mesh, args.points)
+    out["direct"] = direct_leg(ctx, stb)
     if not args.no_mixed:
         out["mixed"] = mixed_leg(args, ctx, stb, step, paramsmx, vtx_d, tet_d, nv, nt, rec)
     if not args.no_serving:

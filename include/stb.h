@@ -186,6 +186,20 @@ stb_status stb_potential_D_dev(stb_ctx* ctx, const stb_mesh* mesh, const stb_qua
 stb_status stb_inner_values_D(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
                               int64_t k, const double* pts, const int32_t* panel, double* out);
 
+/* Energetic forms of the identity and the double layer with the outer rule
+ * of eq. int_bform (A = I, A = K, the same rule as the single layer's
+ * matrix rows): out[i] = c_id b_I(v, phi_i) + b_K(v, phi_i) for every test
+ * panel i (out: nt entries, host), v in V_h^1 by its nv vertex values
+ * (host).  b_I(v, phi_i) = sum_q w_iq v(x_iq) with panel i's own linear
+ * function; b_K(v, phi_i) = sum_q w_iq (K v)(x_iq), K v the direct value of
+ * the double layer at the outer points.  With v the data g (or its
+ * interpolant), c_id = 1/2 gives the right-hand side of the direct method
+ * (eq. df_dir) for the interior problem, c_id = -1/2 for the exterior one.
+ * Needs the mesh's outward normals.  Works through the outer points in
+ * chunks of 32,768. */
+stb_status stb_dl_energetic(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
+                            const double* v, double c_id, double* out);
+
 /* Batched assembly of nmesh meshes of one context (Exp. 3 style workloads
  * of many independent scatterers): the candidate sets of all meshes are one
  * work list of the pair pipeline, so every kernel launch covers the whole

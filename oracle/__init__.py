@@ -70,6 +70,8 @@ def lib():
         L.orc_breakpoints.argtypes = [_D, _D, _D, c_int]
         L.orc_inner_dl.argtypes = [_D, _D, _D, _D, c_int, _D]
         L.orc_potential_dl.argtypes = [i64, _D, i64, _I32, _D, _D, i64, _D, c_int, _D]
+        L.orc_dl_energetic_rows.argtypes = [i64, _D, i64, _I32, _D, _D, i64, _I64, c_int, c_int,
+                                            ctypes.c_double, _D]
         _lib = L
     return _lib
 
@@ -248,4 +250,19 @@ def potential_dl(vtx, tets, nrm, v, pts, n_g=DEFAULT_NG):
     out = np.zeros(pts.shape[0])
     _check(lib().orc_potential_dl(vtx.shape[0], pv, tets.shape[0], pt, pn, pvv, pts.shape[0], pp,
                                   n_g, out.ctypes.data_as(_D)), "potential_dl")
+    return out
+
+
+def dl_energetic_rows(vtx, tets, nrm, v, rows, c_id=0.0, m_q=DEFAULT_MQ, n_g=DEFAULT_NG):
+    """c_id b_I(v, phi_i) + b_K(v, phi_i) for the test panels in rows (eq.
+    int_bform with A = I, K); v in V_h^1 by vertex values."""
+    vtx, pv = _d(vtx)
+    tets, pt = _i32(tets)
+    nrm, pn = _d(np.asarray(nrm).reshape(-1, 3))
+    v, pvv = _d(v)
+    rows, pr = _i64(rows)
+    out = np.zeros(rows.shape[0])
+    _check(lib().orc_dl_energetic_rows(vtx.shape[0], pv, tets.shape[0], pt, pn, pvv, rows.shape[0],
+                                       pr, m_q, n_g, float(c_id), out.ctypes.data_as(_D)),
+           "dl_energetic_rows")
     return out

@@ -941,6 +941,59 @@ int orc_potential_dl(int64_t nv, const double* vtx, int64_t nt, const int32_t* t
   return ORC_OK;
 }
 
+/* Energetic forms of the double layer and the identity with the outer rule
+ * of eq. int_bform (A = K, A = I): for every given test panel i,
+ *   out[r] = c_id * sum_q w_q v(x_q) + sum_q w_q (K v)(x_q),
+ * v in V_h^1 with vertex values v[nv]; v(x_q) is panel i's own linear
+ * function at its outer point, (K v)(x_q) the direct value of the double
+ * layer there (panels in x_q's plane contribute 0). */
+int orc_dl_energetic_rows(int64_t nv, const double* vtx, int64_t nt, const int32_t* tets,
+                          const double* nrm, const double* v, int64_t nrows, const int64_t* rows,
+                          int m_q, int n_g, double c_id, double* out) {
+  int rc = check_mesh(nv, vtx, nt, tets);
+  if (rc) return rc;
+  if (n_g < 1 || n_g > ORC_MAX_NG || m_q < 1 || m_q > 16) return ORC_E_ARG;
+  orc_panel* panels = (orc_panel*)malloc(sizeof(orc_panel) * (size_t)(nt > 0 ? nt : 1));
+  double* tetc = (double*)malloc(sizeof(double) * 16 * (size_t)(nt > 0 ? nt : 1));
+  double* sg = (double*)malloc(sizeof(double) * (size_t)(nt > 0 ? nt : 1));
+  for (int64_t j = 0; j < nt; ++j) {
+    gather_tet(vtx, tets, j, tetc + 16 * j);
+    rc = panel_setup(tetc + 16 * j, panels + j);
+    if (!rc) rc = normal_sign(panels + j, nrm + 3 * j, sg + j);
+    if (rc) { free(panels); free(tetc); free(sg); return rc; }
+  }
+  double gx[ORC_MAX_NG], gw[ORC_MAX_NG];
+  orc_gauss_legendre01(n_g, gx, gw);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t r = 0; r < nrows; ++r) {
+    int64_t i = rows[r];
+    if (i < 0 || i >= nt) { bad = 1; continue; }
+    double pts[4 * 4 * 256], w[4 * 256], vi[4], c[4];
+    int np = orc_outer_points(tetc + 16 * i, m_q, pts, w);
+    for (int k = 0; k < 4; ++k) vi[k] = v[tets[4 * i + k]];
+    linear_coeffs(panels + i, vi, c);
+    double acc = 0.0;
+    for (int q = 0; q < np; ++q) {
+      const double* x = pts + 4 * q;
+      double d3[3] = {x[1] - panels[i].o[0], x[2] - panels[i].o[1], x[3] - panels[i].o[2]};
+      double vq = c[0] + c[1] * x[0] + c[2] * dot3(d3, panels[i].e1) + c[3] * dot3(d3, panels[i].e2);
+      double kv = 0.0;
+      for (int64_t j = 0; j < nt; ++j) {
+        double vv[4];
+        for (int k = 0; k < 4; ++k) vv[k] = v[tets[4 * j + k]];
+        kv += inner_panel_dl(panels + j, tetc + 16 * j, x, sg[j], vv, n_g, gx, gw);
+      }
+      acc += w[q] * (c_id * vq + kv);
+    }
+    out[r] = acc;
+  }
+  free(panels);
+  free(tetc);
+  free(sg);
+  return bad ? ORC_E_ARG : ORC_OK;
+}
+
 int orc_pair_causal(const double* vtx, const int32_t* tets, int64_t i, int64_t j, int m_q) {
   double ti[16], tj[16], pts[4 * 4 * 256], w[4 * 256];
   gather_tet(vtx, tets, i, ti);

@@ -88,6 +88,14 @@ int orc_inner_dl(const double* x4, const double* tet, const double* nrm,
 int orc_potential_dl(int64_t nv, const double* vtx, int64_t nt,
                      const int32_t* tets, const double* nrm, const double* v,
                      int64_t np, const double* pts, int n_g, double* out);
+/* c_id b_I(v, phi_i) + b_K(v, phi_i) for the given test panels (eq.
+ * int_bform with A = I and A = K: outer rule of m_q^2 points per face);
+ * v in V_h^1 (vertex values), nrm per-panel outward normals.  K v at an
+ * outer point is the direct value of the double layer there. */
+int orc_dl_energetic_rows(int64_t nv, const double* vtx, int64_t nt,
+                          const int32_t* tets, const double* nrm, const double* v,
+                          int64_t nrows, const int64_t* rows, int m_q, int n_g,
+                          double c_id, double* out);
 /* Exact lit predicate of Sec. 3.3: 1 iff the backward cone of x meets the
  * open panel, i.e. min < 0 < max of phi_Xi(x - y) over the closed panel
  * (eq. sgn_dist_cone).  Also returns min and max when non-NULL. */

@@ -23,7 +23,7 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
            "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_last_path_counts", "stb_mesh_create_dev",
            "stb_outer_points", "stb_solve_gmres", "stb_mesh_set_normals", "stb_potential_D",
-           "stb_potential_D_dev", "stb_inner_values_D",
+           "stb_potential_D_dev", "stb_inner_values_D", "stb_dl_energetic",
            "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble", "stb_autotune",
            "stb_set_tuning", "stb_server_create", "stb_server_add_mesh", "stb_server_submit",
            "stb_server_wait", "stb_server_destroy"]
@@ -97,6 +97,7 @@ def load():
     L.stb_potential_D.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _D, i64, _D, _D]
     L.stb_potential_D_dev.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _VP, i64, _VP, _VP, _VP]
     L.stb_inner_values_D.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
+    L.stb_dl_energetic.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _D, ctypes.c_double, _D]
     L.stb_last_work.argtypes = [_VP, _I64]
     L.stb_last_path_counts.argtypes = [_VP, _I64]
     L.stb_outer_points.argtypes = [_VP, _VP, i32, _D, _D, _I32]
@@ -408,6 +409,17 @@ def potential_D_dev(ctx, mesh, v_ptr, np_, pts_ptr, out_ptr, params=None, stream
     p = params if params is not None else default_params()
     _chk(load().stb_potential_D_dev(ctx.h, mesh.h, ctypes.byref(p), _VP(v_ptr), np_, _VP(pts_ptr),
                                     _VP(out_ptr), _VP(stream) if stream else None), ctx.h)
+
+
+def dl_energetic(ctx, mesh, v, c_id=0.0, params=None):
+    """c_id b_I(v, phi_i) + b_K(v, phi_i) for every test panel (outer rule of
+    eq. int_bform); c_id = 1/2: the interior direct method's right-hand side."""
+    p = params if params is not None else default_params()
+    v, pv = _d(v)
+    out = np.zeros(mesh.nt)
+    _chk(load().stb_dl_energetic(ctx.h, mesh.h, ctypes.byref(p), pv, float(c_id),
+                                 out.ctypes.data_as(_D)), ctx.h)
+    return out
 
 
 def inner_values_D(ctx, mesh, pts, panels, params=None):

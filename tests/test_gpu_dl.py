@@ -1,8 +1,10 @@
-"""The double-layer potential (eq. dlp) on the GPU, through the C ABI,
-against the FP64 oracle (same phi-rule; tolerances as for the single
-layer: relative 1e-10 above 1e-5 of the largest value), and against what
-the mathematics fixes: Gauss's law on closed surfaces and Kirchhoff's
-representation of a wave from an outside point source.
+"""The double-layer potential (eq. dlp) and the energetic forms b_I, b_K
+(eq. int_bform) on the GPU, through the C ABI, against the FP64 oracle
+(same phi-rule; tolerances as for the single layer: relative 1e-10 above
+1e-5 of the largest value), and against what the mathematics fixes:
+Gauss's law on closed surfaces, K 1 = -1/2 on them, Kirchhoff's
+representation of a wave from an outside point source, and the direct
+method (eq. df_dir) converging for the paper's exterior example.
 """
 import numpy as np
 import pytest
@@ -138,6 +140,88 @@ def test_bench_workload_sampled(stb, ctx):
     idx = np.arange(0, 1000, 125)
     uo = oracle.potential_dl(mesh.vtx, mesh.tets, mesh.outward_normals(), v, pts[idx])
     _check(u[idx], uo, "bench workload sample")
+
+
+def test_energetic_forms_vs_oracle(stb, ctx):
+    """c_id b_I(v, phi_i) + b_K(v, phi_i) (outer rule of eq. int_bform) on
+    sampled rows against the oracle, random V_h^1 density."""
+    mesh = inputs.icosphere_mesh(level=1, S=4, T=3.0, jitter=0.2, seed=7)
+    m = _mesh(stb, ctx, mesh)
+    v = inputs.density_normal(mesh.nv, seed=13)
+    got = stb.dl_energetic(ctx, m, v, c_id=0.5)
+    rows = np.arange(3, mesh.nt, 41)
+    ref = oracle.dl_energetic_rows(mesh.vtx, mesh.tets, mesh.outward_normals(), v, rows, c_id=0.5)
+    _check(got[rows], ref, "energetic forms, sampled rows")
+
+
+def test_energetic_forms_exact(stb, ctx):
+    """On a closed polyhedron K 1 = -1/2 inside its faces, so in the static
+    regime b_K(tau, phi_i) = -1/2 sum_q w_iq t_q; b_I of an affine function
+    is its outer-rule sum."""
+    mesh = inputs.icosphere_mesh(level=1, S=3, T=6.0, jitter=0.2, seed=4)
+    m = _mesh(stb, ctx, mesh)
+    ct = mesh.centroid_times()
+    rows = np.where((ct > 3.0) & (ct < mesh.T - 0.5))[0]
+    pts, w, n = stb.outer_points(ctx, m)
+    bk = stb.dl_energetic(ctx, m, mesh.vtx[:, 0].copy(), c_id=0.0, params=stb.default_params(n_g=64))
+    ex = -0.5 * np.einsum("iq,iq->i", w, pts[:, :, 0])
+    print("b_K(tau) worst abs err %.3e over %d static rows" % (np.abs(bk - ex)[rows].max(), rows.size),
+          flush=True)
+    assert np.all(np.abs(bk - ex)[rows] <= 1e-12)
+    a = np.array([0.3, -0.7, 0.4, 1.1])
+    va = 0.2 + mesh.vtx @ a
+    bi = stb.dl_energetic(ctx, m, va, c_id=1.0) - stb.dl_energetic(ctx, m, va, c_id=0.0)
+    exi = np.einsum("iq,iq->i", w, 0.2 + pts @ a)
+    assert np.all(np.abs(bi - exi) <= 1e-14)
+
+
+def test_direct_method_exterior(stb, ctx):
+    """The direct method (eq. df_dir) for the exterior problem of the paper's
+    last example: a spherical wave mu(t - |x - y_S|) / |x - y_S| from y_S
+    inside, mu(t) = t^3 e^-t; Dirichlet data by vertex interpolation, the
+    right-hand side -1/2 b_I(g) + b_K(g), GMRES for the Neumann trace, then
+    u_h = D g - S w_h outside.  Both errors fall under refinement."""
+    ys = np.array([-0.1, -0.2, -0.3])
+
+    def mu(t):
+        tp = np.maximum(t, 0.0)
+        return np.where(t > 0.0, tp ** 3 * np.exp(-tp), 0.0)
+
+    def mu_dt(t):
+        tp = np.maximum(t, 0.0)
+        return np.where(t > 0.0, (3.0 * tp ** 2 - tp ** 3) * np.exp(-tp), 0.0)
+
+    def u(p):
+        r = np.linalg.norm(p[..., 1:] - ys, axis=-1)
+        return mu(p[..., 0] - r) / r
+
+    def u_dn(p, nrm):
+        y = p[..., 1:]
+        r = np.linalg.norm(y - ys, axis=-1)
+        tr = p[..., 0] - r
+        g = (-mu_dt(tr) / r - mu(tr) / (r * r))[..., None] * (y - ys) / r[..., None]
+        return np.einsum("...i,...i->...", g, nrm)
+
+    far = np.array([[4.0, 1.5, 0.0, 0.3], [4.0, 0.2, -1.6, 0.0], [4.0, -1.2, 0.9, -0.6]])
+    errs, ferrs = [], []
+    for level, S in ((1, 8), (2, 16)):
+        mesh = inputs.icosphere_mesh(level=level, S=S, T=4.0, jitter=0.0, seed=0)
+        m = _mesh(stb, ctx, mesh)
+        nrm = mesh.outward_normals()
+        A = stb.assemble_V(ctx, m)
+        g = u(mesh.vtx)
+        b = stb.dl_energetic(ctx, m, g, c_id=-0.5)
+        x, its, rr = stb.solve_gmres(ctx, A, b, restart=100, maxit=20000, rtol=1e-10)
+        cen = mesh.vtx[mesh.tets].mean(axis=1)
+        ex = u_dn(cen, nrm)
+        errs.append(np.linalg.norm(x - ex) / np.linalg.norm(ex))
+        uh = stb.potential_D(ctx, m, g, far) - stb.potential_S(ctx, m, x, far)
+        ferrs.append(np.max(np.abs(uh - u(far)) / np.abs(u(far))))
+        print("case: sphere level %d S %d N %d: GMRES %d products, Neumann rel L2 error %.3e, "
+              "field rel error %.3e" % (level, S, mesh.nt, its, errs[-1], ferrs[-1]), flush=True)
+        A.close()
+    assert errs[1] < 0.6 * errs[0] and errs[1] < 0.08
+    assert ferrs[1] < 0.5 * ferrs[0] and ferrs[1] < 0.03
 
 
 def test_arguments(stb, ctx):

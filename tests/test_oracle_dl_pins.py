@@ -11,6 +11,9 @@ kernels k2, k3 of eq. kfunc) against what the mathematics fixes:
   triangle): the definition k3 v(t - r, y) + k2 dv/dtau integrated by
   nested adaptive quadrature in polar coordinates about the foot point;
 * additivity: a column split in time gives the same sum;
+* on the surface (direct value): K 1 = -1/2 at points inside the faces of
+  a closed polyhedral surface, hence the energetic form b_K(tau, phi_i) =
+  -1/2 sum_q w_iq t_q; b_I of an affine function is its outer-rule sum;
 * Kirchhoff's formula: inside the sphere a wave from an outside point
   source equals S(du/dn) - D(u) of its traces, to the discretisation error,
   which falls under refinement (with the single layer's oracle).
@@ -224,3 +227,36 @@ def test_kirchhoff_representation():
             - oracle.potential_dl(mesh.vtx, mesh.tets, nrm, point_source_wave(mesh.vtx), pts)
         errs.append(np.abs(rep - exact).max() / np.abs(exact).max())
     assert errs[1] < 0.01 and errs[1] < 0.3 * errs[0]
+
+
+def _static_rows(mesh, k=10):
+    """Rows whose outer points see the whole unit sphere inside (0, T)."""
+    ct = mesh.centroid_times()
+    return np.where((ct > 3.0) & (ct < mesh.T - 0.5))[0][::7][:k]
+
+
+def test_surface_direct_value_and_energetic_forms():
+    mesh = inputs.icosphere_mesh(level=1, S=3, T=6.0, jitter=0.2, seed=4)
+    nrm = mesh.outward_normals()
+    rows = _static_rows(mesh)
+    assert len(rows) >= 5
+    P0, _ = oracle.outer_points(mesh.vtx[mesh.tets[rows[0]]])
+    # K 1 = -1/2 inside the faces of a closed polyhedron (static)
+    k1 = oracle.potential_dl(mesh.vtx, mesh.tets, nrm, np.ones(mesh.nv), P0, n_g=64)
+    assert np.all(np.abs(k1 + 0.5) <= 1e-13)
+    k16 = oracle.potential_dl(mesh.vtx, mesh.tets, nrm, np.ones(mesh.nv), P0)
+    assert np.all(np.abs(k16 + 0.5) <= 2e-7)
+    # b_K(tau) = -1/2 sum_q w_q t_q (the k2 term with K 1 = -1/2)
+    tv = mesh.vtx[:, 0].copy()
+    bk = oracle.dl_energetic_rows(mesh.vtx, mesh.tets, nrm, tv, rows, c_id=0.0, n_g=64)
+    ex = np.array([-0.5 * np.dot(W, P[:, 0]) for P, W in
+                   (oracle.outer_points(mesh.vtx[mesh.tets[i]]) for i in rows)])
+    assert np.all(np.abs(bk - ex) <= 1e-13)
+    # b_I of an affine function of (t, x, y, z): its outer-rule sum
+    a = np.array([0.3, -0.7, 0.4, 1.1])
+    va = 0.2 + mesh.vtx @ a
+    bi = oracle.dl_energetic_rows(mesh.vtx, mesh.tets, nrm, va, rows, c_id=1.0) \
+        - oracle.dl_energetic_rows(mesh.vtx, mesh.tets, nrm, va, rows, c_id=0.0)
+    exi = np.array([np.dot(W, 0.2 + P @ a) for P, W in
+                    (oracle.outer_points(mesh.vtx[mesh.tets[i]]) for i in rows)])
+    assert np.all(np.abs(bi - exi) <= 1e-14)
