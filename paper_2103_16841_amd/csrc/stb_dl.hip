@@ -89,8 +89,9 @@ __global__ void k_dl_pairs(int64_t k, const TrialRec* __restrict__ trial,
   for (int q = 0; q < 4; ++q) out4[4 * m + q] = h[q];
 }
 
-// The outer points of rows [r0, r0 + nr) packed without padding: point q of
-// row i goes to off[i] - off[r0] + q (off: exclusive prefix of the counts).
+// The points of entities [r0, r0 + nr) (faces), maxq slots each, packed
+// without padding: point q of entity i goes to off[i] - off[r0] + q (off:
+// exclusive prefix of the counts).
 __global__ void k_pack_outer(int64_t r0, int64_t nr, int maxq, const double* __restrict__ opts,
                              const int64_t* __restrict__ off, double* __restrict__ pts) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -103,37 +104,54 @@ __global__ void k_pack_outer(int64_t r0, int64_t nr, int maxq, const double* __r
   for (int c = 0; c < 4; ++c) dst[c] = src[c];
 }
 
-// out[i] = sum_q w_iq (c_id v_h(x_iq) + (K v)(x_iq)) for rows [r0, r0 + nr):
-// the energetic forms of eq. int_bform with A = I and A = K.  v_h at an
-// outer point of panel i is panel i's own linear function: its hats are
-// (h_m - a_m tau - b_m u - c_m v) / D_m in the local frame.  kv holds K v at
-// the packed points of the chunk.
-__global__ void k_dl_outer_sum(int64_t r0, int64_t nr, int maxq, const TrialRec* __restrict__ trial,
+// Sum of K v over each face's points: kf[f] = sum_q kv[off[f] - off[f0] + q]
+// for faces [f0, f0 + nf) (off: exclusive prefix of the faces' counts).
+__global__ void k_face_ksum(int64_t f0, int64_t nf, const int64_t* __restrict__ off,
+                            const double* __restrict__ kv, double* __restrict__ kf) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nf) return;
+  const int64_t f = f0 + g;
+  double s = 0.0;
+  for (int64_t k = off[f]; k < off[f + 1]; ++k) s += kv[k - off[f0]];
+  kf[f] = s;
+}
+
+// out[i] = sum_q w_iq (c_id v_h(x_iq) + (K v)(x_iq)): the energetic forms of
+// eq. int_bform with A = I and A = K.  v_h at an outer point of panel i is
+// panel i's own linear function: its hats are (h_m - a_m tau - b_m u -
+// c_m v) / D_m in the local frame.  The K part comes per slot (face) of the
+// panel: its per-point weight times the face's sum kf (the outer points of a
+// face are the same for both panels that share it).
+__global__ void k_dl_outer_sum(int64_t nt, int maxq, const TrialRec* __restrict__ trial,
                                const int32_t* __restrict__ tet, const double* __restrict__ v,
                                const double* __restrict__ opts, const double* __restrict__ ow,
-                               const int64_t* __restrict__ off, const double* __restrict__ kv,
+                               const int32_t* __restrict__ onq, const int32_t* __restrict__ pf,
+                               const double* __restrict__ pw, const double* __restrict__ kf,
                                double c_id, double* __restrict__ out) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nr) return;
-  const int64_t i = r0 + g;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
   const TrialRec& T = trial[i];
   double coef[4];
   for (int m = 0; m < 4; ++m) {
     const double Dm = T.fh[m] - T.fa[m] * T.V[m][0] - T.fb[m] * T.V[m][1] - T.fc[m] * T.V[m][2];
     coef[m] = v[tet[4 * i + m]] / Dm;
   }
-  const int nq = (int)(off[i + 1] - off[i]);
-  double acc = 0.0;
-  for (int q = 0; q < nq; ++q) {
+  double id = 0.0;
+  for (int q = 0; q < onq[i]; ++q) {
     const double* x = opts + (i * maxq + q) * 4;
     const double dx = x[1] - T.o[0], dy = x[2] - T.o[1], dz = x[3] - T.o[2];
     const double u = dx * T.e1[0] + dy * T.e1[1] + dz * T.e1[2];
     const double w = dx * T.e2[0] + dy * T.e2[1] + dz * T.e2[2];
     double vq = 0.0;
     for (int m = 0; m < 4; ++m) vq += coef[m] * (T.fh[m] - T.fa[m] * x[0] - T.fb[m] * u - T.fc[m] * w);
-    acc += ow[i * maxq + q] * (c_id * vq + kv[off[i] - off[r0] + q]);
+    id += ow[i * maxq + q] * vq;
   }
-  out[i] = acc;
+  double kk = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const int32_t f = pf[4 * i + k];
+    if (f >= 0) kk += pw[4 * i + k] * kf[f];
+  }
+  out[i] = c_id * id + kk;
 }
 
 unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -273,8 +291,8 @@ stb_status stb_potential_D_dev(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_q
   return dl_core(ctx, mesh, p, v_dev, np, pts_dev, out_dev);
 }
 
-// Outer points per chunk of rows of the energetic form (candidates are about
-// 1e3-1e4 per point: a chunk's candidate lists stay within a few GB).
+// Face points per chunk of the energetic form (candidates are about 1e3-1e4
+// per point: a chunk's candidate lists stay within a few GB).
 constexpr int64_t kDlChunkPoints = 32768;
 
 stb_status stb_dl_energetic(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_params* params,
@@ -289,44 +307,56 @@ stb_status stb_dl_energetic(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad
   if (nt == 0) return STB_OK;
   HIPCHK(ctx, hipSetDevice(ctx->device));
   if ((s = stb_ensure_outer(ctx, mesh, p.m_q))) return s;
-  const int maxq = mesh->maxq;
-  std::vector<int32_t> nq((size_t)nt);
-  std::vector<int64_t> off((size_t)nt + 1, 0);
-  HIPCHK(ctx, hipMemcpyAsync(nq.data(), mesh->d_onq, sizeof(int32_t) * nt, hipMemcpyDeviceToHost,
-                             ctx->stream));
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  for (int64_t i = 0; i < nt; ++i) off[i + 1] = off[i] + nq[i];
-  double *d_v = nullptr, *d_out = nullptr, *d_pts = nullptr, *d_kv = nullptr;
+  if ((s = stb_ensure_faces(ctx, mesh, p.m_q))) return s;
+  const int maxq = mesh->maxq, fq = p.m_q * p.m_q;
+  const int64_t nf = mesh->nf;
+  std::vector<int32_t> nq((size_t)std::max<int64_t>(nf, 1));
+  std::vector<int64_t> off((size_t)nf + 1, 0);
+  if (nf > 0) {
+    HIPCHK(ctx, hipMemcpyAsync(nq.data(), mesh->d_fnq, sizeof(int32_t) * nf, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  for (int64_t f = 0; f < nf; ++f) off[f + 1] = off[f] + nq[f];
+  double *d_v = nullptr, *d_out = nullptr, *d_pts = nullptr, *d_kv = nullptr, *d_kf = nullptr;
   int64_t* d_off = nullptr;
-  const int64_t cap = std::max<int64_t>(kDlChunkPoints, maxq);
-  auto cleanup = [&]() { dfree(d_v); dfree(d_out); dfree(d_pts); dfree(d_kv); dfree(d_off); };
+  const int64_t cap = std::max<int64_t>(kDlChunkPoints, fq);
+  auto cleanup = [&]() { dfree(d_v); dfree(d_out); dfree(d_pts); dfree(d_kv); dfree(d_kf); dfree(d_off); };
   if (dalloc(&d_v, (size_t)mesh->nv) != hipSuccess || dalloc(&d_out, (size_t)nt) != hipSuccess ||
       dalloc(&d_pts, (size_t)cap * 4) != hipSuccess || dalloc(&d_kv, (size_t)cap) != hipSuccess ||
-      dalloc(&d_off, (size_t)nt + 1) != hipSuccess) {
+      dalloc(&d_kf, (size_t)std::max<int64_t>(nf, 1)) != hipSuccess ||
+      dalloc(&d_off, (size_t)nf + 1) != hipSuccess) {
     cleanup();
     return stb_fail(ctx, STB_E_NO_MEMORY, "double-layer energetic buffers");
   }
   hipError_t e = hipMemcpyAsync(d_v, v, sizeof(double) * mesh->nv, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * (nt + 1), hipMemcpyHostToDevice, ctx->stream);
+    e = hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * (nf + 1), hipMemcpyHostToDevice, ctx->stream);
   if (e != hipSuccess) { cleanup(); return stb_fail(ctx, STB_E_DEVICE, "copy failed"); }
+  // K v at every distinct face point, in chunks of faces
   int64_t cand = 0;
-  for (int64_t r0 = 0; r0 < nt;) {
-    int64_t r1 = r0 + 1;
-    while (r1 < nt && off[r1 + 1] - off[r0] <= cap) ++r1;
-    const int64_t nr = r1 - r0, np = off[r1] - off[r0];
-    hipLaunchKernelGGL(k_pack_outer, dim3(grid_for(nr * maxq, 256)), dim3(256), 0, ctx->stream, r0, nr,
-                       maxq, mesh->d_opts, d_off, d_pts);
+  for (int64_t f0 = 0; f0 < nf;) {
+    int64_t f1 = f0 + 1;
+    while (f1 < nf && off[f1 + 1] - off[f0] <= cap) ++f1;
+    const int64_t nfc = f1 - f0, np = off[f1] - off[f0];
+    hipLaunchKernelGGL(k_pack_outer, dim3(grid_for(nfc * fq, 256)), dim3(256), 0, ctx->stream, f0, nfc, fq,
+                       mesh->d_fpts, d_off, d_pts);
     if ((e = hipGetLastError()) != hipSuccess) break;
     if (np > 0) {
       s = dl_core(ctx, mesh, p, d_v, np, d_pts, d_kv);
       if (s) { cleanup(); return s; }
       cand += ctx->work[2];
     }
-    hipLaunchKernelGGL(k_dl_outer_sum, dim3(grid_for(nr, 128)), dim3(128), 0, ctx->stream, r0, nr, maxq,
-                       mesh->d_trial, mesh->d_tet, d_v, mesh->d_opts, mesh->d_ow, d_off, d_kv, c_id, d_out);
+    hipLaunchKernelGGL(k_face_ksum, dim3(grid_for(nfc, 256)), dim3(256), 0, ctx->stream, f0, nfc, d_off, d_kv,
+                       d_kf);
     if ((e = hipGetLastError()) != hipSuccess) break;
-    r0 = r1;
+    f0 = f1;
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_dl_outer_sum, dim3(grid_for(nt, 128)), dim3(128), 0, ctx->stream, nt, maxq,
+                       mesh->d_trial, mesh->d_tet, d_v, mesh->d_opts, mesh->d_ow, mesh->d_onq, mesh->d_pf,
+                       mesh->d_pw, d_kf, c_id, d_out);
+    e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(double) * nt, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
