@@ -1283,7 +1283,8 @@ STB_HD inline void inner_dl_serial(const TrialRec& T, const FaceAng& FA, const d
   apex_of(T, x4, A);
   double wlo = 0.0, whi = 0.0;
   if (A.d == 0.0) return;   // k2 = k3 = 0 in the panel's plane
-  bool lit = A.t - T.tmin > fabs(A.d) && !ball_rejects(T, x4) && lit_test(T, x4, A);
+  const int lq = lit_quick(T, x4, A);   // the vertices decide nearly every pair
+  const bool lit = lq == 1 || (lq == 2 && lit_test(T, x4, A));
   if (!lit || !w_range(T, A, wlo, whi)) return;
   ComboL cb;
   FaceSet F;
@@ -1315,6 +1316,7 @@ STB_HD inline void inner_dl_serial(const TrialRec& T, const FaceAng& FA, const d
       const double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
       const double H = b - a;
       if (!(H > 0.0)) continue;
+      if (piece_misses(T, A, a, H)) continue;   // no ray of the piece meets the panel
       bool ne = L_at(cb, a + 0.5 * H) != 0.0;
       if (!ne) ne = L_at(cb, a + 0.25 * H) != 0.0 || L_at(cb, a + 0.75 * H) != 0.0;
       if (!ne) continue;
