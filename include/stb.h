@@ -200,6 +200,23 @@ stb_status stb_inner_values_D(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad
 stb_status stb_dl_energetic(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
                             const double* v, double c_id, double* out);
 
+/* L2 projection Q_h^1 onto V_h^1 (the data projection of the direct method,
+ * eq. df_dir): c in V_h^1 with (c, lambda_k) = (g, lambda_k) in L2(Sigma)
+ * for every vertex hat lambda_k.  (g, lambda_k) uses a fixed rule of
+ * STB_L2_POINTS points per panel (the 3 x 3 x 3 Gauss-Legendre product rule
+ * collapsed onto the tetrahedron, exact for degree 3):
+ * stb_l2_points writes them, pts [nt][STB_L2_POINTS][4] (t, x, y, z) and
+ * weights [nt][STB_L2_POINTS] (host); the caller evaluates g there and
+ * stb_project_V1 takes those values gq [nt][STB_L2_POINTS] (host) and
+ * writes the nv vertex values of Q_h^1 g (host).  The mass system is solved
+ * by Jacobi-preconditioned CG on the device to a relative residual of
+ * 1e-13 (STB_E_INTERNAL if 1,000 steps do not reach it); iters (optional)
+ * receives the steps. */
+#define STB_L2_POINTS 27
+stb_status stb_l2_points(stb_ctx* ctx, const stb_mesh* mesh, double* pts, double* wts);
+stb_status stb_project_V1(stb_ctx* ctx, const stb_mesh* mesh, const double* gq, double* out,
+                          int32_t* iters);
+
 /* Batched assembly of nmesh meshes of one context (Exp. 3 style workloads
  * of many independent scatterers): the candidate sets of all meshes are one
  * work list of the pair pipeline, so every kernel launch covers the whole

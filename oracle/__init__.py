@@ -70,6 +70,8 @@ def lib():
         L.orc_breakpoints.argtypes = [_D, _D, _D, c_int]
         L.orc_inner_dl.argtypes = [_D, _D, _D, _D, c_int, _D]
         L.orc_potential_dl.argtypes = [i64, _D, i64, _I32, _D, _D, i64, _D, c_int, _D]
+        L.orc_l2_points.argtypes = [_D, _D, _D]
+        L.orc_l2_projection.argtypes = [i64, _D, i64, _I32, _D, _D]
         L.orc_dl_energetic_rows.argtypes = [i64, _D, i64, _I32, _D, _D, i64, _I64, c_int, c_int,
                                             ctypes.c_double, _D]
         _lib = L
@@ -265,4 +267,24 @@ def dl_energetic_rows(vtx, tets, nrm, v, rows, c_id=0.0, m_q=DEFAULT_MQ, n_g=DEF
     _check(lib().orc_dl_energetic_rows(vtx.shape[0], pv, tets.shape[0], pt, pn, pvv, rows.shape[0],
                                        pr, m_q, n_g, float(c_id), out.ctypes.data_as(_D)),
            "dl_energetic_rows")
+    return out
+
+
+def l2_points(tet):
+    """The 27 points and weights of the projection rule on one panel."""
+    tet, pt = _d(tet)
+    pts = np.zeros((27, 4))
+    w = np.zeros(27)
+    _check(lib().orc_l2_points(pt, pts.ctypes.data_as(_D), w.ctypes.data_as(_D)), "l2_points")
+    return pts, w
+
+
+def l2_projection(vtx, tets, gq):
+    """Vertex values of Q_h^1 g from g at every panel's 27 rule points."""
+    vtx, pv = _d(vtx)
+    tets, pt = _i32(tets)
+    gq, pg = _d(np.asarray(gq).reshape(-1))
+    out = np.zeros(vtx.shape[0])
+    _check(lib().orc_l2_projection(vtx.shape[0], pv, tets.shape[0], pt, pg, out.ctypes.data_as(_D)),
+           "l2_projection")
     return out

@@ -994,6 +994,110 @@ int orc_dl_energetic_rows(int64_t nv, const double* vtx, int64_t nt, const int32
   return bad ? ORC_E_ARG : ORC_OK;
 }
 
+/* ---------------- L2 projection onto V_h^1 (eq. df_dir's Q_h^1) ----------------
+ * (c, lambda_k) = (g, lambda_k) in L2(Sigma), dS = the 3-volume of the
+ * panel in its (tau, u, v) frame.  The integrals of g use a fixed rule
+ * (ORC_L2_PTS points per panel): the 3 x 3 x 3 Gauss-Legendre product rule
+ * on the unit cube pulled back to the tetrahedron by
+ * (a, b, c) -> (a, (1 - a) b, (1 - a)(1 - b) c), Jacobian (1 - a)^2 (1 - b);
+ * the mass matrix is exact, vol (1 + delta_kl) / 20 per panel.  Dense
+ * Gaussian elimination (small meshes only). */
+#define ORC_L2_PTS 27
+
+static void l2_rule(double lam[ORC_L2_PTS][4], double w[ORC_L2_PTS]) {
+  double gx[3], gw[3];
+  orc_gauss_legendre01(3, gx, gw);
+  int p = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        double a = gx[i], b = gx[j], c = gx[k];
+        double xi1 = a, xi2 = (1.0 - a) * b, xi3 = (1.0 - a) * (1.0 - b) * c;
+        lam[p][0] = 1.0 - xi1 - xi2 - xi3;
+        lam[p][1] = xi1;
+        lam[p][2] = xi2;
+        lam[p][3] = xi3;
+        w[p] = gw[i] * gw[j] * gw[k] * (1.0 - a) * (1.0 - a) * (1.0 - b);
+        ++p;
+      }
+}
+
+static double panel_volume(const orc_panel* P) {
+  double a1[3], a2[3], a3[3], cr[3];
+  sub3(P->V[1], P->V[0], a1);
+  sub3(P->V[2], P->V[0], a2);
+  sub3(P->V[3], P->V[0], a3);
+  cross3(a1, a2, cr);
+  return fabs(dot3(cr, a3)) / 6.0;
+}
+
+int orc_l2_points(const double* tet, double* pts, double* w) {
+  orc_panel P;
+  int rc = panel_setup(tet, &P);
+  if (rc) return rc;
+  double lam[ORC_L2_PTS][4], wr[ORC_L2_PTS];
+  l2_rule(lam, wr);
+  double vol = panel_volume(&P);
+  for (int p = 0; p < ORC_L2_PTS; ++p) {
+    for (int c = 0; c < 4; ++c) {
+      double x = 0.0;
+      for (int m = 0; m < 4; ++m) x += lam[p][m] * tet[4 * m + c];
+      pts[4 * p + c] = x;
+    }
+    w[p] = 6.0 * vol * wr[p];
+  }
+  return ORC_L2_PTS;
+}
+
+int orc_l2_projection(int64_t nv, const double* vtx, int64_t nt, const int32_t* tets,
+                      const double* gq, double* out) {
+  int rc = check_mesh(nv, vtx, nt, tets);
+  if (rc) return rc;
+  if (nv > 20000) return ORC_E_ARG;
+  double lam[ORC_L2_PTS][4], wr[ORC_L2_PTS];
+  l2_rule(lam, wr);
+  double* M = (double*)calloc((size_t)nv * (size_t)(nv + 1), sizeof(double));   /* [nv][nv + 1] */
+  if (!M) return ORC_E_ARG;
+  for (int64_t j = 0; j < nt; ++j) {
+    double tet[16];
+    orc_panel P;
+    gather_tet(vtx, tets, j, tet);
+    if ((rc = panel_setup(tet, &P))) { free(M); return rc; }
+    double vol = panel_volume(&P);
+    for (int a = 0; a < 4; ++a) {
+      int64_t k = tets[4 * j + a];
+      for (int b = 0; b < 4; ++b) M[k * (nv + 1) + tets[4 * j + b]] += vol * (a == b ? 2.0 : 1.0) / 20.0;
+      double f = 0.0;
+      for (int p = 0; p < ORC_L2_PTS; ++p) f += 6.0 * vol * wr[p] * gq[j * ORC_L2_PTS + p] * lam[p][a];
+      M[k * (nv + 1) + nv] += f;
+    }
+  }
+  for (int64_t col = 0; col < nv; ++col) {
+    int64_t piv = col;
+    for (int64_t r = col + 1; r < nv; ++r)
+      if (fabs(M[r * (nv + 1) + col]) > fabs(M[piv * (nv + 1) + col])) piv = r;
+    if (M[piv * (nv + 1) + col] == 0.0) { free(M); return ORC_E_PANEL; }
+    if (piv != col)
+      for (int64_t q = 0; q <= nv; ++q) {
+        double t = M[col * (nv + 1) + q];
+        M[col * (nv + 1) + q] = M[piv * (nv + 1) + q];
+        M[piv * (nv + 1) + q] = t;
+      }
+    for (int64_t r = col + 1; r < nv; ++r) {
+      double f = M[r * (nv + 1) + col] / M[col * (nv + 1) + col];
+      if (f == 0.0) continue;
+      for (int64_t q = col; q <= nv; ++q) M[r * (nv + 1) + q] -= f * M[col * (nv + 1) + q];
+    }
+  }
+  for (int64_t r = nv - 1; r >= 0; --r) {
+    double x = M[r * (nv + 1) + nv];
+    for (int64_t q = r + 1; q < nv; ++q) x -= M[r * (nv + 1) + q] * out[q];
+    out[r] = x / M[r * (nv + 1) + r];
+  }
+  free(M);
+  return ORC_OK;
+}
+
 int orc_pair_causal(const double* vtx, const int32_t* tets, int64_t i, int64_t j, int m_q) {
   double ti[16], tj[16], pts[4 * 4 * 256], w[4 * 256];
   gather_tet(vtx, tets, i, ti);

@@ -96,6 +96,13 @@ int orc_dl_energetic_rows(int64_t nv, const double* vtx, int64_t nt,
                           const int32_t* tets, const double* nrm, const double* v,
                           int64_t nrows, const int64_t* rows, int m_q, int n_g,
                           double c_id, double* out);
+/* L2 projection onto V_h^1: orc_l2_points writes the 27 points (pts[27][4])
+ * and weights of the fixed panel rule; orc_l2_projection takes g at those
+ * points for every panel (gq[nt][27]) and writes the nv vertex values of
+ * Q_h^1 g (dense solve, nv <= 20000). */
+int orc_l2_points(const double* tet, double* pts, double* w);
+int orc_l2_projection(int64_t nv, const double* vtx, int64_t nt,
+                      const int32_t* tets, const double* gq, double* out);
 /* Exact lit predicate of Sec. 3.3: 1 iff the backward cone of x meets the
  * open panel, i.e. min < 0 < max of phi_Xi(x - y) over the closed panel
  * (eq. sgn_dist_cone).  Also returns min and max when non-NULL. */

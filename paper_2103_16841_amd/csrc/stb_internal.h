@@ -46,6 +46,11 @@ struct stb_mesh {
   // double layer: +1 where the outward normal of Gamma is the panel frame's
   // normal n, else -1 (set by stb_mesh_set_normals)
   double* d_nsign = nullptr;        // [nt]
+  // L2 projection onto V_h^1: vertex -> (4 panel + local vertex), ascending
+  // panel per vertex; 6 x the panels' 3-volumes (built on first use)
+  int64_t* d_v2t_ptr = nullptr;     // [nv + 1]
+  int64_t* d_v2t = nullptr;         // [4 nt]
+  double* d_vol6 = nullptr;         // [nt]
   // outer points for one m_q (recomputed when m_q changes)
   int mq = 0;
   int maxq = 0;
@@ -143,6 +148,9 @@ void stb_free_faces(stb_mesh* m);
 // unit's values and causal count; work as stb_run_pairs.
 stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* units, int nunit,
                              unsigned long long work[4]);
+
+// Frees the L2 projection's adjacency (stb_proj.hip).
+void stb_free_projection(stb_mesh* m);
 
 // Potential with device inputs/outputs on ctx's stream and workspace (the
 // mesh may belong to another context of the same device).

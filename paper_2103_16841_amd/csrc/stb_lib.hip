@@ -672,6 +672,7 @@ void stb_mesh_destroy(stb_mesh* m) {
   if (!m) return;
   dfree(m->d_vtx); dfree(m->d_tet); dfree(m->d_trial); dfree(m->d_fang);
   dfree(m->d_nsign);
+  stb_free_projection(m);
   dfree(m->d_opts); dfree(m->d_ow); dfree(m->d_onq); dfree(m->d_box);
   stb_free_faces(m);
   delete m;

@@ -24,6 +24,7 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_last_path_counts", "stb_mesh_create_dev",
            "stb_outer_points", "stb_solve_gmres", "stb_mesh_set_normals", "stb_potential_D",
            "stb_potential_D_dev", "stb_inner_values_D", "stb_dl_energetic",
+           "stb_l2_points", "stb_project_V1",
            "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble", "stb_autotune",
            "stb_set_tuning", "stb_server_create", "stb_server_add_mesh", "stb_server_submit",
            "stb_server_wait", "stb_server_destroy"]
@@ -98,6 +99,8 @@ def load():
     L.stb_potential_D_dev.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _VP, i64, _VP, _VP, _VP]
     L.stb_inner_values_D.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
     L.stb_dl_energetic.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _D, ctypes.c_double, _D]
+    L.stb_l2_points.argtypes = [_VP, _VP, _D, _D]
+    L.stb_project_V1.argtypes = [_VP, _VP, _D, _D, ctypes.POINTER(ctypes.c_int32)]
     L.stb_last_work.argtypes = [_VP, _I64]
     L.stb_last_path_counts.argtypes = [_VP, _I64]
     L.stb_outer_points.argtypes = [_VP, _VP, i32, _D, _D, _I32]
@@ -420,6 +423,28 @@ def dl_energetic(ctx, mesh, v, c_id=0.0, params=None):
     _chk(load().stb_dl_energetic(ctx.h, mesh.h, ctypes.byref(p), pv, float(c_id),
                                  out.ctypes.data_as(_D)), ctx.h)
     return out
+
+
+L2_POINTS = 27
+
+
+def l2_points(ctx, mesh):
+    """Points [nt][27][4] and weights [nt][27] of the projection's rule."""
+    pts = np.zeros((mesh.nt, L2_POINTS, 4))
+    w = np.zeros((mesh.nt, L2_POINTS))
+    _chk(load().stb_l2_points(ctx.h, mesh.h, pts.ctypes.data_as(_D), w.ctypes.data_as(_D)), ctx.h)
+    return pts, w
+
+
+def project_V1(ctx, mesh, gq, nv):
+    """Vertex values of the L2 projection Q_h^1 g from g at the l2_points."""
+    gq, pg = _d(gq, (-1,))
+    if gq.shape[0] != mesh.nt * L2_POINTS:
+        raise ValueError("need g at the %d points of every panel" % L2_POINTS)
+    out = np.zeros(nv)
+    it = ctypes.c_int32()
+    _chk(load().stb_project_V1(ctx.h, mesh.h, pg, out.ctypes.data_as(_D), ctypes.byref(it)), ctx.h)
+    return out, it.value
 
 
 def inner_values_D(ctx, mesh, pts, panels, params=None):

@@ -175,12 +175,32 @@ def test_energetic_forms_exact(stb, ctx):
     assert np.all(np.abs(bi - exi) <= 1e-14)
 
 
+def test_projection_vs_oracle(stb, ctx):
+    """Q_h^1: the rule's points and weights, and the projection of a smooth
+    function, against the oracle; a V_h^1 function is reproduced."""
+    mesh = inputs.icosphere_mesh(level=1, S=4, T=3.0, jitter=0.2, seed=7)
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    P, W = stb.l2_points(ctx, m)
+    Po = np.array([oracle.l2_points(mesh.vtx[mesh.tets[j]])[0] for j in range(mesh.nt)])
+    Wo = np.array([oracle.l2_points(mesh.vtx[mesh.tets[j]])[1] for j in range(mesh.nt)])
+    assert np.abs(P - Po).max() <= 1e-14 and np.abs(W - Wo).max() <= 1e-15
+    f = lambda p: np.sin(p[..., 0]) * np.cos(2.0 * p[..., 1]) + p[..., 2] * p[..., 3]
+    c, its = stb.project_V1(ctx, m, f(P), mesh.nv)
+    co = oracle.l2_projection(mesh.vtx, mesh.tets, f(Po))
+    print("projection: %d CG steps, worst abs err %.3e (max |c| %.3f)" % (its, np.abs(c - co).max(),
+                                                                          np.abs(co).max()), flush=True)
+    assert np.abs(c - co).max() <= 1e-10 * np.abs(co).max()
+    a = np.array([0.3, -0.7, 0.4, 1.1])
+    c1, _ = stb.project_V1(ctx, m, 0.2 + P @ a, mesh.nv)
+    assert np.abs(c1 - (0.2 + mesh.vtx @ a)).max() <= 1e-12
+
+
 def test_direct_method_exterior(stb, ctx):
     """The direct method (eq. df_dir) for the exterior problem of the paper's
     last example: a spherical wave mu(t - |x - y_S|) / |x - y_S| from y_S
-    inside, mu(t) = t^3 e^-t; Dirichlet data by vertex interpolation, the
-    right-hand side -1/2 b_I(g) + b_K(g), GMRES for the Neumann trace, then
-    u_h = D g - S w_h outside.  Both errors fall under refinement."""
+    inside, mu(t) = t^3 e^-t; Dirichlet data projected, Q_h^1 g, the
+    right-hand side -1/2 b_I(Q g) + b_K(Q g), GMRES for the Neumann trace,
+    then u_h = D Q g - S w_h outside.  Both errors fall under refinement."""
     ys = np.array([-0.1, -0.2, -0.3])
 
     def mu(t):
@@ -209,7 +229,8 @@ def test_direct_method_exterior(stb, ctx):
         m = _mesh(stb, ctx, mesh)
         nrm = mesh.outward_normals()
         A = stb.assemble_V(ctx, m)
-        g = u(mesh.vtx)
+        P, _ = stb.l2_points(ctx, m)
+        g, _ = stb.project_V1(ctx, m, u(P), mesh.nv)
         b = stb.dl_energetic(ctx, m, g, c_id=-0.5)
         x, its, rr = stb.solve_gmres(ctx, A, b, restart=100, maxit=20000, rtol=1e-10)
         cen = mesh.vtx[mesh.tets].mean(axis=1)

@@ -260,3 +260,51 @@ def test_surface_direct_value_and_energetic_forms():
     exi = np.array([np.dot(W, 0.2 + P @ a) for P, W in
                     (oracle.outer_points(mesh.vtx[mesh.tets[i]]) for i in rows)])
     assert np.all(np.abs(bi - exi) <= 1e-14)
+
+
+# --- the L2 projection onto V_h^1 (eq. df_dir's Q_h^1) -----------------------
+
+def _rule_values(mesh, f):
+    P = np.array([oracle.l2_points(mesh.vtx[mesh.tets[j]])[0] for j in range(mesh.nt)])
+    return P, f(P)
+
+
+def test_projection_reproduces_V1():
+    """Q_h^1 is a projection: a function of V_h^1 (random vertex values,
+    linear on every panel) comes back unchanged."""
+    mesh = inputs.icosphere_mesh(level=1, S=3, T=3.0, jitter=0.2, seed=7)
+    v = np.random.default_rng(3).standard_normal(mesh.nv)
+    # g at the rule points: the panel's linear interpolant of v
+    g = np.zeros((mesh.nt, 27))
+    for j in range(mesh.nt):
+        T = mesh.vtx[mesh.tets[j]]
+        P, _ = oracle.l2_points(T)
+        # barycentric coordinates of each point in (t, x, y, z): least squares on the panel's affine hull
+        E = (T[1:] - T[0]).T                            # 4 x 3
+        bc = np.linalg.lstsq(E, (P - T[0]).T, rcond=None)[0].T
+        lamq = np.concatenate([1.0 - bc.sum(axis=1, keepdims=True), bc], axis=1)
+        g[j] = lamq @ v[mesh.tets[j]]
+    c = oracle.l2_projection(mesh.vtx, mesh.tets, g)
+    assert np.abs(c - v).max() <= 1e-11
+
+
+def _tet_volume4(T):
+    E = (T[1:] - T[0])
+    return math.sqrt(np.linalg.det(E @ E.T)) / 6.0
+
+
+def test_projection_keeps_integrals_of_quadratics():
+    """1 is in V_h^1, so int Q g = int g; for quadratic g the panel integrals
+    follow from the 10-point rule (vertices and edge midpoints) exactly."""
+    mesh = inputs.icosphere_mesh(level=1, S=3, T=3.0, jitter=0.2, seed=7)
+    for f in (lambda p: p[..., 0] ** 2, lambda p: p[..., 1] * p[..., 2] + p[..., 0] * p[..., 3]):
+        _, g = _rule_values(mesh, f)
+        c = oracle.l2_projection(mesh.vtx, mesh.tets, g)
+        iq = ig = 0.0
+        for j in range(mesh.nt):
+            T = mesh.vtx[mesh.tets[j]]
+            vol = _tet_volume4(T)
+            iq += vol / 4.0 * c[mesh.tets[j]].sum()
+            mids = [0.5 * (T[a] + T[b]) for a in range(4) for b in range(a + 1, 4)]
+            ig += vol * (-sum(f(T[a]) for a in range(4)) / 20.0 + sum(f(m) for m in mids) / 5.0)
+        assert abs(iq - ig) <= 1e-12 * max(1.0, abs(ig))
