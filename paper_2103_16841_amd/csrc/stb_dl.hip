@@ -2,11 +2,13 @@
 // of eq. kfunc) of a density in V_h^1 (continuous, linear on every panel;
 // def. st_be), at points off or on the surface.
 //
-// The candidates (point, panel) come from the single layer's cull; one lane
-// evaluates one candidate completely (inner_dl_serial: lit test,
-// breakpoints, the empty-piece test and the Gauss nodes of every piece) and
-// writes the potentials of the panel's four hat functions; a second kernel
-// sums them per point against the vertex values in a fixed order.
+// The candidates (point, panel) come from the single layer's cull.  Three
+// stages give the potentials of each candidate panel's four hat functions:
+// per candidate the lit test and the breakpoints, which list the pieces;
+// per piece the empty-piece test and the Gauss nodes (dense work); per
+// candidate the sum of its pieces.  A last kernel sums the hats per point
+// against the vertex values in a fixed order.  stb_inner_values_D keeps one
+// lane per pair (inner_dl_serial) for checks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,24 +36,6 @@ __global__ void k_normal_sign(int64_t nt, const TrialRec* __restrict__ trial,
   bool ok = l > 0.0 && isfinite(l) && fabs(c) >= 0.5 * l;
   nsign[j] = c > 0.0 ? 1.0 : -1.0;
   status[j] = ok ? 0 : 1;
-}
-
-__global__ __launch_bounds__(256) void k_dl_hats(int64_t nnz, const int32_t* __restrict__ rowof,
-                                                 const int32_t* __restrict__ cols,
-                                                 const TrialRec* __restrict__ trial,
-                                                 const FaceAng* __restrict__ fang,
-                                                 const double* __restrict__ nsign,
-                                                 const double* __restrict__ pts,
-                                                 const double* __restrict__ gl, int ng,
-                                                 double* __restrict__ out4) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nnz) return;
-  const int32_t j = cols[c];
-  const double* xp = pts + 4 * (int64_t)rowof[c];
-  double x4[4] = {xp[0], xp[1], xp[2], xp[3]};
-  double h[4];
-  inner_dl_serial(trial[j], fang[j], x4, nsign[j], ng, gl, gl + kMaxNg, h);
-  for (int m = 0; m < 4; ++m) out4[4 * c + m] = h[m];
 }
 
 // u(p) = sum over p's candidates and the panel's vertices of v(vertex) *
@@ -87,6 +71,166 @@ __global__ void k_dl_pairs(int64_t k, const TrialRec* __restrict__ trial,
   double h[4];
   inner_dl_serial(trial[j], fang[j], x4, nsign[j], ng, gl, gl + kMaxNg, h);
   for (int q = 0; q < 4; ++q) out4[4 * m + q] = h[q];
+}
+
+// ---- split evaluation: candidates -> pieces -> nodes -> candidates ----
+//
+// Stage 1 (one lane per candidate): apex data, lit test, w-range,
+// breakpoints; the pieces the ray test does not rule out are appended to a
+// list, each candidate's contiguously and in phi order (a block takes one
+// range of the list with one atomic); the candidate keeps C_k, d^2, the
+// w-range and the factor nsign d / 4 pi.  Stage 2 (one lane per piece): the
+// empty-piece test and the Gauss nodes, three sums per piece.  Stage 3 (one
+// lane per candidate): its pieces summed in order, then the four hats.
+constexpr int kDlCb = 8;   // C[4], d2, wlo, whi, factor
+
+__global__ __launch_bounds__(256) void k_dl_split(int64_t c0, int64_t n, const int32_t* __restrict__ rowof,
+                                                  const int32_t* __restrict__ cols,
+                                                  const TrialRec* __restrict__ trial,
+                                                  const FaceAng* __restrict__ fang,
+                                                  const double* __restrict__ nsign,
+                                                  const double* __restrict__ pts, double* __restrict__ cb,
+                                                  int64_t* __restrict__ poff, int32_t* __restrict__ pcnt,
+                                                  double* __restrict__ pa, double* __restrict__ ph,
+                                                  int32_t* __restrict__ pc, int64_t cap,
+                                                  unsigned long long* __restrict__ counter) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = k < n;
+  double bp[kMaxBp];
+  int nb = -1;   // -1: nothing to integrate; 0: periodic (two trapezoid halves)
+  unsigned np = 0;
+  Apex A;
+  const TrialRec* T = nullptr;
+  if (valid) {
+    const int64_t c = c0 + k;
+    const int32_t j = cols[c];
+    T = trial + j;
+    const double* xp = pts + 4 * (int64_t)rowof[c];
+    double x4[4] = {xp[0], xp[1], xp[2], xp[3]};
+    apex_of(*T, x4, A);
+    double wlo = 0.0, whi = 0.0;
+    double* o = cb + kDlCb * k;
+    o[7] = 0.0;
+    if (A.d != 0.0) {
+      const int lq = lit_quick(*T, x4, A);
+      const bool lit = lq == 1 || (lq == 2 && lit_test(*T, x4, A));
+      if (lit && w_range(*T, A, wlo, whi)) {
+        for (int q = 0; q < 4; ++q) o[q] = A.C[q];
+        o[4] = A.d * A.d;
+        o[5] = wlo;
+        o[6] = whi;
+        o[7] = nsign[j] * A.d / (4.0 * kPi);
+        nb = breakpoints(*T, fang[j], A, bp);
+        sort_bp(bp, nb);
+        if (nb == 0) {
+          np = 2;
+        } else {
+          for (int m = 0; m < nb; ++m) {
+            const double a = bp[m], e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
+            if (e - a > 0.0 && !piece_misses(*T, A, a, e - a)) ++np;
+          }
+        }
+      }
+    }
+  }
+  __shared__ unsigned s_cnt;
+  __shared__ unsigned long long s_base;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const unsigned my = np ? atomicAdd(&s_cnt, np) : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) s_base = s_cnt ? atomicAdd(counter, (unsigned long long)s_cnt) : 0ull;
+  __syncthreads();
+  if (!valid) return;
+  const unsigned long long base = s_base + my;
+  poff[k] = (int64_t)base;
+  pcnt[k] = (int32_t)np;
+  if (np == 0 || base + np > (unsigned long long)cap) return;
+  int64_t w = (int64_t)base;
+  if (nb == 0) {
+    for (int h = 0; h < 2; ++h, ++w) { pa[w] = (double)h; ph[w] = -1.0; pc[w] = (int32_t)k; }
+    return;
+  }
+  for (int m = 0; m < nb; ++m) {
+    const double a = bp[m], e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
+    if (!(e - a > 0.0) || piece_misses(*T, A, a, e - a)) continue;
+    pa[w] = a; ph[w] = e - a; pc[w] = (int32_t)k; ++w;
+  }
+}
+
+// Stage 2: one lane per piece.  A trapezoid half (ph < 0) takes its n_g
+// nodes of the periodic rule; a Gauss piece is tested at its midpoint and
+// quarter points first.
+__global__ __launch_bounds__(256) void k_dl_piece_nodes(int64_t npc, int64_t c0, const double* __restrict__ pa,
+                                                        const double* __restrict__ ph,
+                                                        const int32_t* __restrict__ pc,
+                                                        const double* __restrict__ cb,
+                                                        const int32_t* __restrict__ cols,
+                                                        const TrialRec* __restrict__ trial,
+                                                        const double* __restrict__ gl, int ng,
+                                                        double* __restrict__ out3) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npc) return;
+  const int64_t k = pc[p];
+  const double* o = cb + kDlCb * k;
+  const TrialRec& T = trial[cols[c0 + k]];
+  ComboL L;
+  FaceSet F;
+  for (int q = 0; q < 4; ++q) {
+    L.C[q] = o[q]; L.fa[q] = T.fa[q]; L.fb[q] = T.fb[q]; L.fc[q] = T.fc[q];
+    F.fa[q] = T.fa[q]; F.fb[q] = T.fb[q]; F.fc[q] = T.fc[q];
+  }
+  L.d2 = o[4]; L.wlo = o[5]; L.whi = o[6];
+  const double a = pa[p], H = ph[p];
+  double ia = 0.0, ic = 0.0, is = 0.0;
+  auto node = [&](double phi, double wt) {
+    double sn, cs, sa, sh;
+    sincos_small(phi, &sn, &cs);
+    dl_eval(F, L.C, L.d2, L.wlo, L.whi, cs, sn, sa, sh);
+    ia += wt * sa;
+    ic += (wt * sh) * cs;
+    is += (wt * sh) * sn;
+  };
+  if (H < 0.0) {
+    const double ht = kTwoPi / (2 * ng);
+    for (int g = 0; g < ng; ++g) node((a * ng + g) * ht, ht);
+  } else {
+    bool ne = L_at(L, a + 0.5 * H) != 0.0;
+    if (!ne) ne = L_at(L, a + 0.25 * H) != 0.0 || L_at(L, a + 0.75 * H) != 0.0;
+    if (ne)
+      for (int g = 0; g < ng; ++g) {
+        const double u = gl[g];
+        const double sm = u * u * (3.0 - 2.0 * u);
+        const double ds = 6.0 * u * (1.0 - u);
+        node(a + H * sm, H * ds * gl[kMaxNg + g]);
+      }
+  }
+  out3[3 * p] = ia;
+  out3[3 * p + 1] = ic;
+  out3[3 * p + 2] = is;
+}
+
+// Stage 3: per candidate, its pieces in order, then the hats
+// lambda_m(t, p) = C_m / D_m and grad lambda_m = -(b_m, c_m) / D_m.
+__global__ void k_dl_finish(int64_t c0, int64_t n, const int32_t* __restrict__ cols,
+                            const TrialRec* __restrict__ trial, const double* __restrict__ cb,
+                            const int64_t* __restrict__ poff, const int32_t* __restrict__ pcnt,
+                            const double* __restrict__ out3, double* __restrict__ out4) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double ia = 0.0, ic = 0.0, is = 0.0;
+  for (int64_t p = poff[k]; p < poff[k] + pcnt[k]; ++p) {
+    ia += out3[3 * p];
+    ic += out3[3 * p + 1];
+    is += out3[3 * p + 2];
+  }
+  const double* o = cb + kDlCb * k;
+  const TrialRec& T = trial[cols[c0 + k]];
+  double* h = out4 + 4 * (c0 + k);
+  for (int m = 0; m < 4; ++m) {
+    const double Dm = T.fh[m] - T.fa[m] * T.V[m][0] - T.fb[m] * T.V[m][1] - T.fc[m] * T.V[m][2];
+    h[m] = pcnt[k] ? o[7] * (o[m] * ia - T.fb[m] * ic - T.fc[m] * is) / Dm : 0.0;
+  }
 }
 
 // The points of entities [r0, r0 + nr) (faces), maxq slots each, packed
@@ -158,6 +302,65 @@ unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
+// Candidates per pass of the split evaluation, and initial pieces per candidate.
+constexpr int64_t kDlCandChunk = int64_t(1) << 23;
+constexpr int64_t kDlPiecesPer = 12;
+
+// The hats of candidates [0, nnz) into h4 through the three stages.
+static stb_status dl_split(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p, int64_t nnz,
+                           const int32_t* d_rowof, const int32_t* d_cols, const double* d_pts, double* d_h4) {
+  if (nnz == 0) return STB_OK;
+  hipStream_t st = ctx->stream;
+  const int64_t chunk = std::min(nnz, kDlCandChunk);
+  double *d_cb = nullptr, *d_pa = nullptr, *d_ph = nullptr, *d_o3 = nullptr;
+  int64_t* d_poff = nullptr;
+  int32_t *d_pcnt = nullptr, *d_pc = nullptr;
+  unsigned long long* d_ctr = nullptr;
+  int64_t cap = chunk * kDlPiecesPer;
+  auto free_pieces = [&]() { dfree(d_pa); dfree(d_ph); dfree(d_pc); dfree(d_o3); d_pa = d_ph = d_o3 = nullptr; d_pc = nullptr; };
+  auto cleanup = [&]() { dfree(d_cb); dfree(d_poff); dfree(d_pcnt); dfree(d_ctr); free_pieces(); };
+  auto alloc_pieces = [&]() {
+    return dalloc(&d_pa, (size_t)cap) == hipSuccess && dalloc(&d_ph, (size_t)cap) == hipSuccess &&
+           dalloc(&d_pc, (size_t)cap) == hipSuccess && dalloc(&d_o3, (size_t)cap * 3) == hipSuccess;
+  };
+  if (dalloc(&d_cb, (size_t)chunk * kDlCb) != hipSuccess || dalloc(&d_poff, (size_t)chunk) != hipSuccess ||
+      dalloc(&d_pcnt, (size_t)chunk) != hipSuccess || dalloc(&d_ctr, 1) != hipSuccess || !alloc_pieces()) {
+    cleanup();
+    return stb_fail(ctx, STB_E_NO_MEMORY, "double-layer pieces");
+  }
+  hipError_t e = hipSuccess;
+  for (int64_t c0 = 0; c0 < nnz && e == hipSuccess;) {
+    const int64_t n = std::min(chunk, nnz - c0);
+    unsigned long long npc = 0;
+    for (;;) {
+      e = hipMemsetAsync(d_ctr, 0, sizeof(unsigned long long), st);
+      if (e != hipSuccess) break;
+      hipLaunchKernelGGL(k_dl_split, dim3(grid_for(n, 256)), dim3(256), 0, st, c0, n, d_rowof, d_cols,
+                         mesh->d_trial, mesh->d_fang, mesh->d_nsign, d_pts, d_cb, d_poff, d_pcnt, d_pa, d_ph,
+                         d_pc, cap, d_ctr);
+      if ((e = hipGetLastError()) != hipSuccess) break;
+      if ((e = hipMemcpyAsync(&npc, d_ctr, sizeof(npc), hipMemcpyDeviceToHost, st)) != hipSuccess) break;
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
+      if ((int64_t)npc <= cap) break;
+      free_pieces();                       // the list overflowed: grow it and redo the pass
+      cap = (int64_t)npc + npc / 8 + 1024;
+      if (!alloc_pieces()) { cleanup(); return stb_fail(ctx, STB_E_NO_MEMORY, "double-layer pieces"); }
+    }
+    if (e != hipSuccess) break;
+    if (npc > 0)
+      hipLaunchKernelGGL(k_dl_piece_nodes, dim3(grid_for((int64_t)npc, 256)), dim3(256), 0, st, (int64_t)npc, c0,
+                         d_pa, d_ph, d_pc, d_cb, d_cols, mesh->d_trial, ctx->d_gl, p.n_g, d_o3);
+    hipLaunchKernelGGL(k_dl_finish, dim3(grid_for(n, 256)), dim3(256), 0, st, c0, n, d_cols, mesh->d_trial, d_cb,
+                       d_poff, d_pcnt, d_o3, d_h4);
+    e = hipGetLastError();
+    c0 += n;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) return stb_fail(ctx, STB_E_DEVICE, "double layer failed: %s", hipGetErrorString(e));
+  return STB_OK;
+}
+
 // Double-layer potential with device inputs and output on the context stream.
 static stb_status dl_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p, const double* d_v,
                           int64_t np, const double* d_pts, double* d_out) {
@@ -180,9 +383,7 @@ static stb_status dl_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p
     cleanup();
     return stb_fail(ctx, STB_E_NO_MEMORY, "double-layer candidates");
   }
-  if (nnz > 0)
-    hipLaunchKernelGGL(k_dl_hats, dim3(grid_for(nnz, 256)), dim3(256), 0, ctx->stream, nnz, d_rowof,
-                       d_cols, mesh->d_trial, mesh->d_fang, mesh->d_nsign, d_pts, ctx->d_gl, p.n_g, d_h);
+  if ((s = dl_split(ctx, mesh, p, nnz, d_rowof, d_cols, d_pts, d_h))) { cleanup(); return s; }
   hipLaunchKernelGGL(k_dl_point_sum, dim3(grid_for(np * 64, 256)), dim3(256), 0, ctx->stream, np, d_rowptr,
                      d_cols, mesh->d_tet, d_v, d_h, d_out);
   hipError_t e = hipGetLastError();
