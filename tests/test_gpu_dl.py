@@ -245,6 +245,49 @@ def test_direct_method_exterior(stb, ctx):
     assert ferrs[1] < 0.5 * ferrs[0] and ferrs[1] < 0.03
 
 
+def test_device_pointer_path(stb, ctx):
+    """stb_potential_D_dev with device-resident vertex values, points and
+    output equals the host entry point bit for bit."""
+    import torch
+    mesh = inputs.icosphere_mesh(level=1, S=4, T=3.0, jitter=0.2, seed=7)
+    m = _mesh(stb, ctx, mesh)
+    v = inputs.density_normal(mesh.nv, seed=21)
+    pts = inputs.shell_points(200, mesh.T, rmin=1.1, rmax=2.5, seed=22)
+    dev = torch.device("cuda:0")
+    vd = torch.from_numpy(v).to(dev)
+    pd = torch.from_numpy(pts).to(dev)
+    ud = torch.empty(pts.shape[0], dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    stb.potential_D_dev(ctx, m, vd.data_ptr(), pts.shape[0], pd.data_ptr(), ud.data_ptr())
+    torch.cuda.synchronize()
+    u = stb.potential_D(ctx, m, v, pts)
+    assert np.array_equal(ud.cpu().numpy(), u)
+    assert np.count_nonzero(u) > 100
+
+
+def test_projection_arguments(stb, ctx):
+    mesh = inputs.icosphere_mesh(level=0, S=2, T=2.0, jitter=0.0, seed=0)
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    P, W = stb.l2_points(ctx, m)
+    assert P.shape == (mesh.nt, 27, 4) and abs(W.sum() - _area_times_T(mesh)) <= 1e-12 * W.sum()
+    with pytest.raises(ValueError):
+        stb.project_V1(ctx, m, np.ones(mesh.nt * 27 - 1), mesh.nv)
+    g = np.ones(mesh.nt * 27)
+    g[5] = np.nan
+    with pytest.raises(stb.StbError):
+        stb.project_V1(ctx, m, g, mesh.nv)
+    c, its = stb.project_V1(ctx, m, np.zeros(mesh.nt * 27), mesh.nv)
+    assert its == 0 and np.all(c == 0.0)
+
+
+def _area_times_T(mesh):
+    """|Sigma| = T x the area of the spatial triangles (extruded meshes)."""
+    X = mesh.vtx[:, 1:]
+    tri = X[np.asarray(mesh.tri)]
+    area = 0.5 * np.linalg.norm(np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0]), axis=1).sum()
+    return area * mesh.T
+
+
 def test_arguments(stb, ctx):
     mesh = inputs.icosphere_mesh(level=0, S=2, T=2.0, jitter=0.0, seed=0)
     m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
