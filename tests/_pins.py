@@ -310,3 +310,22 @@ def point_source_wave_dn(p, n):
     g = (-_pulse_dt(tr) / (4.0 * np.pi * r) - _pulse(tr) / (4.0 * np.pi * r * r))[..., None] \
         * (y - POINT_SOURCE) / r[..., None]
     return np.einsum("...i,...i->...", g, n)
+
+
+# --- a panel whose cone sections have no breakpoints ---------------------
+
+BIG_TET = np.array([[0.0, -10.0, -10.0, 0.0], [0.0, 10.0, -10.0, 0.0], [0.0, 0.0, 10.0, 0.0],
+                    [20.0, 0.0, 0.0, 0.0]])
+BIG_TET_POINTS = [[2.0, 0.0, 0.0, 0.5], [3.0, 0.5, -0.3, 0.8], [1.5, 1.0, 1.0, -0.3]]
+
+
+def big_tet_closed_form(x4, vv, sgn=1.0):
+    """No breakpoints: the whole cone section r in [|d|, t - tmin] lies in
+    the panel, so the gamma term integrates to 0 over the circle and
+    D v = (d_n / 2) v(t, p) (1/|d| - 1/(t - tmin))."""
+    t, x, y, z = x4
+    M = np.column_stack([np.ones(4), BIG_TET[:, :3]])          # v = c0 + c_t t + c_x x + c_y y
+    c = np.linalg.solve(M, np.asarray(vv, float))
+    alpha = c[0] + c[1] * t + c[2] * x + c[3] * y
+    dn = sgn * z
+    return 0.5 * dn * alpha * (1.0 / abs(z) - 1.0 / (t - BIG_TET[:, 0].min()))

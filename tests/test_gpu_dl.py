@@ -11,7 +11,8 @@ import pytest
 
 import oracle
 from paper_2103_16841_amd import inputs
-from _pins import point_source_wave, point_source_wave_dn
+from _pins import (point_source_wave, point_source_wave_dn, BIG_TET, BIG_TET_POINTS,
+                   big_tet_closed_form)
 
 pytestmark = pytest.mark.gpu
 
@@ -286,6 +287,20 @@ def _area_times_T(mesh):
     tri = X[np.asarray(mesh.tri)]
     area = 0.5 * np.linalg.norm(np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0]), axis=1).sum()
     return area * mesh.T
+
+
+def test_periodic_case_one_panel(stb, ctx):
+    """A one-panel mesh whose cone sections have no breakpoints (the
+    periodic rule of both stages) against the closed form."""
+    m = stb.Mesh(ctx, BIG_TET, np.array([[0, 1, 2, 3]]))
+    vv = np.array([1.0, 2.0, 3.0, 4.0])
+    for sgn in (1.0, -1.0):
+        m.set_normals(np.array([[0.0, 0.0, sgn]]))
+        u = stb.potential_D(ctx, m, vv, np.array(BIG_TET_POINTS))
+        ref = np.array([big_tet_closed_form(x, vv, sgn) for x in BIG_TET_POINTS])
+        assert np.all(np.abs(u - ref) <= 1e-13)
+        h = stb.inner_values_D(ctx, m, np.array(BIG_TET_POINTS), np.zeros(3, dtype=np.int32))
+        assert np.all(np.abs(h @ vv - ref) <= 1e-13)
 
 
 def test_arguments(stb, ctx):

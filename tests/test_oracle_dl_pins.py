@@ -26,7 +26,8 @@ from scipy import integrate
 
 import oracle
 from paper_2103_16841_amd import inputs
-from _pins import _ray_interval, point_source_wave, point_source_wave_dn
+from _pins import (_ray_interval, point_source_wave, point_source_wave_dn, BIG_TET,
+                   BIG_TET_POINTS, big_tet_closed_form)
 
 FOUR_PI = 4.0 * math.pi
 
@@ -308,3 +309,12 @@ def test_projection_keeps_integrals_of_quadratics():
             mids = [0.5 * (T[a] + T[b]) for a in range(4) for b in range(a + 1, 4)]
             ig += vol * (-sum(f(T[a]) for a in range(4)) / 20.0 + sum(f(m) for m in mids) / 5.0)
         assert abs(iq - ig) <= 1e-12 * max(1.0, abs(ig))
+
+
+@pytest.mark.parametrize("x4", BIG_TET_POINTS)
+def test_periodic_case_closed_form(x4):
+    assert oracle.breakpoints(x4, BIG_TET).size == 0
+    vv = [1.0, 2.0, 3.0, 4.0]
+    for sgn in (1.0, -1.0):
+        got = oracle.inner_dl(x4, BIG_TET, [0.0, 0.0, sgn], vv)
+        assert abs(got - big_tet_closed_form(x4, vv, sgn)) <= 1e-13
