@@ -66,6 +66,8 @@
 #define ORC_TANG_TOL 0.05
 #define ORC_VTX_TOL 0.05
 #define ORC_FLAT_TOL 1e-10
+/* edge parameters within this of [0, 1] count as on the closed edge */
+#define ORC_EDGE_TOL 1e-10
 
 enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_PANEL = -2 };
 
@@ -382,7 +384,11 @@ static int breakpoints(const orc_panel* P, const orc_apex* A, double* bp) {
       }
       for (int m = 0; m < nl; ++m) {
         double l = lam[m];
-        if (!(l >= 0.0 && l <= 1.0)) continue;
+        /* closed edges: a cone through a vertex gives roots at 0 or 1 up to
+         * rounding, which are kept (at the vertex) */
+        if (!(l >= -ORC_EDGE_TOL && l <= 1.0 + ORC_EDGE_TOL)) continue;
+        if (l < 0.0) l = 0.0;
+        if (l > 1.0) l = 1.0;
         if (a0 + a1 * l < 0.0) continue;   /* forward cone branch */
         double ou = bu + l * du, ov = bv + l * dv;
         /* a crossing at the foot point itself (s = 0) has no angle */

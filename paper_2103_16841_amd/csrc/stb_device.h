@@ -37,6 +37,7 @@ constexpr int kMaxNg = 64;        // Gauss nodes per phi piece
 constexpr double kTangHint = 0.05;
 constexpr double kVtxHint = 0.05;
 constexpr double kFlatTol = 1e-10;
+constexpr double kEdgeTol = 1e-10;   // edge parameters this close to [0, 1] are on the edge
 constexpr double kLitDead = 1e-12;
 
 // Per-panel record used when the panel is the trial panel (64 doubles).
@@ -612,8 +613,11 @@ STB_HD inline int breakpoints_t(const TrialRec& T, const FaceAng& FA, const Apex
       double lam[2];
       int nl = roots2(qa, qb, qc, lam);
       for (int m = 0; m < nl; ++m) {
+        // closed edges: a cone through a vertex gives roots at 0 or 1 up to
+        // rounding, which are kept (clamped onto the vertex)
         double l = lam[m];
-        if (!(l >= 0.0 && l <= 1.0)) continue;
+        if (!(l >= -kEdgeTol && l <= 1.0 + kEdgeTol)) continue;
+        l = fmin(fmax(l, 0.0), 1.0);
         if (a0 + a1 * l < 0.0) continue;
         double ou = bu + l * du, ov = bv + l * dv;
         if (ou * ou + ov * ov <= 1e-20 * sc * sc) continue;

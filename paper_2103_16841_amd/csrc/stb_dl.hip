@@ -83,6 +83,10 @@ __global__ void k_dl_pairs(int64_t k, const TrialRec* __restrict__ trial,
 // empty-piece test and the Gauss nodes, three sums per piece.  Stage 3 (one
 // lane per candidate): its pieces summed in order, then the four hats.
 constexpr int kDlCb = 8;   // C[4], d2, wlo, whi, factor
+// Pieces narrower than this take the full evaluation at every node: their
+// nodes sit within rounding of the breakpoints, where the gap structure is
+// ambiguous.
+constexpr double kDlRecipeMinH = 1e-8;
 
 __global__ __launch_bounds__(256) void k_dl_split(int64_t c0, int64_t n, const int32_t* __restrict__ rowof,
                                                   const int32_t* __restrict__ cols,
@@ -160,7 +164,9 @@ __global__ __launch_bounds__(256) void k_dl_split(int64_t c0, int64_t n, const i
 
 // Stage 2: one lane per piece.  A trapezoid half (ph < 0) takes its n_g
 // nodes of the periodic rule; a Gauss piece is tested at its midpoint and
-// quarter points first.
+// quarter points first, and that test's recipe (the endpoint formulas of at
+// most two gaps) gives every node its gaps from two faces per gap instead of
+// the four-face sweep; without a recipe, the full evaluation (dl_eval).
 __global__ __launch_bounds__(256) void k_dl_piece_nodes(int64_t npc, int64_t c0, const double* __restrict__ pa,
                                                         const double* __restrict__ ph,
                                                         const int32_t* __restrict__ pc,
@@ -195,15 +201,59 @@ __global__ __launch_bounds__(256) void k_dl_piece_nodes(int64_t npc, int64_t c0,
     const double ht = kTwoPi / (2 * ng);
     for (int g = 0; g < ng; ++g) node((a * ng + g) * ht, ht);
   } else {
-    bool ne = L_at(L, a + 0.5 * H) != 0.0;
-    if (!ne) ne = L_at(L, a + 0.25 * H) != 0.0 || L_at(L, a + 0.75 * H) != 0.0;
-    if (ne)
+    // the empty-piece test also yields the piece's recipe (the gap
+    // structure at its midpoint, else at the first non-zero quarter point)
+    uint32_t rec = 0u;
+    double sn, cs;
+    sincos_small(a + 0.5 * H, &sn, &cs);
+    bool ne = L_eval_recipe(L, cs, sn, &rec) != 0.0;
+    if (!ne) {
+      sincos_small(a + 0.25 * H, &sn, &cs);
+      ne = L_eval_recipe(L, cs, sn, &rec) != 0.0;
+    }
+    if (!ne) {
+      sincos_small(a + 0.75 * H, &sn, &cs);
+      ne = L_eval_recipe(L, cs, sn, &rec) != 0.0;
+    }
+    const int ngap = recipe_gaps(rec);
+    if (ne && rec != 0u && H >= kDlRecipeMinH) {
+      // every node from the recipe's endpoint formulas only
+      Endpoint E[2 * kRecipeGaps];
+      for (int q = 0; q < 2 * ngap; ++q) {
+        const uint32_t id = (rec >> (8 * (q >> 1) + ((q & 1) ? 0 : 4))) & 15u;
+        const int f = id >= 2 ? (int)(id - 2) >> 1 : 0;
+        E[q].a = L.fa[f]; E[q].fb = L.fb[f]; E[q].fc = L.fc[f]; E[q].C = L.C[f];
+        E[q].cst = id < 2;
+        E[q].cval = id == 0 ? L.wlo : L.whi;
+        E[q].isb = id >= 2 && ((id - 2) & 1u);
+      }
+      for (int g = 0; g < ng; ++g) {
+        const double u = gl[g];
+        const double sm = u * u * (3.0 - 2.0 * u);
+        const double wt = H * (6.0 * u * (1.0 - u)) * gl[kMaxNg + g];
+        sincos_small(a + H * sm, &sn, &cs);
+        double sa = 0.0, sh = 0.0;
+        for (int q = 0; q < ngap; ++q) {
+          const double w0 = endpoint_value(E[2 * q], L.d2, L.wlo, L.whi, cs, sn);
+          const double w1 = endpoint_value(E[2 * q + 1], L.d2, L.wlo, L.whi, cs, sn);
+          if (w1 > w0) {
+            const double q0 = 1.0 / fma(w0, w0, L.d2), q1 = 1.0 / fma(w1, w1, L.d2);
+            sa += 2.0 * (w0 * q0 - w1 * q1);
+            sh += log(w1 / w0) + 2.0 * L.d2 * (q1 - q0);
+          }
+        }
+        ia += wt * sa;
+        ic += (wt * sh) * cs;
+        is += (wt * sh) * sn;
+      }
+    } else if (ne) {
       for (int g = 0; g < ng; ++g) {
         const double u = gl[g];
         const double sm = u * u * (3.0 - 2.0 * u);
         const double ds = 6.0 * u * (1.0 - u);
         node(a + H * sm, H * ds * gl[kMaxNg + g]);
       }
+    }
   }
   out3[3 * p] = ia;
   out3[3 * p + 1] = ic;

@@ -303,6 +303,29 @@ def test_periodic_case_one_panel(stb, ctx):
         assert np.all(np.abs(h @ vv - ref) <= 1e-13)
 
 
+def test_points_on_vertex_light_cones(stb, ctx):
+    """Points exactly on the light cones of mesh vertices (the cone passes
+    through a panel vertex: a breakpoint that only the closed-edge events
+    give), single and double layer against the oracle."""
+    mesh = inputs.icosphere_mesh(level=1, S=8, T=4.0, jitter=0.0, seed=0)
+    m = _mesh(stb, ctx, mesh)
+    rng = np.random.default_rng(31)
+    pts = []
+    for _ in range(60):
+        v = mesh.vtx[rng.integers(0, mesh.nv)]
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        r = rng.choice([0.5, 1.0, 1.5, 2.0])
+        pts.append([v[0] + r, *(v[1:] + r * d)])
+    pts.append([4.0, 0.2, -1.6, 0.0])
+    pts = np.array(pts)
+    w = inputs.density_normal(mesh.nt, seed=32)
+    v = inputs.density_normal(mesh.nv, seed=33)
+    _check(stb.potential_S(ctx, m, w, pts), oracle.potential(mesh.vtx, mesh.tets, w, pts), "single layer")
+    _check(stb.potential_D(ctx, m, v, pts),
+           oracle.potential_dl(mesh.vtx, mesh.tets, mesh.outward_normals(), v, pts), "double layer")
+
+
 def test_arguments(stb, ctx):
     mesh = inputs.icosphere_mesh(level=0, S=2, T=2.0, jitter=0.0, seed=0)
     m = stb.Mesh(ctx, mesh.vtx, mesh.tets)

@@ -318,3 +318,20 @@ def test_periodic_case_closed_form(x4):
     for sgn in (1.0, -1.0):
         got = oracle.inner_dl(x4, BIG_TET, [0.0, 0.0, sgn], vv)
         assert abs(got - big_tet_closed_form(x4, vv, sgn)) <= 1e-13
+
+
+def test_cone_through_a_vertex_breaks_there():
+    """A point on the light cone of a panel vertex: the cone meets the three
+    edges at that vertex, so the vertex's direction is a breakpoint (edge
+    events on the closed edges; the roots sit at 0 or 1 only up to
+    rounding)."""
+    mesh = inputs.icosphere_mesh(level=2, S=16, T=4.0, jitter=0.0, seed=0)
+    T = mesh.vtx[mesh.tets[3718]]
+    x4 = np.array([4.0, 0.2, -1.6, 0.0])
+    k = 2                                           # |x - y_2| = t - tau_2 = 2
+    assert abs(np.linalg.norm(x4[1:] - T[k, 1:]) - (x4[0] - T[k, 0])) <= 1e-15
+    o, e1, e2, n = oracle.panel_frame(T)
+    w = T[k, 1:] - x4[1:]
+    ang = math.atan2(w @ e2, w @ e1) % (2.0 * math.pi)
+    bp = oracle.breakpoints(x4, T)
+    assert np.min(np.abs(bp - ang)) <= 1e-12
