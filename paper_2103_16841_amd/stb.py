@@ -201,11 +201,11 @@ class Context:
 
 
 class Mesh:
-    def __init__(self, ctx, vtx, tets, _handle=None, _nt=None):
+    def __init__(self, ctx, vtx, tets, _handle=None, _nt=None, _nv=None):
         L = load()
         self.ctx = ctx
         if _handle is not None:
-            self.h, self.nt = _handle, _nt
+            self.h, self.nt, self.nv = _handle, _nt, _nv
             return
         vtx, pv = _d(vtx)
         tets = np.ascontiguousarray(tets, dtype=np.int32)
@@ -214,6 +214,7 @@ class Mesh:
                                tets.ctypes.data_as(_I32), ctypes.byref(h)), ctx.h)
         self.h = h
         self.nt = int(tets.shape[0])
+        self.nv = int(vtx.shape[0])
 
     @classmethod
     def from_device(cls, ctx, vtx_ptr, nv, tet_ptr, nt, stream=None):
@@ -221,7 +222,7 @@ class Mesh:
         h = _VP()
         _chk(load().stb_mesh_create_dev(ctx.h, nv, _VP(vtx_ptr), nt, _VP(tet_ptr),
                                         _VP(stream) if stream else None, ctypes.byref(h)), ctx.h)
-        return cls(ctx, None, None, _handle=h, _nt=int(nt))
+        return cls(ctx, None, None, _handle=h, _nt=int(nt), _nv=int(nv))
 
     def set_normals(self, nrm):
         """Outward spatial normals of the panels (nt x 3), for the double layer."""
@@ -436,8 +437,10 @@ def l2_points(ctx, mesh):
     return pts, w
 
 
-def project_V1(ctx, mesh, gq, nv):
-    """Vertex values of the L2 projection Q_h^1 g from g at the l2_points."""
+def project_V1(ctx, mesh, gq, nv=None):
+    """Vertex values of the L2 projection Q_h^1 g from g at the l2_points;
+    returns them and the CG steps taken."""
+    nv = mesh.nv if nv is None else nv
     gq, pg = _d(gq, (-1,))
     if gq.shape[0] != mesh.nt * L2_POINTS:
         raise ValueError("need g at the %d points of every panel" % L2_POINTS)
