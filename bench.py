@@ -9,7 +9,7 @@ One step = the whole path on the icosphere workload (radius 1, level 2,
   16-RHS FP32 matrix-core product, potential at 1,000 shell points.
 value = causal element-pairs assembled per second of step time.
 
-Prints one JSON line.  --gpus > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus > 1 is refused: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -390,8 +390,8 @@ def batch_main(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d refused); the multi-GPU "
-              "sharding is described in DESIGN.md, not built" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus %d refused); sharding across GPUs is "
+              "a design, not built" % args.gpus, file=sys.stderr)
         return 2
     if args.workload == "batch":
         return batch_main(args)

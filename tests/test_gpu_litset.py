@@ -1,5 +1,5 @@
 """Lit-set sizes of single points (the culling study of Sec. 3.3 / Exp. 1,
-on this build's own meshes): for a point x at time t = T, the lit set
+on synthetic icosphere meshes): for a point x at time t = T, the lit set
 Sigma_N(x) is the set of panels its backward light cone meets, a
 two-dimensional slice of the three-dimensional space-time boundary, so
 |Sigma_N(x)| grows like N^(2/3) under uniform refinement in space and time;
