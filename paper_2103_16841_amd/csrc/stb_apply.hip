@@ -15,27 +15,45 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // One wavefront per 16-row block.  MFMA 16x16x4 (FP32) operand layout:
 //   A: lane l holds A[l % 16][l / 16];  B: lane l holds B[l / 16][l % 16];
 //   D: lane l, register v holds D[4 (l / 16) + v][l % 16].
+// One workgroup (four wavefronts) per 16-row block: wavefront v takes the
+// block's quads v, v + 4, ... (two independent MFMA chains, even and odd
+// steps), and the four partial tiles are summed in LDS in a fixed order.
 __global__ __launch_bounds__(256) void k_bell_mfma(int64_t nblk, int64_t n,
                                                    const int64_t* __restrict__ bptr,
                                                    const int32_t* __restrict__ bcol,
                                                    const float* __restrict__ bval,
                                                    const float* __restrict__ w32,
                                                    double* __restrict__ y) {
-  int64_t blk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
-  if (blk >= nblk) return;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int64_t blk = blockIdx.x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kk = lane >> 4, jj = lane & 15;
-  for (int64_t q = bptr[blk]; q < bptr[blk + 1]; ++q) {
-    float a = bval[q * 64 + lane];
-    int32_t col = bcol[q * 4 + kk];
-    float b = col >= 0 ? w32[(int64_t)col * 16 + jj] : 0.f;
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  const int64_t q0 = bptr[blk], q1 = bptr[blk + 1];
+  int64_t q = q0 + wv;
+  for (; q + 4 < q1; q += 8) {
+    const float a0 = bval[q * 64 + lane], a1 = bval[(q + 4) * 64 + lane];
+    const int32_t c0 = bcol[q * 4 + kk], c1 = bcol[(q + 4) * 4 + kk];
+    const float b0 = c0 >= 0 ? w32[(int64_t)c0 * 16 + jj] : 0.f;
+    const float b1 = c1 >= 0 ? w32[(int64_t)c1 * 16 + jj] : 0.f;
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc1, 0, 0, 0);
   }
+  if (q < q1) {
+    const float a0 = bval[q * 64 + lane];
+    const int32_t c0 = bcol[q * 4 + kk];
+    const float b0 = c0 >= 0 ? w32[(int64_t)c0 * 16 + jj] : 0.f;
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc0, 0, 0, 0);
+  }
+  __shared__ float part[4][4][64];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) part[wv][v][lane] = acc0[v] + acc1[v];
+  __syncthreads();
+  if (wv != 0) return;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    int64_t row = blk * 16 + 4 * kk + v;
-    if (row < n) y[row * 16 + jj] = (double)acc[v];
+    const float t = ((part[0][v][lane] + part[1][v][lane]) + part[2][v][lane]) + part[3][v][lane];
+    const int64_t row = blk * 16 + 4 * kk + v;
+    if (row < n) y[row * 16 + jj] = (double)t;
   }
 }
 
@@ -94,6 +112,19 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_count(int64_t nblk, int64_t
   if (threadIdx.x == 0) nquad[b] = (red[0] + 3) / 4;
 }
 
+// Slots per pass of the value fill: a [kFillSlots][16] FP32 tile in LDS.
+constexpr int kFillSlots = 512;
+
+// The block's slot of column c (c must be marked).
+__device__ __forceinline__ int blk_slot(const uint32_t* bits, const int* pre, int32_t c) {
+  return pre[c >> 5] + __popc(bits[c >> 5] & ((1u << (c & 31)) - 1u));
+}
+
+// Fills one block: column of every slot, then the values.  Slot s of row r
+// sits at bval[q0 * 64 + 16 s + r] (the MFMA A-operand order), so a range
+// of slots is one contiguous range of bval: the values of kFillSlots slots
+// are scattered into an LDS tile (zero where a row lacks the column) and the
+// tile is copied out whole.
 __global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t n, int64_t ncols,
                                                           const int64_t* __restrict__ rowptr,
                                                           const int32_t* __restrict__ cols,
@@ -107,6 +138,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t 
   int nw = (int)((ncols + 31) / 32);
   uint32_t* bits = lds;
   int* pre = reinterpret_cast<int*>(lds + nw);
+  float* tile = reinterpret_cast<float*>(lds + 2 * nw);
+  __shared__ int64_t klo[16], khi[16];
   blk_mark(b, n, rowptr, cols, bits, nw);
   // exclusive prefix of popcounts over the words: per-thread chunk, then a
   // serial scan of the 256 chunk sums by thread 0
@@ -124,10 +157,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t 
   __syncthreads();
   for (int w = w0; w < w1; ++w) pre[w] += csum[threadIdx.x];
   __syncthreads();
-  int64_t q0 = qptr[b], nq = qptr[b + 1] - q0;
-  for (int64_t k = threadIdx.x; k < nq * 4; k += kBlkThreads) bcol[q0 * 4 + k] = -1;
-  for (int64_t k = threadIdx.x; k < nq * 64; k += kBlkThreads) bval[q0 * 64 + k] = 0.f;
-  __syncthreads();
+  const int64_t q0 = qptr[b], nq = qptr[b + 1] - q0;
+  const int nslot = nw > 0 ? pre[nw - 1] + __popc(bits[nw - 1]) : 0;
   for (int w = threadIdx.x; w < nw; w += kBlkThreads) {
     uint32_t m = bits[w];
     int slot = pre[w];
@@ -138,14 +169,34 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_fill(int64_t nblk, int64_t 
       m &= m - 1;
     }
   }
-  int64_t r1 = (b + 1) * 16 < n ? (b + 1) * 16 : n;
-  for (int64_t r = b * 16; r < r1; ++r)
-    for (int64_t k = rowptr[r] + threadIdx.x; k < rowptr[r + 1]; k += kBlkThreads) {
-      int32_t c = cols[k];
-      uint32_t below = bits[c >> 5] & ((1u << (c & 31)) - 1u);
-      int slot = pre[c >> 5] + __popc(below);
-      bval[(q0 + slot / 4) * 64 + (slot % 4) * 16 + (int)(r - b * 16)] = (float)vals[k];
+  for (int64_t k = nslot + threadIdx.x; k < nq * 4; k += kBlkThreads) bcol[q0 * 4 + k] = -1;
+  for (int64_t k = (int64_t)nslot * 16 + threadIdx.x; k < nq * 64; k += kBlkThreads) bval[q0 * 64 + k] = 0.f;
+  const int64_t rb = b * 16;
+  const int nr = (int)((rb + 16 < n ? rb + 16 : n) - rb);
+  for (int s0 = 0; s0 < nslot; s0 += kFillSlots) {
+    const int ns = nslot - s0 < kFillSlots ? nslot - s0 : kFillSlots;
+    for (int e = threadIdx.x; e < ns * 16; e += kBlkThreads) tile[e] = 0.f;
+    if ((int)threadIdx.x < 2 * nr) {
+      // the row's first entry with slot >= s0 (lanes 0..nr-1) or >= s0 + ns
+      // (lanes nr..2nr-1): slots increase along a row's sorted columns
+      const bool first = (int)threadIdx.x < nr;
+      const int rr = first ? (int)threadIdx.x : (int)threadIdx.x - nr;
+      const int target = first ? s0 : s0 + ns;
+      int64_t lo = rowptr[rb + rr], hi = rowptr[rb + rr + 1];
+      while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (blk_slot(bits, pre, cols[mid]) < target) lo = mid + 1; else hi = mid;
+      }
+      if (first) klo[rr] = lo; else khi[rr] = lo;
     }
+    __syncthreads();
+    for (int r = 0; r < nr; ++r)
+      for (int64_t k = klo[r] + threadIdx.x; k < khi[r]; k += kBlkThreads)
+        tile[(blk_slot(bits, pre, cols[k]) - s0) * 16 + r] = (float)vals[k];
+    __syncthreads();
+    for (int e = threadIdx.x; e < ns * 16; e += kBlkThreads) bval[q0 * 64 + (int64_t)s0 * 16 + e] = tile[e];
+    __syncthreads();
+  }
 }
 
 stb_status stb_build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st) {
@@ -168,7 +219,10 @@ stb_status stb_build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st) {
   HIPCHK(ctx, hipMemcpy(&nquad, M->d_bptr + nblk, sizeof(int64_t), hipMemcpyDeviceToHost));
   HIPCHK(ctx, dalloc(&M->d_bcol, (size_t)nquad * 4));
   HIPCHK(ctx, dalloc(&M->d_bval, (size_t)nquad * 64));
-  hipLaunchKernelGGL(k_blk_fill, dim3((unsigned)nblk), dim3(kBlkThreads), lds, st, nblk, n, ncols,
+  const size_t lds_fill = lds + sizeof(float) * 16 * kFillSlots;
+  HIPCHK(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blk_fill),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_fill));
+  hipLaunchKernelGGL(k_blk_fill, dim3((unsigned)nblk), dim3(kBlkThreads), lds_fill, st, nblk, n, ncols,
                      M->d_rowptr, M->d_cols, M->d_vals, M->d_bptr, M->d_bcol, M->d_bval);
   HIPCHK(ctx, hipGetLastError());
   M->nblk = nblk;
@@ -188,9 +242,8 @@ stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y,
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, w, w32);
   }
   if (M->nblk > 0) {
-    int64_t threads = M->nblk * 64;
-    hipLaunchKernelGGL(k_bell_mfma, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, M->nblk,
-                       M->n, M->d_bptr, M->d_bcol, M->d_bval, w32, y);
+    hipLaunchKernelGGL(k_bell_mfma, dim3((unsigned)M->nblk), dim3(256), 0, st, M->nblk, M->n, M->d_bptr,
+                       M->d_bcol, M->d_bval, w32, y);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
