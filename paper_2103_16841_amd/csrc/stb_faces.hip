@@ -131,13 +131,15 @@ __global__ void k_face_combine(int64_t nnz, int64_t r0, const int32_t* __restric
                                const int32_t* __restrict__ cols, const int32_t* __restrict__ pf,
                                const double* __restrict__ pw, int64_t f0, int64_t nfu,
                                const int64_t* __restrict__ frowptr,
-                               const int32_t* __restrict__ fcols, const double* __restrict__ S,
+                               const int32_t* __restrict__ fcols, const int32_t* __restrict__ prim,
+                               const int64_t* __restrict__ rowptr, const double* __restrict__ S,
                                const uint8_t* __restrict__ lit, double* __restrict__ vals,
                                unsigned long long* __restrict__ causal) {
   unsigned long long n = 0;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nnz;
        c += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = r0 + rowof[c];
+    const int32_t li = rowof[c];
+    const int64_t i = r0 + li;
     const int32_t j = cols[c];
     double acc = 0.0;
     bool any = false;
@@ -145,10 +147,14 @@ __global__ void k_face_combine(int64_t nnz, int64_t r0, const int32_t* __restric
       const int64_t lf = (int64_t)pf[4 * i + s] - f0;
       if (pf[4 * i + s] < 0 || lf < 0 || lf >= nfu) continue;
       int64_t lo = frowptr[lf], hi = frowptr[lf + 1];
-      while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (fcols[mid] < j) lo = mid + 1;
-        else hi = mid;
+      if (prim[lf] == li) {
+        lo += c - rowptr[li];   // the face's candidates are this row's, in order
+      } else {
+        while (lo < hi) {
+          const int64_t mid = lo + ((hi - lo) >> 1);
+          if (fcols[mid] < j) lo = mid + 1;
+          else hi = mid;
+        }
       }
       if (lo < frowptr[lf + 1] && fcols[lo] == j) {
         acc += pw[4 * i + s] * S[lo];
@@ -283,7 +289,8 @@ static void face_range(const stb_mesh* m, int64_t r0, int64_t r1, int64_t* f0, i
 // Face CSR of a unit (faces f0 .. f1, local rows): each face's row is its
 // primary panel's candidate row.
 static stb_status face_rows(stb_ctx* ctx, const FaceUnit& fu, int64_t f0, int64_t f1,
-                            int64_t** frowptr, int32_t** fcols, int32_t** frowof, int64_t* fnnz) {
+                            int64_t** frowptr, int32_t** fcols, int32_t** frowof, int32_t** fprim,
+                            int64_t* fnnz) {
   const int64_t nfu = f1 - f0;
   std::vector<int32_t> prim((size_t)std::max<int64_t>(nfu, 1), -1);
   for (int64_t i = fu.r0; i < fu.r1; ++i)
@@ -327,7 +334,8 @@ static stb_status face_rows(stb_ctx* ctx, const FaceUnit& fu, int64_t f0, int64_
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) s = stb_fail(ctx, STB_E_DEVICE, "face rows: %s", hipGetErrorString(e));
   }
-  dfree(d_prim);
+  if (s == STB_OK) *fprim = d_prim;   // kept for the combine (primary rows index directly)
+  else dfree(d_prim);
   dfree(d_cnt);
   return s;
 }
@@ -340,7 +348,7 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
   struct U {
     int64_t f0 = 0, f1 = 0, fnnz = 0, of = 0, op = 0, oc = 0;
     int64_t* frowptr = nullptr;
-    int32_t *fcols = nullptr, *frowof = nullptr;
+    int32_t *fcols = nullptr, *frowof = nullptr, *fprim = nullptr;
   };
   std::vector<U> u((size_t)nunit);
   TrialRec* trial_g = nullptr;
@@ -350,7 +358,7 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
   uint8_t* lit_g = nullptr;
   unsigned long long* d_causal = nullptr;
   auto cleanup = [&]() {
-    for (auto& x : u) { dfree(x.frowptr); dfree(x.fcols); dfree(x.frowof); }
+    for (auto& x : u) { dfree(x.frowptr); dfree(x.fcols); dfree(x.frowof); dfree(x.fprim); }
     dfree(trial_g); dfree(fang_g); dfree(apex_g); dfree(ones_g); dfree(S_g);
     dfree(apexn_g); dfree(rows_g); dfree(cols_g); dfree(lit_g); dfree(d_causal);
   };
@@ -361,7 +369,7 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
     U& x = u[(size_t)k];
     if ((s = stb_ensure_faces(ctx, fu.mesh, p.m_q))) { cleanup(); return s; }
     face_range(fu.mesh, fu.r0, fu.r1, &x.f0, &x.f1);
-    if ((s = face_rows(ctx, fu, x.f0, x.f1, &x.frowptr, &x.fcols, &x.frowof, &x.fnnz))) {
+    if ((s = face_rows(ctx, fu, x.f0, x.f1, &x.frowptr, &x.fcols, &x.frowof, &x.fprim, &x.fnnz))) {
       cleanup();
       return s;
     }
@@ -445,7 +453,7 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
     const int64_t blocks = std::min<int64_t>((fu.nnz + 255) / 256, (int64_t)std::max(ctx->ncu, 1) * 32);
     hipLaunchKernelGGL(k_face_combine, dim3((unsigned)blocks), dim3(256), 0, st, fu.nnz, fu.r0, fu.rowof,
                        fu.cols, fu.mesh->d_pf, fu.mesh->d_pw, x.f0, x.f1 - x.f0, x.frowptr, x.fcols,
-                       S_g + x.oc, lit_g + x.oc, fu.vals, d_causal + k);
+                       x.fprim, fu.rowptr, S_g + x.oc, lit_g + x.oc, fu.vals, d_causal + k);
     e = hipGetLastError();
     if (e != hipSuccess) break;
   }
