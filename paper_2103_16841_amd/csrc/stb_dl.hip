@@ -88,6 +88,23 @@ constexpr int kDlCb = 8;   // C[4], d2, wlo, whi, factor
 // ambiguous.
 constexpr double kDlRecipeMinH = 1e-8;
 
+// Breakpoint slots 0..23 of a lane in LDS (slot s of lane t at s * B + t),
+// the rare rest in private memory: the private lists of all resident lanes
+// would not stay in the caches.
+constexpr int kDlBpLds = 24;
+struct DlBp {
+  double* lds;
+  int stride;
+  double* spill;
+  __device__ __forceinline__ void put(int i, double v) {
+    if (i < kDlBpLds) lds[i * stride] = v;
+    else spill[i - kDlBpLds] = v;
+  }
+  __device__ __forceinline__ double get(int i) const {
+    return i < kDlBpLds ? lds[i * stride] : spill[i - kDlBpLds];
+  }
+};
+
 __global__ __launch_bounds__(256) void k_dl_split(int64_t c0, int64_t n, const int32_t* __restrict__ rowof,
                                                   const int32_t* __restrict__ cols,
                                                   const TrialRec* __restrict__ trial,
@@ -100,7 +117,9 @@ __global__ __launch_bounds__(256) void k_dl_split(int64_t c0, int64_t n, const i
                                                   unsigned long long* __restrict__ counter) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = k < n;
-  double bp[kMaxBp];
+  __shared__ double s_bp[kDlBpLds * 256];
+  double spill[kMaxBp - kDlBpLds];
+  DlBp bp{s_bp + threadIdx.x, (int)blockDim.x, spill};
   int nb = -1;   // -1: nothing to integrate; 0: periodic (two trapezoid halves)
   unsigned np = 0;
   Apex A;
@@ -124,13 +143,13 @@ __global__ __launch_bounds__(256) void k_dl_split(int64_t c0, int64_t n, const i
         o[5] = wlo;
         o[6] = whi;
         o[7] = nsign[j] * A.d / (4.0 * kPi);
-        nb = breakpoints(*T, fang[j], A, bp);
-        sort_bp(bp, nb);
+        nb = breakpoints_t(*T, fang[j], A, bp);
+        sort_bp_t(bp, nb);
         if (nb == 0) {
           np = 2;
         } else {
           for (int m = 0; m < nb; ++m) {
-            const double a = bp[m], e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
+            const double a = bp.get(m), e = (m + 1 < nb) ? bp.get(m + 1) : bp.get(0) + kTwoPi;
             if (e - a > 0.0 && !piece_misses(*T, A, a, e - a)) ++np;
           }
         }
@@ -156,7 +175,7 @@ __global__ __launch_bounds__(256) void k_dl_split(int64_t c0, int64_t n, const i
     return;
   }
   for (int m = 0; m < nb; ++m) {
-    const double a = bp[m], e = (m + 1 < nb) ? bp[m + 1] : bp[0] + kTwoPi;
+    const double a = bp.get(m), e = (m + 1 < nb) ? bp.get(m + 1) : bp.get(0) + kTwoPi;
     if (!(e - a > 0.0) || piece_misses(*T, A, a, e - a)) continue;
     pa[w] = a; ph[w] = e - a; pc[w] = (int32_t)k; ++w;
   }
