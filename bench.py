@@ -42,7 +42,7 @@ def node_flops(counts):
 # copy), average over the 18 assembly launch groups of one profiled run
 # (profiles/node_stage_icosphere_L2_S32.md).  Set to None whenever the node
 # kernels change until they are profiled again.
-K_NODES_TRAFFIC_BYTES = 1.487e10
+K_NODES_TRAFFIC_BYTES = 1.489e10
 
 def parse():
     ap = argparse.ArgumentParser()
