@@ -59,6 +59,8 @@ def lib():
         L.orc_entry.argtypes = [_D, _I32, i64, i64, c_int, c_int, _D, P(Stats)]
         L.orc_assemble_rows.argtypes = [i64, _D, i64, _I32, i64, _I64, c_int, c_int, _D,
                                         P(Stats)]
+        L.orc_assemble_rows_mag.argtypes = [i64, _D, i64, _I32, i64, _I64, c_int, c_int, _D, _D,
+                                            P(Stats)]
         L.orc_matvec_rows.argtypes = [i64, _D, i64, _I32, i64, _I64, c_int, c_int, _D, _D]
         L.orc_potential.argtypes = [i64, _D, i64, _I32, _D, i64, _D, c_int, _D]
         L.orc_lit.argtypes = [_D, _D, _D, _D]
@@ -152,17 +154,22 @@ def entry(vtx, tets, i, j, m_q=DEFAULT_MQ, n_g=DEFAULT_NG):
     return out.value
 
 
-def assemble_rows(vtx, tets, rows=None, m_q=DEFAULT_MQ, n_g=DEFAULT_NG, stats=None):
+def assemble_rows(vtx, tets, rows=None, m_q=DEFAULT_MQ, n_g=DEFAULT_NG, stats=None, mag=False):
+    """Rows of A (all columns).  mag=True: also the size of each entry's
+    outer-sum terms, sum_q |w_q I_q| (returns (A, M))."""
     vtx, pv = _d(vtx)
     tets, pt = _i32(tets)
     nt = tets.shape[0]
     rows = np.arange(nt) if rows is None else rows
     rows, pr = _i64(rows)
     out = np.zeros((rows.shape[0], nt))
+    M = np.zeros((rows.shape[0], nt)) if mag else None
     st = stats if stats is not None else Stats()
-    _check(lib().orc_assemble_rows(vtx.shape[0], pv, nt, pt, rows.shape[0], pr, m_q, n_g,
-                                   out.ctypes.data_as(_D), ctypes.byref(st)), "assemble_rows")
-    return out
+    _check(lib().orc_assemble_rows_mag(vtx.shape[0], pv, nt, pt, rows.shape[0], pr, m_q, n_g,
+                                       out.ctypes.data_as(_D),
+                                       M.ctypes.data_as(_D) if mag else None, ctypes.byref(st)),
+           "assemble_rows")
+    return (out, M) if mag else out
 
 
 def matvec_rows(vtx, tets, w, rows=None, m_q=DEFAULT_MQ, n_g=DEFAULT_NG):

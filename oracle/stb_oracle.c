@@ -815,9 +815,24 @@ static int check_mesh(int64_t nv, const double* vtx, int64_t nt, const int32_t* 
   return ORC_OK;
 }
 
-int orc_assemble_rows(int64_t nv, const double* vtx, int64_t nt, const int32_t* tets,
-                      int64_t nrows, const int64_t* rows, int m_q, int n_g, double* out,
-                      orc_stats* st) {
+/* Compensated running sum (Neumaier's variant of Kahan's: the rounding
+ * error of every addition is kept, whichever operand is larger, so a
+ * compensation is not lost when a large term follows small ones). */
+typedef struct { double s, c; } orc_csum;
+static void csum_add(orc_csum* a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+  else a->c += (x - t) + a->s;
+  a->s = t;
+}
+static double csum_value(const orc_csum* a) { return a->s + a->c; }
+
+/* Rows of A and, when mag is not NULL, the size of each entry's terms
+ * mag[r*nt + j] = sum_q |w_q I_q| (the outer sum of eq. int_bform before
+ * its top- and bottom-face terms cancel). */
+int orc_assemble_rows_mag(int64_t nv, const double* vtx, int64_t nt, const int32_t* tets,
+                          int64_t nrows, const int64_t* rows, int m_q, int n_g, double* out,
+                          double* mag, orc_stats* st) {
   int rc = check_mesh(nv, vtx, nt, tets);
   if (rc) return rc;
   if (n_g < 1 || n_g > ORC_MAX_NG || m_q < 1 || m_q > 16) return ORC_E_ARG;
@@ -839,12 +854,16 @@ int orc_assemble_rows(int64_t nv, const double* vtx, int64_t nt, const int32_t* 
     int np = orc_outer_points(tetc + 16 * i, m_q, pts, w);
     orc_stats ls = {0, 0, 0, 0};
     for (int64_t j = 0; j < nt; ++j) {
-      double s = 0.0;
+      double s = 0.0, a = 0.0;
       for (int q = 0; q < np; ++q) {
         double I = inner_panel(panels + j, tetc + 16 * j, pts + 4 * q, n_g, gx, gw, &ls);
-        if (I != 0.0) s += w[q] * I;
+        if (I != 0.0) {
+          s += w[q] * I;
+          a += fabs(w[q] * I);
+        }
       }
       out[r * nt + j] = s;
+      if (mag) mag[r * nt + j] = a;
     }
     s_eval += ls.n_eval; s_sub += ls.n_sub; s_bp += ls.n_bp; s_lit += ls.n_lit;
   }
@@ -853,6 +872,12 @@ int orc_assemble_rows(int64_t nv, const double* vtx, int64_t nt, const int32_t* 
   if (bad) return ORC_E_ARG;
   if (st) { st->n_eval += s_eval; st->n_sub += s_sub; st->n_bp += s_bp; st->n_lit += s_lit; }
   return ORC_OK;
+}
+
+int orc_assemble_rows(int64_t nv, const double* vtx, int64_t nt, const int32_t* tets,
+                      int64_t nrows, const int64_t* rows, int m_q, int n_g, double* out,
+                      orc_stats* st) {
+  return orc_assemble_rows_mag(nv, vtx, nt, tets, nrows, rows, m_q, n_g, out, NULL, st);
 }
 
 int orc_matvec_rows(int64_t nv, const double* vtx, int64_t nt, const int32_t* tets,
@@ -865,14 +890,9 @@ int orc_matvec_rows(int64_t nv, const double* vtx, int64_t nt, const int32_t* te
   for (int64_t r = 0; r < nrows; ++r) {
     rc = orc_assemble_rows(nv, vtx, nt, tets, 1, rows + r, m_q, n_g, A, NULL);
     if (rc) { free(A); return rc; }
-    double s = 0.0, comp = 0.0;     /* Kahan */
-    for (int64_t j = 0; j < nt; ++j) {
-      double yk = A[j] * w[j] - comp;
-      double tk = s + yk;
-      comp = (tk - s) - yk;
-      s = tk;
-    }
-    y[r] = s;
+    orc_csum acc = {0.0, 0.0};
+    for (int64_t j = 0; j < nt; ++j) csum_add(&acc, A[j] * w[j]);
+    y[r] = csum_value(&acc);
   }
   free(A);
   return ORC_OK;
@@ -893,16 +913,12 @@ int orc_potential(int64_t nv, const double* vtx, int64_t nt, const int32_t* tets
   orc_gauss_legendre01(n_g, gx, gw);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t p = 0; p < np; ++p) {
-    double s = 0.0, comp = 0.0;
+    orc_csum acc = {0.0, 0.0};
     for (int64_t j = 0; j < nt; ++j) {
       double I = inner_panel(panels + j, tetc + 16 * j, pts + 4 * p, n_g, gx, gw, NULL);
-      if (I == 0.0) continue;
-      double yk = w[j] * I - comp;
-      double tk = s + yk;
-      comp = (tk - s) - yk;
-      s = tk;
+      if (I != 0.0) csum_add(&acc, w[j] * I);
     }
-    out[p] = s;
+    out[p] = csum_value(&acc);
   }
   free(panels);
   free(tetc);
@@ -928,18 +944,14 @@ int orc_potential_dl(int64_t nv, const double* vtx, int64_t nt, const int32_t* t
   orc_gauss_legendre01(n_g, gx, gw);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t p = 0; p < np; ++p) {
-    double s = 0.0, comp = 0.0;
+    orc_csum acc = {0.0, 0.0};
     for (int64_t j = 0; j < nt; ++j) {
       double vv[4];
       for (int k = 0; k < 4; ++k) vv[k] = v[tets[4 * j + k]];
       double I = inner_panel_dl(panels + j, tetc + 16 * j, pts + 4 * p, sg[j], vv, n_g, gx, gw);
-      if (I == 0.0) continue;
-      double yk = I - comp;
-      double tk = s + yk;
-      comp = (tk - s) - yk;
-      s = tk;
+      if (I != 0.0) csum_add(&acc, I);
     }
-    out[p] = s;
+    out[p] = csum_value(&acc);
   }
   free(panels);
   free(tetc);

@@ -66,7 +66,15 @@ int orc_assemble_rows(int64_t nv, const double* vtx, int64_t nt,
                       const int32_t* tets, int64_t nrows, const int64_t* rows,
                       int m_q, int n_g, double* out, orc_stats* st);
 
-/* y[r] = sum_j A[rows[r]][j] w[j]  (compensated sum). */
+/* Same rows and, when mag is not NULL, mag[r*nt + j] = sum_q |w_q I_q|:
+ * the size of the outer-sum terms of entry (rows[r], j) of eq. int_bform,
+ * whose top- and bottom-face terms cancel in A itself. */
+int orc_assemble_rows_mag(int64_t nv, const double* vtx, int64_t nt,
+                          const int32_t* tets, int64_t nrows, const int64_t* rows,
+                          int m_q, int n_g, double* out, double* mag,
+                          orc_stats* st);
+
+/* y[r] = sum_j A[rows[r]][j] w[j]  (compensated sum, Neumaier). */
 int orc_matvec_rows(int64_t nv, const double* vtx, int64_t nt,
                     const int32_t* tets, int64_t nrows, const int64_t* rows,
                     int m_q, int n_g, const double* w, double* y);

@@ -16,11 +16,14 @@ def load_cube():
             if k[0] == "causal":
                 causal = int(k[1])
             elif k[0] == "entry":
-                ent.append((int(k[1]), int(k[2]), float(k[3])))
+                ent.append((int(k[1]), int(k[2]), float(k[3]), float(k[4])))
             elif k[0] == "matvec":
-                mv.append((int(k[1]), float(k[2])))
+                mv.append((int(k[1]), float(k[2]), float(k[3])))
     rows = np.array([e[0] for e in ent], dtype=np.int32)
     cols = np.array([e[1] for e in ent], dtype=np.int32)
     vals = np.array([e[2] for e in ent])
-    y = np.array([v for _, v in sorted(mv)])
-    return causal, rows, cols, vals, y
+    mags = np.array([e[3] for e in ent])
+    mv.sort()
+    y = np.array([v[1] for v in mv])
+    ybound = np.array([v[2] for v in mv])
+    return causal, rows, cols, vals, mags, y, ybound

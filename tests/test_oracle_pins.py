@@ -157,7 +157,11 @@ def _column(mesh, tri_index):
 @pytest.mark.parametrize("jitter", [0.0, 0.2])
 def test_static_limit_column_is_laplace(jitter):
     """If 0 < t - |x - y| < T on the whole triangle, the column's panels
-    together see the full triangle: sum_j V phi_j(x) = (1/4pi) int dA/|x-y|."""
+    together see the full triangle: sum_j V phi_j(x) = (1/4pi) int dA/|x-y|.
+    The bound is the phi-rule's own error at 48 nodes per piece (measured
+    at most 2e-15 on these cases; at 32 nodes it is still up to 5e-11, at
+    16 up to 9e-7): a dropped term, a wrong sign or a lost piece of one
+    panel shows up far above it."""
     mesh = inputs.icosphere_mesh(level=1, S=6, T=6.0, jitter=jitter, seed=11)
     TC = mesh.tet_coords()
     rng = np.random.default_rng(5)
@@ -169,9 +173,9 @@ def test_static_limit_column_is_laplace(jitter):
             x = cen * (1.0 + off) + 0.03 * rng.standard_normal(3)
             dmax = max(np.linalg.norm(x - v) for v in tri)
             x4 = np.concatenate([[dmax + 2.0], x])
-            s = sum(oracle.inner(x4, TC[j], n_g=32) for j in _column(mesh, b))
+            s = sum(oracle.inner(x4, TC[j], n_g=48) for j in _column(mesh, b))
             exact = triangle_laplace(x, tri) / FOUR_PI
-            assert abs(s - exact) <= 1e-10 * exact
+            assert abs(s - exact) <= 1e-13 * exact
 
 
 def test_triangle_laplace_formula_itself():
@@ -390,3 +394,96 @@ def test_sphere_surface_converges_to_half_integral():
         u = oracle.potential(m.vtx, m.tets, w, [np.concatenate([[t], x])])[0]
         errs.append(abs(u - exact))
     assert errs[2] < 1e-3 and errs[0] / errs[2] > 5.0
+
+
+# ------------------------------------------------------- products of rows
+
+def _exact_dot(a, w):
+    """sum_j fl(a_j w_j) in exact rational arithmetic, rounded once: the
+    products rounded as the oracle forms them, their sum exact."""
+    from fractions import Fraction
+    acc = Fraction(0)
+    for x in (a * w).tolist():
+        if x != 0.0:
+            acc += Fraction(x)
+    return float(acc)
+
+
+def test_matvec_rows_is_the_exact_product(cube, cube_A):
+    """orc_matvec_rows against the product of the oracle's own rows summed
+    in exact rational arithmetic (the rounded products A_ij w_j added
+    exactly, one rounding at the end), on the cube and on icosphere rows,
+    with densities chosen to
+    cancel: a wrong index, a dropped term or a broken compensation fails.
+    The compensated sum's bound is 2u |y| + 2 n u^2 sum_j |A_ij w_j|."""
+    u = 2.0 ** -53
+    rng = np.random.default_rng(21)
+    cases = []
+    w = rng.standard_normal(cube.nt)
+    cases.append((cube, np.arange(cube.nt), cube_A, w))
+    # heavy cancellation: w_j = s / A_ij on causal entries of row 40, so the
+    # terms are +-s (up to one rounding each) and sum to nearly zero
+    row = 40
+    a = cube_A[row]
+    w2 = np.zeros(cube.nt)
+    nz = np.flatnonzero(a)
+    sg = np.where(np.arange(nz.size) % 2 == 0, 1.0, -1.0)
+    w2[nz] = sg * 1e8 / a[nz]
+    cases.append((cube, np.array([row]), cube_A[[row]], w2))
+    ico = inputs.icosphere_mesh(level=1, S=6, T=3.0, jitter=0.2, seed=13)
+    rows = np.sort(rng.choice(ico.nt, 6, replace=False))
+    Ai = oracle.assemble_rows(ico.vtx, ico.tets, rows=rows)
+    cases.append((ico, rows, Ai, rng.standard_normal(ico.nt) * np.exp(rng.uniform(-20, 20, ico.nt))))
+    for mesh, rows, Arows, w in cases:
+        y = oracle.matvec_rows(mesh.vtx, mesh.tets, w, rows=rows)
+        for k in range(rows.size):
+            exact = _exact_dot(Arows[k], w)
+            absum = float(np.abs(Arows[k] * w).sum())
+            bound = 2.0 * u * abs(exact) + 2.0 * mesh.nt * u * u * absum
+            assert abs(y[k] - exact) <= bound, (rows[k], y[k], exact, bound)
+            # and plainly against numpy's product of the same row
+            assert abs(y[k] - float(Arows[k] @ w)) <= 64 * mesh.nt * u * absum
+
+
+def test_matvec_rows_compensation_matters(cube):
+    """Rows whose plain left-to-right sum loses everything: densities make
+    the terms 1e16, 1, -1e16, 1, ... (each up to one rounding), so the sum
+    is about the count of ones plus the terms' rounding residues.  A plain
+    sum, or a Kahan sum whose compensation is folded into the next large
+    term, keeps about one of the ones; the oracle's compensated sum must
+    match the exact rational value to 2u |sum| + 2 n u^2 sum |x|."""
+    u = 2.0 ** -53
+    for row in (100, 143):
+        A = oracle.assemble_rows(cube.vtx, cube.tets, rows=[row])[0]
+        nz = np.flatnonzero(A)
+        nz = nz[:(nz.size // 4) * 4]
+        w = np.zeros(cube.nt)
+        terms = np.array([1e16 if k % 4 == 0 else (-1e16 if k % 4 == 2 else 1.0)
+                          for k in range(nz.size)])
+        w[nz] = terms / A[nz]
+        prod = A * w
+        exact = _exact_dot(A, w)
+        plain = 0.0
+        for x in prod:
+            plain += x
+        y = oracle.matvec_rows(cube.vtx, cube.tets, w, rows=[row])[0]
+        absum = float(np.abs(prod).sum())
+        assert abs(plain - exact) > 4.0            # the plain sum is visibly wrong
+        assert abs(y - exact) <= 2 * u * abs(exact) + 2 * cube.nt * u * u * absum, (row, y, exact)
+
+
+def test_entry_magnitude_is_the_outer_terms(cube, cube_A):
+    """M_ij = sum_q |w_q I_q| from assemble_rows(mag=True) against the outer
+    rule's points and weights and single inner integrals, on sampled entries;
+    M >= |A| everywhere, and M = 0 exactly where A is."""
+    A, M = oracle.assemble_rows(cube.vtx, cube.tets, mag=True)
+    assert np.array_equal(A, cube_A)
+    assert np.all(M >= np.abs(A))
+    assert np.array_equal(M == 0.0, A == 0.0)
+    rng = np.random.default_rng(4)
+    TC = cube.tet_coords()
+    for i, j in zip(rng.integers(0, cube.nt, 12), rng.integers(0, cube.nt, 12)):
+        P, w = oracle.outer_points(TC[i])
+        terms = np.array([wq * oracle.inner(x, TC[j]) for x, wq in zip(P, w)])
+        assert abs(M[i, j] - np.abs(terms).sum()) <= 1e-15 * max(M[i, j], 1e-300)
+        assert abs(A[i, j] - terms.sum()) <= 1e-15 * max(M[i, j], 1e-300)
