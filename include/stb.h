@@ -66,9 +66,10 @@ typedef enum { STB_FP64 = 0, STB_MIXED = 1 } stb_precision;
  * FP32 about the middle of the pair's admissible range, with Kahan-summed
  * FP32 node sums; lit test, breakpoints, empty-piece tests, angles and the
  * quadratics' coefficients stay FP64.  Every entry carries a first-order
- * bound of its FP32 error; entries whose bound exceeds 5e-6 of their size
- * are recomputed with FP64 nodes, which keeps entries within 1e-6 relative
- * of the FP64 assembly. */
+ * bound of its FP32 error; entries whose bound exceeds 3e-6 of their size
+ * are recomputed with FP64 nodes (the bound overestimates the error by at
+ * least a factor 3 on every entry measured), which keeps entries within
+ * 1e-6 relative of the FP64 assembly. */
 typedef struct {
   int32_t m_q;
   int32_t n_g;
@@ -259,10 +260,13 @@ stb_status stb_set_tuning(stb_ctx* ctx, const int32_t* cfg16);
  * slots, each with its own stream and workspace, take requests in arrival
  * order; a request starts as soon as a slot is free and its device
  * footprint (inputs, outputs and, for a potential, its exact candidate
- * arrays) fits hbm_budget_bytes beside the requests in flight (0: half of
- * the free device memory).  Requests in different slots run concurrently
- * on the device.  Results do not depend on what else is in flight.
- * stb_server_submit and stb_server_wait are thread-safe. */
+ * arrays and the growth of its slot's pipeline workspace) fits
+ * hbm_budget_bytes beside the requests in flight and the workspaces the
+ * slots hold (0: half of the free device memory).  Requests in different
+ * slots run concurrently on the device.  Results do not depend on what else
+ * is in flight.  stb_server_submit, stb_server_wait and
+ * stb_server_add_mesh are thread-safe (a mesh may be added while requests
+ * run). */
 typedef struct stb_server stb_server;
 
 typedef enum { STB_REQ_MATVEC16 = 0, STB_REQ_POTENTIAL = 1 } stb_request_kind;
@@ -308,6 +312,15 @@ void stb_server_destroy(stb_server* server);
  * eq. int_bform with g in place of V w). */
 stb_status stb_outer_points(stb_ctx* ctx, const stb_mesh* mesh, int32_t m_q, double* pts,
                             double* weights, int32_t* counts);
+
+/* Right-hand side of the discrete indirect system (eq. df_ind) for boundary
+ * data g: b[i] = b(g, phi_i) = sum_q w_iq g(x_iq), the outer rule of
+ * eq. int_bform with g in place of V w (the same integration by parts).
+ * g: the data at the outer points of stb_outer_points for the same m_q,
+ * [nt][4 m_q^2] (host; entries past a panel's count are ignored, must be
+ * finite); b: nt doubles (host, caller-allocated).  Sums in q order. */
+stb_status stb_outer_rhs(stb_ctx* ctx, const stb_mesh* mesh, int32_t m_q, const double* g,
+                         double* b);
 
 /* Solves the discrete indirect system A x = b (eq. df_ind) for the square
  * matrix of one whole mesh by restarted GMRES(restart) on the device: FP64

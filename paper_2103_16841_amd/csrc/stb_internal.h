@@ -92,7 +92,7 @@ struct stb_mat {
 
 
 stb_status stb_fail(stb_ctx* ctx, stb_status s, const char* fmt, ...);
-extern "C" stb_status stb_mirror_host(stb_mat* M);
+
 
 #define HIPCHK(ctx, call)                                                                    \
   do {                                                                                       \

@@ -254,71 +254,6 @@ __global__ void k_inner_values(int64_t k, const TrialRec* __restrict__ trial,
   out[m] = inner_serial(trial[panel[m]], x4, ng, gl, gl + kMaxNg, nullptr);
 }
 
-// Diagnostics of one (point, panel) pair: sorted breakpoints, then per
-// piece its L at the midpoint and its node sum.  out: [0] = nb, [1..nb] =
-// breakpoints, then 2 nb values.
-__global__ void k_debug_pair(const TrialRec* __restrict__ trial, const double* __restrict__ x,
-                             int32_t panel, const double* __restrict__ gl, int ng,
-                             double* __restrict__ out) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  const TrialRec& T = trial[panel];
-  double x4[4] = {x[0], x[1], x[2], x[3]};
-  Apex A;
-  apex_of(T, x4, A);
-  double bp[kMaxBp];
-  FaceAng FA;
-  face_angles(T, FA);
-  int nb = breakpoints(T, FA, A, bp);
-  sort_bp(bp, nb);
-  out[0] = nb;
-  for (int k = 0; k < nb; ++k) out[1 + k] = bp[k];
-  double wlo = 0.0, whi = 0.0;
-  bool ok = w_range(T, A, wlo, whi);
-  ComboL cb;
-  for (int k = 0; k < 4; ++k) {
-    cb.C[k] = A.C[k]; cb.fa[k] = T.fa[k]; cb.fb[k] = T.fb[k]; cb.fc[k] = T.fc[k];
-  }
-  cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
-  for (int k = 0; k < nb; ++k) {
-    double a = bp[k];
-    double b = (k + 1 < nb) ? bp[k + 1] : bp[0] + kTwoPi;
-    double H = b - a;
-    double acc = 0.0;
-    if (ok && H > 0.0)
-      for (int g = 0; g < ng; ++g) acc += node_value(cb, a, H, gl[g], gl[kMaxNg + g]);
-    out[1 + nb + 2 * k] = ok ? L_at(cb, a + 0.5 * H) : -1.0;
-    out[2 + nb + 2 * k] = acc;
-  }
-  // then the panel record and the apex data
-  const double* tr = reinterpret_cast<const double*>(&T);
-  for (int k = 0; k < 64; ++k) out[1 + 3 * kMaxBp + k] = tr[k];
-  out[1 + 3 * kMaxBp + 64] = A.t;
-  out[1 + 3 * kMaxBp + 65] = A.pu;
-  out[1 + 3 * kMaxBp + 66] = A.pv;
-  out[1 + 3 * kMaxBp + 67] = A.d;
-  for (int k = 0; k < 4; ++k) out[1 + 3 * kMaxBp + 68 + k] = A.C[k];
-}
-
-extern "C" stb_status stb_debug_pair(stb_ctx* ctx, const stb_mesh* mesh, int32_t ng,
-                                     const double* x4, int32_t panel, double* out /*1+3*kMaxBp+72*/) {
-  if (!ctx || !mesh || !x4 || !out || panel < 0 || panel >= mesh->nt || ng < 2 || ng > kMaxNg)
-    return stb_fail(ctx, STB_E_INVALID_ARG, "bad arguments");
-  HIPCHK(ctx, hipSetDevice(ctx->device));
-  stb_status s = stb_ensure_gl(ctx, ng);
-  if (s) return s;
-  double *d_x = nullptr, *d_out = nullptr;
-  HIPCHK(ctx, dalloc(&d_x, 4));
-  HIPCHK(ctx, dalloc(&d_out, 1 + 3 * kMaxBp + 72));
-  HIPCHK(ctx, hipMemcpy(d_x, x4, 32, hipMemcpyHostToDevice));
-  hipLaunchKernelGGL(k_debug_pair, dim3(1), dim3(64), 0, ctx->stream, mesh->d_trial, d_x, panel,
-                     ctx->d_gl, ng, d_out);
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  HIPCHK(ctx, hipMemcpy(out, d_out, 8 * (1 + 3 * kMaxBp + 72), hipMemcpyDeviceToHost));
-  dfree(d_x);
-  dfree(d_out);
-  return STB_OK;
-}
-
 // Potential per evaluation point: ordered sum over its candidates of
 // w_j I_j (exact zeros skipped).
 // u(p) = sum_j w_j I_pj over the point's candidates: one wavefront per
@@ -512,6 +447,24 @@ stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const st
                        nrows, d_rows, m->nt, m->d_trial, *d_rowptr, *d_cols, *d_rowof);
     HIPCHK(ctx, hipGetLastError());
   }
+  return STB_OK;
+}
+
+// Host copy of a matrix store (for stb_mat_get / stb_mat_to_dense).
+static stb_status mirror_host(stb_mat* M) {
+  if (M->host_valid) return STB_OK;
+  stb_ctx* ctx = M->ctx;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  M->h_rowptr.resize((size_t)M->n + 1);
+  M->h_cols.resize((size_t)M->nnz);
+  M->h_vals.resize((size_t)M->nnz);
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(M->h_rowptr.data(), M->d_rowptr, 8 * (M->n + 1), hipMemcpyDeviceToHost));
+  if (M->nnz) {
+    HIPCHK(ctx, hipMemcpy(M->h_cols.data(), M->d_cols, 4 * M->nnz, hipMemcpyDeviceToHost));
+    HIPCHK(ctx, hipMemcpy(M->h_vals.data(), M->d_vals, 8 * M->nnz, hipMemcpyDeviceToHost));
+  }
+  M->host_valid = true;
   return STB_OK;
 }
 
@@ -771,27 +724,10 @@ stb_status stb_mat_info(const stb_mat* M, int64_t* n, int64_t* nc, int64_t* nsto
   return STB_OK;
 }
 
-stb_status stb_mirror_host(stb_mat* M) {
-  if (M->host_valid) return STB_OK;
-  stb_ctx* ctx = M->ctx;
-  HIPCHK(ctx, hipSetDevice(ctx->device));
-  M->h_rowptr.resize((size_t)M->n + 1);
-  M->h_cols.resize((size_t)M->nnz);
-  M->h_vals.resize((size_t)M->nnz);
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  HIPCHK(ctx, hipMemcpy(M->h_rowptr.data(), M->d_rowptr, 8 * (M->n + 1), hipMemcpyDeviceToHost));
-  if (M->nnz) {
-    HIPCHK(ctx, hipMemcpy(M->h_cols.data(), M->d_cols, 4 * M->nnz, hipMemcpyDeviceToHost));
-    HIPCHK(ctx, hipMemcpy(M->h_vals.data(), M->d_vals, 8 * M->nnz, hipMemcpyDeviceToHost));
-  }
-  M->host_valid = true;
-  return STB_OK;
-}
-
 stb_status stb_mat_to_dense(const stb_mat* Mc, double* out) {
   if (!Mc || !out) return fail(Mc ? Mc->ctx : nullptr, STB_E_INVALID_ARG, "NULL argument");
   stb_mat* M = const_cast<stb_mat*>(Mc);
-  stb_status s = stb_mirror_host(M);
+  stb_status s = mirror_host(M);
   if (s) return s;
   std::memset(out, 0, sizeof(double) * (size_t)M->n * (size_t)M->n);
   for (int64_t i = 0; i < M->n; ++i)
@@ -803,7 +739,7 @@ stb_status stb_mat_get(const stb_mat* Mc, int64_t k, const int32_t* row, const i
   if (!Mc || (k > 0 && (!row || !col || !out)) || k < 0)
     return fail(Mc ? Mc->ctx : nullptr, STB_E_INVALID_ARG, "bad arguments");
   stb_mat* M = const_cast<stb_mat*>(Mc);
-  stb_status s = stb_mirror_host(M);
+  stb_status s = mirror_host(M);
   if (s) return s;
   for (int64_t m = 0; m < k; ++m) {
     if (row[m] < 0 || row[m] >= M->n || col[m] < 0 || col[m] >= M->n)

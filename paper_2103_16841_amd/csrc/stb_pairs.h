@@ -31,5 +31,9 @@ struct PairJob {
 // tested and pieces.  Synchronises the context stream.
 stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long work[4]);
 void stb_free_workspace(stb_ctx* ctx);
+// Device bytes of ctx's pipeline workspace now, and after a run over nnz
+// candidates with maxq apexes each (the workspace only grows).
+int64_t stb_pairs_ws_held(const stb_ctx* ctx);
+int64_t stb_pairs_ws_need(const stb_ctx* ctx, int64_t nnz, int maxq);
 // Chooses the launch shape of every stage on a sample job (see stb_pairs.hip).
 stb_status stb_tune_pairs(stb_ctx* ctx, const PairJob& sample);

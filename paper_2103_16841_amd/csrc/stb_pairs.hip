@@ -672,11 +672,11 @@ __global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo) {
 // one of the entry.  Each far I_q carries a first-order bound of its FP32
 // rounding error (from the node evaluations, see L_eval_far); when
 // sum_q |w_q| bound_q exceeds kMixedTol |entry|, the candidate is flagged for
-// recomputation with FP64 nodes.  The bound overestimates the error (the
-// largest error/bound ratio seen is 0.32, and the terms' errors partly
-// cancel), so kMixedTol = 5e-6 keeps the entries within 1e-6 of the FP64
-// values.  Causal pairs are counted when check = 0.
-constexpr double kMixedTol = 5e-6;
+// recomputation with FP64 nodes.  The largest error/bound ratio seen is
+// 0.32, so kMixedTol = 3e-6 keeps every kept FP32 entry within
+// 0.32 * 3e-6 < 1e-6 of its FP64 value without relying on the terms' errors
+// cancelling.  Causal pairs are counted when check = 0.
+constexpr double kMixedTol = 3e-6;
 
 // Segment of global candidate cg: last s with off[s] <= cg.
 __device__ __forceinline__ int seg_of(const int64_t* off, int nseg, int64_t cg) {
@@ -819,6 +819,33 @@ static size_t ws_bytes(int64_t cc, int64_t cb, int64_t cp) {
   return b;
 }
 
+// List capacities a run over nnz candidates with maxq apexes each asks for.
+static void ws_want(int64_t nnz, int maxq, int64_t* cc, int64_t* cb, int64_t* cp) {
+  const int64_t kCandMax = (int64_t)1 << 24;
+  *cc = std::min<int64_t>(nnz, kCandMax);
+  *cb = std::min<int64_t>(*cc * maxq, (int64_t)1 << 26);
+  *cp = std::min<int64_t>(*cb * 8, (int64_t)1 << 28);
+}
+
+int64_t stb_pairs_ws_held(const stb_ctx* ctx) {
+  const PairWorkspace* w = ctx->ws;
+  return w ? (int64_t)ws_bytes(w->cap_cand, w->cap_combo, w->cap_piece) : 0;
+}
+
+int64_t stb_pairs_ws_need(const stb_ctx* ctx, int64_t nnz, int maxq) {
+  if (nnz <= 0) return stb_pairs_ws_held(ctx);
+  int64_t cc, cb, cp;
+  ws_want(nnz, maxq, &cc, &cb, &cp);
+  const PairWorkspace* w = ctx->ws;
+  if (w) {
+    if (w->cap_cand >= cc && w->cap_combo >= cb && w->cap_piece >= cp) return stb_pairs_ws_held(ctx);
+    cc = std::max(cc, w->cap_cand);
+    cb = std::max(cb, w->cap_combo);
+    cp = std::max(cp, w->cap_piece);
+  }
+  return (int64_t)ws_bytes(cc, cb, cp);
+}
+
 static stb_status ensure_workspace(stb_ctx* ctx, int64_t want_cand, int64_t want_combo,
                                    int64_t want_piece) {
   PairWorkspace* w = ctx->ws;
@@ -888,10 +915,8 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
   if (job.nnz <= 0) return STB_OK;
   // sizes: the whole candidate set when it is small, else chunks of up to
   // 2^24 candidates (the combo key holds 24 bits of candidate index)
-  const int64_t kCandMax = (int64_t)1 << 24;
-  const int64_t want_cand = std::min<int64_t>(job.nnz, kCandMax);
-  const int64_t want_combo = std::min<int64_t>(want_cand * job.maxq, (int64_t)1 << 26);
-  const int64_t want_piece = std::min<int64_t>(want_combo * 8, (int64_t)1 << 28);
+  int64_t want_cand, want_combo, want_piece;
+  ws_want(job.nnz, job.maxq, &want_cand, &want_combo, &want_piece);
   stb_status s = ensure_workspace(ctx, want_cand, want_combo, want_piece);
   if (s) return s;
   PairWorkspace* w = ctx->ws;

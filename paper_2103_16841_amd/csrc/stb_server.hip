@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "stb_internal.h"
+#include "stb_pairs.h"
 
 using namespace stb;
 
@@ -46,10 +47,14 @@ struct ServedMesh {
 
 struct stb_server {
   stb_ctx* ctx = nullptr;
+  // in_use: the requests in flight plus every slot's pipeline workspace
+  // (held between requests; slot_ws[k] of it belongs to slot k)
   int64_t budget = 0, in_use = 0;
   std::vector<stb_ctx*> slots;
+  std::vector<int64_t> slot_ws;
   std::vector<std::thread> workers;
-  std::vector<ServedMesh> meshes;
+  // a deque: registering a mesh never moves the ones already served
+  std::deque<ServedMesh> meshes;
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_mem;
   std::deque<uint64_t> queue;
@@ -71,8 +76,7 @@ int64_t potential_bytes(int64_t nt, int64_t np, int64_t nnz) {
   return nt * 8 + np * (32 + 8 + 64 + 8) + nnz * (4 + 4 + 8);
 }
 
-stb_status run_request(stb_server* S, stb_ctx* c, const stb_request& r, std::string* err) {
-  const ServedMesh& sm = S->meshes[(size_t)r.mesh];
+stb_status run_request(stb_ctx* c, const ServedMesh& sm, const stb_request& r, std::string* err) {
   hipStream_t st = c->stream;
   stb_status s = STB_OK;
   if (r.kind == STB_REQ_MATVEC16) {
@@ -117,9 +121,12 @@ stb_status run_request(stb_server* S, stb_ctx* c, const stb_request& r, std::str
   return s;
 }
 
-// Exact footprint of a request (a potential needs its cull count).
-stb_status footprint(stb_server* S, stb_ctx* c, const stb_request& r, int64_t* bytes) {
-  const ServedMesh& sm = S->meshes[(size_t)r.mesh];
+// Exact footprint of a request (a potential needs its cull count): its own
+// buffers (*bytes) and the size slot context c's pipeline workspace will
+// have after it (*ws).
+stb_status footprint(stb_ctx* c, const ServedMesh& sm, const stb_request& r, int64_t* bytes,
+                     int64_t* ws) {
+  *ws = stb_pairs_ws_held(c);
   if (r.kind == STB_REQ_MATVEC16) {
     *bytes = matvec_bytes(sm.mat);
     return STB_OK;
@@ -143,6 +150,7 @@ stb_status footprint(stb_server* S, stb_ctx* c, const stb_request& r, int64_t* b
   dfree(box);
   dfree(pts);
   *bytes = potential_bytes(sm.mesh->nt, r.np, nnz);
+  *ws = stb_pairs_ws_need(c, nnz, 1);
   return s;
 }
 
@@ -152,6 +160,7 @@ void worker(stb_server* S, int slot) {
   for (;;) {
     uint64_t id = 0;
     stb_request r;
+    ServedMesh sm{};
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] { return S->stopping || !S->queue.empty(); });
@@ -159,24 +168,44 @@ void worker(stb_server* S, int slot) {
       id = S->queue.front();
       S->queue.pop_front();
       r = S->tickets[id].req;
+      sm = S->meshes[(size_t)r.mesh];   // a copy, taken under the lock
     }
     std::string err;
-    int64_t bytes = 0;
-    stb_status s = footprint(S, c, r, &bytes);
-    if (s == STB_OK && bytes > S->budget)
-      s = stb_fail(c, STB_E_NO_MEMORY, "request needs %lld bytes, budget %lld", (long long)bytes,
-                   (long long)S->budget);
+    int64_t bytes = 0, ws = 0;
+    stb_status s = footprint(c, sm, r, &bytes, &ws);
+    int64_t grow = 0;
     if (s == STB_OK) {
-      // admission by HBM footprint
+      std::lock_guard<std::mutex> lk(S->mu);
+      grow = std::max<int64_t>(0, ws - S->slot_ws[(size_t)slot]);
+      // the other slots' workspaces stay held while this request runs
+      const int64_t others = [&] {
+        int64_t o = 0;
+        for (size_t k = 0; k < S->slot_ws.size(); ++k)
+          if ((int)k != slot) o += S->slot_ws[k];
+        return o;
+      }();
+      if (bytes + ws + others > S->budget)
+        s = stb_fail(c, STB_E_NO_MEMORY, "request needs %lld bytes (+%lld of workspace), budget %lld",
+                     (long long)bytes, (long long)ws, (long long)S->budget);
+    }
+    if (s == STB_OK) {
+      // admission by HBM footprint: the request's buffers and the growth of
+      // this slot's workspace beside everything already in use
       {
         std::unique_lock<std::mutex> lk(S->mu);
-        S->cv_mem.wait(lk, [&] { return S->in_use + bytes <= S->budget; });
-        S->in_use += bytes;
+        S->cv_mem.wait(lk, [&] { return S->in_use + bytes + grow <= S->budget; });
+        S->in_use += bytes + grow;
+        S->slot_ws[(size_t)slot] += grow;
       }
-      s = run_request(S, c, r, &err);
+      s = run_request(c, sm, r, &err);
       {
         std::lock_guard<std::mutex> lk(S->mu);
         S->in_use -= bytes;
+        // the workspace the slot really holds now (it may have been sized down
+        // to fit the device)
+        const int64_t held = stb_pairs_ws_held(c);
+        S->in_use += held - S->slot_ws[(size_t)slot];
+        S->slot_ws[(size_t)slot] = held;
       }
       S->cv_mem.notify_all();
     } else {
@@ -227,6 +256,7 @@ stb_status stb_server_create(stb_ctx* ctx, int64_t hbm_budget_bytes, int32_t nsl
     }
     c->tuned = ctx->tuned;
     S->slots.push_back(c);
+    S->slot_ws.push_back(0);
   }
   for (int k = 0; k < nslots; ++k) S->workers.emplace_back(worker, S, k);
   *out = S;

@@ -58,9 +58,54 @@ __global__ void k_residual(int64_t n, const double* __restrict__ b, double* __re
   if (i < n) r[i] = b[i] - r[i];
 }
 
+// b_i = sum_{q < n_i} w_iq g_iq, q ascending: the right-hand side of the
+// indirect system from data g at panel i's outer points (eq. df_ind with the
+// outer rule of eq. int_bform).
+__global__ void k_outer_rhs(int64_t nt, int maxq, const double* __restrict__ w,
+                            const int32_t* __restrict__ nq, const double* __restrict__ g,
+                            double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  double s = 0.0;
+  for (int q = 0; q < nq[i]; ++q) s = fma(w[i * maxq + q], g[i * maxq + q], s);
+  b[i] = s;
+}
+
 }  // namespace
 
 extern "C" {
+
+stb_status stb_outer_rhs(stb_ctx* ctx, const stb_mesh* mesh_c, int32_t m_q, const double* g,
+                         double* b) {
+  if (!ctx || !mesh_c || !g || !b) return stb_fail(ctx, STB_E_INVALID_ARG, "NULL argument");
+  if (m_q < 1 || m_q > 4) return stb_fail(ctx, STB_E_INVALID_ARG, "m_q must be in [1,4], got %d", m_q);
+  stb_mesh* mesh = const_cast<stb_mesh*>(mesh_c);
+  if (mesh->ctx != ctx) return stb_fail(ctx, STB_E_INVALID_ARG, "mesh belongs to another context");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  stb_status s = stb_ensure_outer(ctx, mesh, m_q);
+  if (s) return s;
+  const int64_t nt = mesh->nt, maxq = mesh->maxq;
+  if (nt == 0) return STB_OK;
+  for (int64_t k = 0; k < nt * maxq; ++k)
+    if (!std::isfinite(g[k])) return stb_fail(ctx, STB_E_INVALID_ARG, "non-finite data at outer point %lld", (long long)k);
+  double *d_g = nullptr, *d_b = nullptr;
+  if (dalloc(&d_g, (size_t)(nt * maxq)) != hipSuccess || dalloc(&d_b, (size_t)nt) != hipSuccess) {
+    dfree(d_g); dfree(d_b);
+    return stb_fail(ctx, STB_E_NO_MEMORY, "right-hand side buffers");
+  }
+  hipError_t e = hipMemcpyAsync(d_g, g, sizeof(double) * nt * maxq, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_outer_rhs, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, ctx->stream, nt,
+                       (int)maxq, mesh->d_ow, mesh->d_onq, d_g, d_b);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(b, d_b, sizeof(double) * nt, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(d_g);
+  dfree(d_b);
+  if (e != hipSuccess) return stb_fail(ctx, STB_E_DEVICE, "right-hand side: %s", hipGetErrorString(e));
+  return STB_OK;
+}
 
 stb_status stb_outer_points(stb_ctx* ctx, const stb_mesh* mesh_c, int32_t m_q, double* pts,
                             double* weights, int32_t* counts) {

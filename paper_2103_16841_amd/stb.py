@@ -22,7 +22,7 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
            "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
            "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_last_path_counts", "stb_mesh_create_dev",
-           "stb_outer_points", "stb_solve_gmres", "stb_mesh_set_normals", "stb_potential_D",
+           "stb_outer_points", "stb_outer_rhs", "stb_solve_gmres", "stb_mesh_set_normals", "stb_potential_D",
            "stb_potential_D_dev", "stb_inner_values_D", "stb_dl_energetic",
            "stb_l2_points", "stb_project_V1",
            "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble", "stb_autotune",
@@ -104,6 +104,7 @@ def load():
     L.stb_last_work.argtypes = [_VP, _I64]
     L.stb_last_path_counts.argtypes = [_VP, _I64]
     L.stb_outer_points.argtypes = [_VP, _VP, i32, _D, _D, _I32]
+    L.stb_outer_rhs.argtypes = [_VP, _VP, i32, _D, _D]
     L.stb_solve_gmres.argtypes = [_VP, _VP, _D, _D, i32, i32, ctypes.c_double, _I32,
                                   ctypes.POINTER(ctypes.c_double)]
     L.stb_last_kernel_times.argtypes = [_VP, _D, _I64, _I64]
@@ -150,6 +151,25 @@ def _d(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a, a.ctypes.data_as(_D)
+
+
+def _vec(a, n, what):
+    """A contiguous FP64 vector of exactly n entries (ValueError otherwise):
+    the library reads and writes as many as the mesh or matrix says."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 1 or a.shape[0] != n:
+        raise ValueError("%s must have shape (%d,), got %s" % (what, n, a.shape))
+    return a, a.ctypes.data_as(_D)
+
+
+def _points(pts):
+    """Points as a contiguous (k, 4) FP64 array (t, x, y, z)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    if pts.ndim == 1 and pts.size == 0:
+        pts = pts.reshape(0, 4)
+    if pts.ndim != 2 or pts.shape[1] != 4:
+        raise ValueError("points must have shape (k, 4) (t, x, y, z), got %s" % (pts.shape,))
+    return pts, pts.ctypes.data_as(_D)
 
 
 class Context:
@@ -209,6 +229,9 @@ class Mesh:
             return
         vtx, pv = _d(vtx)
         tets = np.ascontiguousarray(tets, dtype=np.int32)
+        if vtx.ndim != 2 or vtx.shape[1] != 4 or tets.ndim != 2 or tets.shape[1] != 4:
+            raise ValueError("vertices must be (nv, 4) (t, x, y, z) and panels (nt, 4), got %s, %s"
+                             % (vtx.shape, tets.shape))
         h = _VP()
         _chk(L.stb_mesh_create(ctx.h, vtx.shape[0], pv, tets.shape[0],
                                tets.ctypes.data_as(_I32), ctypes.byref(h)), ctx.h)
@@ -287,6 +310,8 @@ class Matrix:
 
     def apply(self, w):
         w = np.ascontiguousarray(w, dtype=np.float64)
+        if w.ndim not in (1, 2) or w.shape[0] != self.n or (w.ndim == 2 and w.shape[1] < 1):
+            raise ValueError("w must have shape (%d,) or (%d, nrhs), got %s" % (self.n, self.n, w.shape))
         nrhs = 1 if w.ndim == 1 else w.shape[1]
         y = np.zeros_like(w)
         _chk(load().stb_apply(self.ctx.h, self.h, nrhs, w.ctypes.data_as(_D),
@@ -345,8 +370,8 @@ def assemble_V(ctx, mesh, params=None):
 
 def potential_S(ctx, mesh, w, pts, params=None):
     p = params if params is not None else default_params()
-    w, pw = _d(w)
-    pts, pp = _d(pts, (-1, 4))
+    w, pw = _vec(w, mesh.nt, "w")
+    pts, pp = _points(pts)
     out = np.zeros(pts.shape[0])
     _chk(load().stb_potential_S(ctx.h, mesh.h, ctypes.byref(p), pw, pts.shape[0], pp,
                                 out.ctypes.data_as(_D)), ctx.h)
@@ -367,17 +392,32 @@ def outer_points(ctx, mesh, m_q=3):
 
 def energetic_rhs(ctx, mesh, g, m_q=3):
     """b_i = sum_q w_iq g(x_q): the right-hand side of the indirect system
-    for boundary data g (a function of an array [k][4] of points (t,x,y,z))."""
+    for boundary data g (a function of an array [k][4] of points (t,x,y,z)).
+    The caller's g is sampled at the outer points; the sum runs in the
+    library (stb_outer_rhs)."""
     pts, w, n = outer_points(ctx, mesh, m_q)
-    vals = np.asarray(g(pts.reshape(-1, 4)), dtype=np.float64).reshape(w.shape)
-    return (w * vals).sum(axis=1)
+    vals = np.asarray(g(pts.reshape(-1, 4)), dtype=np.float64)
+    if vals.shape != (pts.shape[0] * pts.shape[1],):
+        raise ValueError("g must return one value per point")
+    return outer_rhs(ctx, mesh, vals.reshape(w.shape), m_q)
+
+
+def outer_rhs(ctx, mesh, gq, m_q=3):
+    """b_i = sum_q w_iq gq[i, q] for data gq at the outer points [nt][4 m_q^2]."""
+    gq = np.ascontiguousarray(gq, dtype=np.float64)
+    if gq.shape != (mesh.nt, 4 * m_q * m_q):
+        raise ValueError("gq must be [%d, %d]" % (mesh.nt, 4 * m_q * m_q))
+    b = np.zeros(mesh.nt)
+    _chk(load().stb_outer_rhs(ctx.h, mesh.h, m_q, gq.ctypes.data_as(_D), b.ctypes.data_as(_D)),
+         ctx.h)
+    return b
 
 
 def solve_gmres(ctx, A, b, x0=None, restart=100, maxit=2000, rtol=1e-10):
     """x with A x = b by restarted GMRES on the device; returns (x, products,
     relative residual)."""
-    b, pb = _d(b)
-    x = np.zeros(b.shape[0]) if x0 is None else np.array(x0, dtype=np.float64)
+    b, pb = _vec(b, A.n, "b")
+    x = np.zeros(A.n) if x0 is None else _vec(np.array(x0, dtype=np.float64), A.n, "x0")[0]
     it = ctypes.c_int32(0)
     rr = ctypes.c_double(0.0)
     _chk(load().stb_solve_gmres(ctx.h, A.h, pb, x.ctypes.data_as(_D), restart, maxit, rtol,
@@ -388,8 +428,10 @@ def solve_gmres(ctx, A, b, x0=None, restart=100, maxit=2000, rtol=1e-10):
 def inner_values(ctx, mesh, pts, panels, params=None):
     """V phi_panel (pt) for each (point, panel) pair."""
     p = params if params is not None else default_params()
-    pts, pp = _d(pts, (-1, 4))
+    pts, pp = _points(pts)
     panels = np.ascontiguousarray(panels, dtype=np.int32)
+    if panels.ndim != 1 or panels.shape[0] != pts.shape[0]:
+        raise ValueError("one panel index per point")
     out = np.zeros(pts.shape[0])
     _chk(load().stb_inner_values(ctx.h, mesh.h, ctypes.byref(p), pts.shape[0], pp,
                                  panels.ctypes.data_as(_I32), out.ctypes.data_as(_D)), ctx.h)
@@ -400,8 +442,8 @@ def potential_D(ctx, mesh, v, pts, params=None):
     """Retarded double-layer potential of the V_h^1 density with vertex
     values v at points (t,x,y,z); the mesh needs its outward normals."""
     p = params if params is not None else default_params()
-    v, pv = _d(v)
-    pts, pp = _d(pts, (-1, 4))
+    v, pv = _vec(v, mesh.nv, "v (vertex values)")
+    pts, pp = _points(pts)
     out = np.zeros(pts.shape[0])
     _chk(load().stb_potential_D(ctx.h, mesh.h, ctypes.byref(p), pv, pts.shape[0], pp,
                                 out.ctypes.data_as(_D)), ctx.h)
@@ -419,7 +461,7 @@ def dl_energetic(ctx, mesh, v, c_id=0.0, params=None):
     """c_id b_I(v, phi_i) + b_K(v, phi_i) for every test panel (outer rule of
     eq. int_bform); c_id = 1/2: the interior direct method's right-hand side."""
     p = params if params is not None else default_params()
-    v, pv = _d(v)
+    v, pv = _vec(v, mesh.nv, "v (vertex values)")
     out = np.zeros(mesh.nt)
     _chk(load().stb_dl_energetic(ctx.h, mesh.h, ctypes.byref(p), pv, float(c_id),
                                  out.ctypes.data_as(_D)), ctx.h)
@@ -454,8 +496,10 @@ def inner_values_D(ctx, mesh, pts, panels, params=None):
     """Double-layer potentials of the 4 hat functions of each panel at each
     point: [k, 4], column q for the panel's q-th vertex."""
     p = params if params is not None else default_params()
-    pts, pp = _d(pts, (-1, 4))
+    pts, pp = _points(pts)
     panels = np.ascontiguousarray(panels, dtype=np.int32)
+    if panels.ndim != 1 or panels.shape[0] != pts.shape[0]:
+        raise ValueError("one panel index per point")
     out = np.zeros((pts.shape[0], 4))
     _chk(load().stb_inner_values_D(ctx.h, mesh.h, ctypes.byref(p), pts.shape[0], pp,
                                    panels.ctypes.data_as(_I32), out.ctypes.data_as(_D)), ctx.h)
@@ -497,13 +541,21 @@ class Server:
 
     def submit_matvec(self, mesh_id, W):
         W = np.ascontiguousarray(W, dtype=np.float64)
+        n = self._sizes.get(mesh_id)
+        if n is None:
+            raise ValueError("unknown mesh id %r" % (mesh_id,))
+        if W.shape != (n, 16):
+            raise ValueError("W must have shape (%d, 16), got %s" % (n, W.shape))
         out = np.empty_like(W)
         req = Request(STB_REQ_MATVEC16, mesh_id, 0, W.ctypes.data, None, out.ctypes.data)
         return self._submit(req, (W, out))
 
     def submit_potential(self, mesh_id, w, pts):
-        w = np.ascontiguousarray(w, dtype=np.float64)
-        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 4)
+        n = self._sizes.get(mesh_id)
+        if n is None:
+            raise ValueError("unknown mesh id %r" % (mesh_id,))
+        w, _ = _vec(w, n, "w")
+        pts, _ = _points(pts)
         out = np.empty(pts.shape[0])
         req = Request(STB_REQ_POTENTIAL, mesh_id, pts.shape[0], w.ctypes.data, pts.ctypes.data,
                       out.ctypes.data)

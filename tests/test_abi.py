@@ -46,3 +46,80 @@ def test_null_arguments_are_rejected():
     assert L.stb_ctx_create(0, None) == 1
     assert L.stb_mat_info(None, None, None, None, None) == 1
     assert L.stb_mat_to_dense(None, None) == 1
+
+
+def _exported_stb_symbols():
+    """Names of the stb_* functions the library exports (defined, global)."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", stb_build.LIB], stdout=subprocess.PIPE,
+                         text=True, check=True).stdout
+    names = set()
+    for line in out.splitlines():
+        parts = line.split()
+        if len(parts) == 3 and parts[1] in ("T", "W") and re.fullmatch(r"stb_[A-Za-z0-9_]+", parts[2]):
+            names.add(parts[2])
+    return sorted(names)
+
+
+def test_library_exports_nothing_undeclared():
+    """Every exported stb_* function is declared in include/stb.h: no debug
+    or internal entry point leaks into the product library's interface."""
+    if not os.path.exists(stb_build.LIB):
+        pytest.fail("libstb.so not built")
+    extra = sorted(set(_exported_stb_symbols()) - set(_declared()))
+    assert not extra, extra
+
+
+def test_binding_rejects_misshaped_arrays():
+    """The binding checks array shapes before a pointer reaches the library
+    (which reads and writes as many values as the mesh or matrix says)."""
+    import numpy as np
+    from paper_2103_16841_amd import stb
+
+    class FakeMesh:
+        nt, nv, h = 10, 8, None
+
+    class FakeCtx:
+        h = None
+
+    m, c = FakeMesh(), FakeCtx()
+    with pytest.raises(ValueError):
+        stb.potential_S(c, m, np.zeros(9), np.zeros((3, 4)))
+    with pytest.raises(ValueError):
+        stb.potential_S(c, m, np.zeros(10), np.zeros((3, 3)))
+    with pytest.raises(ValueError):
+        stb.potential_D(c, m, np.zeros(10), np.zeros((3, 4)))
+    with pytest.raises(ValueError):
+        stb.dl_energetic(c, m, np.zeros(7))
+    with pytest.raises(ValueError):
+        stb.inner_values(c, m, np.zeros((3, 4)), np.zeros(2, dtype=np.int32))
+    with pytest.raises(ValueError):
+        stb.outer_rhs(c, m, np.zeros((10, 35)))
+    with pytest.raises(ValueError):
+        stb.Mesh(c, np.zeros((4, 3)), np.zeros((1, 4), dtype=np.int32))
+
+    class FakeMatrix(stb.Matrix):
+        def __init__(self):
+            self.n, self.ctx, self.h = 10, c, None
+
+    with pytest.raises(ValueError):
+        FakeMatrix().apply(np.zeros(11))
+    with pytest.raises(ValueError):
+        FakeMatrix().apply(np.zeros((9, 16)))
+    with pytest.raises(ValueError):
+        stb.solve_gmres(c, FakeMatrix(), np.zeros(9))
+
+    class FakeServer(stb.Server):
+        def __init__(self):
+            self._sizes = {0: 10}
+            self.h = None
+
+    S = FakeServer()
+    with pytest.raises(ValueError):
+        S.submit_matvec(0, np.zeros((10, 8)))
+    with pytest.raises(ValueError):
+        S.submit_matvec(1, np.zeros((10, 16)))
+    with pytest.raises(ValueError):
+        S.submit_potential(0, np.zeros(9), np.zeros((5, 4)))
+    with pytest.raises(ValueError):
+        S.submit_potential(0, np.zeros(10), np.zeros(5))
