@@ -3,9 +3,10 @@
 The batched results must equal the per-mesh assemblies bit for bit (the
 pipeline's sums keep a fixed order, independent of how candidates are
 grouped), and the small meshes of the batch are checked against the FP64
-oracle to the per-entry parity bound of tests/_tol.py.  The mix follows the batched workload (icospheres of random
-level and slab count, jittered, seed 3) at reduced sizes: levels 0-1 and
-2-8 slabs, so that the oracle can check it in seconds.
+oracle to the per-entry parity bound of tests/_tol.py.  The mix follows
+the batched workload (icospheres of random level and slab count, jittered,
+seed 3) at reduced sizes: levels 0-1 and 2-8 slabs, so that the oracle can
+check it in seconds.
 """
 import numpy as np
 import pytest
@@ -15,7 +16,7 @@ from paper_2103_16841_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-from _tol import assert_entries
+from _tol import assert_entries, oracle_rows
 
 
 @pytest.fixture(scope="module")
@@ -66,9 +67,9 @@ def test_batch_small_meshes_vs_oracle(stb, ctx, mix):
     mats = stb.batch_assemble(ctx, meshes)
     for m, M in zip(small, mats):
         print("case:", m.name, flush=True)
-        ref, mag = oracle.assemble_rows(m.vtx, m.tets, mag=True)
+        ref, mag, pert = oracle_rows(m.vtx, m.tets)
         D = M.to_dense()
-        assert_entries(D, ref, mag, what=m.name)
+        assert_entries(D, ref, mag, pert, what=m.name)
         assert np.array_equal(D != 0.0, ref != 0.0)
         assert M.n_causal == np.count_nonzero(ref)
 

@@ -18,7 +18,7 @@ from paper_2103_16841_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-from _tol import MTOL, RTOL, assert_entries_mixed, rel_err_entries, row_bound
+from _tol import MTOL, assert_entries_mixed, oracle_rows, rel_err_entries, row_bound
 
 
 @pytest.fixture(scope="module")
@@ -43,13 +43,8 @@ def cube():
 
 
 @pytest.fixture(scope="module")
-def cube_AM(cube):
-    return oracle.assemble_rows(cube.vtx, cube.tets, mag=True)
-
-
-@pytest.fixture(scope="module")
-def cube_ref(cube_AM):
-    return cube_AM[0]
+def cube_AMP(cube):
+    return oracle_rows(cube.vtx, cube.tets)
 
 
 def _mixed(stb, ctx, mesh, eta=None):
@@ -60,8 +55,8 @@ def _mixed(stb, ctx, mesh, eta=None):
 
 
 @pytest.mark.parametrize("eta", [None, 0.0])
-def test_cube_10000_entries_and_matvec(stb, ctx, cube, cube_AM, eta):
-    cube_ref, cube_M = cube_AM
+def test_cube_10000_entries_and_matvec(stb, ctx, cube, cube_AMP, eta):
+    cube_ref, cube_M, cube_P = cube_AMP
     print("case: cube mixed eta", eta, flush=True)
     _, A, kt = _mixed(stb, ctx, cube, eta)
     n = cube.nt
@@ -69,7 +64,7 @@ def test_cube_10000_entries_and_matvec(stb, ctx, cube, cube_AM, eta):
     rows, cols = (flat // n).astype(np.int32), (flat % n).astype(np.int32)
     got = A.get(rows, cols)
     ref = cube_ref[rows, cols]
-    assert_entries_mixed(got, ref, cube_M[rows, cols], what="cube mixed")
+    assert_entries_mixed(got, ref, cube_M[rows, cols], cube_P[rows, cols], what="cube mixed")
     print("max relative error %.3e" % rel_err_entries(got, ref), flush=True)
     assert np.array_equal(got != 0.0, ref != 0.0)
     assert A.n_causal == np.count_nonzero(cube_ref)
@@ -77,7 +72,7 @@ def test_cube_10000_entries_and_matvec(stb, ctx, cube, cube_AM, eta):
     w = inputs.density_time(cube, lambda t: np.sin(np.pi * t / 2) ** 2)
     y = A.apply(w)
     yo = cube_ref @ w
-    rs = MTOL * (np.abs(cube_ref) @ np.abs(w)) + RTOL * row_bound(cube_M, w)
+    rs = MTOL * (np.abs(cube_ref) @ np.abs(w)) + row_bound(cube_M, w, cube_P)
     assert np.all(np.abs(y - yo) <= rs)
     if eta == 0.0:
         assert kt["nodes_fp32"][2] > 0, kt
@@ -88,10 +83,10 @@ def test_cube_10000_entries_and_matvec(stb, ctx, cube, cube_AM, eta):
 def test_small_icospheres_full(stb, ctx, L, S, T, jit, eta):
     mesh = inputs.icosphere_mesh(level=L, S=S, T=T, jitter=jit, seed=1)
     print("case:", mesh.name, "mixed eta", eta, flush=True)
-    ref, mag = oracle.assemble_rows(mesh.vtx, mesh.tets, mag=True)
+    ref, mag, pert = oracle_rows(mesh.vtx, mesh.tets)
     _, A, kt = _mixed(stb, ctx, mesh, eta)
     D = A.to_dense()
-    assert_entries_mixed(D, ref, mag, what=mesh.name)
+    assert_entries_mixed(D, ref, mag, pert, what=mesh.name)
     assert np.array_equal(D != 0.0, ref != 0.0)
     assert kt["nodes_fp32"][2] > 0, kt
 
@@ -104,11 +99,11 @@ def test_icosphere_level2_sampled_rows(stb, ctx):
     m, A, kt = _mixed(stb, ctx, mesh)
     print("mixed kernels", kt, flush=True)
     rows = np.sort(np.random.default_rng(17).choice(mesh.nt, 24, replace=False))
-    ref, mag = oracle.assemble_rows(mesh.vtx, mesh.tets, rows=rows, mag=True)
+    ref, mag, pert = oracle_rows(mesh.vtx, mesh.tets, rows=rows)
     rr = np.repeat(rows, mesh.nt).astype(np.int32)
     cc = np.tile(np.arange(mesh.nt), rows.size).astype(np.int32)
     got = A.get(rr, cc).reshape(rows.size, mesh.nt)
-    assert_entries_mixed(got, ref, mag, what="icosphere L2 mixed rows")
+    assert_entries_mixed(got, ref, mag, pert, what="icosphere L2 mixed rows")
     print("max relative error %.3e" % rel_err_entries(got, ref), flush=True)
     assert np.array_equal(got != 0.0, ref != 0.0)
     A64 = stb.assemble_V(ctx, m)

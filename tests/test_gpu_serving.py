@@ -127,6 +127,39 @@ def test_admission_and_errors(stb, ctx, served):
         S.wait(S.submit_potential(i1, np.ones(ms[1].nt), big))
     with pytest.raises(stb.StbError):
         S.submit_matvec(i1, np.zeros((ms[1].nt, 16)))   # no matrix registered
-    with pytest.raises(stb.StbError):
-        S.submit_matvec(17, Ws[0])                        # unknown mesh
+    with pytest.raises(ValueError):
+        S.submit_matvec(17, Ws[0])                        # unknown mesh: the binding refuses
+    import ctypes
+    req = stb.Request(stb.STB_REQ_MATVEC16, 17, 0, Ws[0].ctypes.data, None, Ws[0].ctypes.data)
+    t = ctypes.c_uint64()
+    assert stb.load().stb_server_submit(S.h, ctypes.byref(req), ctypes.byref(t)) == 5  # and the library
+    S.close()
+
+
+def test_add_mesh_while_requests_run(stb, ctx, served):
+    """Meshes registered while other requests run: the served meshes never
+    move (the workers copy a mesh's handles under the server's lock), and
+    every result equals the direct call."""
+    import threading
+    ms, handles, mats = served
+    S = stb.Server(ctx, nslots=3)
+    i0 = S.add_mesh(handles[0], mats[0])
+    Ws = [np.random.default_rng(40 + k).standard_normal((ms[0].nt, 16)) for k in range(24)]
+    out = {}
+
+    def submitter():
+        ts = [(k, S.submit_matvec(i0, W)) for k, W in enumerate(Ws)]
+        for k, t in ts:
+            out[k] = S.wait(t)[0]
+    th = threading.Thread(target=submitter)
+    th.start()
+    extra = [S.add_mesh(handles[k % len(handles)], mats[k % len(mats)]) for k in range(64)]
+    th.join()
+    for k, W in enumerate(Ws):
+        assert np.array_equal(out[k], mats[0].apply(W))
+    w = inputs.density_normal(ms[1].nt, seed=8)
+    pts = inputs.shell_points(32, ms[1].T, seed=10)
+    k1 = next(e for e, k in zip(extra, range(64)) if k % len(handles) == 1)
+    u, _ = S.wait(S.submit_potential(k1, w, pts))
+    assert np.array_equal(u, stb.potential_S(ctx, handles[1], w, pts))
     S.close()
