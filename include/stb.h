@@ -107,16 +107,17 @@ stb_status stb_mesh_create_dev(stb_ctx* ctx, int64_t nv, const double* vtx_dev, 
 void stb_mesh_destroy(stb_mesh* mesh);
 int64_t stb_mesh_size(const stb_mesh* mesh);
 
-/* Assemble A over all causal pairs into a device-resident sparse store
- * (rows of candidate columns from a conservative causal cull; every stored
- * value that is not causal is +0.0).  params NULL = defaults. */
+/* Assemble A over all causal pairs into a device-resident sparse store:
+ * CSR rows holding exactly the causal pairs of the row (columns ascending;
+ * the conservative cull's other candidates are evaluated and dropped), so
+ * every entry not stored is +0.0.  params NULL = defaults. */
 stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,
                           stb_mat** out);
 void stb_mat_destroy(stb_mat* mat);
 
 /* n: matrix order; n_causal_pairs: exact number of causal pairs (Sec. 3.3
- * lit predicate at the outer points); n_stored: stored candidate entries;
- * bytes: device bytes held by the store. */
+ * lit predicate at the outer points); n_stored: stored entries (equal to
+ * n_causal_pairs); bytes: device bytes held by the store. */
 stb_status stb_mat_info(const stb_mat* mat, int64_t* n, int64_t* n_causal_pairs,
                         int64_t* n_stored, int64_t* bytes);
 /* Dense copy, n x n row-major FP64 (caller-owned host buffer). */
@@ -127,7 +128,7 @@ stb_status stb_mat_get(const stb_mat* mat, int64_t k, const int32_t* row, const 
 
 /* Export the store in CSR form into caller-allocated host arrays: rowptr
  * (n + 1 entries), cols and vals (n_stored entries each, see stb_mat_info);
- * columns ascend within a row; stored entries of non-causal pairs are 0.0.
+ * columns ascend within a row; every stored entry is a causal pair.
  * Any of the three pointers may be NULL to skip that array. */
 stb_status stb_mat_export(const stb_mat* mat, int64_t* rowptr, int32_t* cols, double* vals);
 

@@ -10,7 +10,8 @@ SOURCES = [os.path.join(CSRC, "stb_lib.hip"), os.path.join(CSRC, "stb_pairs.hip"
            os.path.join(CSRC, "stb_batch.hip"), os.path.join(CSRC, "stb_server.hip"),
            os.path.join(CSRC, "stb_apply.hip"),
            os.path.join(CSRC, "stb_faces.hip"), os.path.join(CSRC, "stb_solve.hip"),
-           os.path.join(CSRC, "stb_dl.hip"), os.path.join(CSRC, "stb_proj.hip")]
+           os.path.join(CSRC, "stb_dl.hip"), os.path.join(CSRC, "stb_proj.hip"),
+           os.path.join(CSRC, "stb_scan.hip")]
 HEADERS = [os.path.join(CSRC, "stb_device.h"), os.path.join(CSRC, "stb_internal.h"),
            os.path.join(CSRC, "stb_pairs.h"), os.path.join(ROOT, "include", "stb.h")]
 

@@ -42,8 +42,9 @@ __global__ void k_gather_stride(int64_t n, int64_t stride, const int32_t* __rest
 namespace {
 
 // Device bytes per candidate held during a wave: the mesh's store (cols,
-// vals), the candidate's row, the concatenated row/column/value copies.
-constexpr int64_t kBytesPerCand = 4 + 8 + 4 + 4 + 4 + 8;
+// vals), the candidate's row, the concatenated row/column/value copies, the
+// causal flag, and at most as much again for the compacted store.
+constexpr int64_t kBytesPerCand = 4 + 8 + 4 + 4 + 4 + 8 + 1 + 12;
 
 struct WaveMesh {
   int idx;
@@ -168,19 +169,21 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
     }
     TrialRec* trial_g = nullptr;
     FaceAng* fang_g = nullptr;
+    uint8_t* keep_g = nullptr;   // [cands] 1 where the pair is causal
     double *apex_g = nullptr, *apexw_g = nullptr, *vals_g = nullptr;
     int32_t *apexn_g = nullptr, *rows_g = nullptr, *cols_g = nullptr;
     int64_t* seg_off = nullptr;
     unsigned long long* seg_causal = nullptr;
     auto cleanup = [&](bool keep) {
       dfree(trial_g); dfree(fang_g); dfree(apex_g); dfree(apexw_g); dfree(apexn_g); dfree(rows_g); dfree(cols_g);
-      dfree(vals_g); dfree(seg_off); dfree(seg_causal);
+      dfree(vals_g); dfree(seg_off); dfree(seg_causal); dfree(keep_g);
       release(w, keep);
     };
     // FP64: through the shared faces (stb_faces.hip), which stages its own
     // lists; mixed precision: the panels' outer points, staged here
     const bool faces = p.prec == STB_FP64;
-    bool ok = faces || (dalloc(&trial_g, (size_t)panels) == hipSuccess &&
+    bool ok = dalloc(&keep_g, (size_t)std::max<int64_t>(cands, 1)) == hipSuccess;
+    ok = ok && (faces || (dalloc(&trial_g, (size_t)panels) == hipSuccess &&
                         dalloc(&fang_g, (size_t)panels) == hipSuccess &&
                         dalloc(&apex_g, (size_t)panels * maxq * 4) == hipSuccess &&
                         dalloc(&apexw_g, (size_t)panels * maxq) == hipSuccess &&
@@ -189,7 +192,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
                         dalloc(&cols_g, (size_t)cands) == hipSuccess &&
                         dalloc(&vals_g, (size_t)cands) == hipSuccess &&
                         dalloc(&seg_off, w.size() + 1) == hipSuccess &&
-                        dalloc(&seg_causal, w.size()) == hipSuccess);
+                        dalloc(&seg_causal, w.size()) == hipSuccess));
     if (!ok) {
       cleanup(false);
       return stb_fail(ctx, STB_E_NO_MEMORY, "batch wave of %lld candidates does not fit", (long long)cands);
@@ -259,6 +262,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
         fu[m].cols = w[m].M->d_cols;
         fu[m].nnz = w[m].M->nnz;
         fu[m].vals = w[m].M->d_vals;
+        fu[m].keep = keep_g + w[m].off_cand;
       }
       unsigned long long work[4];
       s = stb_face_assemble(ctx, p, fu.data(), (int)fu.size(), work);
@@ -288,6 +292,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
     J.mixed = p.prec == STB_MIXED;
     J.eta_far = p.eta_far;
     J.out = vals_g;
+    J.lit_out = keep_g;
     J.nseg = (int)w.size();
     J.seg_off = seg_off;
     J.seg_causal = seg_causal;
@@ -310,6 +315,11 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
       w[m].M->n_causal = (int64_t)h_causal[m];
       causal[(size_t)w[m].idx] += (int64_t)h_causal[m];
     }
+    }
+    // each store keeps its causal entries only
+    for (size_t m = 0; m < w.size(); ++m) {
+      s = stb_keep_causal(ctx, w[m].M, keep_g + w[m].off_cand, st);
+      if (s) { cleanup(false); return s; }
     }
     // products of the wave's row blocks, then release (or hand over) the stores
     for (size_t m = 0; m < w.size() && W_dev; ++m) {

@@ -134,6 +134,7 @@ __global__ void k_face_combine(int64_t nnz, int64_t r0, const int32_t* __restric
                                const int32_t* __restrict__ fcols, const int32_t* __restrict__ prim,
                                const int64_t* __restrict__ rowptr, const double* __restrict__ S,
                                const uint8_t* __restrict__ lit, double* __restrict__ vals,
+                               uint8_t* __restrict__ keep,
                                unsigned long long* __restrict__ causal) {
   unsigned long long n = 0;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nnz;
@@ -162,6 +163,7 @@ __global__ void k_face_combine(int64_t nnz, int64_t r0, const int32_t* __restric
       }
     }
     vals[c] = any ? acc : 0.0;
+    if (keep) keep[c] = any ? 1 : 0;
     n += any ? 1ull : 0ull;
   }
   for (int off = 32; off > 0; off >>= 1) n += __shfl_down(n, off, 64);
@@ -453,7 +455,7 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
     const int64_t blocks = std::min<int64_t>((fu.nnz + 255) / 256, (int64_t)std::max(ctx->ncu, 1) * 32);
     hipLaunchKernelGGL(k_face_combine, dim3((unsigned)blocks), dim3(256), 0, st, fu.nnz, fu.r0, fu.rowof,
                        fu.cols, fu.mesh->d_pf, fu.mesh->d_pw, x.f0, x.f1 - x.f0, x.frowptr, x.fcols,
-                       x.fprim, fu.rowptr, S_g + x.oc, lit_g + x.oc, fu.vals, d_causal + k);
+                       x.fprim, fu.rowptr, S_g + x.oc, lit_g + x.oc, fu.vals, fu.keep, d_causal + k);
     e = hipGetLastError();
     if (e != hipSuccess) break;
   }

@@ -140,6 +140,7 @@ struct FaceUnit {
   const int32_t* cols = nullptr;    // [nnz] trial panel (mesh-local)
   int64_t nnz = 0;
   double* vals = nullptr;           // [nnz] out
+  uint8_t* keep = nullptr;          // optional [nnz] out: 1 where the pair is causal
   int64_t n_causal = 0;             // out
 };
 stb_status stb_ensure_faces(stb_ctx* ctx, stb_mesh* m, int mq);
@@ -148,6 +149,11 @@ void stb_free_faces(stb_mesh* m);
 // unit's values and causal count; work as stb_run_pairs.
 stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* units, int nunit,
                              unsigned long long work[4]);
+
+// Drops the stored candidates whose flag is 0 (non-causal pairs): M keeps
+// exactly its causal entries, rows and column order unchanged, nnz =
+// the number of flags set.  Synchronises st.
+stb_status stb_keep_causal(stb_ctx* ctx, stb_mat* M, const uint8_t* d_flag, hipStream_t st);
 
 // Frees the L2 projection's adjacency (stb_proj.hip).
 void stb_free_projection(stb_mesh* m);
@@ -163,3 +169,11 @@ stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y,
 void stb_free_blocked(stb_mat* M);
 // Exclusive prefix sum of n counts into out[0..n] (device memory); syncs st.
 stb_status stb_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, hipStream_t st);
+
+// Device-wide exclusive prefix sum (stb_scan.hip): out[0] = 0, out[i + 1] =
+// in[0] + ... + in[i] for i < n (n + 1 outputs), enqueued on st; tmp holds
+// stb_scan_tmp_elems<T>(n) elements.  No allocation, no memset.
+template <typename T>
+int64_t stb_scan_tmp_elems(int64_t n);
+template <typename T>
+hipError_t stb_scan(const T* in, T* out, int64_t n, T* tmp, hipStream_t st);

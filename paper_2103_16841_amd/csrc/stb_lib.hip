@@ -12,7 +12,6 @@
 //                Gauss nodes, ordered sums, store.
 // The store is CSR over the candidate columns (values aligned with them).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -289,6 +288,47 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
   if (lane == 0) y[row * nrhs + col] = s;
 }
 
+// Compaction of a store to its causal entries: one wavefront per row counts
+// the row's flags; after the scan of the counts, one wavefront per row
+// copies the flagged entries in order (ballot + mbcnt give each lane its
+// slot among the 64 entries in flight).
+__global__ __launch_bounds__(256) void k_keep_count(int64_t n, const int64_t* __restrict__ rowptr,
+                                                    const uint8_t* __restrict__ flag,
+                                                    int64_t* __restrict__ cnt) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  int64_t c = 0;
+  for (int64_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64) c += flag[k] ? 1 : 0;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  if (lane == 0) cnt[row] = c;
+}
+
+__global__ __launch_bounds__(256) void k_keep_fill(int64_t n, const int64_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ cols,
+                                                   const double* __restrict__ vals,
+                                                   const uint8_t* __restrict__ flag,
+                                                   const int64_t* __restrict__ nrowptr,
+                                                   int32_t* __restrict__ ncols,
+                                                   double* __restrict__ nvals) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  int64_t out = nrowptr[row];
+  for (int64_t k0 = rowptr[row]; k0 < rowptr[row + 1]; k0 += 64) {
+    const int64_t k = k0 + lane;
+    const bool p = k < rowptr[row + 1] && flag[k] != 0;
+    const uint64_t bal = __ballot(p);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+    if (p) {
+      ncols[out + rank] = cols[k];
+      nvals[out + rank] = vals[k];
+    }
+    out += __popcll(bal);
+  }
+}
+
 // ---------------------------------------------------------------- host helpers
 
 // Gauss-Legendre on [0,1] by Newton iteration on the three-term recurrence.
@@ -360,19 +400,16 @@ stb_status stb_ensure_outer(stb_ctx* ctx, stb_mesh* m, int mq) {
   return STB_OK;
 }
 
-// Exclusive scan of n int64 counts into out[0..n] (device), via hipcub.
+// Exclusive scan of n int64 counts into out[0..n] (device), with the
+// library's own three-pass scan (stb_scan.hip); synchronises st.
 stb_status stb_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t* out, int64_t n,
                               hipStream_t st) {
-  size_t bytes = 0;
-  HIPCHK(ctx, hipcub::DeviceScan::InclusiveSum(nullptr, bytes, in, out + 1, (int)n, st));
-  void* tmp = nullptr;
-  HIPCHK(ctx, hipMalloc(&tmp, bytes > 0 ? bytes : 1));
-  hipError_t e1 = hipMemsetAsync(out, 0, sizeof(int64_t), st);
-  hipError_t e2 = hipcub::DeviceScan::InclusiveSum(tmp, bytes, in, out + 1, (int)n, st);
-  hipError_t e3 = hipStreamSynchronize(st);
-  (void)hipFree(tmp);
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
-    return fail(ctx, STB_E_DEVICE, "scan failed");
+  int64_t* tmp = nullptr;
+  HIPCHK(ctx, dalloc(&tmp, (size_t)stb_scan_tmp_elems<int64_t>(n)));
+  hipError_t e = stb_scan<int64_t>(in, out, n, tmp, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dfree(tmp);
+  if (e != hipSuccess) return fail(ctx, STB_E_DEVICE, "scan failed: %s", hipGetErrorString(e));
   return STB_OK;
 }
 
@@ -447,6 +484,49 @@ stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const st
                        nrows, d_rows, m->nt, m->d_trial, *d_rowptr, *d_cols, *d_rowof);
     HIPCHK(ctx, hipGetLastError());
   }
+  return STB_OK;
+}
+
+stb_status stb_keep_causal(stb_ctx* ctx, stb_mat* M, const uint8_t* d_flag, hipStream_t st) {
+  const int64_t n = M->n;
+  int64_t *cnt = nullptr, *rp = nullptr;
+  int32_t* cols = nullptr;
+  double* vals = nullptr;
+  auto cleanup = [&]() { dfree(cnt); dfree(rp); dfree(cols); dfree(vals); };
+  if (dalloc(&cnt, (size_t)std::max<int64_t>(n, 1)) != hipSuccess || dalloc(&rp, (size_t)n + 1) != hipSuccess) {
+    cleanup();
+    return fail(ctx, STB_E_NO_MEMORY, "causal store: row counts");
+  }
+  const unsigned g = (unsigned)((n * 64 + 255) / 256);
+  if (n > 0) hipLaunchKernelGGL(k_keep_count, dim3(g), dim3(256), 0, st, n, M->d_rowptr, d_flag, cnt);
+  HIPCHK(ctx, hipGetLastError());
+  stb_status s = stb_exclusive_scan(ctx, cnt, rp, n, st);
+  if (s) { cleanup(); return s; }
+  int64_t nk = 0;
+  hipError_t e = hipMemcpy(&nk, rp + n, sizeof(int64_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) { cleanup(); return fail(ctx, STB_E_DEVICE, "causal store: %s", hipGetErrorString(e)); }
+  if (dalloc(&cols, (size_t)nk) != hipSuccess || dalloc(&vals, (size_t)nk) != hipSuccess) {
+    cleanup();
+    return fail(ctx, STB_E_NO_MEMORY, "causal store of %lld entries", (long long)nk);
+  }
+  if (n > 0)
+    hipLaunchKernelGGL(k_keep_fill, dim3(g), dim3(256), 0, st, n, M->d_rowptr, M->d_cols, M->d_vals, d_flag,
+                       rp, cols, vals);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { cleanup(); return fail(ctx, STB_E_DEVICE, "causal store: %s", hipGetErrorString(e)); }
+  dfree(cnt);
+  dfree(M->d_rowptr);
+  dfree(M->d_cols);
+  dfree(M->d_vals);
+  dfree(M->d_vals32);
+  M->d_vals32 = nullptr;
+  stb_free_blocked(M);
+  M->d_rowptr = rp;
+  M->d_cols = cols;
+  M->d_vals = vals;
+  M->nnz = nk;
+  M->host_valid = false;
   return STB_OK;
 }
 
@@ -654,8 +734,9 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   s = stb_cull(ctx, mesh->nt, mesh->d_box, mesh, &M->d_rowptr, &M->d_cols, &d_rowof, &M->nnz);
   if (s) { dfree(d_rowof); stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
-  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess) {
-    dfree(d_rowof); stb_mat_destroy(M);
+  uint8_t* d_keep = nullptr;
+  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess || dalloc(&d_keep, (size_t)M->nnz) != hipSuccess) {
+    dfree(d_rowof); dfree(d_keep); stb_mat_destroy(M);
     return fail(ctx, STB_E_NO_MEMORY, "store of %lld entries does not fit", (long long)M->nnz);
   }
   unsigned long long causal = 0, work[4];
@@ -670,6 +751,7 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
     U.cols = M->d_cols;
     U.nnz = M->nnz;
     U.vals = M->d_vals;
+    U.keep = d_keep;
     s = stb_face_assemble(ctx, p, &U, 1, work);
     causal = (unsigned long long)U.n_causal;
   } else {
@@ -688,10 +770,14 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
     J.mixed = true;
     J.eta_far = p.eta_far;
     J.out = M->d_vals;
+    J.lit_out = d_keep;
     J.n_causal = &causal;
     s = stb_run_pairs(ctx, J, work);
   }
   dfree(d_rowof);
+  // the resident store keeps the causal entries only
+  if (s == STB_OK) s = stb_keep_causal(ctx, M, d_keep, ctx->stream);
+  dfree(d_keep);
   if (s) { stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
   HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));

@@ -35,7 +35,6 @@
 // percent of what the FP64 arithmetic takes, while each stage runs at full
 // lane occupancy with its own register budget.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -265,7 +264,7 @@ __global__ __launch_bounds__(kBlk) void k_lit_deep(Geo g, Lists L, int64_t c0, i
 }
 
 // Lit combos contiguous per candidate, in apex order, candidates in order:
-// counts, an exclusive prefix sum (hipcub), then the keys.
+// counts, an exclusive prefix sum (stb_scan.hip), then the keys.
 __global__ void k_emit_count(Lists L, int64_t nc) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c < nc) L.ccnt[c] = __popcll(L.mask[c]);
@@ -800,10 +799,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Lay the lists out in one allocation.
 static size_t scan_bytes_for(int64_t cc) {
-  size_t bytes = 0;
-  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (const int32_t*)nullptr, (int32_t*)nullptr,
-                                         (int)(cc + 1));
-  return bytes;
+  return (size_t)stb_scan_tmp_elems<int32_t>(cc) * sizeof(int32_t);
 }
 
 static size_t ws_bytes(int64_t cc, int64_t cb, int64_t cp) {
@@ -976,10 +972,7 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
                          (int64_t)ndeep);
     hipLaunchKernelGGL(k_emit_count, dim3((unsigned)((nc + 1 + 255) / 256)), dim3(256), 0, st, L, nc);
     HIPCHK(ctx, hipGetLastError());
-    {
-      size_t sb = L.scan_bytes;
-      HIPCHK(ctx, hipcub::DeviceScan::ExclusiveSum(L.scan_tmp, sb, L.ccnt, L.coff, (int)(nc + 1), st));
-    }
+    HIPCHK(ctx, stb_scan<int32_t>(L.ccnt, L.coff, nc, (int32_t*)L.scan_tmp, st));
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, L, nc);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(0));

@@ -84,7 +84,7 @@ def test_cube_causal_count(cube, cube_gpu, cube_ref):
     _, A = cube_gpu
     per_row = oracle.count_causal_per_row(cube.vtx, cube.tets)
     assert A.n_causal == per_row.sum() == np.count_nonzero(cube_ref)
-    assert A.n_stored >= A.n_causal
+    assert A.n_stored == A.n_causal           # the store keeps the causal pairs only
 
 
 def test_cube_matvec(cube, cube_gpu, cube_M, cube_P):
@@ -215,6 +215,10 @@ def test_icosphere_causal_count_property(ico2, ico2_gpu):
     got = A.get(rr, cc).reshape(rows.size, ico2.nt)
     assert np.array_equal((got != 0).sum(axis=1), per)
     assert A.n_causal > 0.9 * per.mean() * ico2.nt / 2
+    assert A.n_stored == A.n_causal
+    rp, cols, vals = A.export()
+    assert np.all(vals != 0.0) and np.all(np.diff(rp) >= 0)
+    assert all(np.all(np.diff(cols[rp[i]:rp[i + 1]]) > 0) for i in range(0, ico2.nt, 97))
 
 
 def test_bench_potential_sampled_points(stb, ctx, ico2, ico2_gpu):
