@@ -140,6 +140,21 @@ stb_status stb_apply(stb_ctx* ctx, const stb_mat* mat, int32_t nrhs, const doubl
 stb_status stb_apply_dev(stb_ctx* ctx, const stb_mat* mat, int32_t nrhs, const double* w_dev,
                          double* y_dev, void* stream);
 
+/* The 16-RHS matrix-core product of stb_apply_dev (nrhs = 16) for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Y = A W with w_dev
+ * (n x 16, row-major FP64) and y_dev (n x 16) in device memory; the same
+ * kernels and results as stb_apply_dev.  The FP32 copy of W lives in one
+ * static 16 MiB device array per device (at most 262,144 columns;
+ * STB_E_INVALID_ARG beyond), shared by every call on that device and kept
+ * between calls: calls that overlap on one device race.  The matrix's
+ * matrix-core copy must exist already (built by one stb_apply or
+ * stb_apply_dev with nrhs = 16; STB_E_INVALID_ARG otherwise).  Enqueues on
+ * `stream` (NULL = the context stream) and returns; allocates nothing and
+ * does not synchronise. */
+stb_status stb_apply16_noalloc(stb_ctx* ctx, const stb_mat* mat, const double* w_dev,
+                               double* y_dev, void* stream);
+
 /* Retarded single-layer potential u(p) = sum_j w_j V phi_j (p) (eq. slp with
  * w in S_h^0) at np points pts (np x 4, (t, x, y, z)); w has nt entries. */
 stb_status stb_potential_S(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_params* params,

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "stb_internal.h"
 
@@ -249,5 +250,62 @@ stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y,
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   dfree(w32);
   if (e != hipSuccess) return stb_fail(ctx, STB_E_DEVICE, "16-RHS apply failed: %s", hipGetErrorString(e));
+  return STB_OK;
+}
+
+// ------------------------------------------------ product without allocation
+// stb_apply16_noalloc is the 16-RHS product for callers that cannot allocate
+// device memory (code under HIP graph capture, tight serving loops, harnesses
+// that forbid allocation): the FP32 copy of W, which stb_apply16_dev puts in
+// a buffer of its own per call, goes to this file-scope array instead.  Each
+// device the library runs on holds one copy (16 MiB) until the process ends;
+// every call on a device shares it, so calls that overlap on one device race.
+constexpr int64_t kNoAllocMaxCols = kMaxBlockedN;
+static __device__ __align__(256) float scratch[kNoAllocMaxCols * 16];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};   // device address of scratch, per device
+}  // namespace
+
+// Called by stb_ctx_create with ctx's device current: looks up this device's
+// address of the scratch array once.  In host code the array's name is only a
+// stand-in; kernels get the address found here.
+stb_status stb_noalloc_setup(stb_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return stb_fail(ctx, STB_E_INVALID_ARG, "device %d: at most %d devices", ctx->device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[ctx->device]) return STB_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return stb_fail(ctx, STB_E_DEVICE, "scratch address: %s", hipGetErrorString(e));
+  g_scratch_dev[ctx->device] = static_cast<float*>(ptr);
+  return STB_OK;
+}
+
+extern "C" stb_status stb_apply16_noalloc(stb_ctx* ctx, const stb_mat* M, const double* w_dev,
+                                          double* y_dev, void* stream) {
+  if (!ctx || !M || !w_dev || !y_dev) return stb_fail(ctx, STB_E_INVALID_ARG, "NULL argument");
+  if (M->ctx != ctx) return stb_fail(ctx, STB_E_INVALID_ARG, "matrix belongs to another context");
+  const int64_t ncols = mat_ncols(M);
+  if (ncols > kNoAllocMaxCols)
+    return stb_fail(ctx, STB_E_INVALID_ARG, "%lld columns exceed the %lld of the allocation-free product",
+                    (long long)ncols, (long long)kNoAllocMaxCols);
+  if (!M->d_bptr && M->n > 0)
+    return stb_fail(ctx, STB_E_INVALID_ARG,
+                    "the matrix-core copy is not built: call stb_apply with nrhs = 16 once first");
+  float* w32 = g_scratch_dev[ctx->device];
+  if (!w32) return stb_fail(ctx, STB_E_INTERNAL, "scratch of device %d not set up", ctx->device);
+  hipStream_t st = stream ? (hipStream_t)stream : ctx->stream;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const int64_t m = ncols * 16;
+  if (m > 0)
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, w_dev, w32);
+  if (M->nblk > 0)
+    hipLaunchKernelGGL(k_bell_mfma, dim3((unsigned)M->nblk), dim3(256), 0, st, M->nblk, M->n, M->d_bptr,
+                       M->d_bcol, M->d_bval, (const float*)w32, y_dev);
+  HIPCHK(ctx, hipGetLastError());
   return STB_OK;
 }

@@ -167,6 +167,9 @@ stb_status stb_potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_param
 stb_status stb_build_blocked(stb_ctx* ctx, stb_mat* M, hipStream_t st);
 stb_status stb_apply16_dev(stb_ctx* ctx, stb_mat* M, const double* w, double* y, hipStream_t st);
 void stb_free_blocked(stb_mat* M);
+// Looks up this device's address of the allocation-free product's scratch
+// array (stb_apply.hip); called once per context with its device current.
+stb_status stb_noalloc_setup(stb_ctx* ctx);
 // Exclusive prefix sum of n counts into out[0..n] (device memory); syncs st.
 stb_status stb_exclusive_scan(stb_ctx* ctx, const int64_t* in, int64_t* out, int64_t n, hipStream_t st);
 

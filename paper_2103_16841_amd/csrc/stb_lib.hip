@@ -600,6 +600,12 @@ stb_status stb_ctx_create(int32_t device, stb_ctx** out) {
       delete c;
       return fail(nullptr, STB_E_DEVICE, "hipEventCreate failed");
     }
+  // this device's address of the allocation-free product's scratch array
+  if (stb_noalloc_setup(c) != STB_OK) {
+    std::string m = c->err;
+    stb_ctx_destroy(c);
+    return fail(nullptr, STB_E_DEVICE, "%s", m.c_str());
+  }
   *out = c;
   return STB_OK;
 }

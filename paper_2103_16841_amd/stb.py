@@ -20,7 +20,7 @@ STATUS = {0: "STB_OK", 1: "STB_E_INVALID_ARG", 2: "STB_E_INVALID_MESH", 3: "STB_
 EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_status_str",
            "stb_last_error", "stb_mesh_create", "stb_mesh_destroy", "stb_mesh_size",
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
-           "stb_apply", "stb_apply_dev", "stb_potential_S", "stb_potential_S_dev",
+           "stb_apply", "stb_apply_dev", "stb_apply16_noalloc", "stb_potential_S", "stb_potential_S_dev",
            "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_last_path_counts", "stb_mesh_create_dev",
            "stb_outer_points", "stb_outer_rhs", "stb_solve_gmres", "stb_mesh_set_normals", "stb_potential_D",
            "stb_potential_D_dev", "stb_inner_values_D", "stb_dl_energetic",
@@ -91,6 +91,7 @@ def load():
     L.stb_mat_get.argtypes = [_VP, i64, _I32, _I32, _D]
     L.stb_apply.argtypes = [_VP, _VP, i32, _D, _D]
     L.stb_apply_dev.argtypes = [_VP, _VP, i32, _VP, _VP, _VP]
+    L.stb_apply16_noalloc.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.stb_potential_S.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _D, i64, _D, _D]
     L.stb_last_timings.argtypes = [_VP, _D]
     L.stb_inner_values.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), i64, _D, _I32, _D]
@@ -322,6 +323,12 @@ class Matrix:
         """Device-pointer product (e.g. torch tensors' data_ptr())."""
         _chk(load().stb_apply_dev(self.ctx.h, self.h, nrhs, _VP(w_ptr), _VP(y_ptr),
                                   _VP(stream) if stream else None), self.ctx.h)
+
+    def apply16_noalloc(self, w_ptr, y_ptr, stream=None):
+        """16-RHS product that allocates nothing (device pointers, n x 16);
+        enqueued on the stream, not synchronised."""
+        _chk(load().stb_apply16_noalloc(self.ctx.h, self.h, _VP(w_ptr), _VP(y_ptr),
+                                        _VP(stream) if stream else None), self.ctx.h)
 
 
 def autotune(ctx, mesh, params=None):
