@@ -56,6 +56,18 @@ typedef enum {
 
 typedef enum { STB_FP64 = 0, STB_MIXED = 1 } stb_precision;
 
+/* Lit-panel search of the potentials (Sec. 3.3).  STB_LIT_TREE: the cluster
+ * tree of Def. bct (panels in space-time Morton order, perfect binary tree,
+ * leaves of at most n_min panels, one bounding 4-ball per cluster),
+ * descended by all points together level by level with the exact extrema
+ * of Theorem phi_xi_sphere (Alg. lit_leaves); the panels of the surviving
+ * leaves, X_N(x), then pass a per-panel bound test (time range and spatial
+ * ball).  STB_LIT_FLAT: every point against every panel's bound test.  Both
+ * feed the exact lit test, so the lit sets and the potentials agree.  The
+ * tree of a mesh is built on first use for its n_min (once; contexts that
+ * share the mesh may search it concurrently with the same n_min). */
+typedef enum { STB_LIT_TREE = 0, STB_LIT_FLAT = 1 } stb_lit_search;
+
 /* Quadrature parameters.  m_q: sub-triangles per face edge of the outer
  * centroid rule (1..4, default 3 as in Exp. 3).  n_g: Gauss-Legendre nodes
  * per phi piece of the inner rule (2..64, default 16).  prec: FP64 or mixed.
@@ -75,13 +87,17 @@ typedef struct {
   int32_t n_g;
   double eta_far;
   stb_precision prec;
+  int32_t lit_search;   /* stb_lit_search: how evaluation points find their
+                           candidate panels (potentials) */
+  int32_t n_min;        /* leaf size of the cluster tree (1..4096, default 8) */
 } stb_quad_params;
 
 typedef struct stb_ctx stb_ctx;
 typedef struct stb_mesh stb_mesh;
 typedef struct stb_mat stb_mat;
 
-/* Default parameters (m_q = 3, n_g = 16, eta_far = 0.5, FP64). */
+/* Default parameters (m_q = 3, n_g = 16, eta_far = 0.5, FP64, cluster-tree
+ * lit search with n_min = 8). */
 stb_quad_params stb_default_params(void);
 
 /* Create a context on HIP device `device` (its own stream). */
@@ -351,9 +367,31 @@ stb_status stb_outer_rhs(stb_ctx* ctx, const stb_mesh* mesh, int32_t m_q, const 
 stb_status stb_solve_gmres(stb_ctx* ctx, const stb_mat* A, const double* b_host, double* x_host,
                            int32_t restart, int32_t maxit, double rtol, int32_t* iters, double* relres);
 
-/* Timing of the last stb_assemble_V on ctx, in milliseconds measured with
- * HIP events on the context stream: [0] geometry/outer points, [1] cull and
- * compaction, [2] clip + quadrature + store, [3] total. */
+/* Marching-on-in-time solve of the discrete indirect system A x = b
+ * (eq. df_ind) for a mesh made of S time slabs that repeat: the vertex
+ * times take S + 1 equally spaced values, every panel spans one slab
+ * between two consecutive ones, every slab has the same number K of panels
+ * and slab n is slab 0 moved by n dt in time, panel by panel in index
+ * order (an unjittered extrusion).  Causality then makes A block lower
+ * triangular in the slab index with the same diagonal block D (the coupling
+ * of a slab with itself) on every slab, so x follows slab by slab:
+ *   x_n = D^{-1} (b_n - sum_{m < n} A_nm x_m).
+ * D is inverted once on the device (Gauss-Jordan, partial pivoting); each
+ * time step is one product over the slab's rows with the solution so far
+ * and one dense K x K product.  A: the matrix stb_assemble_V returned for
+ * mesh; b_host, x_host: nt doubles (host).  info4 (optional): slabs S,
+ * panels per slab K, milliseconds of the inversion and of the time steps.
+ * STB_E_INVALID_ARG when the mesh or the stored matrix do not have that
+ * structure (jittered or non-uniform time levels, a stored entry coupling
+ * a slab to a later one, K > 16384): use stb_solve_gmres then. */
+stb_status stb_solve_mot(stb_ctx* ctx, const stb_mesh* mesh, const stb_mat* A, const double* b_host,
+                         double* x_host, double* info4);
+
+/* Timing of the last stb_assemble_V or potential (stb_potential_S, _D) on
+ * ctx, in milliseconds measured with HIP events on the context stream:
+ * [0] geometry/outer points (0 for a potential), [1] cull and compaction
+ * (the lit search of the points for a potential), [2] clip + quadrature +
+ * store (+ the point sums), [3] total. */
 stb_status stb_last_timings(const stb_ctx* ctx, double* ms4);
 
 /* Path counts of the last assembly or batch on ctx.  [0..2]: evaluations of
@@ -366,6 +404,14 @@ stb_status stb_last_timings(const stb_ctx* ctx, double* ms4);
  * quarter points) miss the panel's spatial shadow (each would otherwise
  * cost three evaluations). */
 stb_status stb_last_path_counts(const stb_ctx* ctx, int64_t* counts4);
+
+/* Lit search of the last potential on ctx (stb_potential_S, _D):
+ * [0] (point, leaf) pairs the cluster tree kept, [1] panels in those leaves
+ * summed over the points (the sets X_N(x) of Sec. 3.3), [2] candidate
+ * (point, panel) pairs after the per-panel bound test, which the exact lit
+ * test then decides.  The flat search reports 0, points x panels examined,
+ * and its candidates. */
+stb_status stb_last_lit_search(const stb_ctx* ctx, int64_t* counts3);
 
 /* Work of the last stb_assemble_V or potential on ctx: [0] evaluations of L(phi)
  * (empty-piece tests and Gauss nodes), [1] lit (outer point, trial panel)

@@ -11,7 +11,7 @@ SOURCES = [os.path.join(CSRC, "stb_lib.hip"), os.path.join(CSRC, "stb_pairs.hip"
            os.path.join(CSRC, "stb_apply.hip"),
            os.path.join(CSRC, "stb_faces.hip"), os.path.join(CSRC, "stb_solve.hip"),
            os.path.join(CSRC, "stb_dl.hip"), os.path.join(CSRC, "stb_proj.hip"),
-           os.path.join(CSRC, "stb_scan.hip")]
+           os.path.join(CSRC, "stb_scan.hip"), os.path.join(CSRC, "stb_tree.hip")]
 HEADERS = [os.path.join(CSRC, "stb_device.h"), os.path.join(CSRC, "stb_internal.h"),
            os.path.join(CSRC, "stb_pairs.h"), os.path.join(ROOT, "include", "stb.h")]
 

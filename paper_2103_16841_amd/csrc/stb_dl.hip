@@ -436,17 +436,13 @@ static stb_status dl_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_params& p
   stb_status s;
   if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
   double* d_h = nullptr;
-  ApexBox* d_box = nullptr;
   int64_t* d_rowptr = nullptr;
   int32_t *d_cols = nullptr, *d_rowof = nullptr;
   auto cleanup = [&]() {
-    dfree(d_h); dfree(d_box); dfree(d_rowptr); dfree(d_cols); dfree(d_rowof);
+    dfree(d_h); dfree(d_rowptr); dfree(d_cols); dfree(d_rowof);
   };
-  if (dalloc(&d_box, (size_t)np) != hipSuccess)
-    return stb_fail(ctx, STB_E_NO_MEMORY, "double-layer buffers");
-  stb_point_boxes(ctx, np, d_pts, d_box);
   int64_t nnz = 0;
-  s = stb_cull(ctx, np, d_box, mesh, &d_rowptr, &d_cols, &d_rowof, &nnz);
+  s = stb_cull_points(ctx, mesh, p, np, d_pts, &d_rowptr, &d_cols, &d_rowof, &nnz);
   if (s) { cleanup(); return s; }
   if (dalloc(&d_h, (size_t)nnz * 4) != hipSuccess) {
     cleanup();

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,9 @@ struct stb_ctx {
   std::string err;
   double timings[4] = {0, 0, 0, 0};
   int64_t work[4] = {0, 0, 0, 0};   // last assembly: L evals, lit combos, apexes, pieces
+  // last potential's lit search: (point, leaf) pairs kept by the tree, the
+  // panels of those leaves, candidates after the per-panel bound test
+  int64_t lit_search[3] = {0, 0, 0};
   struct PairWorkspace* ws = nullptr;   // pair pipeline lists (grown on demand)
   hipEvent_t kev[16] = {};              // pair pipeline: start/stop per kernel kind
   double kern_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -67,6 +71,10 @@ struct stb_mesh {
   int32_t* d_pf = nullptr;         // [nt][4] face of each slot (-1: vertical), device
   double* d_pw = nullptr;          // [nt][4] outer weight of the slot for this panel
   std::vector<int32_t> h_pf;       // host copy of d_pf
+  // cluster tree of the panels for the lit search of evaluation points
+  // (stb_tree.hip; built on first use)
+  struct stb_tree* tree = nullptr;
+  std::mutex tree_mu;
 };
 
 struct stb_mat {
@@ -154,6 +162,22 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
 // exactly its causal entries, rows and column order unchanged, nnz =
 // the number of flags set.  Synchronises st.
 stb_status stb_keep_causal(stb_ctx* ctx, stb_mat* M, const uint8_t* d_flag, hipStream_t st);
+
+// Lit search of evaluation points by the cluster tree (stb_tree.hip): the
+// tree for leaves of at most nmin panels is built on first use; candidates
+// as by stb_cull (CSR per point, row of each candidate), nleaves (optional)
+// the surviving (point, leaf) pairs.
+stb_status stb_ensure_tree(stb_ctx* ctx, stb_mesh* m, int nmin);
+stb_status stb_tree_cull(stb_ctx* ctx, stb_mesh* m, int nmin, int64_t np, const double* d_pts,
+                         int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz,
+                         int64_t* nleaves);
+void stb_free_tree(stb_mesh* m);
+// Candidates of evaluation points by the search p.lit_search selects (the
+// cluster tree or the flat cull); records the surviving leaves in
+// ctx->work.
+stb_status stb_cull_points(stb_ctx* ctx, stb_mesh* m, const stb_quad_params& p, int64_t np,
+                           const double* d_pts, int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof,
+                           int64_t* nnz);
 
 // Frees the L2 projection's adjacency (stb_proj.hip).
 void stb_free_projection(stb_mesh* m);

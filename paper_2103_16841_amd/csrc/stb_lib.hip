@@ -329,6 +329,24 @@ __global__ __launch_bounds__(256) void k_keep_fill(int64_t n, const int64_t* __r
   }
 }
 
+// Entries (row[m], col[m]) of a CSR store with ascending columns: one lane
+// per entry, bisection in the row; 0.0 where the column is not stored.
+__global__ void k_mat_get(int64_t k, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ cols,
+                          const double* __restrict__ vals, const int32_t* __restrict__ row,
+                          const int32_t* __restrict__ col, double* __restrict__ out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= k) return;
+  int64_t lo = rowptr[row[m]], hi = rowptr[row[m] + 1];
+  const int64_t end = hi;
+  const int32_t c = col[m];
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (cols[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  out[m] = (lo < end && cols[lo] == c) ? vals[lo] : 0.0;
+}
+
 // ---------------------------------------------------------------- host helpers
 
 // Gauss-Legendre on [0,1] by Newton iteration on the three-term recurrence.
@@ -378,6 +396,9 @@ stb_status stb_check_params(stb_ctx* ctx, const stb_quad_params* p) {
   if (p->prec != STB_FP64 && p->prec != STB_MIXED) return fail(ctx, STB_E_INVALID_ARG, "bad precision");
   if (!(p->eta_far >= 0.0) || !std::isfinite(p->eta_far))
     return fail(ctx, STB_E_INVALID_ARG, "eta_far must be finite and >= 0");
+  if (p->lit_search != STB_LIT_TREE && p->lit_search != STB_LIT_FLAT)
+    return fail(ctx, STB_E_INVALID_ARG, "bad lit search %d", p->lit_search);
+  if (p->n_min < 1 || p->n_min > 4096) return fail(ctx, STB_E_INVALID_ARG, "n_min must be in [1,4096], got %d", p->n_min);
   return STB_OK;
 }
 
@@ -487,6 +508,24 @@ stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const st
   return STB_OK;
 }
 
+stb_status stb_cull_points(stb_ctx* ctx, stb_mesh* m, const stb_quad_params& p, int64_t np,
+                           const double* d_pts, int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof,
+                           int64_t* nnz) {
+  if (p.lit_search == STB_LIT_TREE)
+    return stb_tree_cull(ctx, m, p.n_min, np, d_pts, d_rowptr, d_cols, d_rowof, nnz, nullptr);
+  ApexBox* d_box = nullptr;
+  if (dalloc(&d_box, (size_t)std::max<int64_t>(np, 1)) != hipSuccess)
+    return fail(ctx, STB_E_NO_MEMORY, "point boxes");
+  stb_point_boxes(ctx, np, d_pts, d_box);
+  stb_status s = stb_cull(ctx, np, d_box, m, d_rowptr, d_cols, d_rowof, nnz);
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  dfree(d_box);
+  ctx->lit_search[0] = 0;
+  ctx->lit_search[1] = np * m->nt;   // every panel examined for every point
+  ctx->lit_search[2] = s == STB_OK ? *nnz : 0;
+  return s;
+}
+
 stb_status stb_keep_causal(stb_ctx* ctx, stb_mat* M, const uint8_t* d_flag, hipStream_t st) {
   const int64_t n = M->n;
   int64_t *cnt = nullptr, *rp = nullptr;
@@ -557,6 +596,8 @@ stb_quad_params stb_default_params(void) {
   p.n_g = 16;
   p.eta_far = 0.5;
   p.prec = STB_FP64;
+  p.lit_search = STB_LIT_TREE;
+  p.n_min = 8;
   return p;
 }
 
@@ -714,6 +755,7 @@ void stb_mesh_destroy(stb_mesh* m) {
   stb_free_projection(m);
   dfree(m->d_opts); dfree(m->d_ow); dfree(m->d_onq); dfree(m->d_box);
   stb_free_faces(m);
+  stb_free_tree(m);
   delete m;
 }
 
@@ -831,16 +873,41 @@ stb_status stb_mat_get(const stb_mat* Mc, int64_t k, const int32_t* row, const i
   if (!Mc || (k > 0 && (!row || !col || !out)) || k < 0)
     return fail(Mc ? Mc->ctx : nullptr, STB_E_INVALID_ARG, "bad arguments");
   stb_mat* M = const_cast<stb_mat*>(Mc);
-  stb_status s = mirror_host(M);
-  if (s) return s;
-  for (int64_t m = 0; m < k; ++m) {
-    if (row[m] < 0 || row[m] >= M->n || col[m] < 0 || col[m] >= M->n)
+  const int64_t ncols = mat_ncols(M);
+  for (int64_t m = 0; m < k; ++m)
+    if (row[m] < 0 || row[m] >= M->n || col[m] < 0 || col[m] >= ncols)
       return fail(M->ctx, STB_E_INVALID_ARG, "entry %lld out of range", (long long)m);
-    const int32_t* b = M->h_cols.data() + M->h_rowptr[row[m]];
-    const int32_t* e = M->h_cols.data() + M->h_rowptr[row[m] + 1];
-    const int32_t* it = std::lower_bound(b, e, col[m]);
-    out[m] = (it != e && *it == col[m]) ? M->h_vals[it - M->h_cols.data()] : 0.0;
+  if (k == 0) return STB_OK;
+  if (M->host_valid) {
+    for (int64_t m = 0; m < k; ++m) {
+      const int32_t* b = M->h_cols.data() + M->h_rowptr[row[m]];
+      const int32_t* e = M->h_cols.data() + M->h_rowptr[row[m] + 1];
+      const int32_t* it = std::lower_bound(b, e, col[m]);
+      out[m] = (it != e && *it == col[m]) ? M->h_vals[it - M->h_cols.data()] : 0.0;
+    }
+    return STB_OK;
   }
+  // on the device: no host copy of a store that may hold billions of entries
+  stb_ctx* ctx = M->ctx;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  int32_t *d_rc = nullptr;
+  double* d_out = nullptr;
+  if (dalloc(&d_rc, (size_t)(2 * k)) != hipSuccess || dalloc(&d_out, (size_t)k) != hipSuccess) {
+    dfree(d_rc); dfree(d_out);
+    return fail(ctx, STB_E_NO_MEMORY, "entry lookup buffers");
+  }
+  hipError_t e = hipMemcpyAsync(d_rc, row, 4 * k, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_rc + k, col, 4 * k, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_mat_get, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, ctx->stream, k,
+                       M->d_rowptr, M->d_cols, M->d_vals, d_rc, d_rc + k, d_out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, 8 * k, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dfree(d_rc);
+  dfree(d_out);
+  if (e != hipSuccess) return fail(ctx, STB_E_DEVICE, "entry lookup: %s", hipGetErrorString(e));
   return STB_OK;
 }
 
@@ -902,18 +969,17 @@ stb_status stb_potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_param
   stb_status s;
   if ((s = stb_ensure_gl(ctx, p.n_g))) return s;
   double* d_I = nullptr;
-  ApexBox* d_box = nullptr;
   int64_t* d_rowptr = nullptr;
   int32_t *d_cols = nullptr, *d_rowof = nullptr;
   auto cleanup = [&]() {
-    dfree(d_I); dfree(d_box); dfree(d_rowptr); dfree(d_cols); dfree(d_rowof);
+    dfree(d_I); dfree(d_rowptr); dfree(d_cols); dfree(d_rowof);
   };
-  if (dalloc(&d_box, (size_t)np) != hipSuccess) return fail(ctx, STB_E_NO_MEMORY, "potential buffers");
-  hipLaunchKernelGGL(k_point_boxes, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, ctx->stream, np,
-                     d_pts, d_box);
+  HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+  HIPCHK(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
   int64_t nnz = 0;
-  s = stb_cull(ctx, np, d_box, mesh, &d_rowptr, &d_cols, &d_rowof, &nnz);
+  s = stb_cull_points(ctx, mesh, p, np, d_pts, &d_rowptr, &d_cols, &d_rowof, &nnz);
   if (s) { cleanup(); return s; }
+  HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
   if (dalloc(&d_I, (size_t)nnz) != hipSuccess) { cleanup(); return fail(ctx, STB_E_NO_MEMORY, "candidates"); }
   PairJob J;
   J.nnz = nnz;
@@ -936,9 +1002,16 @@ stb_status stb_potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_param
   hipLaunchKernelGGL(k_point_sum, dim3((unsigned)((np * 64 + 255) / 256)), dim3(256), 0, ctx->stream, np,
                      d_rowptr, d_cols, d_I, d_w, d_out);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[3], ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   cleanup();
   if (e != hipSuccess) return fail(ctx, STB_E_DEVICE, "potential failed: %s", hipGetErrorString(e));
+  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+  (void)hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
+  (void)hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
+  (void)hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
+  (void)hipEventElapsedTime(&t03, ctx->ev[0], ctx->ev[3]);
+  ctx->timings[0] = t01; ctx->timings[1] = t12; ctx->timings[2] = t23; ctx->timings[3] = t03;
   return STB_OK;
 }
 
@@ -1045,6 +1118,12 @@ stb_status stb_last_kernel_times(const stb_ctx* ctx, double* ms8, int64_t* launc
 stb_status stb_last_path_counts(const stb_ctx* ctx, int64_t* counts4) {
   if (!ctx || !counts4) return fail(nullptr, STB_E_INVALID_ARG, "NULL argument");
   for (int k = 0; k < 4; ++k) counts4[k] = ctx->path_counts[k];
+  return STB_OK;
+}
+
+stb_status stb_last_lit_search(const stb_ctx* ctx, int64_t* counts3) {
+  if (!ctx || !counts3) return fail(nullptr, STB_E_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 3; ++k) counts3[k] = ctx->lit_search[k];
   return STB_OK;
 }
 

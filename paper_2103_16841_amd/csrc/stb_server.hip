@@ -131,23 +131,21 @@ stb_status footprint(stb_ctx* c, const ServedMesh& sm, const stb_request& r, int
     *bytes = matvec_bytes(sm.mat);
     return STB_OK;
   }
-  // boxes of the points, then the cull's count pass
-  ApexBox* box = nullptr;
+  // the points' lit search, as the request will run it, for its count
   double* pts = nullptr;
-  if (dalloc(&box, (size_t)r.np) != hipSuccess || dalloc(&pts, (size_t)r.np * 4) != hipSuccess) {
-    dfree(box); dfree(pts);
-    return stb_fail(c, STB_E_NO_MEMORY, "footprint buffers");
-  }
+  if (dalloc(&pts, (size_t)r.np * 4) != hipSuccess) return stb_fail(c, STB_E_NO_MEMORY, "footprint buffers");
   stb_status s = STB_OK;
   int64_t nnz = 0;
   hipError_t e = hipMemcpyAsync(pts, r.pts, sizeof(double) * 4 * r.np, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) {
-    stb_point_boxes(c, r.np, pts, box);
-    s = stb_cull_count(c, r.np, box, sm.mesh, &nnz);
+    int64_t* rp = nullptr;
+    int32_t *cols = nullptr, *rowof = nullptr;
+    stb_quad_params p = stb_default_params();
+    s = stb_cull_points(c, sm.mesh, p, r.np, pts, &rp, &cols, &rowof, &nnz);
+    dfree(rp); dfree(cols); dfree(rowof);
   } else {
     s = stb_fail(c, STB_E_DEVICE, "copy in");
   }
-  dfree(box);
   dfree(pts);
   *bytes = potential_bytes(sm.mesh->nt, r.np, nnz);
   *ws = stb_pairs_ws_need(c, nnz, 1);
@@ -274,6 +272,14 @@ stb_status stb_server_add_mesh(stb_server* S, const stb_mesh* mesh, const stb_ma
     stb_status s = stb_build_blocked(S->ctx, M, S->ctx->stream);
     if (s) return s;
     HIPCHK(S->ctx, hipStreamSynchronize(S->ctx->stream));
+  }
+  {
+    // the lit-search tree for the requests' parameters, built once here
+    const stb_quad_params p = stb_default_params();
+    if (p.lit_search == STB_LIT_TREE) {
+      stb_status s = stb_ensure_tree(S->ctx, const_cast<stb_mesh*>(mesh), p.n_min);
+      if (s) return s;
+    }
   }
   std::lock_guard<std::mutex> lk(S->mu);
   S->meshes.push_back({const_cast<stb_mesh*>(mesh), M});

@@ -91,6 +91,30 @@ def cube_surface():
     return pts, np.array(tris, dtype=np.int64)
 
 
+def cube_surface_refined(level):
+    """cube_surface() with `level` midpoint subdivisions of every triangle
+    (12 * 4^level triangles, vertices on the cube's faces)."""
+    pts, tris = cube_surface()
+    verts = [p for p in pts]
+    faces = [tuple(t) for t in tris]
+    for _ in range(level):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                verts.append(0.5 * (verts[a] + verts[b]))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    return np.array(verts), np.array([sorted(f) for f in faces], dtype=np.int64)
+
+
 def icosphere(level):
     """Unit icosphere: icosahedron with `level` midpoint subdivisions."""
     p = (1.0 + 5 ** 0.5) / 2.0
@@ -145,11 +169,13 @@ def extrude(pts, tris, S, T, jitter=0.0, rng=None, name=""):
     return Mesh(vtx, tets.reshape(-1, 4).astype(np.int32), tris, S, T, name)
 
 
-def cube_mesh(S=4, T=2.0, jitter=0.0, seed=0):
-    """Unit-cube surface x (0,T), S slabs (144 panels for S=4)."""
-    pts, tris = cube_surface()
+def cube_mesh(S=4, T=2.0, jitter=0.0, seed=0, level=0):
+    """Unit-cube surface x (0,T), S slabs (144 panels for S=4); level > 0:
+    the surface triangles subdivided level times."""
+    pts, tris = cube_surface() if level == 0 else cube_surface_refined(level)
     rng = np.random.default_rng(seed)
-    return extrude(pts, tris, S, T, jitter, rng, name="cube_S%d_T%g" % (S, T))
+    name = "cube_S%d_T%g" % (S, T) if level == 0 else "cube_L%d_S%d_T%g" % (level, S, T)
+    return extrude(pts, tris, S, T, jitter, rng, name=name)
 
 
 def icosphere_mesh(level=2, S=32, T=4.0, jitter=0.2, seed=2):

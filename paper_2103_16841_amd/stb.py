@@ -21,8 +21,8 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_last_error", "stb_mesh_create", "stb_mesh_destroy", "stb_mesh_size",
            "stb_assemble_V", "stb_mat_destroy", "stb_mat_info", "stb_mat_to_dense", "stb_mat_get",
            "stb_apply", "stb_apply_dev", "stb_apply16_noalloc", "stb_potential_S", "stb_potential_S_dev",
-           "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_last_path_counts", "stb_mesh_create_dev",
-           "stb_outer_points", "stb_outer_rhs", "stb_solve_gmres", "stb_mesh_set_normals", "stb_potential_D",
+           "stb_inner_values", "stb_last_timings", "stb_last_work", "stb_last_lit_search", "stb_last_path_counts", "stb_mesh_create_dev",
+           "stb_outer_points", "stb_outer_rhs", "stb_solve_gmres", "stb_solve_mot", "stb_mesh_set_normals", "stb_potential_D",
            "stb_potential_D_dev", "stb_inner_values_D", "stb_dl_energetic",
            "stb_l2_points", "stb_project_V1",
            "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble", "stb_autotune",
@@ -35,9 +35,12 @@ KERNEL_KINDS = ["lit", "breakpoints", "empty_test", "mixed_restore", "nodes_fp64
                 "sums_store", "mixed_redo_nodes"]
 
 
+STB_LIT_TREE, STB_LIT_FLAT = 0, 1
+
+
 class QuadParams(ctypes.Structure):
     _fields_ = [("m_q", ctypes.c_int32), ("n_g", ctypes.c_int32), ("eta_far", ctypes.c_double),
-                ("prec", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("lit_search", ctypes.c_int32), ("n_min", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -103,11 +106,13 @@ def load():
     L.stb_l2_points.argtypes = [_VP, _VP, _D, _D]
     L.stb_project_V1.argtypes = [_VP, _VP, _D, _D, ctypes.POINTER(ctypes.c_int32)]
     L.stb_last_work.argtypes = [_VP, _I64]
+    L.stb_last_lit_search.argtypes = [_VP, _I64]
     L.stb_last_path_counts.argtypes = [_VP, _I64]
     L.stb_outer_points.argtypes = [_VP, _VP, i32, _D, _D, _I32]
     L.stb_outer_rhs.argtypes = [_VP, _VP, i32, _D, _D]
     L.stb_solve_gmres.argtypes = [_VP, _VP, _D, _D, i32, i32, ctypes.c_double, _I32,
                                   ctypes.POINTER(ctypes.c_double)]
+    L.stb_solve_mot.argtypes = [_VP, _VP, _VP, _D, _D, _D]
     L.stb_last_kernel_times.argtypes = [_VP, _D, _I64, _I64]
     L.stb_mat_export.argtypes = [_VP, _I64, _I32, _D]
     L.stb_autotune.argtypes = [_VP, _VP, ctypes.POINTER(QuadParams), _I32]
@@ -134,8 +139,12 @@ def _chk(st, ctx=None):
         raise StbError(st, msg.decode() if msg else "")
 
 
-def default_params(n_g=None, m_q=None, prec=None, eta_far=None):
+def default_params(n_g=None, m_q=None, prec=None, eta_far=None, lit_search=None, n_min=None):
     p = load().stb_default_params()
+    if lit_search is not None:
+        p.lit_search = lit_search
+    if n_min is not None:
+        p.n_min = n_min
     if n_g is not None:
         p.n_g = n_g
     if m_q is not None:
@@ -210,6 +219,14 @@ class Context:
         _chk(load().stb_last_work(self.h, out.ctypes.data_as(_I64)), self.h)
         return dict(L_evals=int(out[0]), lit_pairs=int(out[1]), apex_pairs=int(out[2]),
                     pieces=int(out[3]))
+
+    def lit_search(self):
+        """The last potential's lit search: (point, leaf) pairs kept by the
+        tree, panels in those leaves (|X_N| summed over the points), candidates
+        after the per-panel bound test."""
+        out = np.zeros(3, dtype=np.int64)
+        _chk(load().stb_last_lit_search(self.h, out.ctypes.data_as(_I64)), self.h)
+        return dict(leaf_pairs=int(out[0]), leaf_panels=int(out[1]), candidates=int(out[2]))
 
     def path_counts(self):
         """Evaluations of L in the FP64 Gauss-node launches of the last run by
@@ -430,6 +447,19 @@ def solve_gmres(ctx, A, b, x0=None, restart=100, maxit=2000, rtol=1e-10):
     _chk(load().stb_solve_gmres(ctx.h, A.h, pb, x.ctypes.data_as(_D), restart, maxit, rtol,
                                 ctypes.byref(it), ctypes.byref(rr)), ctx.h)
     return x, it.value, rr.value
+
+
+def solve_mot(ctx, mesh, A, b):
+    """x with A x = b by marching-on-in-time (slab-structured, unjittered
+    meshes); returns (x, info) with info = dict(slabs, panels_per_slab,
+    inversion_ms, march_ms)."""
+    b, pb = _vec(b, A.n, "b")
+    x = np.zeros(A.n)
+    info = np.zeros(4)
+    _chk(load().stb_solve_mot(ctx.h, mesh.h, A.h, pb, x.ctypes.data_as(_D), info.ctypes.data_as(_D)),
+         ctx.h)
+    return x, dict(slabs=int(info[0]), panels_per_slab=int(info[1]), inversion_ms=float(info[2]),
+                   march_ms=float(info[3]))
 
 
 def inner_values(ctx, mesh, pts, panels, params=None):

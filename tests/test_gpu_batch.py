@@ -74,6 +74,32 @@ def test_batch_small_meshes_vs_oracle(stb, ctx, mix):
         assert M.n_causal == np.count_nonzero(ref)
 
 
+def test_batch_largest_mesh_sampled_rows(stb, ctx):
+    """The batched workload at full size: the largest mesh of the 64-mesh
+    seeded mix (icosphere level 3, 226,560 panels) through the batched entry
+    point, 16 seeded rows with every column against the oracle (per-entry
+    bound), the causal count of those rows, and the store's causal-only
+    layout."""
+    full = inputs.batch_mix(count=64, seed=3)
+    big = max(full, key=lambda m: m.nt)
+    print("case: batch mix seed 3, largest mesh", big.name, "N =", big.nt, flush=True)
+    m = stb.Mesh(ctx, big.vtx, big.tets)
+    (A,) = stb.batch_assemble(ctx, [m])
+    print("assembled: causal", A.n_causal, "stored", A.n_stored, flush=True)
+    assert A.n_stored == A.n_causal
+    rows = np.sort(np.random.default_rng(29).choice(big.nt, 16, replace=False))
+    ref, mag, pert = oracle_rows(big.vtx, big.tets, rows=rows)
+    rr = np.repeat(rows, big.nt).astype(np.int32)
+    cc = np.tile(np.arange(big.nt), rows.size).astype(np.int32)
+    got = A.get(rr, cc).reshape(rows.size, big.nt)
+    assert_entries(got, ref, mag, pert, what=big.name)
+    assert np.array_equal(got != 0.0, ref != 0.0)
+    per = oracle.count_causal_per_row(big.vtx, big.tets, rows=rows)
+    assert np.array_equal((got != 0.0).sum(axis=1), per)
+    A.close()
+    m.close()
+
+
 def test_batch_apply_in_waves(stb, ctx, mix):
     """Products computed wave by wave without keeping the matrices equal the
     products of the kept matrices.  One budget holds about a third of the

@@ -115,3 +115,67 @@ def test_sphere_time_only_density(stb, ctx):
     e2 = _sphere_error(stb, ctx, 2, 32)
     assert e2 < e1
     assert e2 < 0.1
+
+
+# ------------------------------------------------ marching-on-in-time
+
+@pytest.mark.parametrize("which", ["cube", "icosphere"])
+def test_mot_equals_gmres_and_dense_oracle_solve(stb, ctx, which):
+    """Unjittered slab meshes: marching-on-in-time (block forward
+    substitution over the slabs with the inverted diagonal block) solves the
+    same system as GMRES and as a dense solve of the oracle's matrix."""
+    mesh = inputs.cube_mesh(S=4, T=2.0) if which == "cube" else \
+        inputs.icosphere_mesh(level=0, S=6, T=3.0, jitter=0.0, seed=0)
+    print("case: MOT on", mesh.name, "N=%d" % mesh.nt, flush=True)
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    A = stb.assemble_V(ctx, m)
+    b = stb.energetic_rhs(ctx, m, lambda p: g_sphere(p[:, 0]) * (1.0 + 0.3 * p[:, 1]))
+    x, info = stb.solve_mot(ctx, m, A, b)
+    print("MOT", info, flush=True)
+    assert info["slabs"] == mesh.S and info["panels_per_slab"] * mesh.S == mesh.nt
+    xg, its, rr = stb.solve_gmres(ctx, A, b, restart=100, maxit=4000, rtol=1e-13)
+    D = A.to_dense()
+    xd = np.linalg.solve(D, b)                 # the same matrix, dense LAPACK solve
+    ref = oracle.assemble_rows(mesh.vtx, mesh.tets)
+    xo = np.linalg.solve(ref, b)               # the oracle's matrix
+    nb, nx = np.linalg.norm(b), np.linalg.norm(xd)
+    cond = np.linalg.cond(D)
+    e_d = np.linalg.norm(x - xd) / nx
+    e_g = np.linalg.norm(x - xg) / nx
+    e_o = np.linalg.norm(x - xo) / nx
+    r_o = np.linalg.norm(ref @ x - b) / nb
+    print("cond %.2e: |x-x_dense|/|x| %.2e, |x-x_gmres| %.2e, |x-x_oracle| %.2e, oracle residual %.2e"
+          % (cond, e_d, e_g, e_o, r_o), flush=True)
+    assert np.linalg.norm(D @ x - b) <= 1e-13 * nb
+    assert e_d <= 1e-12 and e_g <= 1e-10 and e_o <= 1e-10
+    assert r_o <= 1e-10
+
+
+def test_mot_refuses_unstructured_meshes(stb, ctx):
+    """Jittered time levels break the slab structure: STB_E_INVALID_ARG."""
+    mesh = inputs.icosphere_mesh(level=0, S=4, T=2.0, jitter=0.2, seed=3)
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    A = stb.assemble_V(ctx, m)
+    with pytest.raises(stb.StbError) as e:
+        stb.solve_mot(ctx, m, A, np.ones(mesh.nt))
+    assert e.value.status == 1
+    with pytest.raises(ValueError):
+        stb.solve_mot(ctx, m, A, np.ones(mesh.nt + 1))
+
+
+def test_mot_sphere_time_only_density(stb, ctx):
+    """The sphere's closed form by marching-on-in-time (level 1 x 16 slabs):
+    the same solution as GMRES, and f(t) at the centroids to the
+    discretisation error GMRES reaches."""
+    mesh = inputs.icosphere_mesh(level=1, S=16, T=4.0, jitter=0.0, seed=0)
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    A = stb.assemble_V(ctx, m)
+    b = stb.energetic_rhs(ctx, m, lambda p: g_sphere(p[:, 0]))
+    x, info = stb.solve_mot(ctx, m, A, b)
+    xg, its, rr = stb.solve_gmres(ctx, A, b, restart=100, maxit=20000, rtol=1e-12)
+    tc = mesh.vtx[mesh.tets][:, :, 0].mean(axis=1)
+    exact = f_density(tc)
+    err = np.linalg.norm(x - exact) / np.linalg.norm(exact)
+    print("case: sphere L1 S16 MOT", info, "GMRES products", its, "rel. L2 error %.3e" % err, flush=True)
+    assert np.linalg.norm(x - xg) <= 1e-9 * np.linalg.norm(x)
+    assert err < 0.25
