@@ -262,14 +262,15 @@ __global__ __launch_bounds__(256) void k_point_sum(int64_t np, const int64_t* __
                                                    const double* __restrict__ I,
                                                    const double* __restrict__ w,
                                                    double* __restrict__ out) {
-  int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
-  if (i >= np) return;
-  double s = 0.0;
-  for (int64_t c = rowptr[i] + lane; c < rowptr[i + 1]; c += 64)
-    if (I[c] != 0.0) s += w[cols[c]] * I[c];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) out[i] = s;
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < np; i += waves) {
+    double s = 0.0;
+    for (int64_t c = rowptr[i] + lane; c < rowptr[i + 1]; c += 64)
+      if (I[c] != 0.0) s += w[cols[c]] * I[c];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) out[i] = s;
+  }
 }
 
 // y = A w (FP64 CSR), one wavefront per row, fixed-order reduction.
@@ -278,14 +279,15 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
                                               const double* __restrict__ vals,
                                               const double* __restrict__ w, int nrhs, int col,
                                               double* __restrict__ y) {
-  int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  double s = 0.0;
-  for (int64_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64)
-    s += vals[k] * w[(int64_t)cols[k] * nrhs + col];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) y[row * nrhs + col] = s;
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; row < n; row += waves) {
+    double s = 0.0;
+    for (int64_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64)
+      s += vals[k] * w[(int64_t)cols[k] * nrhs + col];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) y[row * nrhs + col] = s;
+  }
 }
 
 // Compaction of a store to its causal entries: one wavefront per row counts
@@ -596,8 +598,8 @@ stb_quad_params stb_default_params(void) {
   p.n_g = 16;
   p.eta_far = 0.5;
   p.prec = STB_FP64;
-  p.lit_search = STB_LIT_TREE;
-  p.n_min = 8;
+  p.lit_search = STB_LIT_FLAT;
+  p.n_min = 64;
   return p;
 }
 
@@ -931,7 +933,7 @@ stb_status stb_apply_dev(stb_ctx* ctx, const stb_mat* M, int32_t nrhs, const dou
   int64_t threads = M->n * 64;
   for (int c = 0; c < nrhs; ++c) {
     if (M->n > 0) {
-      hipLaunchKernelGGL(k_spmv, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, M->n,
+      hipLaunchKernelGGL(k_spmv, dim3((unsigned)std::min<int64_t>((threads + 255) / 256, 1 << 20)), dim3(256), 0, st, M->n,
                          M->d_rowptr, M->d_cols, M->d_vals, w, nrhs, c, y);
       HIPCHK(ctx, hipGetLastError());
     }
@@ -999,8 +1001,8 @@ stb_status stb_potential_core(stb_ctx* ctx, stb_mesh* mesh, const stb_quad_param
   s = stb_run_pairs(ctx, J, work);
   if (s) { cleanup(); return s; }
   for (int k = 0; k < 4; ++k) ctx->work[k] = (int64_t)work[k];
-  hipLaunchKernelGGL(k_point_sum, dim3((unsigned)((np * 64 + 255) / 256)), dim3(256), 0, ctx->stream, np,
-                     d_rowptr, d_cols, d_I, d_w, d_out);
+  hipLaunchKernelGGL(k_point_sum, dim3((unsigned)std::min<int64_t>((np * 64 + 255) / 256, 1 << 20)), dim3(256), 0,
+                     ctx->stream, np, d_rowptr, d_cols, d_I, d_w, d_out);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[3], ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);

@@ -408,8 +408,8 @@ enum { JOB_R1Q = 0, JOB_R2 = 1, JOB_FULL = 2, JOB_FP32 = 3, JOB_R1X = 4 };
 // within rounding of the breakpoints, where the structure is ambiguous.
 constexpr double kRecipeMinH = 1e-8;
 
-__device__ __forceinline__ unsigned route_of(const Lists& L, int32_t p, uint32_t rec) {
-  if ((L.key[L.pc[p]] >> 7) & 1u) return JOB_FP32;
+// Route of a non-empty piece among the FP64 node kernels by its recipe.
+__device__ __forceinline__ unsigned route_fp64(const Lists& L, int32_t p, uint32_t rec) {
   const double H = L.ph[p];
   const int ng = recipe_gaps(rec);
   if (rec == 0u || !(H >= kRecipeMinH)) return JOB_FULL;
@@ -417,6 +417,11 @@ __device__ __forceinline__ unsigned route_of(const Lists& L, int32_t p, uint32_t
   const uint32_t i0 = (rec >> 4) & 15u, i1 = rec & 15u;
   const bool qe = i0 >= 2 && i1 >= 2 && !((i0 - 2) & 1u) && !((i1 - 2) & 1u);
   return qe ? JOB_R1Q : JOB_R1X;
+}
+
+__device__ __forceinline__ unsigned route_of(const Lists& L, int32_t p, uint32_t rec) {
+  if ((L.key[L.pc[p]] >> 7) & 1u) return JOB_FP32;
+  return route_fp64(L, p, rec);
 }
 
 __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
@@ -512,7 +517,7 @@ __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
 template <int NG, bool QE>
 __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* __restrict__ jobs,
                                                        int64_t njob, const double* __restrict__ gl,
-                                                       int ng) {
+                                                       int ng, int ctr) {
   const int B = (int)blockDim.x;
   unsigned long long evals = 0;
   for (int64_t base = (int64_t)blockIdx.x * B; base < njob; base += (int64_t)gridDim.x * B) {
@@ -566,7 +571,7 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
     evals += (unsigned long long)ng;
     L.pv[p] = acc;
   }
-  block_count(L.cnt + CNT_EVAL_NODES, evals);
+  block_count(L.cnt + ctr, evals);
 }
 
 // The n_g nodes of one piece.  Gauss piece [a, a + H]: phi = a + H s(u_g),
@@ -636,8 +641,10 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes32(Lists L, int64_t njob,
     }
     evals += (unsigned long long)ng;
     L.pv[p] = (double)acc;
-    // the bound also covers the summation: Kahan leaves O(ulp) of the sum
-    L.pe[p] = eacc + 1.2e-7f * fabsf(acc);
+    // the bound also covers the summation: Kahan leaves O(ulp) of the sum.
+    // The piece is non-empty (its FP64 test found L > 0): a sum of zero means
+    // FP32 lost the whole lit sliver, so the entry must be recomputed.
+    L.pe[p] = acc == 0.0f ? INFINITY : eacc + 1.2e-7f * fabsf(acc);
   }
   block_count(L.cnt + CNT_EVAL_NODES32, evals);
 }
@@ -746,28 +753,42 @@ __global__ __launch_bounds__(kBlk) void k_store(Geo g, Lists L, int64_t c0, int6
 }
 
 // Mixed precision: the non-empty pieces of the far combos of every flagged
-// candidate go to the FP64 job list again.
+// candidate go to the FP64 node kernels again, routed by their recipes as in
+// the FP64 pass (the job lists and their counters start empty), so that a
+// recomputed entry is the FP64 assembly's value through the same outer
+// points, bit for bit.
 __global__ __launch_bounds__(kBlk) void k_redo(Geo g, Lists L, int64_t nc) {
   __shared__ AllocLds sh;
   for (int64_t base = (int64_t)blockIdx.x * kBlk; base < nc; base += (int64_t)gridDim.x * kBlk) {
     const int64_t c = base + threadIdx.x;
     const bool v = c < nc && L.redo[c];
-    unsigned n = 0;
+    unsigned cnt[5] = {0, 0, 0, 0, 0};
     int32_t k0 = 0, nk = 0;
     if (v) {
       k0 = L.combo0[c];
       nk = __popcll(L.mask[c]);
       for (int32_t k = k0; k < k0 + nk; ++k) {
         if (!((L.key[k] >> 7) & 1u)) continue;
-        for (int32_t p = L.p0[k]; p < L.p0[k] + L.np[k]; ++p) n += L.pne[p];
+        for (int32_t p = L.p0[k]; p < L.p0[k] + L.np[k]; ++p)
+          if (L.pne[p]) ++cnt[route_fp64(L, p, L.prec[p])];
       }
     }
-    unsigned long long s = block_alloc(L.cnt + CNT_JOBR, n, sh);
+    unsigned long long sl[5];
+    sl[JOB_R1Q] = block_alloc(L.cnt + CNT_JOB, cnt[JOB_R1Q], sh);
+    sl[JOB_R2] = block_alloc(L.cnt + CNT_JOB2, cnt[JOB_R2], sh);
+    sl[JOB_FULL] = block_alloc(L.cnt + CNT_JOBF, cnt[JOB_FULL], sh);
+    sl[JOB_R1X] = block_alloc(L.cnt + CNT_JOB1X, cnt[JOB_R1X], sh);
     if (v) {
       for (int32_t k = k0; k < k0 + nk; ++k) {
         if (!((L.key[k] >> 7) & 1u)) continue;
-        for (int32_t p = L.p0[k]; p < L.p0[k] + L.np[k]; ++p)
-          if (L.pne[p]) L.job[s++] = p;
+        for (int32_t p = L.p0[k]; p < L.p0[k] + L.np[k]; ++p) {
+          if (!L.pne[p]) continue;
+          const unsigned r = route_fp64(L, p, L.prec[p]);
+          if (r == JOB_R1X) L.job[L.cap_piece - 1 - (int64_t)(sl[r]++)] = p;
+          else if (r == JOB_R1Q) L.job[sl[r]++] = p;
+          else if (r == JOB_R2) L.job2[sl[r]++] = p;
+          else L.jobf[sl[r]++] = p;
+        }
       }
     }
   }
@@ -1014,14 +1035,14 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       HIPCHK(ctx, t0(4));
       if (njob)
         hipLaunchKernelGGL((k_nodes_rec<1, true>), dim3(gfor(4, njob)), dim3(ctx->tune_block[4]), 0, st,
-                           L, L.job, (int64_t)njob, job.gl, job.ng);
+                           L, L.job, (int64_t)njob, job.gl, job.ng, (int)CNT_EVAL_NODES);
       if (njob1x)
         hipLaunchKernelGGL((k_nodes_rec<1, false>), dim3(gfor(4, njob1x)), dim3(ctx->tune_block[4]), 0,
                            st, L, L.job + (L.cap_piece - (int64_t)njob1x), (int64_t)njob1x, job.gl,
-                           job.ng);
+                           job.ng, (int)CNT_EVAL_NODES);
       if (njob2)
         hipLaunchKernelGGL((k_nodes_rec<2, false>), dim3(gfor(4, njob2)), dim3(ctx->tune_block[4]), 0,
-                           st, L, L.job2, (int64_t)njob2, job.gl, job.ng);
+                           st, L, L.job2, (int64_t)njob2, job.gl, job.ng, (int)CNT_EVAL_NODES);
       if (njobf)
         hipLaunchKernelGGL(k_nodes, dim3(gfor(4, njobf)), dim3(ctx->tune_block[4]), 0, st, L, L.jobf,
                            (int64_t)njobf, job.gl, job.ng, (int)CNT_EVAL_NODES);
@@ -1052,17 +1073,35 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       unsigned long long nredo = 0, njr = 0;
       if ((s = rd(CNT_REDO, &nredo))) return s;
       if (nredo) {
+        // the FP64 job lists were consumed by the launches above (same stream)
+        HIPCHK(ctx, hipMemsetAsync(L.cnt + CNT_JOB, 0, 4 * sizeof(unsigned long long), st));
+        static_assert(CNT_JOB1X == CNT_JOB + 1 && CNT_JOB2 == CNT_JOB + 2 && CNT_JOBF == CNT_JOB + 3,
+                      "job counters contiguous");
         hipLaunchKernelGGL(k_redo, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, nc);
         HIPCHK(ctx, hipGetLastError());
-        if ((s = rd(CNT_JOBR, &njr))) return s;
-      }
-      if (njr) {
-        HIPCHK(ctx, t0(7));
-        hipLaunchKernelGGL(k_nodes, dim3(gfor(4, njr)), dim3(ctx->tune_block[4]), 0, st, L, L.job,
-                           (int64_t)njr,
-                           job.gl, job.ng, (int)CNT_EVAL_REDO);
-        HIPCHK(ctx, hipGetLastError());
-        HIPCHK(ctx, t1(7));
+        unsigned long long hr[CNT_N];
+        HIPCHK(ctx, hipMemcpyAsync(hr, L.cnt, sizeof(hr), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        const unsigned long long r1 = hr[CNT_JOB], r1x = hr[CNT_JOB1X], r2 = hr[CNT_JOB2], rf = hr[CNT_JOBF];
+        njr = r1 + r1x + r2 + rf;
+        if (njr) {
+          HIPCHK(ctx, t0(7));
+          if (r1)
+            hipLaunchKernelGGL((k_nodes_rec<1, true>), dim3(gfor(4, r1)), dim3(ctx->tune_block[4]), 0, st, L,
+                               L.job, (int64_t)r1, job.gl, job.ng, (int)CNT_EVAL_REDO);
+          if (r1x)
+            hipLaunchKernelGGL((k_nodes_rec<1, false>), dim3(gfor(4, r1x)), dim3(ctx->tune_block[4]), 0, st,
+                               L, L.job + (L.cap_piece - (int64_t)r1x), (int64_t)r1x, job.gl, job.ng,
+                               (int)CNT_EVAL_REDO);
+          if (r2)
+            hipLaunchKernelGGL((k_nodes_rec<2, false>), dim3(gfor(4, r2)), dim3(ctx->tune_block[4]), 0, st,
+                               L, L.job2, (int64_t)r2, job.gl, job.ng, (int)CNT_EVAL_REDO);
+          if (rf)
+            hipLaunchKernelGGL(k_nodes, dim3(gfor(4, rf)), dim3(ctx->tune_block[4]), 0, st, L, L.jobf,
+                               (int64_t)rf, job.gl, job.ng, (int)CNT_EVAL_REDO);
+          HIPCHK(ctx, hipGetLastError());
+          HIPCHK(ctx, t1(7));
+        }
       }
       HIPCHK(ctx, t0(3));
       if (njr)

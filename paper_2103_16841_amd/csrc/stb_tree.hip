@@ -60,6 +60,13 @@ __device__ __forceinline__ bool ball_maybe_lit(const double* __restrict__ x, con
 
 constexpr int kTreeThreads = 256;
 
+// Blocks for n threads' worth of work, capped: the kernels loop over their
+// items (a dispatch holds fewer than 2^32 work-items).
+inline unsigned tree_grid(int64_t nthreads) {
+  const int64_t b = (nthreads + kTreeThreads - 1) / kTreeThreads;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)1 << 20));
+}
+
 // Level of the descent: cnt[e] = 2 (inner cluster) or 1 (leaf, on the last
 // level) when entry e = (point, cluster) survives, else 0.
 __global__ __launch_bounds__(kTreeThreads) void k_tree_test(int64_t nf, const int32_t* __restrict__ fp,
@@ -67,11 +74,11 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_test(int64_t nf, const in
                                                             const double* __restrict__ pts,
                                                             const Ball* __restrict__ balls, int last,
                                                             int64_t* __restrict__ cnt) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nf) return;
-  const double* x = pts + 4 * (int64_t)fp[e];
-  const bool keep = ball_maybe_lit(x, balls[fv[e]]);
-  cnt[e] = keep ? (last ? 1 : 2) : 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += (int64_t)gridDim.x * blockDim.x) {
+    const double* x = pts + 4 * (int64_t)fp[e];
+    const bool keep = ball_maybe_lit(x, balls[fv[e]]);
+    cnt[e] = keep ? (last ? 1 : 2) : 0;
+  }
 }
 
 // Survivors' sons (heap order: sons of v are 2v + 1, 2v + 2) or, on the last
@@ -80,18 +87,18 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_push(int64_t nf, const in
                                                             const int32_t* __restrict__ fv,
                                                             const int64_t* __restrict__ off, int last,
                                                             int32_t* __restrict__ np_, int32_t* __restrict__ nv_) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nf) return;
-  const int64_t o = off[e], n = off[e + 1] - o;
-  if (n == 0) return;
-  if (last) {
-    np_[o] = fp[e];
-    nv_[o] = fv[e];
-  } else {
-    np_[o] = fp[e];
-    nv_[o] = 2 * fv[e] + 1;
-    np_[o + 1] = fp[e];
-    nv_[o + 1] = 2 * fv[e] + 2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = off[e], n = off[e + 1] - o;
+    if (n == 0) continue;
+    if (last) {
+      np_[o] = fp[e];
+      nv_[o] = fv[e];
+    } else {
+      np_[o] = fp[e];
+      nv_[o] = 2 * fv[e] + 1;
+      np_[o + 1] = fp[e];
+      nv_[o + 1] = 2 * fv[e] + 2;
+    }
   }
 }
 
@@ -123,18 +130,19 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_leafcount(int64_t nf, con
                                                                  const PanelBound* __restrict__ pb,
                                                                  const double* __restrict__ pts,
                                                                  int64_t* __restrict__ cnt) {
-  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (e >= nf) return;
-  const double* x = pts + 4 * (int64_t)fp[e];
-  const int64_t l = fv[e] - first_leaf;
-  const int64_t b = leafptr[l], n = leafptr[l + 1] - b;
-  int64_t c = 0;
-  for (int64_t k0 = 0; k0 < n; k0 += 64) {
-    const bool ok = k0 + lane < n && panel_maybe_lit(x, pb[b + k0 + lane]);
-    c += __popcll(__ballot(ok));
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < nf; e += waves) {
+    const double* x = pts + 4 * (int64_t)fp[e];
+    const int64_t l = fv[e] - first_leaf;
+    const int64_t b = leafptr[l], n = leafptr[l + 1] - b;
+    int64_t c = 0;
+    for (int64_t k0 = 0; k0 < n; k0 += 64) {
+      const bool ok = k0 + lane < n && panel_maybe_lit(x, pb[b + k0 + lane]);
+      c += __popcll(__ballot(ok));
+    }
+    if (lane == 0) cnt[e] = c;
   }
-  if (lane == 0) cnt[e] = c;
 }
 
 __global__ __launch_bounds__(kTreeThreads) void k_tree_leaffill(int64_t nf, const int32_t* __restrict__ fp,
@@ -147,24 +155,25 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_leaffill(int64_t nf, cons
                                                                 const int64_t* __restrict__ off,
                                                                 int32_t* __restrict__ rows,
                                                                 int32_t* __restrict__ cols) {
-  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (e >= nf) return;
-  const int32_t p = fp[e];
-  const double* x = pts + 4 * (int64_t)p;
-  const int64_t l = fv[e] - first_leaf;
-  const int64_t b = leafptr[l], n = leafptr[l + 1] - b;
-  int64_t o = off[e];
-  for (int64_t k0 = 0; k0 < n; k0 += 64) {
-    const bool ok = k0 + lane < n && panel_maybe_lit(x, pb[b + k0 + lane]);
-    const uint64_t bal = __ballot(ok);
-    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-    if (ok) {
-      rows[o + rank] = p;
-      cols[o + rank] = perm[b + k0 + lane];
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < nf; e += waves) {
+    const int32_t p = fp[e];
+    const double* x = pts + 4 * (int64_t)p;
+    const int64_t l = fv[e] - first_leaf;
+    const int64_t b = leafptr[l], n = leafptr[l + 1] - b;
+    int64_t o = off[e];
+    for (int64_t k0 = 0; k0 < n; k0 += 64) {
+      const bool ok = k0 + lane < n && panel_maybe_lit(x, pb[b + k0 + lane]);
+      const uint64_t bal = __ballot(ok);
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+      if (ok) {
+        rows[o + rank] = p;
+        cols[o + rank] = perm[b + k0 + lane];
+      }
+      o += __popcll(bal);
     }
-    o += __popcll(bal);
   }
 }
 
@@ -174,11 +183,10 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_leafsize(int64_t nf, cons
                                                                 int64_t first_leaf,
                                                                 const int64_t* __restrict__ leafptr,
                                                                 unsigned long long* __restrict__ total) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long n = 0;
-  if (e < nf) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = fv[e] - first_leaf;
-    n = (unsigned long long)(leafptr[l + 1] - leafptr[l]);
+    n += (unsigned long long)(leafptr[l + 1] - leafptr[l]);
   }
   for (int off = 32; off > 0; off >>= 1) n += __shfl_down(n, off, 64);
   if ((threadIdx.x & 63) == 0 && n) atomicAdd(total, n);
@@ -189,22 +197,22 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_leafsize(int64_t nf, cons
 __global__ __launch_bounds__(kTreeThreads) void k_rows_to_ptr(int64_t np, int64_t nnz,
                                                               const int32_t* __restrict__ rows,
                                                               int64_t* __restrict__ rowptr) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p > np) return;
-  int64_t lo = 0, hi = nnz;
-  while (lo < hi) {
-    const int64_t mid = lo + ((hi - lo) >> 1);
-    if (rows[mid] < p) lo = mid + 1;
-    else hi = mid;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= np; p += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nnz;
+    while (lo < hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (rows[mid] < p) lo = mid + 1;
+      else hi = mid;
+    }
+    rowptr[p] = lo;
   }
-  rowptr[p] = lo;
 }
 
 __global__ void k_root_frontier(int64_t np, int32_t* __restrict__ fp, int32_t* __restrict__ fv) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
-  fp[p] = (int32_t)p;
-  fv[p] = 0;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    fp[p] = (int32_t)p;
+    fv[p] = 0;
+  }
 }
 
 }  // namespace
@@ -391,7 +399,7 @@ stb_status stb_tree_cull(stb_ctx* ctx, stb_mesh* m, int nmin, int64_t np, const 
     return stb_fail(ctx, STB_E_NO_MEMORY, "tree frontier");
   }
   if (np > 0)
-    hipLaunchKernelGGL(k_root_frontier, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, np, fp, fv);
+    hipLaunchKernelGGL(k_root_frontier, dim3(tree_grid(np)), dim3(kTreeThreads), 0, st, np, fp, fv);
   for (int d = 0; d <= T->depth && nf > 0; ++d) {
     const int last = d == T->depth;
     if (dalloc(&cnt, (size_t)nf) != hipSuccess || dalloc(&off, (size_t)nf + 1) != hipSuccess ||
@@ -399,7 +407,7 @@ stb_status stb_tree_cull(stb_ctx* ctx, stb_mesh* m, int nmin, int64_t np, const 
       cleanup();
       return stb_fail(ctx, STB_E_NO_MEMORY, "tree frontier of %lld entries", (long long)nf);
     }
-    const unsigned g = (unsigned)((nf + kTreeThreads - 1) / kTreeThreads);
+    const unsigned g = tree_grid(nf);
     hipLaunchKernelGGL(k_tree_test, dim3(g), dim3(kTreeThreads), 0, st, nf, fp, fv, d_pts, T->d_ball, last, cnt);
     hipError_t e = stb_scan<int64_t>(cnt, off, nf, tmp, st);
     int64_t nn = 0;
@@ -427,8 +435,8 @@ stb_status stb_tree_cull(stb_ctx* ctx, stb_mesh* m, int nmin, int64_t np, const 
     cleanup();
     return stb_fail(ctx, STB_E_NO_MEMORY, "tree leaves");
   }
-  const unsigned gw = (unsigned)((std::max<int64_t>(nf, 1) * 64 + kTreeThreads - 1) / kTreeThreads);
-  const unsigned g1 = (unsigned)((std::max<int64_t>(nf, 1) + kTreeThreads - 1) / kTreeThreads);
+  const unsigned gw = tree_grid(std::max<int64_t>(nf, 1) * 64);
+  const unsigned g1 = tree_grid(std::max<int64_t>(nf, 1));
   hipError_t e = hipMemsetAsync(d_union, 0, 8, st);
   if (nf > 0) {
     hipLaunchKernelGGL(k_tree_leafsize, dim3(g1), dim3(kTreeThreads), 0, st, nf, fv, first_leaf, T->d_leafptr,
@@ -458,7 +466,7 @@ stb_status stb_tree_cull(stb_ctx* ctx, stb_mesh* m, int nmin, int64_t np, const 
   if (nf > 0)
     hipLaunchKernelGGL(k_tree_leaffill, dim3(gw), dim3(kTreeThreads), 0, st, nf, fp, fv, first_leaf,
                        T->d_leafptr, T->d_pb, T->d_perm, d_pts, off, *d_rowof, *d_cols);
-  hipLaunchKernelGGL(k_rows_to_ptr, dim3((unsigned)((np + 1 + 255) / 256)), dim3(256), 0, st, np, total, *d_rowof,
+  hipLaunchKernelGGL(k_rows_to_ptr, dim3(tree_grid(np + 1)), dim3(kTreeThreads), 0, st, np, total, *d_rowof,
                      *d_rowptr);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -37,7 +37,7 @@ def test_status_strings_and_defaults():
     assert L.stb_status_str(0) == b"ok"
     assert L.stb_status_str(2) == b"invalid mesh"
     p = stb.default_params()
-    assert (p.m_q, p.n_g, p.prec) == (3, 16, 0)
+    assert (p.m_q, p.n_g, p.prec, p.lit_search, p.n_min) == (3, 16, 0, stb.STB_LIT_FLAT, 64)
 
 
 def test_null_arguments_are_rejected():

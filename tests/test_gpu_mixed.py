@@ -108,3 +108,26 @@ def test_icosphere_level2_sampled_rows(stb, ctx):
     assert np.array_equal(got != 0.0, ref != 0.0)
     A64 = stb.assemble_V(ctx, m)
     assert A64.n_causal == A.n_causal
+
+
+def test_mixed_against_fp64_through_the_same_points(stb, ctx):
+    """Every entry of the mixed assembly within 1e-6 (relative, no floor) of
+    the FP64 assembly through the same per-panel outer points (the mixed path
+    with no far pairs); the entries the mixed path recomputes in FP64 are
+    that assembly's values bit for bit."""
+    mesh = inputs.icosphere_mesh(level=1, S=8, T=4.0, jitter=0.2, seed=6)
+    print("case:", mesh.name, "mixed vs FP64 per panel", flush=True)
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    Amx = stb.assemble_V(ctx, m, stb.default_params(prec=stb.STB_MIXED, eta_far=0.0))
+    redone = ctx.kernel_times()["mixed_restore"][2]
+    App = stb.assemble_V(ctx, m, stb.default_params(prec=stb.STB_MIXED, eta_far=1e300))
+    assert ctx.kernel_times()["nodes_fp32"][2] == 0
+    rm, cm, vm = Amx.export()
+    rp, cp, vp = App.export()
+    assert np.array_equal(rm, rp) and np.array_equal(cm, cp)
+    err = np.abs(vm - vp) / np.abs(vp)
+    print("entries %d, recomputed %d, equal %d, max rel err %.3e" %
+          (vm.size, redone, int(np.count_nonzero(vm == vp)), err.max()), flush=True)
+    assert redone > 0
+    assert np.count_nonzero(vm == vp) >= redone
+    assert err.max() <= MTOL
