@@ -715,6 +715,78 @@ STB_HD __forceinline__ bool piece_misses(const TrialRec& T, const Apex& A, doubl
   return ray_misses(T, A, cc + ss, sc - cs, tol) && ray_misses(T, A, cc - ss, sc + cs, tol);
 }
 
+// The same question for every piece of a pair at once, in angle space.  When
+// the foot point p lies outside the shadow, the directions whose rays meet
+// the shadow form one wedge [lo, lo + w] (w < pi) between its two extreme
+// vertex directions; a direction more than kWedgeMargin outside it misses
+// the shadow by a margin far above rounding.  One wedge per pair (two
+// arctangents) replaces a sin/cos and up to three ray tests per piece.  No
+// wedge (every piece is evaluated) when p is inside the shadow, on or near
+// its boundary, or within 1e-4 (|t - tmin| + diam) of a vertex, where the
+// vertex directions are not resolved.
+constexpr double kWedgeMargin = 1e-8;
+
+struct ShadowWedge {
+  double lo, w;
+  bool ok;
+};
+
+STB_HD __forceinline__ ShadowWedge shadow_wedge(const TrialRec& T, const Apex& A) {
+  const double sc = fabs(A.t - T.tmin) + T.diam;
+  double du[4], dv[4], n2[4];
+  bool nearp = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    du[k] = T.V[k][1] - A.pu;
+    dv[k] = T.V[k][2] - A.pv;
+    n2[k] = du[k] * du[k] + dv[k] * dv[k];
+    nearp = nearp || n2[k] < 1e-8 * sc * sc;
+  }
+  // the clockwise extreme: no vertex clockwise of it; the counterclockwise
+  // extreme: none counterclockwise of it (cross products, collinear allowed)
+  double ulo = 0.0, vlo = 0.0, uhi = 0.0, vhi = 0.0;
+  bool flo = false, fhi = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    bool first = true, last = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double cr = du[i] * dv[k] - dv[i] * du[k];
+      const double tol = 1e-12 * sqrt(n2[i] * n2[k]);
+      first = first && cr >= -tol;
+      last = last && cr <= tol;
+    }
+    const bool tlo = first && !flo, thi = last && !fhi;
+    ulo = tlo ? du[i] : ulo;
+    vlo = tlo ? dv[i] : vlo;
+    uhi = thi ? du[i] : uhi;
+    vhi = thi ? dv[i] : vhi;
+    flo = flo || first;
+    fhi = fhi || last;
+  }
+  ShadowWedge W{0.0, 0.0, false};
+  if (nearp || !flo || !fhi) return W;
+  const double lo = atan2_bp(vlo, ulo);
+  double w = atan2_bp(vhi, uhi) - lo;
+  w = w < 0.0 ? w + kTwoPi : w;
+  W.lo = lo;
+  W.w = w;
+  W.ok = w < kPi - 1e-6;
+  return W;
+}
+
+STB_HD __forceinline__ bool wedge_misses_dir(const ShadowWedge& W, double phi) {
+  double r = phi - W.lo;
+  r -= kTwoPi * floor(r * (1.0 / kTwoPi));
+  return r > W.w + kWedgeMargin && r < kTwoPi - kWedgeMargin;
+}
+
+// piece_misses by the wedge: the piece's midpoint and quarter points.
+STB_HD __forceinline__ bool wedge_misses(const ShadowWedge& W, double a, double H) {
+  return W.ok && wedge_misses_dir(W, a + 0.5 * H) && wedge_misses_dir(W, a + 0.25 * H) &&
+         wedge_misses_dir(W, a + 0.75 * H);
+}
+
 // Sorts a[0..n).  Up to 16 values (nearly every (apex, panel) pair): into
 // registers (padded with +inf), Batcher's odd-even merge network, back --
 // independent loads and stores instead of the insertion sort's dependent

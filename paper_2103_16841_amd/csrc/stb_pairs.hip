@@ -16,8 +16,9 @@
 //             phi-breakpoints (sorted) and the pieces between them, appended
 //             to the piece list, contiguous per combo in phi order; a combo
 //             without breakpoints gets two half-periods of the trapezoid rule.
-//             A piece whose three test points all lie on rays that miss the
-//             panel's spatial shadow is empty and is not listed.
+//             A piece whose three test points all lie outside the wedge of
+//             directions that meet the panel's spatial shadow is empty and is
+//             not listed.
 //   k_empty   one lane per piece: L at the midpoint, then, for the pieces where
 //             it is zero, at the quarter points (block-local queue); the
 //             non-empty pieces go to the job list.
@@ -211,7 +212,39 @@ struct Geo {
 // for every (candidate, apex), then the edge and face minima only for the
 // few apexes the vertices leave open, densely -- a wave that ran them
 // inline would pay the long path whenever one of its 64 lanes needs it.
-__global__ __launch_bounds__(kBlk, 5) void k_lit(Geo g, Lists L, int64_t c0, int64_t nc) {
+// The first pass's fields of a panel record (its first 256 bytes), copied
+// into registers once per candidate: read through the reference, the loads
+// sink into the tests' branches and every apex waits for them again.
+__device__ __forceinline__ TrialRec lit_fields(const TrialRec* __restrict__ p) {
+  const double2* s = reinterpret_cast<const double2*>(p);
+  double2 r[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) r[i] = s[i];
+  TrialRec T;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T.o[c] = (&r[0].x)[c];
+    T.e1[c] = (&r[0].x)[3 + c];
+    T.e2[c] = (&r[0].x)[6 + c];
+    T.n[c] = (&r[0].x)[9 + c];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T.V[k][c] = (&r[0].x)[12 + 3 * k + c];
+  T.tmin = r[12].x;
+  T.tmax = r[12].y;
+  T.diam = r[13].x;
+  T.cx = r[13].y;
+  T.cy = r[14].x;
+  T.cz = r[14].y;
+  T.rad = r[15].x;
+  return T;
+}
+static_assert(offsetof(TrialRec, tmin) == 24 * sizeof(double) && offsetof(TrialRec, rad) == 30 * sizeof(double),
+              "lit_fields layout");
+
+__global__ __launch_bounds__(kBlk, 4) void k_lit(Geo g, Lists L, int64_t c0, int64_t nc) {
   const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
   unsigned long long pairs = 0;
@@ -223,11 +256,15 @@ __global__ __launch_bounds__(kBlk, 5) void k_lit(Geo g, Lists L, int64_t c0, int
     if (v) {
       const int64_t cg = c0 + c;
       const int32_t i = g.rows[cg];
-      const TrialRec& T = g.trial[g.cols[cg]];
+      const TrialRec T = lit_fields(g.trial + g.cols[cg]);
       nq = g.apex_n ? g.apex_n[i] : 1;
-      const double* xr = g.apex + (int64_t)i * g.maxq * 4;
+      const double4* xr = reinterpret_cast<const double4*>(g.apex + (int64_t)i * g.maxq * 4);
+      // the next apex is loaded while this one is tested
+      double4 xn = xr[0];
       for (int q = 0; q < nq; ++q) {
-        double x4[4] = {xr[4 * q], xr[4 * q + 1], xr[4 * q + 2], xr[4 * q + 3]};
+        const double4 xc = xn;
+        if (q + 1 < nq) xn = xr[q + 1];
+        double x4[4] = {xc.x, xc.y, xc.z, xc.w};
         Apex A;
         apex_frame(T, x4, A);
         const int r = lit_quick(T, x4, A);
@@ -347,11 +384,12 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
         if (nb == 0) {
           np = 2;
         } else {
+          const ShadowWedge W = shadow_wedge(T, A);
           for (int m = 0; m < nb; ++m) {
             const double a = bp.get(m);
             double e = (m + 1 < nb) ? bp.get(m + 1) : bp.get(0) + kTwoPi;
             if (!(e - a > 0.0)) continue;
-            if (piece_misses(T, A, a, e - a)) {
+            if (wedge_misses(W, a, e - a)) {
               miss |= 1ull << m;
               ++nmiss;
             } else {
