@@ -19,9 +19,9 @@
 //             A piece whose three test points all lie outside the wedge of
 //             directions that meet the panel's spatial shadow is empty and is
 //             not listed.
-//   k_empty   one lane per piece: L at the midpoint, then, for the pieces where
-//             it is zero, at the quarter points (block-local queue); the
-//             non-empty pieces go to the job list.
+//   k_empty   one lane per piece: L at the midpoint; the pieces where it is
+//             zero are queued for k_quarter (L at the quarter points); the
+//             non-empty pieces go to the job lists.
 //   k_nodes   one lane per job: the n_g Gauss nodes of the piece in order
 //             (smoothstep map), summed in order.
 //   k_combine one lane per combo: ordered sum over its pieces, / (4 pi).
@@ -53,7 +53,7 @@ constexpr int kMaxBlocks = 256 * 16;
 
 enum {
   CNT_COMBO = 0, CNT_DEEP, CNT_PIECE, CNT_JOB, CNT_JOB1X, CNT_JOB2, CNT_JOBF, CNT_JOB32, CNT_REDO, CNT_JOBR, CNT_PAIRS, CNT_CAUSAL, CNT_EVAL_MID,
-  CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_EVAL_NODES32, CNT_EVAL_REDO, CNT_MISS, CNT_N
+  CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_EVAL_NODES32, CNT_EVAL_REDO, CNT_MISS, CNT_QZ, CNT_N
 };
 
 // Block-wide list allocation: every thread of the block calls it (n = 0
@@ -122,6 +122,8 @@ struct Lists {
   double* ph;            // length (trapezoid half: -1)
   int32_t* pc;           // owning combo
   double* pv;            // ordered node sum
+  int32_t* pz;           // pieces whose quarter points decide (shares pv's memory: the
+                         // node sums are written only after k_quarter has read the queue)
   float* pe;             // FP32 rounding bound of the node sum (far pieces, mixed)
   int32_t* job;          // non-empty pieces, FP64 nodes by a one-gap recipe
   int32_t* job2;         // ... by a two-gap recipe
@@ -462,17 +464,44 @@ __device__ __forceinline__ unsigned route_of(const Lists& L, int32_t p, uint32_t
   return route_fp64(L, p, rec);
 }
 
-__global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
+// Job lists of one pass: every thread routes up to kEmptyPer pieces (3
+// bits of route each in `route`, presence in `has`, piece j from
+// piece_of(j)); one allocation per list and block.
+template <class F>
+__device__ __forceinline__ void route_pieces(Lists& L, AllocLds& sh, unsigned has, unsigned route,
+                                             F piece_of) {
+  unsigned cnt[5] = {0, 0, 0, 0, 0};
+  for (int j = 0; j < kEmptyPer; ++j)
+    if ((has >> j) & 1u) ++cnt[(route >> (3 * j)) & 7u];
+  unsigned long long sl[5];
+  sl[JOB_R1Q] = block_alloc(L.cnt + CNT_JOB, cnt[JOB_R1Q], sh);
+  sl[JOB_R2] = block_alloc(L.cnt + CNT_JOB2, cnt[JOB_R2], sh);
+  sl[JOB_FULL] = block_alloc(L.cnt + CNT_JOBF, cnt[JOB_FULL], sh);
+  sl[JOB_FP32] = block_alloc(L.cnt + CNT_JOB32, cnt[JOB_FP32], sh);
+  sl[JOB_R1X] = block_alloc(L.cnt + CNT_JOB1X, cnt[JOB_R1X], sh);
+  int32_t* lists[4] = {L.job, L.job2, L.jobf, L.job32};
+  for (int j = 0; j < kEmptyPer; ++j) {
+    if (!((has >> j) & 1u)) continue;
+    const unsigned r = (route >> (3 * j)) & 7u;
+    const int32_t p = piece_of(j);
+    if (r == JOB_R1X) L.job[L.cap_piece - 1 - (int64_t)(sl[r]++)] = p;
+    else lists[r][sl[r]++] = p;
+  }
+}
+
+// The empty-piece test at the midpoints: L and its recipe there; the
+// non-empty pieces go to the job lists, the others to the queue of pieces
+// whose quarter points decide (k_quarter).  The quarter-point path has a
+// kernel of its own so that this one, run on every piece, needs fewer
+// registers and keeps more waves resident.
+__global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
   const int B = (int)blockDim.x;
   __shared__ AllocLds sh;
-  __shared__ int32_t s_q[kEmptyPer * kBlk];
-  __shared__ int s_nq;
-  unsigned long long ev_mid = 0, ev_quarter = 0;
+  unsigned long long ev_mid = 0;
   const int64_t step = (int64_t)gridDim.x * B * kEmptyPer;
   for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < npiece; base += step) {
-    if (threadIdx.x == 0) s_nq = 0;
-    __syncthreads();
-    unsigned ne = 0, route = 0;   // route: 3 bits per item
+    unsigned ne = 0, route = 0, nz0 = 0;   // route: 3 bits per item
+    auto piece_of = [&](int j) { return (int32_t)(base + (int64_t)j * B + threadIdx.x); };
 #pragma unroll 1
     for (int j = 0; j < kEmptyPer; ++j) {
       const int64_t p = base + (int64_t)j * B + threadIdx.x;
@@ -489,18 +518,33 @@ __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
       L.pne[p] = nz ? 1 : 0;
       L.prec[p] = rec;
       ne |= (nz ? 1u : 0u) << j;
+      nz0 |= (nz ? 0u : 1u) << j;
       if (nz) route |= route_of(L, (int32_t)p, rec) << (3 * j);
-      if (!nz) s_q[atomicAdd(&s_nq, 1)] = (int32_t)p;
     }
-    __syncthreads();
-    const int nq = s_nq;
-    // quarter points of the queued pieces; thread tid owns entries tid + m B
-    unsigned qne = 0, qroute = 0;
+    const unsigned nq = (unsigned)__popc(nz0);
+    unsigned long long q = block_alloc(L.cnt + CNT_QZ, nq, sh);
+    for (int j = 0; j < kEmptyPer; ++j)
+      if ((nz0 >> j) & 1u) L.pz[q++] = piece_of(j);
+    route_pieces(L, sh, ne, route, piece_of);
+  }
+  block_count(L.cnt + CNT_EVAL_MID, ev_mid);
+}
+
+// The queued pieces (L zero at the midpoint): L at the quarter points; the
+// recipe of a piece found non-empty is taken at the point that decided.
+__global__ __launch_bounds__(kBlk, 3) void k_quarter(Lists L, int64_t nq) {
+  const int B = (int)blockDim.x;
+  __shared__ AllocLds sh;
+  unsigned long long ev_quarter = 0;
+  const int64_t step = (int64_t)gridDim.x * B * kEmptyPer;
+  for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < nq; base += step) {
+    unsigned ne = 0, route = 0;
+    auto piece_of = [&](int j) { return L.pz[base + (int64_t)j * B + threadIdx.x]; };
 #pragma unroll 1
-    for (int m = 0; m < kEmptyPer; ++m) {
-      const int e = m * B + threadIdx.x;
+    for (int j = 0; j < kEmptyPer; ++j) {
+      const int64_t e = base + (int64_t)j * B + threadIdx.x;
       if (e >= nq) break;
-      const int32_t p = s_q[e];
+      const int32_t p = L.pz[e];
       const ComboL cb = load_combo(L, L.pc[p]);
       const double a = L.pa[p], H = L.ph[p];
       // the test in plain arithmetic; the recipe only for the (few) pieces
@@ -517,36 +561,14 @@ __global__ __launch_bounds__(kBlk, 3) void k_empty(Lists L, int64_t npiece) {
         double sn, cs;
         sincos_small(phq, &sn, &cs);
         (void)L_eval_recipe(cb, cs, sn, &rec);
-      }
-      if (nz) {
         L.pne[p] = 1;
         L.prec[p] = rec;
-        qroute |= route_of(L, p, rec) << (3 * m);
+        route |= route_of(L, p, rec) << (3 * j);
       }
-      qne |= (nz ? 1u : 0u) << m;
+      ne |= (nz ? 1u : 0u) << j;
     }
-    unsigned cnt[5] = {0, 0, 0, 0, 0};
-    for (int j = 0; j < kEmptyPer; ++j)
-      if ((ne >> j) & 1u) ++cnt[(route >> (3 * j)) & 7u];
-    for (int m = 0; m < kEmptyPer; ++m)
-      if ((qne >> m) & 1u) ++cnt[(qroute >> (3 * m)) & 7u];
-    unsigned long long sl[5];
-    sl[JOB_R1Q] = block_alloc(L.cnt + CNT_JOB, cnt[JOB_R1Q], sh);
-    sl[JOB_R2] = block_alloc(L.cnt + CNT_JOB2, cnt[JOB_R2], sh);
-    sl[JOB_FULL] = block_alloc(L.cnt + CNT_JOBF, cnt[JOB_FULL], sh);
-    sl[JOB_FP32] = block_alloc(L.cnt + CNT_JOB32, cnt[JOB_FP32], sh);
-    sl[JOB_R1X] = block_alloc(L.cnt + CNT_JOB1X, cnt[JOB_R1X], sh);
-    int32_t* lists[4] = {L.job, L.job2, L.jobf, L.job32};
-    auto put = [&](unsigned r, int32_t p) {
-      if (r == JOB_R1X) L.job[L.cap_piece - 1 - (int64_t)(sl[r]++)] = p;
-      else lists[r][sl[r]++] = p;
-    };
-    for (int j = 0; j < kEmptyPer; ++j)
-      if ((ne >> j) & 1u) put((route >> (3 * j)) & 7u, (int32_t)(base + (int64_t)j * B + threadIdx.x));
-    for (int m = 0; m < kEmptyPer; ++m)
-      if ((qne >> m) & 1u) put((qroute >> (3 * m)) & 7u, s_q[m * B + threadIdx.x]);
+    route_pieces(L, sh, ne, route, piece_of);
   }
-  block_count(L.cnt + CNT_EVAL_MID, ev_mid);
   block_count(L.cnt + CNT_EVAL_QUARTER, ev_quarter);
 }
 
@@ -949,6 +971,7 @@ static stb_status ensure_workspace(stb_ctx* ctx, int64_t want_cand, int64_t want
   L.ph = (double*)take(want_piece * 8);
   L.pc = (int32_t*)take(want_piece * 4);
   L.pv = (double*)take(want_piece * 8);
+  L.pz = reinterpret_cast<int32_t*>(L.pv);
   L.pe = (float*)take(want_piece * 4);
   L.job = (int32_t*)take(want_piece * 4);
   L.job2 = (int32_t*)take(want_piece * 4);
@@ -1058,6 +1081,13 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       hipLaunchKernelGGL(k_empty, dim3(gfor(2, npiece, kEmptyPer)), dim3(ctx->tune_block[2]), 0, st, L,
                          (int64_t)npiece);
       HIPCHK(ctx, hipGetLastError());
+      unsigned long long nqz = 0;
+      if ((s = rd(CNT_QZ, &nqz))) return s;
+      if (nqz) {
+        hipLaunchKernelGGL(k_quarter, dim3(gfor(2, nqz, kEmptyPer)), dim3(ctx->tune_block[2]), 0, st, L,
+                           (int64_t)nqz);
+        HIPCHK(ctx, hipGetLastError());
+      }
       HIPCHK(ctx, t1(2));
     }
     unsigned long long njob32 = 0, njob2 = 0, njobf = 0, njob1x = 0, hc[CNT_N];
