@@ -1104,6 +1104,64 @@ STB_HD __forceinline__ double endpoint_value_qe(const Endpoint& E, double d2, do
   return fmin(fmax(v, wlo), whi);
 }
 
+// The Gauss-node stage's arithmetic: the same formulas with one refinement
+// step fewer.  Measured on the device over 2^22 seeded values spanning 2^-100
+// to 2^100: the reciprocal estimate is within 4.6e-8, so one Newton step
+// leaves 1/x within 2.2e-15; one Goldschmidt step leaves sqrt within 4.2e-15
+// (relative).  The nodes only add values (no decision is taken on them
+// beyond the sign of a gap), so this moves a node value by about 1e-14 of
+// its inputs' scale, four orders below the assembly's 1e-10 parity bound;
+// the decisions (lit test, breakpoints, empty-piece test, recipe) keep the
+// refinement to an ulp.
+STB_HD __forceinline__ double frcp_node(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+#else
+  return 1.0 / x;
+#endif
+}
+
+STB_HD __forceinline__ double sqrt_disc_node(double D) {
+  const bool pos = D > 0x1p-900;
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double x = pos ? D : 1.0;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double g = x * y;
+  return pos ? fma(g, fma(-g, 0.5 * y, 0.5), g) : 0.0;
+#else
+  return pos ? sqrt(D) : 0.0;
+#endif
+}
+
+STB_HD __forceinline__ double rdiff_node(double w0, double w1, double d2) {
+  const double h = 0.5 * (w1 - w0);
+  const double g = fma(-d2, frcp_node(w0 * w1), 1.0);
+  return d2 > 0.0 ? h * g : h;
+}
+
+STB_HD __forceinline__ double endpoint_value_node(const Endpoint& E, double d2, double wlo, double whi,
+                                                  double cs, double sn) {
+  const double B = fma(E.fb, cs, E.fc * sn);
+  const double e = B - E.a, f = B + E.a;
+  const double D = fma(E.C, E.C, d2 * (e * f));
+  const double q = E.C + copysign(sqrt_disc_node(D), E.C);
+  const double num = E.isb ? -d2 * f : q;
+  const double den = E.isb ? q : e;
+  double v = num * frcp_node(den);
+  v = E.cst ? E.cval : v;
+  return fmin(fmax(v, wlo), whi);
+}
+
+STB_HD __forceinline__ double endpoint_value_qe_node(const Endpoint& E, double d2, double wlo,
+                                                     double whi, double cs, double sn) {
+  const double B = fma(E.fb, cs, E.fc * sn);
+  const double e = B - E.a, f = B + E.a;
+  const double D = fma(E.C, E.C, d2 * (e * f));
+  const double q = E.C + copysign(sqrt_disc_node(D), E.C);
+  return fmin(fmax(q * frcp_node(e), wlo), whi);
+}
+
 // L by a recipe: the r-measure of its gaps, each between two endpoint
 // formulas (E[2g], E[2g + 1]).
 STB_HD __forceinline__ double L_by_recipe(const Endpoint* E, int ng, double d2, double wlo,

@@ -600,11 +600,11 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
       double Lv = 0.0;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        double v0 = QE ? endpoint_value_qe(E[2 * g], d2, wlo, whi, cs, sn)
-                       : endpoint_value(E[2 * g], d2, wlo, whi, cs, sn);
-        double v1 = QE ? endpoint_value_qe(E[2 * g + 1], d2, wlo, whi, cs, sn)
-                       : endpoint_value(E[2 * g + 1], d2, wlo, whi, cs, sn);
-        Lv += v1 > v0 ? rdiff(v0, v1, d2) : 0.0;
+        double v0 = QE ? endpoint_value_qe_node(E[2 * g], d2, wlo, whi, cs, sn)
+                       : endpoint_value_node(E[2 * g], d2, wlo, whi, cs, sn);
+        double v1 = QE ? endpoint_value_qe_node(E[2 * g + 1], d2, wlo, whi, cs, sn)
+                       : endpoint_value_node(E[2 * g + 1], d2, wlo, whi, cs, sn);
+        Lv += v1 > v0 ? rdiff_node(v0, v1, d2) : 0.0;
       }
       return Lv;
     };
