@@ -285,6 +285,20 @@ __global__ __launch_bounds__(kBlk, 4) void k_lit(Geo g, Lists L, int64_t c0, int
   block_count(L.cnt + CNT_PAIRS, pairs);
 }
 
+// The second pass's fields: the first pass's and the vertices (t, x, y, z).
+__device__ __forceinline__ TrialRec deep_fields(const TrialRec* __restrict__ p) {
+  TrialRec T = lit_fields(p);
+  const double2* s = reinterpret_cast<const double2*>(&p->X[0][0]);
+  double2 r[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = s[i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) T.X[k][c] = (&r[0].x)[4 * k + c];
+  return T;
+}
+
 __global__ __launch_bounds__(kBlk) void k_lit_deep(Geo g, Lists L, int64_t c0, int64_t ndeep) {
   const int B = (int)blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * B + threadIdx.x; k < ndeep; k += (int64_t)gridDim.x * B) {
@@ -293,11 +307,11 @@ __global__ __launch_bounds__(kBlk) void k_lit_deep(Geo g, Lists L, int64_t c0, i
     const int q = (int)(key & 255u);
     const int64_t cg = c0 + c;
     const int32_t i = g.rows[cg];
-    const TrialRec& T = g.trial[g.cols[cg]];
-    const double* xq = g.apex + ((int64_t)i * g.maxq + q) * 4;
-    double x4[4] = {xq[0], xq[1], xq[2], xq[3]};
+    const TrialRec T = deep_fields(g.trial + g.cols[cg]);
+    const double4 xq = reinterpret_cast<const double4*>(g.apex)[(int64_t)i * g.maxq + q];
+    double x4[4] = {xq.x, xq.y, xq.z, xq.w};
     Apex A;
-    apex_of(T, x4, A);
+    apex_frame(T, x4, A);   // the lit test needs the frame only, not the C_k
     if (lit_test(T, x4, A)) atomicOr(reinterpret_cast<unsigned long long*>(L.mask + c), 1ull << q);
   }
 }
