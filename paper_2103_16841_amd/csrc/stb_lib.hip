@@ -273,7 +273,10 @@ __global__ __launch_bounds__(256) void k_point_sum(int64_t np, const int64_t* __
   }
 }
 
-// y = A w (FP64 CSR), one wavefront per row, fixed-order reduction.
+// y = A w (FP64 CSR), one wavefront per row, fixed-order reduction.  Four
+// entries per lane and pass, with four partial sums: the loads of a pass
+// are all in flight before the first product needs them (one entry per pass
+// waits out a column load and a gather every time).
 __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ cols,
                                               const double* __restrict__ vals,
@@ -282,9 +285,19 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
   const int lane = threadIdx.x & 63;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; row < n; row += waves) {
-    double s = 0.0;
-    for (int64_t k = rowptr[row] + lane; k < rowptr[row + 1]; k += 64)
-      s += vals[k] * w[(int64_t)cols[k] * nrhs + col];
+    const int64_t e = rowptr[row + 1];
+    int64_t k = rowptr[row] + lane;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (; k + 192 < e; k += 256) {
+      const int32_t c0 = cols[k], c1 = cols[k + 64], c2 = cols[k + 128], c3 = cols[k + 192];
+      const double v0 = vals[k], v1 = vals[k + 64], v2 = vals[k + 128], v3 = vals[k + 192];
+      s0 = fma(v0, w[(int64_t)c0 * nrhs + col], s0);
+      s1 = fma(v1, w[(int64_t)c1 * nrhs + col], s1);
+      s2 = fma(v2, w[(int64_t)c2 * nrhs + col], s2);
+      s3 = fma(v3, w[(int64_t)c3 * nrhs + col], s3);
+    }
+    for (; k < e; k += 64) s0 = fma(vals[k], w[(int64_t)cols[k] * nrhs + col], s0);
+    double s = (s0 + s1) + (s2 + s3);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if (lane == 0) y[row * nrhs + col] = s;
   }

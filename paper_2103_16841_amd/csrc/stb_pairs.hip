@@ -260,13 +260,15 @@ __global__ __launch_bounds__(kBlk, 4) void k_lit(Geo g, Lists L, int64_t c0, int
       const int32_t i = g.rows[cg];
       const TrialRec T = lit_fields(g.trial + g.cols[cg]);
       nq = g.apex_n ? g.apex_n[i] : 1;
-      const double4* xr = reinterpret_cast<const double4*>(g.apex + (int64_t)i * g.maxq * 4);
+      // (points passed in by a caller are only known to be 8-byte aligned)
+      const double* xr = g.apex + (int64_t)i * g.maxq * 4;
       // the next apex is loaded while this one is tested
-      double4 xn = xr[0];
+      double xn[4] = {xr[0], xr[1], xr[2], xr[3]};
       for (int q = 0; q < nq; ++q) {
-        const double4 xc = xn;
-        if (q + 1 < nq) xn = xr[q + 1];
-        double x4[4] = {xc.x, xc.y, xc.z, xc.w};
+        double x4[4] = {xn[0], xn[1], xn[2], xn[3]};
+        if (q + 1 < nq)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) xn[c] = xr[4 * (q + 1) + c];
         Apex A;
         apex_frame(T, x4, A);
         const int r = lit_quick(T, x4, A);
@@ -308,8 +310,8 @@ __global__ __launch_bounds__(kBlk) void k_lit_deep(Geo g, Lists L, int64_t c0, i
     const int64_t cg = c0 + c;
     const int32_t i = g.rows[cg];
     const TrialRec T = deep_fields(g.trial + g.cols[cg]);
-    const double4 xq = reinterpret_cast<const double4*>(g.apex)[(int64_t)i * g.maxq + q];
-    double x4[4] = {xq.x, xq.y, xq.z, xq.w};
+    const double* xq = g.apex + ((int64_t)i * g.maxq + q) * 4;
+    double x4[4] = {xq[0], xq[1], xq[2], xq[3]};
     Apex A;
     apex_frame(T, x4, A);   // the lit test needs the frame only, not the C_k
     if (lit_test(T, x4, A)) atomicOr(reinterpret_cast<unsigned long long*>(L.mask + c), 1ull << q);
