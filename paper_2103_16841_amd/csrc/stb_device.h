@@ -541,26 +541,27 @@ STB_HD __forceinline__ double acos_bp(double x) {
 // refined reciprocal (within an ulp; the correctly rounded division costs
 // registers that limit the breakpoint kernel's occupancy).
 STB_HD __forceinline__ int roots2(double qa, double qb, double qc, double* r) {
-  if (qa == 0.0) {
-    if (qb == 0.0) return 0;
-    r[0] = -qc * frcp(qb);
-    return 1;
-  }
-  double disc = qb * qb - 4.0 * qa * qc;
-  double rqa = frcp(qa);
-  if (disc < 0.0) {
-    // the cone touching an edge: a double root lost to rounding
-    if (disc >= -1e-12 * (qb * qb + fabs(4.0 * qa * qc))) {
-      r[0] = -0.5 * qb * rqa;
-      return 1;
-    }
-    return 0;
-  }
-  double q = -0.5 * (qb + copysign(sqrt(disc), qb));
-  if (q == 0.0) { r[0] = 0.0; return 1; }
-  r[0] = q * rqa;
-  r[1] = qc * frcp(q);
-  return 2;
+  // every case computed and selected: a lane-divergent branch per case costs
+  // the breakpoint kernel more than the arithmetic
+  const bool lin = qa == 0.0;
+  const double disc = qb * qb - 4.0 * qa * qc;
+  const bool neg = disc < 0.0;
+  const bool near = disc >= -1e-12 * (qb * qb + fabs(4.0 * qa * qc));
+  const double q = -0.5 * (qb + copysign(sqrt(fmax(disc, 0.0)), qb));
+  const double rqa = frcp(lin ? 1.0 : qa);
+  const double rq = frcp(q == 0.0 ? 1.0 : q);
+  const double rqb = frcp(qb == 0.0 ? 1.0 : qb);
+  double r0 = q * rqa, r1 = qc * rq;
+  int n = 2;
+  r0 = q == 0.0 ? 0.0 : r0;
+  n = q == 0.0 ? 1 : n;
+  r0 = neg ? -0.5 * qb * rqa : r0;
+  n = neg ? (near ? 1 : 0) : n;
+  r0 = lin ? -qc * rqb : r0;
+  n = lin ? (qb == 0.0 ? 0 : 1) : n;
+  r[0] = r0;
+  r[1] = r1;
+  return n;
 }
 
 // Breakpoints of L (unsorted); returns count (<= kMaxBp).  The set is the
@@ -603,7 +604,7 @@ STB_HD inline int breakpoints_t(const TrialRec& T, const FaceAng& FA, const Apex
   int nh = 0;
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j) {
-      if (fv[i] < inside && fv[j] < inside) continue;
+      const bool skip = fv[i] < inside && fv[j] < inside;
       double a0 = A.t - T.V[i][0], a1 = T.V[i][0] - T.V[j][0];
       double bu = T.V[i][1] - A.pu, bv = T.V[i][2] - A.pv;
       double du = T.V[j][1] - T.V[i][1], dv = T.V[j][2] - T.V[i][2];
@@ -612,18 +613,20 @@ STB_HD inline int breakpoints_t(const TrialRec& T, const FaceAng& FA, const Apex
       double qc = a0 * a0 - bu * bu - bv * bv - d2;
       double lam[2];
       int nl = roots2(qa, qb, qc, lam);
-      for (int m = 0; m < nl; ++m) {
-        // closed edges: a cone through a vertex gives roots at 0 or 1 up to
-        // rounding, which are kept (clamped onto the vertex)
+      nl = skip ? 0 : nl;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
         double l = lam[m];
-        if (!(l >= -kEdgeTol && l <= 1.0 + kEdgeTol)) continue;
+        bool ok = m < nl && (l >= -kEdgeTol && l <= 1.0 + kEdgeTol);
         l = fmin(fmax(l, 0.0), 1.0);
-        if (a0 + a1 * l < 0.0) continue;
+        ok = ok && !(a0 + a1 * l < 0.0);
         double ou = bu + l * du, ov = bv + l * dv;
-        if (ou * ou + ov * ov <= 1e-20 * sc * sc) continue;
-        bp.put(nh, ou);
-        bp.put(12 + nh, ov);
-        ++nh;
+        ok = ok && !(ou * ou + ov * ov <= 1e-20 * sc * sc);
+        if (ok) {
+          bp.put(nh, ou);
+          bp.put(12 + nh, ov);
+          ++nh;
+        }
       }
     }
   for (int m = 0; m < nh; ++m) bp.put(m, wrap_2pi(atan2_bp(bp.get(12 + m), bp.get(m))));
@@ -781,10 +784,12 @@ STB_HD __forceinline__ bool wedge_misses_dir(const ShadowWedge& W, double phi) {
   return r > W.w + kWedgeMargin && r < kTwoPi - kWedgeMargin;
 }
 
-// piece_misses by the wedge: the piece's midpoint and quarter points.
+// piece_misses by the wedge: the piece's midpoint and quarter points (all
+// three evaluated: no branches for lanes to diverge on).
 STB_HD __forceinline__ bool wedge_misses(const ShadowWedge& W, double a, double H) {
-  return W.ok && wedge_misses_dir(W, a + 0.5 * H) && wedge_misses_dir(W, a + 0.25 * H) &&
-         wedge_misses_dir(W, a + 0.75 * H);
+  const bool m0 = wedge_misses_dir(W, a + 0.5 * H), m1 = wedge_misses_dir(W, a + 0.25 * H),
+             m2 = wedge_misses_dir(W, a + 0.75 * H);
+  return W.ok & m0 & m1 & m2;
 }
 
 // Sorts a[0..n).  Up to 16 values (nearly every (apex, panel) pair): into

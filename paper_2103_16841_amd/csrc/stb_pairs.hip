@@ -406,13 +406,11 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
           for (int m = 0; m < nb; ++m) {
             const double a = bp.get(m);
             double e = (m + 1 < nb) ? bp.get(m + 1) : bp.get(0) + kTwoPi;
-            if (!(e - a > 0.0)) continue;
-            if (wedge_misses(W, a, e - a)) {
-              miss |= 1ull << m;
-              ++nmiss;
-            } else {
-              ++np;
-            }
+            const bool pos = e - a > 0.0;
+            const bool wm = pos & wedge_misses(W, a, e - a);
+            miss |= (uint64_t)wm << m;
+            nmiss += wm ? 1 : 0;
+            np += (pos && !wm) ? 1u : 0u;
           }
         }
       }
@@ -433,11 +431,13 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
           for (int m = 0; m < nb; ++m) {
             double a = bp.get(m);
             double e = (m + 1 < nb) ? bp.get(m + 1) : bp.get(0) + kTwoPi;
-            if (!(e - a > 0.0) || ((miss >> m) & 1ull)) continue;
-            L.pa[s] = a;
-            L.ph[s] = e - a;
-            L.pc[s] = (int32_t)k;
-            ++s;
+            const bool keep = (e - a > 0.0) && !((miss >> m) & 1ull);
+            if (keep) {
+              L.pa[s] = a;
+              L.ph[s] = e - a;
+              L.pc[s] = (int32_t)k;
+            }
+            s += keep ? 1 : 0;
           }
         }
       }
