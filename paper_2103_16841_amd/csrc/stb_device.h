@@ -1167,6 +1167,37 @@ STB_HD __forceinline__ double endpoint_value_qe_node(const Endpoint& E, double d
   return fmin(fmax(q * frcp_node(e), wlo), whi);
 }
 
+// One endpoint formula at the mirror nodes m -+ delta of a piece, from the
+// per-piece P = B(m), Q = b sin m - c cos m of its face and CC = C^2:
+// B(m -+ delta) = P cos delta +- Q sin delta.  vm at m - delta, vp at
+// m + delta; node-stage arithmetic.
+template <bool QE>
+STB_HD __forceinline__ void endpoint_pair_node(const Endpoint& E, double P, double Q, double CC, double d2,
+                                               double wlo, double whi, double cd, double sd, double& vm,
+                                               double& vp) {
+  const double t = P * cd, qs = Q * sd;
+  double v[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const double B = h ? t - qs : t + qs;
+    const double e = B - E.a, f = B + E.a;
+    const double D = fma(d2 * e, f, CC);
+    const double q = E.C + copysign(sqrt_disc_node(D), E.C);
+    double w;
+    if (QE) {
+      w = q * frcp_node(e);
+    } else {
+      const double num = E.isb ? -d2 * f : q;
+      const double den = E.isb ? q : e;
+      w = num * frcp_node(den);
+      w = E.cst ? E.cval : w;
+    }
+    v[h] = fmin(fmax(w, wlo), whi);
+  }
+  vm = v[0];
+  vp = v[1];
+}
+
 // L by a recipe: the r-measure of its gaps, each between two endpoint
 // formulas (E[2g], E[2g + 1]).
 STB_HD __forceinline__ double L_by_recipe(const Endpoint* E, int ng, double d2, double wlo,

@@ -37,7 +37,7 @@ struct stb_ctx {
   int ncu = 0;
   // Gauss-Legendre nodes on [0,1] for the last n_g used (device copy)
   int gl_n = 0;
-  double* d_gl = nullptr;   // [2 * kMaxNg]: x then w
+  double* d_gl = nullptr;   // [4 * kMaxNg]: x, w, 1/2 - s(x), s'(x) w
 };
 
 struct stb_mesh {

@@ -396,9 +396,17 @@ static void gauss_legendre01(int n, double* x, double* w) {
 
 stb_status stb_ensure_gl(stb_ctx* ctx, int ng) {
   if (ctx->gl_n == ng && ctx->d_gl) return STB_OK;
-  double h[2 * kMaxNg] = {0};
+  // nodes u_g and weights w_g on [0, 1], then per node the offset of its
+  // smoothstep-mapped angle from a piece's midpoint, 1/2 - s(u_g), and its
+  // weight factor s'(u_g) w_g (s(u) = 3u^2 - 2u^3), both per unit length
+  double h[4 * kMaxNg] = {0};
   gauss_legendre01(ng, h, h + kMaxNg);
-  if (!ctx->d_gl) HIPCHK(ctx, dalloc(&ctx->d_gl, 2 * kMaxNg));
+  for (int g = 0; g < ng; ++g) {
+    const double u = h[g];
+    h[2 * kMaxNg + g] = 0.5 - u * u * (3.0 - 2.0 * u);
+    h[3 * kMaxNg + g] = (6.0 * u * (1.0 - u)) * h[kMaxNg + g];
+  }
+  if (!ctx->d_gl) HIPCHK(ctx, dalloc(&ctx->d_gl, 4 * kMaxNg));
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_gl, h, sizeof(h), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->gl_n = ng;

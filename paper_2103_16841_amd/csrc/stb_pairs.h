@@ -13,7 +13,7 @@ struct PairJob {
   const double* apex_w = nullptr;    // [rows][maxq] outer weights; nullptr: potential
   const int32_t* apex_n = nullptr;   // [rows] apexes per row; nullptr: one
   int maxq = 1;
-  const double* gl = nullptr;        // [2 kMaxNg]: Gauss nodes on [0,1], then weights
+  const double* gl = nullptr;        // [4 kMaxNg]: Gauss nodes on [0,1], weights, 1/2 - s(x), s'(x) w
   int ng = 0;
   bool mixed = false;                // far combos' Gauss nodes in FP32
   double eta_far = 2.0;              // far: apex farther than eta_far radii from the panel's ball

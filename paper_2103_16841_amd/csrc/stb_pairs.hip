@@ -612,38 +612,51 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
       E[2 * g] = endpoint_load(L, c, (rec >> (8 * g + 4)) & 15u, wlo, whi);
       E[2 * g + 1] = endpoint_load(L, c, (rec >> (8 * g)) & 15u, wlo, whi);
     }
-    auto L_node = [&](double cs, double sn) {
-      double Lv = 0.0;
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        double v0 = QE ? endpoint_value_qe_node(E[2 * g], d2, wlo, whi, cs, sn)
-                       : endpoint_value_node(E[2 * g], d2, wlo, whi, cs, sn);
-        double v1 = QE ? endpoint_value_qe_node(E[2 * g + 1], d2, wlo, whi, cs, sn)
-                       : endpoint_value_node(E[2 * g + 1], d2, wlo, whi, cs, sn);
-        Lv += v1 > v0 ? rdiff_node(v0, v1, d2) : 0.0;
-      }
-      return Lv;
-    };
     // The nodes come in mirror pairs about the piece's midpoint m:
     // phi = m -+ delta with delta = H (1/2 - s(u_g)) (the Gauss nodes are
-    // symmetric and s(1 - u) = 1 - s(u)), sharing one weight; the pair's
-    // cosines and sines follow from those of m and delta by the addition
-    // theorems, one sin/cos evaluation per pair instead of two.
+    // symmetric and s(1 - u) = 1 - s(u)), sharing one weight.  With
+    // P = B(m) and Q = b sin m - c cos m per endpoint face, the addition
+    // theorems give B(m -+ delta) = P cos(delta) +- Q sin(delta): one sin/cos
+    // per pair, two products per face and node.
     const double m = a + 0.5 * H;
     double sm, cm;
     sincos_small(m, &sm, &cm);
+    double P[2 * NG], Q[2 * NG], CC[2 * NG];
+#pragma unroll
+    for (int e = 0; e < 2 * NG; ++e) {
+      P[e] = fma(E[e].fb, cm, E[e].fc * sm);
+      Q[e] = fma(E[e].fb, sm, -(E[e].fc * cm));
+      CC[e] = E[e].C * E[e].C;
+    }
+    // L at m - delta (lm) and m + delta (lp)
+    auto L_pair = [&](double cd, double sd, double& lm, double& lp) {
+      lm = 0.0;
+      lp = 0.0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        double vm[2], vp[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int e = 2 * g + t;
+          endpoint_pair_node<QE>(E[e], P[e], Q[e], CC[e], d2, wlo, whi, cd, sd, vm[t], vp[t]);
+        }
+        lm += vm[1] > vm[0] ? rdiff_node(vm[0], vm[1], d2) : 0.0;
+        lp += vp[1] > vp[0] ? rdiff_node(vp[0], vp[1], d2) : 0.0;
+      }
+    };
     double acc = 0.0;
     for (int gi = 0; gi < (ng >> 1); ++gi) {
-      const double u = gl[gi];
-      const double s = u * u * (3.0 - 2.0 * u);
-      const double ds = 6.0 * u * (1.0 - u);
-      const double wt = (H * ds) * gl[kMaxNg + gi];
       double sd, cd;
-      sincos_small(H * (0.5 - s), &sd, &cd);
-      const double cc = cm * cd, ss = sm * sd, sc = sm * cd, cs = cm * sd;
-      acc += wt * (L_node(cc + ss, sc - cs) + L_node(cc - ss, sc + cs));
+      sincos_small(H * gl[2 * kMaxNg + gi], &sd, &cd);
+      double lm, lp;
+      L_pair(cd, sd, lm, lp);
+      acc += (H * gl[3 * kMaxNg + gi]) * (lm + lp);
     }
-    if (ng & 1) acc += (H * 1.5) * gl[kMaxNg + (ng >> 1)] * L_node(cm, sm);   // u = 1/2
+    if (ng & 1) {   // u = 1/2: the midpoint itself
+      double lm, lp;
+      L_pair(1.0, 0.0, lm, lp);
+      acc += (H * 1.5) * gl[kMaxNg + (ng >> 1)] * lm;
+    }
     evals += (unsigned long long)ng;
     L.pv[p] = acc;
   }
