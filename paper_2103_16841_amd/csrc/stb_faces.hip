@@ -126,7 +126,10 @@ __global__ void k_face_shift(int64_t n, const int32_t* __restrict__ in, int32_t 
 // Matrix entries of panel rows r0 .. r0 + nrow from the face sums, one lane
 // per candidate: per active face slot of the row's panel (slot order), the
 // candidate's column is looked up among the face's candidate columns
-// (ascending) by bisection.
+// (ascending).  A face's columns are those of the panel that owns the face
+// row, a neighbour across the face whose cull found nearly the same columns,
+// so the search starts at the candidate's own rank in its row and gallops
+// from there before it bisects.
 __global__ void k_face_combine(int64_t nnz, int64_t r0, const int32_t* __restrict__ rowof,
                                const int32_t* __restrict__ cols, const int32_t* __restrict__ pf,
                                const double* __restrict__ pw, int64_t f0, int64_t nfu,
@@ -150,12 +153,36 @@ __global__ void k_face_combine(int64_t nnz, int64_t r0, const int32_t* __restric
       int64_t lo = frowptr[lf], hi = frowptr[lf + 1];
       if (prim[lf] == li) {
         lo += c - rowptr[li];   // the face's candidates are this row's, in order
-      } else {
-        while (lo < hi) {
-          const int64_t mid = lo + ((hi - lo) >> 1);
-          if (fcols[mid] < j) lo = mid + 1;
-          else hi = mid;
+      } else if (lo < hi) {
+        // first position in [lo, hi) whose column is >= j: bracket it by
+        // steps of 1, 2, 4, ... from the guess, then bisect the bracket
+        const int64_t g = std::min(std::max(lo + (c - rowptr[li]), lo), hi - 1);
+        int64_t a, b;   // the position lies in [a, b] (b = hi: none)
+        if (fcols[g] < j) {
+          a = g + 1;
+          b = hi;
+          for (int64_t step = 1;; step <<= 1) {
+            const int64_t q = g + step;
+            if (q >= hi) break;
+            if (fcols[q] >= j) { b = q; break; }
+            a = q + 1;
+          }
+        } else {
+          a = lo;
+          b = g;
+          for (int64_t step = 1;; step <<= 1) {
+            const int64_t q = g - step;
+            if (q < lo) break;
+            if (fcols[q] < j) { a = q + 1; break; }
+            b = q;
+          }
         }
+        while (a < b) {
+          const int64_t mid = a + ((b - a) >> 1);
+          if (fcols[mid] < j) a = mid + 1;
+          else b = mid;
+        }
+        lo = a;
       }
       if (lo < frowptr[lf + 1] && fcols[lo] == j) {
         acc += pw[4 * i + s] * S[lo];
