@@ -211,6 +211,21 @@ STB_HD __forceinline__ double sqrt_disc(double D) {
 #endif
 }
 
+// sqrt of a non-negative value to about an ulp (sqrt_disc's sequence; the
+// library's correctly rounded square root adds range scaling and special
+// cases, about twice the instructions).  Used where a decision has a
+// tolerance far above an ulp (lit tests, edge events, tangencies).
+STB_HD __forceinline__ double sqrt_nn(double x) { return sqrt_disc(x); }
+
+// sqrt to about 1e-7 relative: for tolerances only.
+STB_HD __forceinline__ double sqrt_rough(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return x > 0.0 ? x * __builtin_amdgcn_rsq(x) : 0.0;
+#else
+  return sqrt(x);
+#endif
+}
+
 // r(w1) - r(w0) = (w1 - w0) (1 - d^2 / (w0 w1)) / 2 for w1 >= w0 > 0 (or
 // d^2 = 0, where w0 may be 0).
 STB_HD __forceinline__ double rdiff(double w0, double w1, double d2) {
@@ -390,7 +405,7 @@ STB_HD inline bool lit_test(const TrialRec& T, const double* x4, const Apex& A) 
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     double dx = x4[1] - T.X[k][1], dy = x4[2] - T.X[k][2], dz = x4[3] - T.X[k][3];
-    double f = sqrt(dx * dx + dy * dy + dz * dz) - (x4[0] - T.X[k][0]);
+    double f = sqrt_nn(dx * dx + dy * dy + dz * dz) - (x4[0] - T.X[k][0]);
     mn = fmin(mn, f);
     mx = fmax(mx, f);
   }
@@ -408,15 +423,16 @@ STB_HD inline bool lit_test(const TrialRec& T, const double* x4, const Apex& A) 
       double cr0 = P[1] * U[2] - P[2] * U[1];
       double cr1 = P[2] * U[0] - P[0] * U[2];
       double cr2 = P[0] * U[1] - P[1] * U[0];
-      double hw = fabs(Dt) / (2.0 * a) * sqrt(4.0 * (cr0 * cr0 + cr1 * cr1 + cr2 * cr2) / g);
-      double lc = -b / (2.0 * a);
+      const double ra2 = frcp(2.0 * a);
+      double hw = fabs(Dt) * ra2 * sqrt_nn(4.0 * (cr0 * cr0 + cr1 * cr1 + cr2 * cr2) * frcp(g));
+      double lc = -b * ra2;
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
         double l = m ? lc + hw : lc - hw;
         if (!(l > 0.0 && l < 1.0)) continue;
         double y0 = T.X[i][0] + l * Dt;
         double y1 = P[0] + l * U[0], y2 = P[1] + l * U[1], y3 = P[2] + l * U[2];
-        double f = sqrt(y1 * y1 + y2 * y2 + y3 * y3) - (x4[0] - y0);
+        double f = sqrt_nn(y1 * y1 + y2 * y2 + y3 * y3) - (x4[0] - y0);
         mn = fmin(mn, f);
       }
     }
@@ -433,19 +449,20 @@ STB_HD inline bool lit_test(const TrialRec& T, const double* x4, const Apex& A) 
     double D1 = T.V[i1][0] - V0[0], D2 = T.V[i2][0] - V0[0];
     double det = Uu * Wv - Uv * Wu;
     if (!(fabs(det) > 1e-12 * sc2)) continue;
-    double gu = (D1 * Wv - D2 * Uv) / det;
-    double gv = (Uu * D2 - Wu * D1) / det;
+    const double rdet = frcp(det);
+    double gu = (D1 * Wv - D2 * Uv) * rdet;
+    double gv = (Uu * D2 - Wu * D1) * rdet;
     double g2 = gu * gu + gv * gv;
     if (!(g2 < 1.0)) continue;
-    double fac = fabs(A.d) / sqrt(1.0 - g2);
+    double fac = fabs(A.d) * frcp(sqrt_nn(1.0 - g2));
     double yu = A.pu - gu * fac, yv = A.pv - gv * fac;
     double ru = yu - V0[1], rv = yv - V0[2];
-    double al = (ru * Wv - rv * Wu) / det;
-    double be = (Uu * rv - Uv * ru) / det;
+    double al = (ru * Wv - rv * Wu) * rdet;
+    double be = (Uu * rv - Uv * ru) * rdet;
     if (!(al >= 0.0 && be >= 0.0 && al + be <= 1.0)) continue;
     double tau = V0[0] + gu * ru + gv * rv;
     double du = A.pu - yu, dv = A.pv - yv;
-    double f = sqrt(du * du + dv * dv + A.d * A.d) - (A.t - tau);
+    double f = sqrt_nn(du * du + dv * dv + A.d * A.d) - (A.t - tau);
     mn = fmin(mn, f);
   }
   return mn < -dead;
@@ -463,7 +480,7 @@ STB_HD inline int lit_quick(const TrialRec& T, const double* x4, const Apex& A) 
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     double du = A.pu - T.V[k][1], dv = A.pv - T.V[k][2];
-    double f = sqrt(du * du + dv * dv + d2) - (A.t - T.V[k][0]);
+    double f = sqrt_nn(du * du + dv * dv + d2) - (A.t - T.V[k][0]);
     mn = fmin(mn, f);
     mx = fmax(mx, f);
   }
@@ -482,11 +499,11 @@ STB_HD inline int lit_quick(const TrialRec& T, const double* x4, const Apex& A) 
 STB_HD __forceinline__ bool ball_rejects(const TrialRec& T, const double* x4) {
   const double s2 = 1.4142135623730951;
   double tc = 0.5 * (T.tmin + T.tmax), ht = 0.5 * (T.tmax - T.tmin);
-  double r = sqrt(T.rad * T.rad + ht * ht) * (1.0 + 1e-12);
+  double r = sqrt_nn(T.rad * T.rad + ht * ht) * (1.0 + 1e-12);
   double dx = x4[1] - T.cx, dy = x4[2] - T.cy, dz = x4[3] - T.cz;
-  double al = sqrt(dx * dx + dy * dy + dz * dz);
+  double al = sqrt_nn(dx * dx + dy * dy + dz * dz);
   double phi = al - (x4[0] - tc);
-  double dr = al < r / s2 ? al + sqrt(fmax(r * r - al * al, 0.0)) : r * s2;
+  double dr = al < r * (1.0 / s2) ? al + sqrt_nn(r * r - al * al) : r * s2;
   double margin = 1e-9 * (fabs(x4[0] - T.tmin) + T.diam);
   return (phi + r * s2 < -margin) || (phi - dr > margin);
 }
@@ -534,7 +551,7 @@ STB_HD __forceinline__ double atan2_bp(double y, double x) {
 
 // acos x = atan2(sqrt((1 - x)(1 + x)), x) for x in [-1, 1].
 STB_HD __forceinline__ double acos_bp(double x) {
-  return atan2_bp(sqrt(fmax((1.0 - x) * (1.0 + x), 0.0)), x);
+  return atan2_bp(sqrt_nn((1.0 - x) * (1.0 + x)), x);
 }
 
 // Stable roots of qa l^2 + qb l + qc = 0; returns count.  Quotients by the
@@ -547,7 +564,7 @@ STB_HD __forceinline__ int roots2(double qa, double qb, double qc, double* r) {
   const double disc = qb * qb - 4.0 * qa * qc;
   const bool neg = disc < 0.0;
   const bool near = disc >= -1e-12 * (qb * qb + fabs(4.0 * qa * qc));
-  const double q = -0.5 * (qb + copysign(sqrt(fmax(disc, 0.0)), qb));
+  const double q = -0.5 * (qb + copysign(sqrt_nn(disc), qb));
   const double rqa = frcp(lin ? 1.0 : qa);
   const double rq = frcp(q == 0.0 ? 1.0 : q);
   const double rqb = frcp(qb == 0.0 ? 1.0 : qb);
@@ -596,7 +613,7 @@ STB_HD inline int breakpoints_t(const TrialRec& T, const FaceAng& FA, const Apex
   double fv[4];
   for (int k = 0; k < 4; ++k) {
     double du = T.V[k][1] - A.pu, dv = T.V[k][2] - A.pv;
-    fv[k] = sqrt(du * du + dv * dv + d2) - (A.t - T.V[k][0]);
+    fv[k] = sqrt_nn(du * du + dv * dv + d2) - (A.t - T.V[k][0]);
   }
   const double inside = -1e-9 * sc;
   // edge events (at most 12): the in-plane offsets (ou, ov) first, kept in
@@ -639,13 +656,13 @@ STB_HD inline int breakpoints_t(const TrialRec& T, const FaceAng& FA, const Apex
     if (d2 > 0.0) {
       double rhs = a * a - Ck * Ck * rd2;
       if (rhs >= 0.0 && rhs <= beta * beta) {
-        double cv = fmin(sqrt(rhs) / beta, 1.0);
+        const double rb = frcp(beta);
+        double cv = fmin(sqrt_nn(rhs) * rb, 1.0);
         double g = acos_bp(cv);
         // candidates phi_k + g, phi_k - g, phi_k + pi - g, phi_k + pi + g;
         // their directions from (cos, sin) of phi_k = (b, c) / beta and of
         // g = (cv, sqrt(1 - cv^2)) by the addition theorems
-        const double rb = frcp(beta);
-        const double cp = b * rb, sp = c * rb, sg = sqrt(fmax((1.0 - cv) * (1.0 + cv), 0.0));
+        const double cp = b * rb, sp = c * rb, sg = sqrt_nn((1.0 - cv) * (1.0 + cv));
         const double c1 = cp * cv - sp * sg, s1 = sp * cv + cp * sg;   // phi_k + g
         const double c2 = cp * cv + sp * sg, s2 = sp * cv - cp * sg;   // phi_k - g
 #pragma unroll 1
@@ -755,7 +772,7 @@ STB_HD __forceinline__ ShadowWedge shadow_wedge(const TrialRec& T, const Apex& A
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const double cr = du[i] * dv[k] - dv[i] * du[k];
-      const double tol = 1e-12 * sqrt(n2[i] * n2[k]);
+      const double tol = 1e-12 * sqrt_rough(n2[i] * n2[k]);
       first = first && cr >= -tol;
       last = last && cr <= tol;
     }
