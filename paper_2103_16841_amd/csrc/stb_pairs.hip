@@ -640,17 +640,26 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
           const int e = 2 * g + t;
           endpoint_pair_node<QE>(E[e], P[e], Q[e], CC[e], d2, wlo, whi, cd, sd, vm[t], vp[t]);
         }
-        lm += vm[1] > vm[0] ? rdiff_node(vm[0], vm[1], d2) : 0.0;
-        lp += vp[1] > vp[0] ? rdiff_node(vp[0], vp[1], d2) : 0.0;
+        // a gap that closed (end <= start) measures 0: rdiff of equal ends,
+        // so no branch (w >= |d| > 0 when d^2 > 0; rdiff ignores 1/w at d = 0)
+        lm += rdiff_node(vm[0], fmax(vm[1], vm[0]), d2);
+        lp += rdiff_node(vp[0], fmax(vp[1], vp[0]), d2);
       }
     };
     double acc = 0.0;
+    // the next pair's table entries are loaded while this pair is evaluated
+    double t_off = gl[2 * kMaxNg], t_wf = gl[3 * kMaxNg];
     for (int gi = 0; gi < (ng >> 1); ++gi) {
+      const double off = t_off, wf = t_wf;
+      if (gi + 1 < (ng >> 1)) {
+        t_off = gl[2 * kMaxNg + gi + 1];
+        t_wf = gl[3 * kMaxNg + gi + 1];
+      }
       double sd, cd;
-      sincos_small(H * gl[2 * kMaxNg + gi], &sd, &cd);
+      sincos_small(H * off, &sd, &cd);
       double lm, lp;
       L_pair(cd, sd, lm, lp);
-      acc += (H * gl[3 * kMaxNg + gi]) * (lm + lp);
+      acc += (H * wf) * (lm + lp);
     }
     if (ng & 1) {   // u = 1/2: the midpoint itself
       double lm, lp;
