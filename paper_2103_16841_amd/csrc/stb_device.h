@@ -675,7 +675,8 @@ STB_HD inline int breakpoints_t(const TrialRec& T, const FaceAng& FA, const Apex
           if (e == 0.0) continue;
           double wt = Ck * frcp(e);           // double root of Q_k
           if (!(wt >= ad) || !(wt > 0.0)) continue;
-          double rt = r_of_w(wt, d2), st = 0.5 * (wt - d2 * frcp(wt));
+          const double rw = frcp(wt);
+          double rt = d2 > 0.0 ? 0.5 * (wt + d2 * rw) : 0.5 * wt, st = 0.5 * (wt - d2 * rw);
           double y0 = A.t - rt, y1 = A.pu + st * cs, y2 = A.pv + st * sn;
           double worst = -1e300;
 #pragma unroll
@@ -809,33 +810,39 @@ STB_HD __forceinline__ bool wedge_misses(const ShadowWedge& W, double a, double 
   return W.ok & m0 & m1 & m2;
 }
 
-// Sorts a[0..n).  Up to 16 values (nearly every (apex, panel) pair): into
-// registers (padded with +inf), Batcher's odd-even merge network, back --
-// independent loads and stores instead of the insertion sort's dependent
-// chain through private memory.
+// Sorts a[0..n) for n <= M (M a power of 2): into registers (padded with
+// +inf), Batcher's odd-even merge network, back -- independent loads and
+// stores instead of the insertion sort's dependent chain through memory.
+template <int M, class BP>
+STB_HD __forceinline__ void sort_net(BP& a, int n) {
+  double r[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) r[j] = j < n ? a.get(j) : HUGE_VAL;
+#pragma unroll
+  for (int p = 1; p < M; p <<= 1)
+#pragma unroll
+    for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+      for (int j = k % p; j + k < M; j += 2 * k)
+#pragma unroll
+        for (int i = 0; i < k && i + j + k < M; ++i)
+          if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+            const double lo = fmin(r[i + j], r[i + j + k]);
+            const double hi = fmax(r[i + j], r[i + j + k]);
+            r[i + j] = lo;
+            r[i + j + k] = hi;
+          }
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+    if (j < n) a.put(j, r[j]);
+}
+
+// Sorts a[0..n).  Up to 16 values (nearly every (apex, panel) pair) by the
+// network; more by insertion.
 template <class BP>
 STB_HD __forceinline__ void sort_bp_t(BP& a, int n) {
   if (n <= 16) {
-    double r[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) r[j] = j < n ? a.get(j) : HUGE_VAL;
-#pragma unroll
-    for (int p = 1; p < 16; p <<= 1)
-#pragma unroll
-      for (int k = p; k >= 1; k >>= 1)
-#pragma unroll
-        for (int j = k % p; j + k < 16; j += 2 * k)
-#pragma unroll
-          for (int i = 0; i < k && i + j + k < 16; ++i)
-            if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) {
-              const double lo = fmin(r[i + j], r[i + j + k]);
-              const double hi = fmax(r[i + j], r[i + j + k]);
-              r[i + j] = lo;
-              r[i + j + k] = hi;
-            }
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (j < n) a.put(j, r[j]);
+    sort_net<16>(a, n);
     return;
   }
   for (int i = 1; i < n; ++i) {

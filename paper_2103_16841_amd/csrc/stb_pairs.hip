@@ -398,7 +398,10 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
         store_combo(L, k, cb, col);
         if (g.mixed && apex_far(T, x4, g.eta_far)) L.key[k] = key | 0x80u;
         nb = breakpoints_t(T, g.fang[col], A, bp);
-        sort_bp_t(bp, nb);
+        // the 8-wide network when every lane of the wave has at most 8
+        // breakpoints (about half the waves), the 16-wide one otherwise
+        if (__ballot(nb > 8) == 0) sort_net<8>(bp, nb);
+        else sort_bp_t(bp, nb);
         if (nb == 0) {
           np = 2;
         } else {
