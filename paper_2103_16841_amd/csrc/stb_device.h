@@ -1012,15 +1012,20 @@ STB_HD __forceinline__ void order2i(double& s0, double& e0, int& i0, int& j0, do
   s1 = sw ? ts : s1; e1 = sw ? te : e1; i1 = sw ? ti : i1; j1 = sw ? tj : j1;
 }
 
-// L(phi) as L_eval, also returning the recipe of its gap structure.
+// L(phi) as L_eval, also returning the recipe of its gap structure.  The
+// admissible set is found from values alone (as L_eval does); the endpoint
+// formula of each end of the (at most two) kept gaps is then identified by
+// matching its value against the candidates -- the range ends wlo, whi and
+// the faces' roots q / e, -d^2 f / q -- the lowest id first.  Every end is a
+// copy of one of them (fmin, fmax and selects keep the bits), and carrying
+// the ids through every comparison instead costs more selects than the
+// arithmetic itself.
 STB_HD inline double L_eval_recipe(const ComboL& cb, double cs, double sn, uint32_t* recipe) {
   const double kNone = 1e300;
   const double d2 = cb.d2;
   double lo = cb.wlo, hi = cb.whi;
-  int loi = 0, hii = 1;
   bool dead = false;
-  double hs[4], he[4];
-  int hsi[4], hei[4];
+  double hs[4], he[4], r1[4], r2[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     double a = cb.fa[k];
@@ -1031,66 +1036,61 @@ STB_HD inline double L_eval_recipe(const ComboL& cb, double cs, double sn, uint3
     double q = Ck + copysign(sqrt_disc(D), Ck);
     double w1 = q * frcp(e);
     double w2 = -d2 * f * frcp(q);
-    const int ia = 2 + 2 * k, ib = 3 + 2 * k;
-    bool aless = w1 < w2;
-    double mn = aless ? w1 : w2, mx = aless ? w2 : w1;
-    int mni = aless ? ia : ib, mxi = aless ? ib : ia;
+    r1[k] = w1;
+    r2[k] = w2;
+    double mn = fmin(w1, w2), mx = fmax(w1, w2);
     bool pos = e > 0.0, neg = e < 0.0, zer = !(pos || neg);
     bool cut = pos && two;
     dead = dead || (pos && !two) || (zer && Ck == 0.0 && !(d2 * f > 0.0));
-    bool nlo = cut && mn > lo, nhi = cut && mx < hi;
-    lo = nlo ? mn : lo; loi = nlo ? mni : loi;
-    hi = nhi ? mx : hi; hii = nhi ? mxi : hii;
-    bool llo = zer && Ck > 0.0 && w2 > lo, lhi = zer && Ck < 0.0 && w2 < hi;
-    lo = llo ? w2 : lo; loi = llo ? ib : loi;
-    hi = lhi ? w2 : hi; hii = lhi ? ib : hii;
+    lo = cut ? fmax(lo, mn) : lo;
+    hi = cut ? fmin(hi, mx) : hi;
+    lo = (zer && Ck > 0.0) ? fmax(lo, w2) : lo;
+    hi = (zer && Ck < 0.0) ? fmin(hi, w2) : hi;
     bool hole = neg && two;
-    hs[k] = hole ? mn : kNone; hsi[k] = hole ? mni : hii;
-    he[k] = hole ? mx : kNone; hei[k] = hole ? mxi : hii;
+    hs[k] = hole ? mn : kNone;
+    he[k] = hole ? mx : kNone;
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    bool b1 = hs[k] < lo;
-    hs[k] = b1 ? lo : hs[k]; hsi[k] = b1 ? loi : hsi[k];
-    bool b2 = hs[k] > hi;
-    hs[k] = b2 ? hi : hs[k]; hsi[k] = b2 ? hii : hsi[k];
-    bool b3 = he[k] > hi;
-    he[k] = b3 ? hi : he[k]; hei[k] = b3 ? hii : hei[k];
-    bool b4 = he[k] < hs[k];
-    he[k] = b4 ? hs[k] : he[k]; hei[k] = b4 ? hsi[k] : hei[k];
+    hs[k] = fmin(fmax(hs[k], lo), hi);
+    he[k] = fmax(fmin(he[k], hi), hs[k]);
   }
-  order2i(hs[0], he[0], hsi[0], hei[0], hs[1], he[1], hsi[1], hei[1]);
-  order2i(hs[2], he[2], hsi[2], hei[2], hs[3], he[3], hsi[3], hei[3]);
-  order2i(hs[0], he[0], hsi[0], hei[0], hs[2], he[2], hsi[2], hei[2]);
-  order2i(hs[1], he[1], hsi[1], hei[1], hs[3], he[3], hsi[3], hei[3]);
-  order2i(hs[1], he[1], hsi[1], hei[1], hs[2], he[2], hsi[2], hei[2]);
+  order2(hs[0], he[0], hs[1], he[1]);
+  order2(hs[2], he[2], hs[3], he[3]);
+  order2(hs[0], he[0], hs[2], he[2]);
+  order2(hs[1], he[1], hs[3], he[3]);
+  order2(hs[1], he[1], hs[2], he[2]);
   const double kWulp = 8.881784197001252e-16;
   double len = 0.0, c = lo;
-  int ci = loi, ng = 0;
-  uint32_t rec = 0;
+  double gs0 = lo, ge0 = lo, gs1 = lo, ge1 = lo;   // ends of the first two kept gaps
+  int ng = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    bool adv = hs[k] > c;
-    double g1 = adv ? hs[k] : c;
-    int g1i = adv ? hsi[k] : ci;
-    double m = rdiff(c, g1, d2);
-    bool keep = m > kWulp * g1;
+  for (int k = 0; k < 5; ++k) {
+    const double g1 = k < 4 ? fmax(hs[k], c) : hi;
+    const double m = rdiff(c, g1, d2);
+    const bool keep = m > kWulp * g1;
     len += keep ? m : 0.0;
-    if (keep) {
-      if (ng < kRecipeGaps) rec |= (uint32_t)((ci << 4) | g1i) << (8 * ng);
-      ++ng;
+    const bool f0 = keep && ng == 0, f1 = keep && ng == 1;
+    gs0 = f0 ? c : gs0;
+    ge0 = f0 ? g1 : ge0;
+    gs1 = f1 ? c : gs1;
+    ge1 = f1 ? g1 : ge1;
+    ng += keep ? 1 : 0;
+    if (k < 4) c = fmax(he[k], c);
+  }
+  auto id_of = [&](double v) {
+    uint32_t id = 9u;
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+      id = v == r2[k] ? (uint32_t)(3 + 2 * k) : id;
+      id = v == r1[k] ? (uint32_t)(2 + 2 * k) : id;
     }
-    bool ext = he[k] > c;
-    c = ext ? he[k] : c;
-    ci = ext ? hei[k] : ci;
-  }
-  double m = rdiff(c, hi, d2);
-  bool keep = m > kWulp * hi;
-  len += keep ? m : 0.0;
-  if (keep) {
-    if (ng < kRecipeGaps) rec |= (uint32_t)((ci << 4) | hii) << (8 * ng);
-    ++ng;
-  }
+    id = v == cb.whi ? 1u : id;
+    id = v == cb.wlo ? 0u : id;
+    return id;
+  };
+  const uint32_t rec = (ng >= 1 ? (id_of(gs0) << 4) | id_of(ge0) : 0u) |
+                       (ng >= 2 ? ((id_of(gs1) << 4) | id_of(ge1)) << 8 : 0u);
   const bool empty = dead || !(hi > lo);
   *recipe = (empty || ng > kRecipeGaps) ? 0u : (rec | ((uint32_t)ng << 24));
   return empty ? 0.0 : len;
