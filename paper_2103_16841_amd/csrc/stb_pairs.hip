@@ -483,28 +483,59 @@ __device__ __forceinline__ unsigned route_of(const Lists& L, int32_t p, uint32_t
   return route_fp64(L, p, rec);
 }
 
-// Job lists of one pass: every thread routes up to kEmptyPer pieces (3
-// bits of route each in `route`, presence in `has`, piece j from
-// piece_of(j)); one allocation per list and block.
+// Job lists of one pass: every lane routes up to kEmptyPer pieces (3 bits
+// of route each in `route`, presence in `has`, piece j from piece_of(j)).
+// Slots are handed out per wave, for the six lists at once: the lane's
+// counts (at most kEmptyPer each) in 10-bit fields of one 64-bit word, one
+// shuffle scan over the wave, and lane f reserves list f's slots with one
+// atomic when the wave has any (no block barriers; the rare lists are
+// rarely touched).  Every lane of the wave must call it.
+constexpr int JOB_QZ = 5;   // not a job list: the queue for the quarter points
+static_assert(kEmptyPer * 64 < 1024, "per-wave list counts fit 10 bits");
+
 template <class F>
-__device__ __forceinline__ void route_pieces(Lists& L, AllocLds& sh, unsigned has, unsigned route,
-                                             F piece_of) {
-  unsigned cnt[5] = {0, 0, 0, 0, 0};
+__device__ __forceinline__ void route_pieces(Lists& L, unsigned has, unsigned route, F piece_of) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long v = 0;
   for (int j = 0; j < kEmptyPer; ++j)
-    if ((has >> j) & 1u) ++cnt[(route >> (3 * j)) & 7u];
-  unsigned long long sl[5];
-  sl[JOB_R1Q] = block_alloc(L.cnt + CNT_JOB, cnt[JOB_R1Q], sh);
-  sl[JOB_R2] = block_alloc(L.cnt + CNT_JOB2, cnt[JOB_R2], sh);
-  sl[JOB_FULL] = block_alloc(L.cnt + CNT_JOBF, cnt[JOB_FULL], sh);
-  sl[JOB_FP32] = block_alloc(L.cnt + CNT_JOB32, cnt[JOB_FP32], sh);
-  sl[JOB_R1X] = block_alloc(L.cnt + CNT_JOB1X, cnt[JOB_R1X], sh);
-  int32_t* lists[4] = {L.job, L.job2, L.jobf, L.job32};
+    if ((has >> j) & 1u) v += 1ull << (10 * ((route >> (3 * j)) & 7u));
+  unsigned long long incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  const unsigned long long tot = __shfl(incl, 63, 64);
+  unsigned long long b = 0;
+  if (lane < 6) {
+    const int ctr = lane == JOB_R1Q ? CNT_JOB : lane == JOB_R2 ? CNT_JOB2 : lane == JOB_FULL ? CNT_JOBF
+                  : lane == JOB_FP32 ? CNT_JOB32 : lane == JOB_R1X ? CNT_JOB1X : CNT_QZ;
+    const unsigned long long n = (tot >> (10 * lane)) & 1023u;
+    if (n) b = atomicAdd(L.cnt + ctr, n);
+  }
+  const unsigned long long ex = incl - v;
+  unsigned long long s0 = __shfl(b, JOB_R1Q, 64) + (ex & 1023u);
+  unsigned long long s1 = __shfl(b, JOB_R2, 64) + ((ex >> 10) & 1023u);
+  unsigned long long s2 = __shfl(b, JOB_FULL, 64) + ((ex >> 20) & 1023u);
+  unsigned long long s3 = __shfl(b, JOB_FP32, 64) + ((ex >> 30) & 1023u);
+  unsigned long long s4 = __shfl(b, JOB_R1X, 64) + ((ex >> 40) & 1023u);
+  unsigned long long s5 = __shfl(b, JOB_QZ, 64) + ((ex >> 50) & 1023u);
   for (int j = 0; j < kEmptyPer; ++j) {
     if (!((has >> j) & 1u)) continue;
     const unsigned r = (route >> (3 * j)) & 7u;
     const int32_t p = piece_of(j);
-    if (r == JOB_R1X) L.job[L.cap_piece - 1 - (int64_t)(sl[r]++)] = p;
-    else lists[r][sl[r]++] = p;
+    if (r == JOB_R1Q) {   // nearly every piece
+      L.job[s0++] = p;
+      continue;
+    }
+    int32_t* dst = r == JOB_R2 ? L.job2 + s1 : r == JOB_FULL ? L.jobf + s2 : r == JOB_FP32 ? L.job32 + s3
+                 : r == JOB_R1X ? L.job + (L.cap_piece - 1 - (int64_t)s4) : L.pz + s5;
+    *dst = p;
+    s1 += r == JOB_R2 ? 1 : 0;
+    s2 += r == JOB_FULL ? 1 : 0;
+    s3 += r == JOB_FP32 ? 1 : 0;
+    s4 += r == JOB_R1X ? 1 : 0;
+    s5 += r == JOB_QZ ? 1 : 0;
   }
 }
 
@@ -515,11 +546,10 @@ __device__ __forceinline__ void route_pieces(Lists& L, AllocLds& sh, unsigned ha
 // registers and keeps more waves resident.
 __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
   const int B = (int)blockDim.x;
-  __shared__ AllocLds sh;
   unsigned long long ev_mid = 0;
   const int64_t step = (int64_t)gridDim.x * B * kEmptyPer;
   for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < npiece; base += step) {
-    unsigned ne = 0, route = 0, nz0 = 0;   // route: 3 bits per item
+    unsigned has = 0, route = 0;   // route: 3 bits per item
     auto piece_of = [&](int j) { return (int32_t)(base + (int64_t)j * B + threadIdx.x); };
 #pragma unroll 1
     for (int j = 0; j < kEmptyPer; ++j) {
@@ -536,15 +566,10 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
       }
       L.pne[p] = nz ? 1 : 0;
       L.prec[p] = rec;
-      ne |= (nz ? 1u : 0u) << j;
-      nz0 |= (nz ? 0u : 1u) << j;
-      if (nz) route |= route_of(L, (int32_t)p, rec) << (3 * j);
+      has |= 1u << j;
+      route |= (nz ? route_of(L, (int32_t)p, rec) : (unsigned)JOB_QZ) << (3 * j);
     }
-    const unsigned nq = (unsigned)__popc(nz0);
-    unsigned long long q = block_alloc(L.cnt + CNT_QZ, nq, sh);
-    for (int j = 0; j < kEmptyPer; ++j)
-      if ((nz0 >> j) & 1u) L.pz[q++] = piece_of(j);
-    route_pieces(L, sh, ne, route, piece_of);
+    route_pieces(L, has, route, piece_of);
   }
   block_count(L.cnt + CNT_EVAL_MID, ev_mid);
 }
@@ -553,7 +578,6 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
 // recipe of a piece found non-empty is taken at the point that decided.
 __global__ __launch_bounds__(kBlk, 3) void k_quarter(Lists L, int64_t nq) {
   const int B = (int)blockDim.x;
-  __shared__ AllocLds sh;
   unsigned long long ev_quarter = 0;
   const int64_t step = (int64_t)gridDim.x * B * kEmptyPer;
   for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < nq; base += step) {
@@ -586,7 +610,7 @@ __global__ __launch_bounds__(kBlk, 3) void k_quarter(Lists L, int64_t nq) {
       }
       ne |= (nz ? 1u : 0u) << j;
     }
-    route_pieces(L, sh, ne, route, piece_of);
+    route_pieces(L, ne, route, piece_of);
   }
   block_count(L.cnt + CNT_EVAL_QUARTER, ev_quarter);
 }
