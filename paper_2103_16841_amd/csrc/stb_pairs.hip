@@ -514,20 +514,26 @@ __device__ __forceinline__ void route_pieces(Lists& L, unsigned has, unsigned ro
     if (n) b = atomicAdd(L.cnt + ctr, n);
   }
   const unsigned long long ex = incl - v;
-  unsigned long long s0 = __shfl(b, JOB_R1Q, 64) + (ex & 1023u);
+  // the one-gap q/e jobs (nearly every piece) in piece order: item j of
+  // every lane before item j + 1, lanes in order within an item, so that
+  // neighbouring jobs read neighbouring pieces and combos
+  unsigned long long s0 = __shfl(b, JOB_R1Q, 64);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int j = 0; j < kEmptyPer; ++j) {
+    const bool q = ((has >> j) & 1u) && ((route >> (3 * j)) & 7u) == JOB_R1Q;
+    const unsigned long long bal = __ballot(q);
+    if (q) L.job[s0 + __popcll(bal & below)] = piece_of(j);
+    s0 += __popcll(bal);
+  }
   unsigned long long s1 = __shfl(b, JOB_R2, 64) + ((ex >> 10) & 1023u);
   unsigned long long s2 = __shfl(b, JOB_FULL, 64) + ((ex >> 20) & 1023u);
   unsigned long long s3 = __shfl(b, JOB_FP32, 64) + ((ex >> 30) & 1023u);
   unsigned long long s4 = __shfl(b, JOB_R1X, 64) + ((ex >> 40) & 1023u);
   unsigned long long s5 = __shfl(b, JOB_QZ, 64) + ((ex >> 50) & 1023u);
   for (int j = 0; j < kEmptyPer; ++j) {
-    if (!((has >> j) & 1u)) continue;
     const unsigned r = (route >> (3 * j)) & 7u;
+    if (!((has >> j) & 1u) || r == JOB_R1Q) continue;
     const int32_t p = piece_of(j);
-    if (r == JOB_R1Q) {   // nearly every piece
-      L.job[s0++] = p;
-      continue;
-    }
     int32_t* dst = r == JOB_R2 ? L.job2 + s1 : r == JOB_FULL ? L.jobf + s2 : r == JOB_FP32 ? L.job32 + s3
                  : r == JOB_R1X ? L.job + (L.cap_piece - 1 - (int64_t)s4) : L.pz + s5;
     *dst = p;
