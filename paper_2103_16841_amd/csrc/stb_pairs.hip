@@ -449,12 +449,11 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
   block_count(L.cnt + CNT_MISS, nmiss);
 }
 
-// The empty-piece test, kEmptyPer pieces per thread and pass (coalesced:
-// piece base + j B + tid, B the block size), so that one list allocation
-// covers kEmptyPer * B pieces.  L at the midpoint first; the pieces where it is
-// zero go to a block-local LDS queue whose quarter-point evaluations are
-// then shared by all lanes of the block (dense, and on combo data the block
-// has just read).
+// The empty-piece test, kEmptyPer pieces per lane and pass: a wave takes
+// kEmptyPer runs of 64 consecutive pieces (coalesced reads; the job lists
+// keep piece order), so that one list allocation covers 64 kEmptyPer
+// pieces.  L at the midpoint (k_empty); the pieces where it is zero are
+// queued for the quarter points (k_quarter).
 constexpr int kEmptyPer = 8;
 
 // Job lists the empty-piece test routes a non-empty piece to.
@@ -556,10 +555,12 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
   const int64_t step = (int64_t)gridDim.x * B * kEmptyPer;
   for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < npiece; base += step) {
     unsigned has = 0, route = 0;   // route: 3 bits per item
-    auto piece_of = [&](int j) { return (int32_t)(base + (int64_t)j * B + threadIdx.x); };
+    // each wave takes kEmptyPer runs of 64 consecutive pieces
+    const int64_t wbase = base + (int64_t)(threadIdx.x >> 6) * 64 * kEmptyPer + (threadIdx.x & 63);
+    auto piece_of = [&](int j) { return (int32_t)(wbase + (int64_t)j * 64); };
 #pragma unroll 1
     for (int j = 0; j < kEmptyPer; ++j) {
-      const int64_t p = base + (int64_t)j * B + threadIdx.x;
+      const int64_t p = wbase + (int64_t)j * 64;
       if (p >= npiece) break;
       const double H = L.ph[p];
       bool nz = true;   // trapezoid half (H < 0): always evaluated
