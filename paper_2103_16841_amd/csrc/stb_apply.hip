@@ -31,22 +31,23 @@ __global__ __launch_bounds__(256) void k_bell_mfma(int64_t nblk, int64_t n,
   f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
   const int64_t q0 = bptr[blk], q1 = bptr[blk + 1];
   int64_t q = q0 + wv;
-  // four quads per wave and pass: their values, columns and W rows are all
+  // eight quads per wave and pass: their values, columns and W rows are all
   // requested before the first product waits on them
-  for (; q + 12 < q1; q += 16) {
-    float a[4], b[4];
-    int32_t c[4];
+  for (; q + 28 < q1; q += 32) {
+    float a[8], b[8];
+    int32_t c[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       a[u] = bval[(q + 4 * u) * 64 + lane];
       c[u] = bcol[(q + 4 * u) * 4 + kk];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) b[u] = c[u] >= 0 ? w32[(int64_t)c[u] * 16 + jj] : 0.f;
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], acc1, 0, 0, 0);
+    for (int u = 0; u < 8; ++u) b[u] = c[u] >= 0 ? w32[(int64_t)c[u] * 16 + jj] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u + 1], b[u + 1], acc1, 0, 0, 0);
+    }
   }
   for (; q < q1; q += 4) {
     const float a0 = bval[q * 64 + lane];

@@ -273,10 +273,10 @@ __global__ __launch_bounds__(256) void k_point_sum(int64_t np, const int64_t* __
   }
 }
 
-// y = A w (FP64 CSR), one wavefront per row, fixed-order reduction.  Four
-// entries per lane and pass, with four partial sums: the loads of a pass
-// are all in flight before the first product needs them (one entry per pass
-// waits out a column load and a gather every time).
+// y = A w (FP64 CSR), one wavefront per row, fixed-order reduction.  Eight
+// (then four) entries per lane and pass, with four partial sums: the loads
+// of a pass are all in flight before the first product needs them (one
+// entry per pass waits out a column load and a gather every time).
 __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ cols,
                                               const double* __restrict__ vals,
@@ -288,6 +288,26 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
     const int64_t e = rowptr[row + 1];
     int64_t k = rowptr[row] + lane;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (; k + 448 < e; k += 512) {
+      int32_t c[8];
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        c[u] = cols[k + 64 * u];
+        v[u] = vals[k + 64 * u];
+      }
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = w[(int64_t)c[u] * nrhs + col];
+      s0 = fma(v[0], x[0], s0);
+      s1 = fma(v[1], x[1], s1);
+      s2 = fma(v[2], x[2], s2);
+      s3 = fma(v[3], x[3], s3);
+      s0 = fma(v[4], x[4], s0);
+      s1 = fma(v[5], x[5], s1);
+      s2 = fma(v[6], x[6], s2);
+      s3 = fma(v[7], x[7], s3);
+    }
     for (; k + 192 < e; k += 256) {
       const int32_t c0 = cols[k], c1 = cols[k + 64], c2 = cols[k + 128], c3 = cols[k + 192];
       const double v0 = vals[k], v1 = vals[k + 64], v2 = vals[k + 128], v3 = vals[k + 192];
