@@ -681,6 +681,10 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
       }
     };
     double acc = 0.0;
+    // |delta| < H / 2: a piece shorter than pi (all but the rare long ones)
+    // needs no reduction for its sin/cos.  Decided per piece, so that a
+    // piece's value does not depend on the pieces that share its wave.
+    const bool short_piece = H <= kPi;
     // the next pair's table entries are loaded while this pair is evaluated
     double t_off = gl[2 * kMaxNg], t_wf = gl[3 * kMaxNg];
     for (int gi = 0; gi < (ng >> 1); ++gi) {
@@ -690,7 +694,8 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
         t_wf = gl[3 * kMaxNg + gi + 1];
       }
       double sd, cd;
-      sincos_small(H * off, &sd, &cd);
+      if (short_piece) sincos_half_pi(H * off, &sd, &cd);
+      else sincos_small(H * off, &sd, &cd);
       double lm, lp;
       L_pair(cd, sd, lm, lp);
       acc += (H * wf) * (lm + lp);
