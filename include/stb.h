@@ -289,6 +289,18 @@ stb_status stb_autotune(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_param
  * defaults (256 threads, 16 blocks per CU) with cfg16 = NULL. */
 stb_status stb_set_tuning(stb_ctx* ctx, const int32_t* cfg16);
 
+/* Upper limits on the lengths of the pair pipeline's lists on ctx, per
+ * chunk of candidates: max_cand candidates, max_combo lit (outer point,
+ * trial panel) combos, max_piece phi pieces; 0 = no limit (the default).
+ * The pipeline cuts the candidates into chunks whose lists fit and redoes a
+ * chunk whose lists overflowed with a smaller one, so the values assembled
+ * do not depend on the limits.  Set before the first assembly on ctx, they
+ * bound the workspace it allocates (one already larger is kept) at the cost
+ * of more chunks.  Nonzero limits are at least 64 (else STB_E_INVALID_ARG);
+ * a candidate whose own combos or pieces exceed them fails with
+ * STB_E_INTERNAL. */
+stb_status stb_set_pair_lists(stb_ctx* ctx, int64_t max_cand, int64_t max_combo, int64_t max_piece);
+
 /* ------------------------------------------------------------ serving
  * A server answers matvec and potential requests on meshes (and their
  * matrices) resident on one device, with continuous batching: nslots worker

@@ -35,6 +35,9 @@ struct stb_ctx {
   int tune_per_cu[8] = {16, 16, 16, 16, 16, 16, 16, 16};
   bool tuned = false;
   int ncu = 0;
+  // caller's upper limits on the pair lists' lengths: candidates, lit
+  // combos, pieces per chunk (0: none; stb_set_pair_lists)
+  int64_t list_limit[3] = {0, 0, 0};
   // Gauss-Legendre nodes on [0,1] for the last n_g used (device copy)
   int gl_n = 0;
   double* d_gl = nullptr;   // [4 * kMaxNg]: x, w, 1/2 - s(x), s'(x) w

@@ -137,6 +137,24 @@ struct Lists {
   const TrialRec* trial; // panel records of the run
 };
 
+// Item count of a list for a kernel: given by the host (n >= 0), or read
+// from the list's device counter -n - 1, so that the host need not wait for
+// the producer before it launches the consumer.  With a device count the
+// kernel does nothing when one of the first `done` lists (deep, combo,
+// piece: those whose producers have finished) overflowed: a producer skips
+// an allocation that crosses the capacity, so slots below it can be stale,
+// and the host redoes such a chunk with a smaller one (k_store writes
+// nothing for it).
+__device__ __forceinline__ int64_t list_count(const Lists& L, int64_t n, int64_t cap, int done) {
+  if (n >= 0) return n;
+  bool ok = L.cnt[CNT_DEEP] <= (unsigned long long)L.cap_combo;
+  if (done >= 2) ok = ok && L.cnt[CNT_COMBO] <= (unsigned long long)L.cap_combo;
+  if (done >= 3) ok = ok && L.cnt[CNT_PIECE] <= (unsigned long long)L.cap_piece;
+  if (!ok) return 0;
+  const unsigned long long c = L.cnt[-n - 1];
+  return (int64_t)(c < (unsigned long long)cap ? c : (unsigned long long)cap);
+}
+
 // Field positions of ComboL's apex-dependent part in the combo list; the
 // face normals (fa, fb, fc) are the trial panel's and are read from its
 // record, not stored per combo.
@@ -301,8 +319,9 @@ __device__ __forceinline__ TrialRec deep_fields(const TrialRec* __restrict__ p) 
   return T;
 }
 
-__global__ __launch_bounds__(kBlk) void k_lit_deep(Geo g, Lists L, int64_t c0, int64_t ndeep) {
+__global__ __launch_bounds__(kBlk) void k_lit_deep(Geo g, Lists L, int64_t c0, int64_t ndeep_arg) {
   const int B = (int)blockDim.x;
+  const int64_t ndeep = list_count(L, ndeep_arg, L.cap_combo, 1);
   for (int64_t k = (int64_t)blockIdx.x * B + threadIdx.x; k < ndeep; k += (int64_t)gridDim.x * B) {
     const uint32_t key = L.deep[k];
     const int64_t c = key >> 8;
@@ -363,8 +382,9 @@ struct BpLds {
   }
 };
 
-__global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int64_t ncombo) {
+__global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int64_t ncombo_arg) {
   const int B = (int)blockDim.x;
+  const int64_t ncombo = list_count(L, ncombo_arg, L.cap_combo, 2);
   __shared__ AllocLds sh;
   __shared__ double s_bp[kBpLds * kBlk];
   unsigned long long nmiss = 0;
@@ -549,8 +569,9 @@ __device__ __forceinline__ void route_pieces(Lists& L, unsigned has, unsigned ro
 // whose quarter points decide (k_quarter).  The quarter-point path has a
 // kernel of its own so that this one, run on every piece, needs fewer
 // registers and keeps more waves resident.
-__global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
+__global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece_arg) {
   const int B = (int)blockDim.x;
+  const int64_t npiece = list_count(L, npiece_arg, L.cap_piece, 3);
   unsigned long long ev_mid = 0;
   const int64_t step = (int64_t)gridDim.x * B * kEmptyPer;
   for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < npiece; base += step) {
@@ -583,8 +604,9 @@ __global__ __launch_bounds__(kBlk, 4) void k_empty(Lists L, int64_t npiece) {
 
 // The queued pieces (L zero at the midpoint): L at the quarter points; the
 // recipe of a piece found non-empty is taken at the point that decided.
-__global__ __launch_bounds__(kBlk, 3) void k_quarter(Lists L, int64_t nq) {
+__global__ __launch_bounds__(kBlk, 3) void k_quarter(Lists L, int64_t nq_arg) {
   const int B = (int)blockDim.x;
+  const int64_t nq = list_count(L, nq_arg, L.cap_piece, 3);
   unsigned long long ev_quarter = 0;
   const int64_t step = (int64_t)gridDim.x * B * kEmptyPer;
   for (int64_t base = (int64_t)blockIdx.x * B * kEmptyPer; base < nq; base += step) {
@@ -624,12 +646,16 @@ __global__ __launch_bounds__(kBlk, 3) void k_quarter(Lists L, int64_t nq) {
 
 // The n_g nodes of a piece by its recipe (NG gaps): per node only the
 // endpoint formulas of the recipe, not all four faces (see L_eval_recipe).
+// jobs_arg: the job list, or nullptr for the one-gap list's back part (its
+// last njob slots of L.job); njob_arg as for list_count.
 template <int NG, bool QE>
-__global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* __restrict__ jobs,
-                                                       int64_t njob, const double* __restrict__ gl,
+__global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* __restrict__ jobs_arg,
+                                                       int64_t njob_arg, const double* __restrict__ gl,
                                                        int ng, int ctr) {
   const int B = (int)blockDim.x;
   unsigned long long evals = 0;
+  const int64_t njob = list_count(L, njob_arg, L.cap_piece, 3);
+  const int32_t* __restrict__ jobs = jobs_arg ? jobs_arg : L.job + (L.cap_piece - njob);
   for (int64_t base = (int64_t)blockIdx.x * B; base < njob; base += (int64_t)gridDim.x * B) {
     const int64_t k = base + threadIdx.x;
     if (k >= njob) continue;
@@ -716,10 +742,11 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
 // period (no breakpoints): phi = (h n_g + g) 2 pi / (2 n_g), weight
 // 2 pi / (2 n_g).
 __global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, const int32_t* __restrict__ jobs,
-                                                   int64_t njob, const double* __restrict__ gl,
+                                                   int64_t njob_arg, const double* __restrict__ gl,
                                                    int ng, int ctr) {
   const int B = (int)blockDim.x;
   unsigned long long evals = 0;
+  const int64_t njob = list_count(L, njob_arg, L.cap_piece, 3);
   const double ht = kTwoPi / (2 * ng);
   for (int64_t base = (int64_t)blockIdx.x * B; base < njob; base += (int64_t)gridDim.x * B) {
     const int64_t k = base + threadIdx.x;
@@ -746,10 +773,11 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes(Lists L, const int32_t* __res
 // The n_g nodes of a far piece in mixed precision: node angle, sin/cos and
 // the per-face coefficients in FP64, root solves and interval measure in
 // FP32 (L_eval_far), node sum in FP32 with Kahan compensation.
-__global__ __launch_bounds__(kBlk, 4) void k_nodes32(Lists L, int64_t njob,
+__global__ __launch_bounds__(kBlk, 4) void k_nodes32(Lists L, int64_t njob_arg,
                                                      const double* __restrict__ gl, int ng) {
   const int B = (int)blockDim.x;
   unsigned long long evals = 0;
+  const int64_t njob = list_count(L, njob_arg, L.cap_piece, 3);
   const double ht = kTwoPi / (2 * ng);
   for (int64_t base = (int64_t)blockIdx.x * B; base < njob; base += (int64_t)gridDim.x * B) {
     const int64_t k = base + threadIdx.x;
@@ -786,7 +814,8 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes32(Lists L, int64_t njob,
   block_count(L.cnt + CNT_EVAL_NODES32, evals);
 }
 
-__global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo) {
+__global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo_arg) {
+  const int64_t ncombo = list_count(L, ncombo_arg, L.cap_combo, 3);
   int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x;
   for (; k < ncombo; k += (int64_t)gridDim.x * kBlk) {
     const int32_t p0 = L.p0[k], np = L.np[k];
@@ -835,6 +864,10 @@ __global__ __launch_bounds__(kBlk) void k_store(Geo g, Lists L, int64_t c0, int6
                                                 double* __restrict__ out, int check, int nseg,
                                                 const int64_t* __restrict__ seg_off,
                                                 unsigned long long* __restrict__ seg_causal) {
+  // a chunk whose lists overflowed is redone by the host: write nothing
+  if (L.cnt[CNT_DEEP] > (unsigned long long)L.cap_combo || L.cnt[CNT_COMBO] > (unsigned long long)L.cap_combo ||
+      L.cnt[CNT_PIECE] > (unsigned long long)L.cap_piece)
+    return;
   unsigned long long causal = 0, redo = 0;
   for (int64_t base = (int64_t)blockIdx.x * kBlk; base < nc; base += (int64_t)gridDim.x * kBlk) {
     const int64_t c = base + threadIdx.x;
@@ -1072,10 +1105,19 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
   // 2^24 candidates (the combo key holds 24 bits of candidate index)
   int64_t want_cand, want_combo, want_piece;
   ws_want(job.nnz, job.maxq, &want_cand, &want_combo, &want_piece);
+  int64_t* const want[3] = {&want_cand, &want_combo, &want_piece};
+  for (int k = 0; k < 3; ++k)
+    if (ctx->list_limit[k]) *want[k] = std::min(*want[k], ctx->list_limit[k]);
   stb_status s = ensure_workspace(ctx, want_cand, want_combo, want_piece);
   if (s) return s;
   PairWorkspace* w = ctx->ws;
   Lists L = w->L;
+  // the lists' lengths in use: the workspace's, within the caller's limits
+  // (the combo fields' stride follows cap_combo, so a shorter length only
+  // narrows the fields inside their allocation)
+  if (ctx->list_limit[0]) L.cap_cand = std::min(L.cap_cand, ctx->list_limit[0]);
+  if (ctx->list_limit[1]) L.cap_combo = std::min(L.cap_combo, ctx->list_limit[1]);
+  if (ctx->list_limit[2]) L.cap_piece = std::min(L.cap_piece, ctx->list_limit[2]);
   L.trial = job.trial;
   Geo g;
   g.rows = job.rows; g.cols = job.cols; g.trial = job.trial; g.fang = job.fang;
@@ -1086,14 +1128,11 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
   hipStream_t st = ctx->stream;
   unsigned long long h[CNT_N];
   // first guess: ~4 lit apexes and ~4 pieces per lit apex; adapted below
-  int64_t chunk = std::min<int64_t>(w->cap_cand, std::max<int64_t>(1, w->cap_combo / 4));
-  chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, w->cap_piece / 16));
+  int64_t chunk = std::min<int64_t>(L.cap_cand, std::max<int64_t>(1, L.cap_combo / 4));
+  chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, L.cap_piece / 16));
   int64_t c0 = 0;
-  auto rd = [&](int k, unsigned long long* v) -> stb_status {
-    HIPCHK(ctx, hipMemcpyAsync(v, L.cnt + k, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    return STB_OK;
-  };
+  // device count argument of list counter k (see list_count)
+  auto dev = [](int k) { return -(int64_t)k - 1; };
   for (int k = 0; k < 8; ++k) { ctx->kern_ms[k] = 0.0; ctx->kern_n[k] = 0; ctx->kern_units[k] = 0; }
   for (int k = 0; k < 4; ++k) ctx->path_counts[k] = 0;
   for (auto& e : ctx->kev)
@@ -1119,104 +1158,82 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     HIPCHK(ctx, t0(0));
     hipLaunchKernelGGL(k_lit, dim3(gfor(0, nc)), dim3(ctx->tune_block[0]), 0, st, g, L, c0, nc);
     HIPCHK(ctx, hipGetLastError());
-    unsigned long long ndeep = 0;
-    if ((s = rd(CNT_DEEP, &ndeep))) return s;
-    if (ndeep > (unsigned long long)w->cap_combo) {
-      if (nc == 1) return stb_fail(ctx, STB_E_INTERNAL, "pair lists too small for one candidate");
-      chunk = std::max<int64_t>(1, (int64_t)((double)nc * w->cap_combo / ndeep * 0.8));
-      continue;
-    }
-    if (ndeep)
-      hipLaunchKernelGGL(k_lit_deep, dim3(gfor(0, ndeep)), dim3(ctx->tune_block[0]), 0, st, g, L, c0,
-                         (int64_t)ndeep);
+    // the consumers read their counts from the device counters (see
+    // list_count); grids for the lists' upper bounds: at most maxq lit
+    // apexes per candidate, at most the piece list's capacity of jobs
+    const int64_t ub_combo = std::min<int64_t>(nc * job.maxq, L.cap_combo);
+    const int64_t ub_piece = L.cap_piece;
+    hipLaunchKernelGGL(k_lit_deep, dim3(gfor(0, ub_combo)), dim3(ctx->tune_block[0]), 0, st, g, L, c0,
+                       dev(CNT_DEEP));
     hipLaunchKernelGGL(k_emit_count, dim3((unsigned)((nc + 1 + 255) / 256)), dim3(256), 0, st, L, nc);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, stb_scan<int32_t>(L.ccnt, L.coff, nc, (int32_t*)L.scan_tmp, st));
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, L, nc);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(0));
-    unsigned long long ncombo = 0, npiece = 0, njob = 0;
-    if ((s = rd(CNT_COMBO, &ncombo))) return s;
-    if (ncombo > (unsigned long long)w->cap_combo) {
-      if (nc == 1) return stb_fail(ctx, STB_E_INTERNAL, "pair lists too small for one candidate");
-      chunk = std::max<int64_t>(1, (int64_t)((double)nc * w->cap_combo / ncombo * 0.8));
-      continue;
-    }
     HIPCHK(ctx, t0(1));
-    hipLaunchKernelGGL(k_bp, dim3(gfor(1, ncombo)), dim3(ctx->tune_block[1]), 0, st, g, L, c0,
-                       (int64_t)ncombo);
+    hipLaunchKernelGGL(k_bp, dim3(gfor(1, ub_combo)), dim3(ctx->tune_block[1]), 0, st, g, L, c0,
+                       dev(CNT_COMBO));
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(1));
-    if ((s = rd(CNT_PIECE, &npiece))) return s;
-    if (npiece > (unsigned long long)w->cap_piece) {
-      if (nc == 1) return stb_fail(ctx, STB_E_INTERNAL, "pair lists too small for one candidate");
-      chunk = std::max<int64_t>(1, (int64_t)((double)nc * w->cap_piece / npiece * 0.8));
-      continue;
-    }
-    if (npiece) {
-      HIPCHK(ctx, t0(2));
-      hipLaunchKernelGGL(k_empty, dim3(gfor(2, npiece, kEmptyPer)), dim3(ctx->tune_block[2]), 0, st, L,
-                         (int64_t)npiece);
-      HIPCHK(ctx, hipGetLastError());
-      unsigned long long nqz = 0;
-      if ((s = rd(CNT_QZ, &nqz))) return s;
-      if (nqz) {
-        hipLaunchKernelGGL(k_quarter, dim3(gfor(2, nqz, kEmptyPer)), dim3(ctx->tune_block[2]), 0, st, L,
-                           (int64_t)nqz);
-        HIPCHK(ctx, hipGetLastError());
-      }
-      HIPCHK(ctx, t1(2));
-    }
-    unsigned long long njob32 = 0, njob2 = 0, njobf = 0, njob1x = 0, hc[CNT_N];
-    HIPCHK(ctx, hipMemcpyAsync(hc, L.cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    njob = hc[CNT_JOB];
-    njob2 = hc[CNT_JOB2];
-    njob1x = hc[CNT_JOB1X];
-    njobf = hc[CNT_JOBF];
-    njob32 = hc[CNT_JOB32];
-    if (njob + njob1x + njob2 + njobf) {
-      // FP64 nodes: one-gap recipes, two-gap recipes, full evaluations
-      HIPCHK(ctx, t0(4));
-      if (njob)
-        hipLaunchKernelGGL((k_nodes_rec<1, true>), dim3(gfor(4, njob)), dim3(ctx->tune_block[4]), 0, st,
-                           L, L.job, (int64_t)njob, job.gl, job.ng, (int)CNT_EVAL_NODES);
-      if (njob1x)
-        hipLaunchKernelGGL((k_nodes_rec<1, false>), dim3(gfor(4, njob1x)), dim3(ctx->tune_block[4]), 0,
-                           st, L, L.job + (L.cap_piece - (int64_t)njob1x), (int64_t)njob1x, job.gl,
-                           job.ng, (int)CNT_EVAL_NODES);
-      if (njob2)
-        hipLaunchKernelGGL((k_nodes_rec<2, false>), dim3(gfor(4, njob2)), dim3(ctx->tune_block[4]), 0,
-                           st, L, L.job2, (int64_t)njob2, job.gl, job.ng, (int)CNT_EVAL_NODES);
-      if (njobf)
-        hipLaunchKernelGGL(k_nodes, dim3(gfor(4, njobf)), dim3(ctx->tune_block[4]), 0, st, L, L.jobf,
-                           (int64_t)njobf, job.gl, job.ng, (int)CNT_EVAL_NODES);
-      HIPCHK(ctx, hipGetLastError());
-      HIPCHK(ctx, t1(4));
-    }
-    if (njob32) {
+    HIPCHK(ctx, t0(2));
+    hipLaunchKernelGGL(k_empty, dim3(gfor(2, ub_piece, kEmptyPer)), dim3(ctx->tune_block[2]), 0, st, L,
+                       dev(CNT_PIECE));
+    hipLaunchKernelGGL(k_quarter, dim3(gfor(2, ub_piece, kEmptyPer)), dim3(ctx->tune_block[2]), 0, st, L,
+                       dev(CNT_QZ));
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, t1(2));
+    // FP64 nodes: one-gap recipes (front and back of the one-gap list),
+    // two-gap recipes, full evaluations
+    HIPCHK(ctx, t0(4));
+    hipLaunchKernelGGL((k_nodes_rec<1, true>), dim3(gfor(4, ub_piece)), dim3(ctx->tune_block[4]), 0, st, L,
+                       L.job, dev(CNT_JOB), job.gl, job.ng, (int)CNT_EVAL_NODES);
+    hipLaunchKernelGGL((k_nodes_rec<1, false>), dim3(gfor(4, ub_piece)), dim3(ctx->tune_block[4]), 0, st,
+                       L, nullptr, dev(CNT_JOB1X), job.gl, job.ng, (int)CNT_EVAL_NODES);
+    hipLaunchKernelGGL((k_nodes_rec<2, false>), dim3(gfor(4, ub_piece)), dim3(ctx->tune_block[4]), 0, st,
+                       L, L.job2, dev(CNT_JOB2), job.gl, job.ng, (int)CNT_EVAL_NODES);
+    hipLaunchKernelGGL(k_nodes, dim3(gfor(4, ub_piece)), dim3(ctx->tune_block[4]), 0, st, L, L.jobf,
+                       dev(CNT_JOBF), job.gl, job.ng, (int)CNT_EVAL_NODES);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, t1(4));
+    if (g.mixed) {
       HIPCHK(ctx, t0(5));
-      hipLaunchKernelGGL(k_nodes32, dim3(gfor(5, njob32)), dim3(ctx->tune_block[5]), 0, st, L,
-                         (int64_t)njob32,
-                         job.gl, job.ng);
+      hipLaunchKernelGGL(k_nodes32, dim3(gfor(5, ub_piece)), dim3(ctx->tune_block[5]), 0, st, L,
+                         dev(CNT_JOB32), job.gl, job.ng);
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(5));
     }
     HIPCHK(ctx, t0(6));
-    if (ncombo) {
-      hipLaunchKernelGGL(k_combine, dim3(grid_for(ncombo)), dim3(kBlk), 0, st, L, (int64_t)ncombo);
-      HIPCHK(ctx, hipGetLastError());
-    }
-    const bool check = g.mixed && g.apex_w && njob32;
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(ub_combo)), dim3(kBlk), 0, st, L, dev(CNT_COMBO));
+    HIPCHK(ctx, hipGetLastError());
+    const bool check = g.mixed && g.apex_w;
     hipLaunchKernelGGL(k_store, dim3(grid_for(nc)), dim3(kBlk), 0, st, g, L, c0, nc, job.out,
                        check ? 1 : 0, job.nseg, job.seg_off, job.seg_causal);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, t1(6));
+    // the chunk's one wait: its list counts
+    unsigned long long hc[CNT_N];
+    HIPCHK(ctx, hipMemcpyAsync(hc, L.cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    {
+      // a list overflowed: nothing was stored; redo with a smaller chunk
+      // (a count after an overflowed list is a lower bound)
+      double f = 1.0;
+      if (hc[CNT_DEEP] > (unsigned long long)L.cap_combo) f = std::min(f, (double)L.cap_combo / hc[CNT_DEEP]);
+      if (hc[CNT_COMBO] > (unsigned long long)L.cap_combo) f = std::min(f, (double)L.cap_combo / hc[CNT_COMBO]);
+      if (hc[CNT_PIECE] > (unsigned long long)L.cap_piece) f = std::min(f, (double)L.cap_piece / hc[CNT_PIECE]);
+      if (f < 1.0) {
+        if (nc == 1) return stb_fail(ctx, STB_E_INTERNAL, "pair lists too small for one candidate");
+        chunk = std::max<int64_t>(1, (int64_t)((double)nc * f * 0.8));
+        continue;
+      }
+    }
+    const unsigned long long ncombo = hc[CNT_COMBO], npiece = hc[CNT_PIECE];
+    const unsigned long long njob = hc[CNT_JOB], njob1x = hc[CNT_JOB1X], njob2 = hc[CNT_JOB2];
     if (check) {
       // mixed: entries whose FP32 error bound is too large for their size
       // are recomputed with FP64 nodes
-      unsigned long long nredo = 0, njr = 0;
-      if ((s = rd(CNT_REDO, &nredo))) return s;
+      unsigned long long nredo = hc[CNT_REDO], njr = 0;
       if (nredo) {
         // the FP64 job lists were consumed by the launches above (same stream)
         HIPCHK(ctx, hipMemsetAsync(L.cnt + CNT_JOB, 0, 4 * sizeof(unsigned long long), st));
@@ -1256,8 +1273,12 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
       HIPCHK(ctx, hipGetLastError());
       HIPCHK(ctx, t1(3));
     }
-    HIPCHK(ctx, hipMemcpyAsync(h, L.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (check) {
+      HIPCHK(ctx, hipMemcpyAsync(h, L.cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
+    } else {
+      for (int k = 0; k < CNT_N; ++k) h[k] = hc[k];
+    }
     for (int k = 0; k < 8; ++k) {
       if (!used[k]) continue;
       float ms = 0.0f;
@@ -1286,11 +1307,22 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
     if (job.n_causal) *job.n_causal += h[CNT_CAUSAL];
     c0 += nc;
     // next chunk: as large as the lists allow at this chunk's densities
-    double fc = (double)w->cap_combo / std::max<unsigned long long>(ncombo, 1);
-    double fp = (double)w->cap_piece / std::max<unsigned long long>(npiece, 1);
+    double fc = (double)L.cap_combo / std::max<unsigned long long>(ncombo, 1);
+    double fp = (double)L.cap_piece / std::max<unsigned long long>(npiece, 1);
     int64_t next = (int64_t)((double)nc * std::min(fc, fp) * 0.7);
-    chunk = std::max<int64_t>(1, std::min<int64_t>(next, w->cap_cand));
+    chunk = std::max<int64_t>(1, std::min<int64_t>(next, L.cap_cand));
   }
+  return STB_OK;
+}
+
+extern "C" stb_status stb_set_pair_lists(stb_ctx* ctx, int64_t max_cand, int64_t max_combo,
+                                         int64_t max_piece) {
+  if (!ctx) return stb_fail(nullptr, STB_E_INVALID_ARG, "NULL context");
+  const int64_t v[3] = {max_cand, max_combo, max_piece};
+  for (int k = 0; k < 3; ++k)
+    if (v[k] < 0 || (v[k] > 0 && v[k] < 64))
+      return stb_fail(ctx, STB_E_INVALID_ARG, "list limit %d = %lld: 0 or at least 64", k, (long long)v[k]);
+  for (int k = 0; k < 3; ++k) ctx->list_limit[k] = v[k];
   return STB_OK;
 }
 

@@ -26,7 +26,7 @@ EXPORTS = ["stb_default_params", "stb_ctx_create", "stb_ctx_destroy", "stb_statu
            "stb_potential_D_dev", "stb_inner_values_D", "stb_dl_energetic",
            "stb_l2_points", "stb_project_V1",
            "stb_last_kernel_times", "stb_mat_export", "stb_batch_assemble", "stb_autotune",
-           "stb_set_tuning", "stb_server_create", "stb_server_add_mesh", "stb_server_submit",
+           "stb_set_tuning", "stb_set_pair_lists", "stb_server_create", "stb_server_add_mesh", "stb_server_submit",
            "stb_server_wait", "stb_server_destroy"]
 
 STB_REQ_MATVEC16, STB_REQ_POTENTIAL = 0, 1
@@ -123,6 +123,7 @@ def load():
     L.stb_server_destroy.argtypes = [_VP]
     L.stb_server_destroy.restype = None
     L.stb_set_tuning.argtypes = [_VP, _I32]
+    L.stb_set_pair_lists.argtypes = [_VP, i64, i64, i64]
     L.stb_batch_assemble.argtypes = [_VP, i32, ctypes.POINTER(_VP), ctypes.POINTER(QuadParams),
                                      i64, ctypes.POINTER(_VP), i32, ctypes.POINTER(_VP),
                                      ctypes.POINTER(_VP), _I64]
@@ -363,6 +364,11 @@ def set_tuning(ctx, blocks=None, per_cu=None):
         return
     cfg = np.asarray(list(blocks) + list(per_cu), dtype=np.int32)
     _chk(load().stb_set_tuning(ctx.h, cfg.ctypes.data_as(_I32)), ctx.h)
+
+
+def set_pair_lists(ctx, max_cand=0, max_combo=0, max_piece=0):
+    """Limit the pair pipeline's list lengths per chunk (0: no limit)."""
+    _chk(load().stb_set_pair_lists(ctx.h, max_cand, max_combo, max_piece), ctx.h)
 
 
 def batch_assemble(ctx, meshes, params=None, hbm_budget=0, keep=True, W_ptrs=None, Y_ptrs=None,

@@ -160,3 +160,34 @@ def test_autotune_keeps_results(stb, ctx):
     with pytest.raises(stb.StbError):
         stb.set_tuning(ctx, [96] * 8, [4] * 8)
     stb.set_tuning(ctx)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_list_limits_keep_results(stb, ctx, prec):
+    """Short pair lists cut the candidates into many chunks, and a chunk
+    whose lists overflow is redone smaller; the values do not change."""
+    print("case: list limits", prec, flush=True)
+    mesh = inputs.icosphere_mesh(level=1, S=6, T=4.0, jitter=0.2, seed=4)
+    p = stb.default_params(prec=stb.STB_MIXED if prec == "mixed" else stb.STB_FP64)
+    m = stb.Mesh(ctx, mesh.vtx, mesh.tets)
+    A = stb.assemble_V(ctx, m, p)
+    ref = A.export()
+    A.close()
+    m.close()
+    c2 = stb.Context(0)
+    try:
+        with pytest.raises(stb.StbError):
+            stb.set_pair_lists(c2, 10, 0, 0)
+        stb.set_pair_lists(c2, 4096, 512, 2048)
+        m2 = stb.Mesh(c2, mesh.vtx, mesh.tets)
+        B = stb.assemble_V(c2, m2, p)
+        chunks = c2.kernel_times()["sums_store"][1]
+        got = B.export()
+        B.close()
+        m2.close()
+        print("chunks", chunks, flush=True)
+        assert chunks > 8
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b)
+    finally:
+        c2.close()
