@@ -413,22 +413,27 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
     cleanup();
     return stb_fail(ctx, STB_E_INVALID_ARG, "face batch too large");
   }
-  bool ok = dalloc(&trial_g, (size_t)std::max<int64_t>(P, 1)) == hipSuccess &&
-            dalloc(&fang_g, (size_t)std::max<int64_t>(P, 1)) == hipSuccess &&
-            dalloc(&apex_g, (size_t)std::max<int64_t>(F, 1) * fq * 4) == hipSuccess &&
-            dalloc(&ones_g, (size_t)std::max<int64_t>(F, 1) * fq) == hipSuccess &&
-            dalloc(&apexn_g, (size_t)std::max<int64_t>(F, 1)) == hipSuccess &&
-            dalloc(&rows_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
-            dalloc(&cols_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
-            dalloc(&S_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
+  // one unit: the pipeline reads the mesh's arrays and the unit's face CSR
+  // in place (its rows and columns need no offsets); several: staged into
+  // concatenated arrays with per-unit offsets
+  const bool direct = nunit == 1;
+  bool ok = dalloc(&S_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
             dalloc(&lit_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
             dalloc(&d_causal, (size_t)nunit) == hipSuccess;
+  if (ok && !direct)
+    ok = dalloc(&trial_g, (size_t)std::max<int64_t>(P, 1)) == hipSuccess &&
+         dalloc(&fang_g, (size_t)std::max<int64_t>(P, 1)) == hipSuccess &&
+         dalloc(&apex_g, (size_t)std::max<int64_t>(F, 1) * fq * 4) == hipSuccess &&
+         dalloc(&ones_g, (size_t)std::max<int64_t>(F, 1) * fq) == hipSuccess &&
+         dalloc(&apexn_g, (size_t)std::max<int64_t>(F, 1)) == hipSuccess &&
+         dalloc(&rows_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
+         dalloc(&cols_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess;
   if (!ok) {
     cleanup();
     return stb_fail(ctx, STB_E_NO_MEMORY, "face lists of %lld candidates do not fit", (long long)C);
   }
   hipError_t e = hipMemsetAsync(d_causal, 0, sizeof(unsigned long long) * nunit, st);
-  for (int k = 0; k < nunit && e == hipSuccess; ++k) {
+  for (int k = 0; k < nunit && e == hipSuccess && !direct; ++k) {
     const FaceUnit& fu = units[k];
     const U& x = u[(size_t)k];
     const stb_mesh* me = fu.mesh;
@@ -459,13 +464,25 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
   }
   PairJob J;
   J.nnz = C;
-  J.rows = rows_g;
-  J.cols = cols_g;
-  J.trial = trial_g;
-  J.fang = fang_g;
-  J.apex = apex_g;
-  J.apex_w = ones_g;
-  J.apex_n = apexn_g;
+  if (direct) {
+    const stb_mesh* me = units[0].mesh;
+    const int64_t f0 = u[0].f0;
+    J.rows = u[0].frowof;
+    J.cols = u[0].fcols;
+    J.trial = me->d_trial;
+    J.fang = me->d_fang;
+    J.apex = me->d_fpts + f0 * fq * 4;
+    J.apex_w = me->d_fones + f0 * fq;
+    J.apex_n = me->d_fnq + f0;
+  } else {
+    J.rows = rows_g;
+    J.cols = cols_g;
+    J.trial = trial_g;
+    J.fang = fang_g;
+    J.apex = apex_g;
+    J.apex_w = ones_g;
+    J.apex_n = apexn_g;
+  }
   J.maxq = fq;
   J.gl = ctx->d_gl;
   J.ng = p.n_g;
