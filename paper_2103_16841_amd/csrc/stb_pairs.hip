@@ -549,9 +549,15 @@ __device__ __forceinline__ void route_pieces(Lists& L, unsigned has, unsigned ro
   unsigned long long s3 = __shfl(b, JOB_FP32, 64) + ((ex >> 30) & 1023u);
   unsigned long long s4 = __shfl(b, JOB_R1X, 64) + ((ex >> 40) & 1023u);
   unsigned long long s5 = __shfl(b, JOB_QZ, 64) + ((ex >> 50) & 1023u);
-  for (int j = 0; j < kEmptyPer; ++j) {
+  // the other lists: only the lane's items that go there (nearly always
+  // none or one of its kEmptyPer), so the wave runs the slowest lane's few
+  unsigned rare = 0;
+  for (int j = 0; j < kEmptyPer; ++j)
+    rare |= (((has >> j) & 1u) && ((route >> (3 * j)) & 7u) != JOB_R1Q ? 1u : 0u) << j;
+  while (rare) {
+    const int j = __ffs(rare) - 1;
+    rare &= rare - 1u;
     const unsigned r = (route >> (3 * j)) & 7u;
-    if (!((has >> j) & 1u) || r == JOB_R1Q) continue;
     const int32_t p = piece_of(j);
     int32_t* dst = r == JOB_R2 ? L.job2 + s1 : r == JOB_FULL ? L.jobf + s2 : r == JOB_FP32 ? L.job32 + s3
                  : r == JOB_R1X ? L.job + (L.cap_piece - 1 - (int64_t)s4) : L.pz + s5;
