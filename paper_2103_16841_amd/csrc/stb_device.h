@@ -84,13 +84,15 @@ STB_HD __forceinline__ double dot3(const double* a, const double* b) {
 // [0, 4 pi)): Cody-Waite reduction by pi/2 with a two-part pi/2, then the
 // Taylor polynomials of sin (to x^17) and cos (to x^18) on [-pi/4, pi/4],
 // whose truncation errors there are below 1e-17.
-// a * b + c as one v_fma_f64 with the addend in a register that stays
-// live (a polynomial coefficient): the compiler otherwise copies the
-// coefficient and uses the two-address v_fmac_f64, two instructions.
+// a * b + c as one v_fma_f64 with the addend a polynomial coefficient in
+// a scalar register pair (the one scalar operand a VOP3 instruction may
+// take): the compiler otherwise copies the coefficient and uses the
+// two-address v_fmac_f64, two instructions, and coefficients kept in vector
+// registers across a loop cost the node kernels a wave per SIMD.
 STB_HD __forceinline__ double fma_keep(double a, double b, double c) {
 #if defined(__HIP_DEVICE_COMPILE__)
   double r;
-  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
   return r;
 #else
   return fma(a, b, c);
@@ -1178,22 +1180,30 @@ STB_HD __forceinline__ double frcp_node(double x) {
 #endif
 }
 
+// A discriminant D <= 2^-900 (no real root, or a double root up to
+// rounding) is taken as 2^-900, one floor instead of a test and two
+// selects: its root 2^-450 vanishes when added to a C_k above 2^-397 in
+// magnitude, as 0 would, and at C_k = 0 it leaves w = 2^-450 / e instead of
+// 0 (the r-measure moves by that much at most).
 STB_HD __forceinline__ double sqrt_disc_node(double D) {
-  const bool pos = D > 0x1p-900;
+  const double x = fmax(D, 0x1p-900);
 #if defined(__HIP_DEVICE_COMPILE__)
-  const double x = pos ? D : 1.0;
   const double y = __builtin_amdgcn_rsq(x);
   const double g = x * y;
-  return pos ? fma(g, fma(-g, 0.5 * y, 0.5), g) : 0.0;
+  return fma(g, fma(-g, 0.5 * y, 0.5), g);
 #else
-  return pos ? sqrt(D) : 0.0;
+  return sqrt(x);
 #endif
 }
 
+// r(w1) - r(w0) = (w1 - w0) (1 - d^2 / (w0 w1)) / 2.  Both ends are at
+// least |d| (the admissible range starts there), so w0 w1 >= d^2 when
+// d != 0; the floor 2^-1000 only acts at d = 0, where it keeps 1 / (w0 w1)
+// finite and the factor exactly 1.
 STB_HD __forceinline__ double rdiff_node(double w0, double w1, double d2) {
   const double h = 0.5 * (w1 - w0);
-  const double g = fma(-d2, frcp_node(w0 * w1), 1.0);
-  return d2 > 0.0 ? h * g : h;
+  const double g = fma(-d2, frcp_node(fmax(w0 * w1, 0x1p-1000)), 1.0);
+  return h * g;
 }
 
 STB_HD __forceinline__ double endpoint_value_node(const Endpoint& E, double d2, double wlo, double whi,
