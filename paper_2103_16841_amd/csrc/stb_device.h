@@ -776,8 +776,10 @@ STB_HD __forceinline__ bool piece_misses(const TrialRec& T, const Apex& A, doubl
 // vertex directions are not resolved.
 constexpr double kWedgeMargin = 1e-8;
 
+// The directions that miss, as an arc: from ms = lo + w + kWedgeMargin
+// over len = 2 pi - w - 2 kWedgeMargin.
 struct ShadowWedge {
-  double lo, w;
+  double ms, len;
   bool ok;
 };
 
@@ -819,24 +821,22 @@ STB_HD __forceinline__ ShadowWedge shadow_wedge(const TrialRec& T, const Apex& A
   const double lo = atan2_bp(vlo, ulo);
   double w = atan2_bp(vhi, uhi) - lo;
   w = w < 0.0 ? w + kTwoPi : w;
-  W.lo = lo;
-  W.w = w;
+  W.ms = lo + w + kWedgeMargin;
+  W.len = kTwoPi - w - 2.0 * kWedgeMargin;
   W.ok = w < kPi - 1e-6;
   return W;
 }
 
-STB_HD __forceinline__ bool wedge_misses_dir(const ShadowWedge& W, double phi) {
-  double r = phi - W.lo;
-  r -= kTwoPi * floor(r * (1.0 / kTwoPi));
-  return r > W.w + kWedgeMargin && r < kTwoPi - kWedgeMargin;
-}
-
-// piece_misses by the wedge: the piece's midpoint and quarter points (all
-// three evaluated: no branches for lanes to diverge on).
+// piece_misses by the wedge: the piece's quarter points and midpoint all on
+// the missing arc.  With u the first quarter point's offset along the arc
+// (reduced mod 2 pi), that is 0 < u and u + H / 2 < len: one reduction
+// instead of three.  Every miss it finds is one of the three points
+// tested separately; the converse fails only when the whole wedge lies
+// between two of the points, and such a piece is kept and evaluated.
 STB_HD __forceinline__ bool wedge_misses(const ShadowWedge& W, double a, double H) {
-  const bool m0 = wedge_misses_dir(W, a + 0.5 * H), m1 = wedge_misses_dir(W, a + 0.25 * H),
-             m2 = wedge_misses_dir(W, a + 0.75 * H);
-  return W.ok & m0 & m1 & m2;
+  double u = fma(0.25, H, a) - W.ms;
+  u -= kTwoPi * floor(u * (1.0 / kTwoPi));
+  return W.ok & (u > 0.0) & (fma(0.5, H, u) < W.len);
 }
 
 // Sorts a[0..n) for n <= M (M a power of 2): into registers (padded with
