@@ -1196,14 +1196,14 @@ STB_HD __forceinline__ double sqrt_disc_node(double D) {
 #endif
 }
 
-// r(w1) - r(w0) = (w1 - w0) (1 - d^2 / (w0 w1)) / 2.  Both ends are at
-// least |d| (the admissible range starts there), so w0 w1 >= d^2 when
+// r(w1) - r(w0) = (w1 - w0) (1 - d^2 / (w0 w1)) / 2, returned doubled (the
+// node sums take the factor 1/2 once, at the end: exact).  Both ends are
+// at least |d| (the admissible range starts there), so w0 w1 >= d^2 when
 // d != 0; the floor 2^-1000 only acts at d = 0, where it keeps 1 / (w0 w1)
 // finite and the factor exactly 1.
-STB_HD __forceinline__ double rdiff_node(double w0, double w1, double d2) {
-  const double h = 0.5 * (w1 - w0);
+STB_HD __forceinline__ double rdiff2_node(double w0, double w1, double d2) {
   const double g = fma(-d2, frcp_node(fmax(w0 * w1, 0x1p-1000)), 1.0);
-  return h * g;
+  return (w1 - w0) * g;
 }
 
 STB_HD __forceinline__ double endpoint_value_node(const Endpoint& E, double d2, double wlo, double whi,
@@ -1229,21 +1229,22 @@ STB_HD __forceinline__ double endpoint_value_qe_node(const Endpoint& E, double d
 }
 
 // One endpoint formula at the mirror nodes m -+ delta of a piece, from the
-// per-piece P = B(m), Q = b sin m - c cos m of its face and CC = C^2:
-// B(m -+ delta) = P cos delta +- Q sin delta.  vm at m - delta, vp at
-// m + delta; node-stage arithmetic.
+// per-piece P = B(m), Q = b sin m - c cos m of its face, CC = C^2 and
+// SG = copysign(1, C): B(m -+ delta) = P cos delta +- Q sin delta, and
+// C + copysign(s, C) as one fma.  vm at m - delta, vp at m + delta;
+// node-stage arithmetic.
 template <bool QE>
-STB_HD __forceinline__ void endpoint_pair_node(const Endpoint& E, double P, double Q, double CC, double d2,
-                                               double wlo, double whi, double cd, double sd, double& vm,
-                                               double& vp) {
-  const double t = P * cd, qs = Q * sd;
+STB_HD __forceinline__ void endpoint_pair_node(const Endpoint& E, double P, double Q, double CC, double SG,
+                                               double d2, double wlo, double whi, double cd, double sd,
+                                               double& vm, double& vp) {
+  const double qs = Q * sd;
   double v[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const double B = h ? t - qs : t + qs;
+    const double B = fma(P, cd, h ? -qs : qs);
     const double e = B - E.a, f = B + E.a;
     const double D = fma(d2 * e, f, CC);
-    const double q = E.C + copysign(sqrt_disc_node(D), E.C);
+    const double q = fma(SG, sqrt_disc_node(D), E.C);
     double w;
     if (QE) {
       w = q * frcp_node(e);

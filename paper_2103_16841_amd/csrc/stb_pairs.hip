@@ -687,14 +687,15 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
     const double m = a + 0.5 * H;
     double sm, cm;
     sincos_small(m, &sm, &cm);
-    double P[2 * NG], Q[2 * NG], CC[2 * NG];
+    double P[2 * NG], Q[2 * NG], CC[2 * NG], SG[2 * NG];
 #pragma unroll
     for (int e = 0; e < 2 * NG; ++e) {
       P[e] = fma(E[e].fb, cm, E[e].fc * sm);
       Q[e] = fma(E[e].fb, sm, -(E[e].fc * cm));
       CC[e] = E[e].C * E[e].C;
+      SG[e] = copysign(1.0, E[e].C);
     }
-    // L at m - delta (lm) and m + delta (lp)
+    // twice L at m - delta (lm) and m + delta (lp): the sum takes the 1/2
     auto L_pair = [&](double cd, double sd, double& lm, double& lp) {
       lm = 0.0;
       lp = 0.0;
@@ -704,12 +705,12 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           const int e = 2 * g + t;
-          endpoint_pair_node<QE>(E[e], P[e], Q[e], CC[e], d2, wlo, whi, cd, sd, vm[t], vp[t]);
+          endpoint_pair_node<QE>(E[e], P[e], Q[e], CC[e], SG[e], d2, wlo, whi, cd, sd, vm[t], vp[t]);
         }
         // a gap that closed (end <= start) measures 0: rdiff of equal ends,
         // so no branch (w >= |d| > 0 when d^2 > 0; rdiff ignores 1/w at d = 0)
-        lm += rdiff_node(vm[0], fmax(vm[1], vm[0]), d2);
-        lp += rdiff_node(vp[0], fmax(vp[1], vp[0]), d2);
+        lm += rdiff2_node(vm[0], fmax(vm[1], vm[0]), d2);
+        lp += rdiff2_node(vp[0], fmax(vp[1], vp[0]), d2);
       }
     };
     double acc = 0.0;
@@ -730,15 +731,16 @@ __global__ __launch_bounds__(kBlk, 4) void k_nodes_rec(Lists L, const int32_t* _
       else sincos_small(H * off, &sd, &cd);
       double lm, lp;
       L_pair(cd, sd, lm, lp);
-      acc += (H * wf) * (lm + lp);
+      acc += wf * (lm + lp);
     }
     if (ng & 1) {   // u = 1/2: the midpoint itself
       double lm, lp;
       L_pair(1.0, 0.0, lm, lp);
-      acc += (H * 1.5) * gl[kMaxNg + (ng >> 1)] * lm;
+      acc += (1.5 * gl[kMaxNg + (ng >> 1)]) * lm;
     }
     evals += (unsigned long long)ng;
-    L.pv[p] = acc;
+    // the weights' common factor H, and the 1/2 the doubled r-measures left
+    L.pv[p] = (0.5 * H) * acc;
   }
   block_count(L.cnt + ctr, evals);
 }
