@@ -258,9 +258,12 @@ STB_HD __forceinline__ double sqrt_rough(double x) {
 // r(w1) - r(w0) = (w1 - w0) (1 - d^2 / (w0 w1)) / 2 for w1 >= w0 > 0 (or
 // d^2 = 0, where w0 may be 0).
 STB_HD __forceinline__ double rdiff(double w0, double w1, double d2) {
+  // the ends lie in the admissible range, so w0 w1 >= d^2 when d != 0; the
+  // floor 2^-1000 acts only at d = 0 (or in an empty range, whose measure
+  // is not used), where it keeps 1 / (w0 w1) finite and the factor exactly 1
   double h = 0.5 * (w1 - w0);
-  double g = fma(-d2, frcp(w0 * w1), 1.0);
-  return d2 > 0.0 ? h * g : h;
+  double g = fma(-d2, frcp(fmax(w0 * w1, 0x1p-1000)), 1.0);
+  return h * g;
 }
 
 // Face data needed by L(phi): fa, fb, fc of the 4 faces.
