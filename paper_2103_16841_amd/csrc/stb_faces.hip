@@ -351,7 +351,8 @@ static stb_status face_rows(stb_ctx* ctx, const FaceUnit& fu, int64_t f0, int64_
                                  : stb_fail(ctx, STB_E_DEVICE, "face rows: %s", hipGetErrorString(e));
   if (s == STB_OK && hipMemcpy(fnnz, *frowptr + nfu, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
     s = stb_fail(ctx, STB_E_DEVICE, "face rows copy");
-  if (s == STB_OK && (dalloc(fcols, (size_t)*fnnz) != hipSuccess || dalloc(frowof, (size_t)*fnnz) != hipSuccess))
+  if (s == STB_OK && (kalloc(ctx, fcols, (size_t)*fnnz) != hipSuccess ||
+                      kalloc(ctx, frowof, (size_t)*fnnz) != hipSuccess))
     s = stb_fail(ctx, STB_E_NO_MEMORY, "face candidates (%lld)", (long long)*fnnz);
   if (s == STB_OK && nfu > 0) {
     hipLaunchKernelGGL(k_face_rows_fill, dim3((unsigned)nfu), dim3(256), 0, st, nfu, d_prim, fu.rowptr,
@@ -387,9 +388,9 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
   uint8_t* lit_g = nullptr;
   unsigned long long* d_causal = nullptr;
   auto cleanup = [&]() {
-    for (auto& x : u) { dfree(x.frowptr); dfree(x.fcols); dfree(x.frowof); dfree(x.fprim); }
-    dfree(trial_g); dfree(fang_g); dfree(apex_g); dfree(ones_g); dfree(S_g);
-    dfree(apexn_g); dfree(rows_g); dfree(cols_g); dfree(lit_g); dfree(d_causal);
+    for (auto& x : u) { dfree(x.frowptr); ctx_keep(ctx, x.fcols); ctx_keep(ctx, x.frowof); dfree(x.fprim); }
+    dfree(trial_g); dfree(fang_g); dfree(apex_g); dfree(ones_g); ctx_keep(ctx, S_g);
+    dfree(apexn_g); dfree(rows_g); dfree(cols_g); ctx_keep(ctx, lit_g); dfree(d_causal);
   };
   stb_status s = STB_OK;
   int64_t F = 0, C = 0, P = 0;
@@ -417,8 +418,8 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
   // in place (its rows and columns need no offsets); several: staged into
   // concatenated arrays with per-unit offsets
   const bool direct = nunit == 1;
-  bool ok = dalloc(&S_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
-            dalloc(&lit_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
+  bool ok = kalloc(ctx, &S_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
+            kalloc(ctx, &lit_g, (size_t)std::max<int64_t>(C, 1)) == hipSuccess &&
             dalloc(&d_causal, (size_t)nunit) == hipSuccess;
   if (ok && !direct)
     ok = dalloc(&trial_g, (size_t)std::max<int64_t>(P, 1)) == hipSuccess &&

@@ -4,6 +4,7 @@
 
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "stb.h"
@@ -41,6 +42,9 @@ struct stb_ctx {
   // Gauss-Legendre nodes on [0,1] for the last n_g used (device copy)
   int gl_n = 0;
   double* d_gl = nullptr;   // [4 * kMaxNg]: x, w, 1/2 - s(x), s'(x) w
+  // large temporaries of the face assembly kept for later calls (ctx_alloc,
+  // ctx_keep): free blocks and the blocks lent out, (address, bytes)
+  std::vector<std::pair<void*, size_t>> kept, lent;
 };
 
 struct stb_mesh {
@@ -124,6 +128,23 @@ static inline hipError_t dalloc(T** p, size_t count) {
 
 static inline void dfree(void* p) {
   if (p) (void)hipFree(p);
+}
+
+// Large temporaries that the context keeps between calls (freeing a block
+// of hundreds of MB takes about 0.3 ms): ctx_alloc lends a kept block of at
+// least `bytes` and at most twice that, else allocates (dropping the kept
+// blocks and retrying once when the device is full); ctx_keep takes a lent
+// block back.  The blocks are freed with the context (ctx_drop_kept).
+hipError_t ctx_alloc(stb_ctx* ctx, void** p, size_t bytes);
+void ctx_keep(stb_ctx* ctx, void* p);
+void ctx_drop_kept(stb_ctx* ctx);
+
+template <typename T>
+static inline hipError_t kalloc(stb_ctx* ctx, T** p, size_t count) {
+  void* v = nullptr;
+  const hipError_t e = ctx_alloc(ctx, &v, (count ? count : 1) * sizeof(T));
+  *p = (T*)v;
+  return e;
 }
 
 // Shared steps (stb_lib.hip).

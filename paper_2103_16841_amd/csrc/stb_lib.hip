@@ -631,6 +631,56 @@ static stb_status mirror_host(stb_mat* M) {
 }
 
 // ---------------------------------------------------------------- C ABI
+hipError_t ctx_alloc(stb_ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  size_t best = (size_t)-1;
+  int bi = -1;
+  for (size_t k = 0; k < ctx->kept.size(); ++k) {
+    const size_t n = ctx->kept[k].second;
+    if (n >= bytes && n / 2 <= bytes && n < best) {
+      best = n;
+      bi = (int)k;
+    }
+  }
+  if (bi >= 0) {
+    ctx->lent.push_back(ctx->kept[(size_t)bi]);
+    ctx->kept.erase(ctx->kept.begin() + bi);
+    *p = ctx->lent.back().first;
+    return hipSuccess;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory && !ctx->kept.empty()) {
+    (void)hipGetLastError();
+    for (auto& b : ctx->kept) (void)hipFree(b.first);
+    ctx->kept.clear();
+    e = hipMalloc(p, bytes);
+  }
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  ctx->lent.push_back({*p, bytes});
+  return hipSuccess;
+}
+
+void ctx_keep(stb_ctx* ctx, void* p) {
+  if (!p) return;
+  for (size_t k = 0; k < ctx->lent.size(); ++k)
+    if (ctx->lent[k].first == p) {
+      ctx->kept.push_back(ctx->lent[k]);
+      ctx->lent.erase(ctx->lent.begin() + (long)k);
+      return;
+    }
+  (void)hipFree(p);   // not lent by ctx_alloc
+}
+
+void ctx_drop_kept(stb_ctx* ctx) {
+  for (auto& b : ctx->kept) (void)hipFree(b.first);
+  for (auto& b : ctx->lent) (void)hipFree(b.first);
+  ctx->kept.clear();
+  ctx->lent.clear();
+}
+
 extern "C" {
 
 stb_quad_params stb_default_params(void) {
@@ -700,6 +750,7 @@ void stb_ctx_destroy(stb_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   dfree(ctx->d_gl);
   stb_free_workspace(ctx);
+  ctx_drop_kept(ctx);
   for (auto& e : ctx->ev) if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->kev) if (e) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -826,8 +877,8 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   if (s) { dfree(d_rowof); stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
   uint8_t* d_keep = nullptr;
-  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess || dalloc(&d_keep, (size_t)M->nnz) != hipSuccess) {
-    dfree(d_rowof); dfree(d_keep); stb_mat_destroy(M);
+  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess || kalloc(ctx, &d_keep, (size_t)M->nnz) != hipSuccess) {
+    dfree(d_rowof); ctx_keep(ctx, d_keep); stb_mat_destroy(M);
     return fail(ctx, STB_E_NO_MEMORY, "store of %lld entries does not fit", (long long)M->nnz);
   }
   unsigned long long causal = 0, work[4];
@@ -868,7 +919,7 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   dfree(d_rowof);
   // the resident store keeps the causal entries only
   if (s == STB_OK) s = stb_keep_causal(ctx, M, d_keep, ctx->stream);
-  dfree(d_keep);
+  ctx_keep(ctx, d_keep);
   if (s) { stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
   HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
