@@ -56,6 +56,12 @@ enum {
   CNT_EVAL_QUARTER, CNT_EVAL_NODES, CNT_EVAL_NODES32, CNT_EVAL_REDO, CNT_MISS, CNT_QZ, CNT_N
 };
 
+// Combo key: (candidate in chunk) << kKeyShift | far << 6 | q, q < 64
+// (4 m_q^2 outer points at most): 25 bits of candidate index.
+constexpr int kKeyShift = 7;
+constexpr uint32_t kKeyFar = 1u << 6;
+constexpr uint32_t kKeyQ = 63u;
+
 // Block-wide list allocation: every thread of the block calls it (n = 0
 // when it has nothing to append), with the same LDS scratch; one atomic per
 // block.  Same-address atomics serialise in the memory system, so they are
@@ -109,8 +115,8 @@ struct Lists {
   void* scan_tmp;        // prefix-sum scratch
   size_t scan_bytes;
   // per combo
-  uint32_t* key;         // (candidate in chunk) << 8 | far << 7 | q
-  uint32_t* deep;        // (candidate in chunk) << 8 | q of lit tests the vertices left open
+  uint32_t* key;         // (candidate in chunk) << kKeyShift | far << 6 | q
+  uint32_t* deep;        // (candidate in chunk) << kKeyShift | q of lit tests the vertices left open
   double* cb;            // C_k, d^2, w-range: structure of arrays, field f at f * cap_combo
   int32_t* ccol;         // trial panel of the combo (its face normals are read from there)
   int32_t* p0;           // first piece
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(kBlk, 4) void k_lit(Geo g, Lists L, int64_t c0, int
     unsigned long long k = block_alloc(L.cnt + CNT_DEEP, n, sh);
     if (v && k + n <= (unsigned long long)L.cap_combo)
       for (int q = 0; q < nq; ++q)
-        if ((und >> q) & 1ull) L.deep[k++] = ((uint32_t)c << 8) | (uint32_t)q;
+        if ((und >> q) & 1ull) L.deep[k++] = ((uint32_t)c << kKeyShift) | (uint32_t)q;
   }
   block_count(L.cnt + CNT_PAIRS, pairs);
 }
@@ -324,8 +330,8 @@ __global__ __launch_bounds__(kBlk) void k_lit_deep(Geo g, Lists L, int64_t c0, i
   const int64_t ndeep = list_count(L, ndeep_arg, L.cap_combo, 1);
   for (int64_t k = (int64_t)blockIdx.x * B + threadIdx.x; k < ndeep; k += (int64_t)gridDim.x * B) {
     const uint32_t key = L.deep[k];
-    const int64_t c = key >> 8;
-    const int q = (int)(key & 255u);
+    const int64_t c = key >> kKeyShift;
+    const int q = (int)(key & kKeyQ);
     const int64_t cg = c0 + c;
     const int32_t i = g.rows[cg];
     const TrialRec T = deep_fields(g.trial + g.cols[cg]);
@@ -357,7 +363,7 @@ __global__ __launch_bounds__(kBlk) void k_emit(Lists L, int64_t nc) {
     uint64_t mm = m;
     while (mm) {
       const int q = __ffsll((long long)mm) - 1;
-      L.key[k++] = ((uint32_t)c << 8) | (uint32_t)q;
+      L.key[k++] = ((uint32_t)c << kKeyShift) | (uint32_t)q;
       mm &= mm - 1;
     }
   }
@@ -398,8 +404,8 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
     unsigned long long miss = 0;   // pieces (by start breakpoint) found empty by the ray test
     if (v) {
       const uint32_t key = L.key[k];
-      const int64_t cg = c0 + (key >> 8);
-      const int q = (int)(key & 63u);
+      const int64_t cg = c0 + (key >> kKeyShift);
+      const int q = (int)(key & kKeyQ);
       const int32_t i = g.rows[cg];
       const int32_t col = g.cols[cg];
       const TrialRec& T = g.trial[col];
@@ -416,7 +422,7 @@ __global__ __launch_bounds__(kBlk, 3) void k_bp(Geo g, Lists L, int64_t c0, int6
         }
         cb.d2 = A.d * A.d; cb.wlo = wlo; cb.whi = whi;
         store_combo(L, k, cb, col);
-        if (g.mixed && apex_far(T, x4, g.eta_far)) L.key[k] = key | 0x80u;
+        if (g.mixed && apex_far(T, x4, g.eta_far)) L.key[k] = key | kKeyFar;
         nb = breakpoints_t(T, g.fang[col], A, bp);
         // the 8-wide network when every lane of the wave has at most 8
         // breakpoints (about half the waves), the 16-wide one otherwise
@@ -498,7 +504,7 @@ __device__ __forceinline__ unsigned route_fp64(const Lists& L, int32_t p, uint32
 }
 
 __device__ __forceinline__ unsigned route_of(const Lists& L, int32_t p, uint32_t rec) {
-  if ((L.key[L.pc[p]] >> 7) & 1u) return JOB_FP32;
+  if (L.key[L.pc[p]] & kKeyFar) return JOB_FP32;
   return route_fp64(L, p, rec);
 }
 
@@ -829,7 +835,7 @@ __global__ __launch_bounds__(kBlk) void k_combine(Lists L, int64_t ncombo_arg) {
     const int32_t p0 = L.p0[k], np = L.np[k];
     // empty pieces have no node sum (not written); far combos' non-empty
     // pieces went through the FP32 nodes and carry a rounding bound
-    const bool far = (L.key[k] >> 7) & 1u;
+    const bool far = (L.key[k] & kKeyFar) != 0;
     double I = 0.0;
     float e = 0.0f;
     for (int s = 0; s < np; ++s) {
@@ -893,7 +899,7 @@ __global__ __launch_bounds__(kBlk) void k_store(Geo g, Lists L, int64_t c0, int6
           const int32_t k = idx++;
           const double I = L.I[k];
           if (I != 0.0) s += wq[q] * I;
-          if (check && ((L.key[k] >> 7) & 1u)) bound += fabs(wq[q]) * (double)L.Ie[k];
+          if (check && (L.key[k] & kKeyFar)) bound += fabs(wq[q]) * (double)L.Ie[k];
         }
       } else if (m) {
         s = L.I[idx];
@@ -946,7 +952,7 @@ __global__ __launch_bounds__(kBlk) void k_redo(Geo g, Lists L, int64_t nc) {
       k0 = L.combo0[c];
       nk = __popcll(L.mask[c]);
       for (int32_t k = k0; k < k0 + nk; ++k) {
-        if (!((L.key[k] >> 7) & 1u)) continue;
+        if (!(L.key[k] & kKeyFar)) continue;
         for (int32_t p = L.p0[k]; p < L.p0[k] + L.np[k]; ++p)
           if (L.pne[p]) ++cnt[route_fp64(L, p, L.prec[p])];
       }
@@ -958,7 +964,7 @@ __global__ __launch_bounds__(kBlk) void k_redo(Geo g, Lists L, int64_t nc) {
     sl[JOB_R1X] = block_alloc(L.cnt + CNT_JOB1X, cnt[JOB_R1X], sh);
     if (v) {
       for (int32_t k = k0; k < k0 + nk; ++k) {
-        if (!((L.key[k] >> 7) & 1u)) continue;
+        if (!(L.key[k] & kKeyFar)) continue;
         for (int32_t p = L.p0[k]; p < L.p0[k] + L.np[k]; ++p) {
           if (!L.pne[p]) continue;
           const unsigned r = route_fp64(L, p, L.prec[p]);
@@ -1016,9 +1022,10 @@ static size_t ws_bytes(int64_t cc, int64_t cb, int64_t cp) {
 
 // List capacities a run over nnz candidates with maxq apexes each asks for.
 static void ws_want(int64_t nnz, int maxq, int64_t* cc, int64_t* cb, int64_t* cp) {
-  const int64_t kCandMax = (int64_t)1 << 24;
+  const int64_t kCandMax = std::min<int64_t>((int64_t)1 << (32 - kKeyShift),
+                                             (int64_t)INT32_MAX / std::max(maxq, 1));
   *cc = std::min<int64_t>(nnz, kCandMax);
-  *cb = std::min<int64_t>(*cc * maxq, (int64_t)1 << 26);
+  *cb = std::min<int64_t>(*cc * maxq, (int64_t)1 << 27);
   *cp = std::min<int64_t>(*cb * 8, (int64_t)1 << 28);
 }
 
@@ -1110,7 +1117,8 @@ stb_status stb_run_pairs(stb_ctx* ctx, const PairJob& job, unsigned long long wo
   for (int k = 0; k < 4; ++k) work[k] = 0;
   if (job.nnz <= 0) return STB_OK;
   // sizes: the whole candidate set when it is small, else chunks of up to
-  // 2^24 candidates (the combo key holds 24 bits of candidate index)
+  // 2^25 candidates (the combo key holds 25 bits of candidate index; the
+  // int32 combo offsets, at most maxq per candidate, bound it too)
   int64_t want_cand, want_combo, want_piece;
   ws_want(job.nnz, job.maxq, &want_cand, &want_combo, &want_piece);
   int64_t* const want[3] = {&want_cand, &want_combo, &want_piece};
