@@ -599,14 +599,15 @@ STB_HD __forceinline__ int roots2(double qa, double qb, double qc, double* r) {
   const double q = -0.5 * (qb + copysign(sqrt_nn(disc), qb));
   const double rqa = frcp(lin ? 1.0 : qa);
   const double rq = frcp(q == 0.0 ? 1.0 : q);
-  const double rqb = frcp(qb == 0.0 ? 1.0 : qb);
   double r0 = q * rqa, r1 = qc * rq;
   int n = 2;
   r0 = q == 0.0 ? 0.0 : r0;
   n = q == 0.0 ? 1 : n;
   r0 = neg ? -0.5 * qb * rqa : r0;
   n = neg ? (near ? 1 : 0) : n;
-  r0 = lin ? -qc * rqb : r0;
+  // linear (qa = 0): disc = qb^2, q = -qb up to the square root's rounding,
+  // so qc / q is the root -qc / qb
+  r0 = lin ? r1 : r0;
   n = lin ? (qb == 0.0 ? 0 : 1) : n;
   r[0] = r0;
   r[1] = r1;
