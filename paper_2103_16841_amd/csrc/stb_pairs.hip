@@ -633,13 +633,12 @@ __global__ __launch_bounds__(kBlk, 3) void k_quarter(Lists L, int64_t nq_arg) {
       const double a = L.pa[p], H = L.ph[p];
       // the test in plain arithmetic; the recipe only for the (few) pieces
       // it finds non-empty, at the point that decided
+      // (both points, independent of each other: a wave nearly always has a
+      // lane that needs the second)
       uint32_t rec = 0u;
-      double phq = a + 0.25 * H;
-      bool nz = L_at(cb, phq) != 0.0;
-      if (!nz) {
-        phq = a + 0.75 * H;
-        nz = L_at(cb, phq) != 0.0;
-      }
+      const double v1 = L_at(cb, a + 0.25 * H), v3 = L_at(cb, a + 0.75 * H);
+      const bool nz = v1 != 0.0 || v3 != 0.0;
+      const double phq = v1 != 0.0 ? a + 0.25 * H : a + 0.75 * H;
       ev_quarter += 2;
       if (nz) {
         double sn, cs;
