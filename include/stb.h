@@ -274,7 +274,7 @@ stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* const* mesh
 
 /* Launch-shape autotuner of the pair pipeline: times every stage (lit
  * test, breakpoints, empty-piece test, FP64 and FP32 Gauss nodes) on a
- * strided sample of about 2^20 of mesh's (test, trial) candidates for each
+ * strided sample of about 2^22 of mesh's (test, trial) candidates for each
  * threads-per-block in {64, 128, 256} and resident blocks per CU in
  * {4, 8, 16, 32}, keeps the fastest per stage in ctx (used by every later
  * assembly, potential and batch on ctx) and, when cfg16 is not NULL, writes
@@ -286,7 +286,8 @@ stb_status stb_autotune(stb_ctx* ctx, const stb_mesh* mesh, const stb_quad_param
 
 /* Set the launch shapes (cfg16 as written by stb_autotune; block sizes
  * multiples of 64 in [64, 256], 1..64 blocks per CU), or restore the
- * defaults (256 threads, 16 blocks per CU) with cfg16 = NULL. */
+ * defaults (256 threads; 32 blocks per CU for stages 0-2, 16 for the
+ * others) with cfg16 = NULL. */
 stb_status stb_set_tuning(stb_ctx* ctx, const int32_t* cfg16);
 
 /* Upper limits on the lengths of the pair pipeline's lists on ctx, per

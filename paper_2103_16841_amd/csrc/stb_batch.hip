@@ -353,7 +353,7 @@ extern "C" stb_status stb_batch_assemble(stb_ctx* ctx, int32_t nmesh, stb_mesh* 
   return STB_OK;
 }
 
-// Autotune the pair pipeline on a strided sample (about 2^20 candidates) of
+// Autotune the pair pipeline on a strided sample (about 2^22 candidates) of
 // one mesh's assembly.
 extern "C" stb_status stb_autotune(stb_ctx* ctx, const stb_mesh* mesh_c,
                                    const stb_quad_params* params, int32_t* cfg16) {
@@ -373,7 +373,7 @@ extern "C" stb_status stb_autotune(stb_ctx* ctx, const stb_mesh* mesh_c,
   auto cleanup = [&]() { dfree(rowptr); dfree(cols); dfree(rowof); dfree(rs); dfree(cs); dfree(out); };
   s = stb_cull(ctx, mesh->nt, mesh->d_box, mesh, &rowptr, &cols, &rowof, &nnz);
   if (s) { cleanup(); return s; }
-  const int64_t want = (int64_t)1 << 20;
+  const int64_t want = (int64_t)1 << 22;
   const int64_t stride = std::max<int64_t>(1, nnz / want);
   const int64_t n = nnz / stride;
   if (n > 0) {
@@ -415,13 +415,13 @@ extern "C" stb_status stb_autotune(stb_ctx* ctx, const stb_mesh* mesh_c,
 extern "C" stb_status stb_set_tuning(stb_ctx* ctx, const int32_t* cfg16) {
   if (!ctx) return stb_fail(nullptr, STB_E_INVALID_ARG, "NULL context");
   for (int k = 0; k < 8; ++k) {
-    int b = cfg16 ? cfg16[k] : 256, pc = cfg16 ? cfg16[8 + k] : 16;
+    int b = cfg16 ? cfg16[k] : 256, pc = cfg16 ? cfg16[8 + k] : kDefaultPerCu[k];
     if (b < 64 || b > 256 || (b & 63) || pc < 1 || pc > 64)
       return stb_fail(ctx, STB_E_INVALID_ARG, "stage %d: block %d / blocks per CU %d out of range", k, b, pc);
   }
   for (int k = 0; k < 8; ++k) {
     ctx->tune_block[k] = cfg16 ? cfg16[k] : 256;
-    ctx->tune_per_cu[k] = cfg16 ? cfg16[8 + k] : 16;
+    ctx->tune_per_cu[k] = cfg16 ? cfg16[8 + k] : kDefaultPerCu[k];
   }
   ctx->tuned = cfg16 != nullptr;
   return STB_OK;

@@ -11,6 +11,12 @@
 #include "stb_device.h"
 
 // ---------------------------------------------------------------- handles
+// Default resident blocks per CU of the pair pipeline's stages (kinds of
+// stb_last_kernel_times): the lit test, breakpoint and empty-piece stages
+// gain from 32 (more blocks to even out their per-item work), the Gauss
+// nodes run best at 16 (measured on the 30,720-panel bench assembly).
+constexpr int kDefaultPerCu[8] = {32, 32, 32, 16, 16, 16, 16, 16};
+
 struct stb_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -33,7 +39,8 @@ struct stb_ctx {
   // launch shapes of the pair pipeline's stages (autotuned or defaults):
   // threads per block and blocks per compute unit, indexed like kern_ms
   int tune_block[8] = {256, 256, 256, 256, 256, 256, 256, 256};
-  int tune_per_cu[8] = {16, 16, 16, 16, 16, 16, 16, 16};
+  int tune_per_cu[8] = {kDefaultPerCu[0], kDefaultPerCu[1], kDefaultPerCu[2], kDefaultPerCu[3],
+                        kDefaultPerCu[4], kDefaultPerCu[5], kDefaultPerCu[6], kDefaultPerCu[7]};
   bool tuned = false;
   int ncu = 0;
   // caller's upper limits on the pair lists' lengths: candidates, lit

@@ -1348,7 +1348,8 @@ extern "C" stb_status stb_set_pair_lists(stb_ctx* ctx, int64_t max_cand, int64_t
 // latency hiding against tail effects and L2 locality of neighbouring
 // items.  Each stage is timed on the sample (HIP events) for every shape
 // with the other stages at their current choice, in order of their share of
-// the time; the fastest shape is kept in the context.
+// the time; a shape replaces the stage's current one only when it is faster
+// by more than 2% (timing noise on the sample is about that size).
 stb_status stb_tune_pairs(stb_ctx* ctx, const PairJob& sample) {
   static const int kStages[] = {4, 5, 2, 1, 0};
   static const int kBlocks[] = {64, 128, 256};
@@ -1358,14 +1359,15 @@ stb_status stb_tune_pairs(stb_ctx* ctx, const PairJob& sample) {
   if (s) return s;
   for (int stage : kStages) {
     if (ctx->kern_n[stage] == 0) continue;   // stage unused on this sample
-    double best = 1e300;
     int bb = ctx->tune_block[stage], bp = ctx->tune_per_cu[stage];
+    if ((s = stb_run_pairs(ctx, sample, work))) return s;
+    double best = ctx->kern_ms[stage];   // the current shape
     for (int b : kBlocks)
       for (int pc : kPerCu) {
         ctx->tune_block[stage] = b;
         ctx->tune_per_cu[stage] = pc;
         if ((s = stb_run_pairs(ctx, sample, work))) return s;
-        if (ctx->kern_ms[stage] < best) {
+        if (ctx->kern_ms[stage] < 0.98 * best) {
           best = ctx->kern_ms[stage];
           bb = b;
           bp = pc;
