@@ -60,8 +60,8 @@ def node_flops(counts):
 # profiles/node_stage_icosphere_L2_S32.md: per launch group of the FP64
 # node stage, and summed over every kernel of one assembly.  Set to None
 # whenever the kernels change until they are profiled again.
-K_NODES_TRAFFIC_BYTES = 8.547e9
-ASSEMBLY_TRAFFIC_BYTES = 3.174e11
+K_NODES_TRAFFIC_BYTES = 1.288e10
+ASSEMBLY_TRAFFIC_BYTES = 3.083e11
 
 
 def parse():
