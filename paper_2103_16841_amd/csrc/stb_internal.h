@@ -160,8 +160,11 @@ stb_status stb_check_params(stb_ctx* ctx, const stb_quad_params* p);
 stb_status stb_ensure_outer(stb_ctx* ctx, stb_mesh* m, int mq);
 // Conservative cull of rows (apex boxes) against all panels of m into CSR
 // candidates (rowptr, cols ascending per row) and the row of each candidate.
+// lend: cols and rowof are blocks lent by ctx (ctx_alloc), to be handed
+// back with ctx_keep.
 stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, const stb_mesh* m,
-                    int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz);
+                    int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz,
+                    bool lend = false);
 stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const stb::ApexBox* d_rows, const stb_mesh* m,
                           int64_t* nnz);
 // Exclusive prefix of the per-row candidate counts (nrows + 1 entries, host).
@@ -191,7 +194,9 @@ stb_status stb_face_assemble(stb_ctx* ctx, const stb_quad_params& p, FaceUnit* u
 
 // Drops the stored candidates whose flag is 0 (non-causal pairs): M keeps
 // exactly its causal entries, rows and column order unchanged, nnz =
-// the number of flags set.  Synchronises st.
+// the number of flags set; the candidate store's columns and values go to
+// ctx_keep (lent blocks back to the context, others freed).  Synchronises
+// st.
 stb_status stb_keep_causal(stb_ctx* ctx, stb_mat* M, const uint8_t* d_flag, hipStream_t st);
 
 // Lit search of evaluation points by the cluster tree (stb_tree.hip): the

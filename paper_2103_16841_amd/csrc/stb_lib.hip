@@ -526,7 +526,7 @@ stb_status stb_cull_count(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, co
 // Cull rows (apex boxes) against all trial panels into CSR candidates, with
 // the row of every candidate alongside.
 stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const stb_mesh* m,
-                       int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz) {
+                       int64_t** d_rowptr, int32_t** d_cols, int32_t** d_rowof, int64_t* nnz, bool lend) {
   int64_t* d_cnt = nullptr;
   HIPCHK(ctx, dalloc(&d_cnt, (size_t)nrows));
   HIPCHK(ctx, dalloc(d_rowptr, (size_t)nrows + 1));
@@ -540,8 +540,8 @@ stb_status stb_cull(stb_ctx* ctx, int64_t nrows, const ApexBox* d_rows, const st
   dfree(d_cnt);
   if (s) return s;
   HIPCHK(ctx, hipMemcpy(nnz, *d_rowptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost));
-  HIPCHK(ctx, dalloc(d_cols, (size_t)*nnz));
-  HIPCHK(ctx, dalloc(d_rowof, (size_t)*nnz));
+  HIPCHK(ctx, lend ? kalloc(ctx, d_cols, (size_t)*nnz) : dalloc(d_cols, (size_t)*nnz));
+  HIPCHK(ctx, lend ? kalloc(ctx, d_rowof, (size_t)*nnz) : dalloc(d_rowof, (size_t)*nnz));
   if (nrows > 0) {
     hipLaunchKernelGGL(k_cull_fill, dim3((unsigned)((nrows + kCullRows - 1) / kCullRows)), dim3(kCullThreads),
                        0, ctx->stream,
@@ -599,8 +599,8 @@ stb_status stb_keep_causal(stb_ctx* ctx, stb_mat* M, const uint8_t* d_flag, hipS
   if (e != hipSuccess) { cleanup(); return fail(ctx, STB_E_DEVICE, "causal store: %s", hipGetErrorString(e)); }
   dfree(cnt);
   dfree(M->d_rowptr);
-  dfree(M->d_cols);
-  dfree(M->d_vals);
+  ctx_keep(ctx, M->d_cols);
+  ctx_keep(ctx, M->d_vals);
   dfree(M->d_vals32);
   M->d_vals32 = nullptr;
   stb_free_blocked(M);
@@ -872,13 +872,24 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
   stb_mat* M = new stb_mat();
   M->ctx = ctx;
   M->n = mesh->nt;
+  // the candidate store (columns, values), the candidates' rows and their
+  // causal flags are blocks lent by the context until the causal-only
+  // store replaces them
   int32_t* d_rowof = nullptr;
-  s = stb_cull(ctx, mesh->nt, mesh->d_box, mesh, &M->d_rowptr, &M->d_cols, &d_rowof, &M->nnz);
-  if (s) { dfree(d_rowof); stb_mat_destroy(M); return s; }
+  auto drop = [&]() {
+    ctx_keep(ctx, d_rowof);
+    d_rowof = nullptr;
+    ctx_keep(ctx, M->d_cols);
+    M->d_cols = nullptr;
+    ctx_keep(ctx, M->d_vals);
+    M->d_vals = nullptr;
+  };
+  s = stb_cull(ctx, mesh->nt, mesh->d_box, mesh, &M->d_rowptr, &M->d_cols, &d_rowof, &M->nnz, true);
+  if (s) { drop(); stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
   uint8_t* d_keep = nullptr;
-  if (dalloc(&M->d_vals, (size_t)M->nnz) != hipSuccess || kalloc(ctx, &d_keep, (size_t)M->nnz) != hipSuccess) {
-    dfree(d_rowof); ctx_keep(ctx, d_keep); stb_mat_destroy(M);
+  if (kalloc(ctx, &M->d_vals, (size_t)M->nnz) != hipSuccess || kalloc(ctx, &d_keep, (size_t)M->nnz) != hipSuccess) {
+    drop(); ctx_keep(ctx, d_keep); stb_mat_destroy(M);
     return fail(ctx, STB_E_NO_MEMORY, "store of %lld entries does not fit", (long long)M->nnz);
   }
   unsigned long long causal = 0, work[4];
@@ -916,11 +927,13 @@ stb_status stb_assemble_V(stb_ctx* ctx, const stb_mesh* mesh_c, const stb_quad_p
     J.n_causal = &causal;
     s = stb_run_pairs(ctx, J, work);
   }
-  dfree(d_rowof);
-  // the resident store keeps the causal entries only
+  ctx_keep(ctx, d_rowof);
+  d_rowof = nullptr;
+  // the resident store keeps the causal entries only (and hands the
+  // candidate store back to the context)
   if (s == STB_OK) s = stb_keep_causal(ctx, M, d_keep, ctx->stream);
   ctx_keep(ctx, d_keep);
-  if (s) { stb_mat_destroy(M); return s; }
+  if (s) { drop(); stb_mat_destroy(M); return s; }
   HIPCHK(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
   HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
   M->n_causal = (int64_t)causal;
