@@ -49,9 +49,11 @@ struct stb_ctx {
   // Gauss-Legendre nodes on [0,1] for the last n_g used (device copy)
   int gl_n = 0;
   double* d_gl = nullptr;   // [4 * kMaxNg]: x, w, 1/2 - s(x), s'(x) w
-  // large temporaries of the face assembly kept for later calls (ctx_alloc,
-  // ctx_keep): free blocks and the blocks lent out, (address, bytes)
+  // large temporaries of the assembly kept for later calls (ctx_alloc,
+  // ctx_keep): free blocks and the blocks lent out, (address, bytes); the
+  // free ones hold kept_bytes <= kKeptMaxBytes
   std::vector<std::pair<void*, size_t>> kept, lent;
+  size_t kept_bytes = 0;
 };
 
 struct stb_mesh {
@@ -141,7 +143,10 @@ static inline void dfree(void* p) {
 // of hundreds of MB takes about 0.3 ms): ctx_alloc lends a kept block of at
 // least `bytes` and at most twice that, else allocates (dropping the kept
 // blocks and retrying once when the device is full); ctx_keep takes a lent
-// block back.  The blocks are freed with the context (ctx_drop_kept).
+// block back, or frees it when the kept blocks would exceed kKeptMaxBytes
+// (a context that assembled a very large mesh does not go on holding its
+// temporaries).  The blocks are freed with the context (ctx_drop_kept).
+constexpr size_t kKeptMaxBytes = (size_t)8 << 30;
 hipError_t ctx_alloc(stb_ctx* ctx, void** p, size_t bytes);
 void ctx_keep(stb_ctx* ctx, void* p);
 void ctx_drop_kept(stb_ctx* ctx);

@@ -644,6 +644,7 @@ hipError_t ctx_alloc(stb_ctx* ctx, void** p, size_t bytes) {
   }
   if (bi >= 0) {
     ctx->lent.push_back(ctx->kept[(size_t)bi]);
+    ctx->kept_bytes -= ctx->kept[(size_t)bi].second;
     ctx->kept.erase(ctx->kept.begin() + bi);
     *p = ctx->lent.back().first;
     return hipSuccess;
@@ -653,6 +654,7 @@ hipError_t ctx_alloc(stb_ctx* ctx, void** p, size_t bytes) {
     (void)hipGetLastError();
     for (auto& b : ctx->kept) (void)hipFree(b.first);
     ctx->kept.clear();
+    ctx->kept_bytes = 0;
     e = hipMalloc(p, bytes);
   }
   if (e != hipSuccess) {
@@ -667,7 +669,13 @@ void ctx_keep(stb_ctx* ctx, void* p) {
   if (!p) return;
   for (size_t k = 0; k < ctx->lent.size(); ++k)
     if (ctx->lent[k].first == p) {
-      ctx->kept.push_back(ctx->lent[k]);
+      const size_t n = ctx->lent[k].second;
+      if (ctx->kept_bytes + n <= kKeptMaxBytes) {
+        ctx->kept.push_back(ctx->lent[k]);
+        ctx->kept_bytes += n;
+      } else {
+        (void)hipFree(p);
+      }
       ctx->lent.erase(ctx->lent.begin() + (long)k);
       return;
     }
@@ -679,6 +687,7 @@ void ctx_drop_kept(stb_ctx* ctx) {
   for (auto& b : ctx->lent) (void)hipFree(b.first);
   ctx->kept.clear();
   ctx->lent.clear();
+  ctx->kept_bytes = 0;
 }
 
 extern "C" {
