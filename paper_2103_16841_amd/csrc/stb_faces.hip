@@ -237,10 +237,11 @@ stb_status stb_ensure_faces(stb_ctx* ctx, stb_mesh* m, int mq) {
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   }
   // unique active faces by sorted vertex ids, numbered in order of first
-  // appearance (panel, slot); open addressing in a power-of-two table at
-  // most one-eighth full
+  // appearance (panel, slot); open addressing in a power-of-two table of at
+  // least 8 entries per panel: at most half full (4 faces per panel, each
+  // shared faces counted once; an eighth for conforming slab meshes)
   size_t tcap = 16;
-  while (tcap < (size_t)nt * 32) tcap <<= 1;
+  while (tcap < (size_t)nt * 8) tcap <<= 1;
   std::vector<int32_t> table(tcap, -1);
   const size_t tmask = tcap - 1;
   std::vector<int32_t> fv;
