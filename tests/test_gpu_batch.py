@@ -191,3 +191,41 @@ def test_list_limits_keep_results(stb, ctx, prec):
             assert np.array_equal(a, b)
     finally:
         c2.close()
+
+
+def test_kept_temporaries_keep_results(stb):
+    """A context lends the temporaries it kept from earlier assemblies (the
+    candidate store, the face sums and flags) to later ones: a mesh, a
+    smaller one and the first again on one context give the same values,
+    bit for bit, as on fresh contexts."""
+    big = inputs.icosphere_mesh(level=1, S=6, T=4.0, jitter=0.2, seed=4)
+    small = inputs.cube_mesh(S=4, T=2.0)
+
+    def fresh(mesh):
+        c = stb.Context(0)
+        try:
+            m = stb.Mesh(c, mesh.vtx, mesh.tets)
+            A = stb.assemble_V(c, m)
+            out = A.export()
+            A.close()
+            m.close()
+            return out
+        finally:
+            c.close()
+
+    ref_big, ref_small = fresh(big), fresh(small)
+    c = stb.Context(0)
+    try:
+        got = []
+        for mesh in (big, small, big):
+            print("case: kept temporaries, mesh of", mesh.nt, "panels", flush=True)
+            m = stb.Mesh(c, mesh.vtx, mesh.tets)
+            A = stb.assemble_V(c, m)
+            got.append(A.export())
+            A.close()
+            m.close()
+        for out, ref in zip(got, (ref_big, ref_small, ref_big)):
+            for a, b in zip(out, ref):
+                assert np.array_equal(a, b)
+    finally:
+        c.close()
